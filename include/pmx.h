@@ -1,0 +1,273 @@
+/*
+ * pmx.h - Kronecker-structured payoff-matrix gradients for poker endgames on
+ * AMD Instinct MI355X (gfx950).  C ABI of libpmx.so.
+ *
+ * What it computes (Farina & Sandholm, "Fast Payoff Matrix Sparsification
+ * Techniques for Structured Extensive-Form Games", AAAI 2022):
+ *
+ *   - Section 2: the payoff matrix A of Player 1 has rows indexed by Player
+ *     1's sequences and columns by Player 2's; a terminal z contributes its
+ *     payoff times the probability of the chance events leading to it.
+ *     First-order solvers need the gradients A y and A^T x every iteration
+ *     (Section 2, application 3).
+ *   - Section 3 (Prop. 1): for a river endgame with deal distribution pi and
+ *     outcome gamma,  A = C (x) F + (L1 W L2) (x) S : every hand pair plays the
+ *     same betting skeleton, so A is a sum of Kronecker products of a small
+ *     betting factor and a hand-comparison factor.  A turn endgame is
+ *     block-diagonal over the river card (Section 3, last paragraph).
+ *   - Section 4 (eq. cf and Technique B): the compatibility term is a rank-one
+ *     product minus a card-collision correction, and the win/lose term,
+ *     with hands sorted by strength, is the inverse of a bidiagonal
+ *     difference operator, i.e. a prefix sum.  The library never forms A: it
+ *     applies each hand factor as a strength-sorted prefix scan with per-card
+ *     inclusion-exclusion corrections.
+ *   - Section 5 (first-order methods): a regret-based solver (here regret
+ *     matching+, alternating, linear averaging) updates all hands in
+ *     parallel; exploitability = half the saddle gap over the initial pot.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  * Players are 0 (Player 1, small blind, acts first, maximizes x^T A y) and
+ *    1 (Player 2).
+ *  * Sequences of each player are numbered in depth-first preorder of the
+ *    betting tree: when a decision node is first visited all its actions get
+ *    consecutive ids in the order fold, check/call, bets and raises by
+ *    ascending size, all-in; children are then visited in action order; a
+ *    chance node (turn + river endgames) visits river cards in the order
+ *    given.  The empty sequence has no id (parent -1).
+ *  * Vectors are sequence-major and hand-contiguous: element (s, h) of player
+ *    p's vector is at [s * stride + h], h indexing the player's hand list in
+ *    the order it was given.  Entries h >= n_hands of a row are padding: they
+ *    are ignored on input and written as 0 on output.
+ *  * A game may hold several independent instances (a batch).  Instance i's
+ *    vector block of player p starts at element vec_offset (game_layout) and
+ *    spans n_seq * stride elements; a batched buffer is the concatenation.
+ *  * Device pointers are caller-owned HIP device allocations; host pointers
+ *    are plain host memory.  Streams are hipStream_t passed as void*
+ *    (NULL = the default stream).  Asynchronous calls only enqueue work.
+ *  * Every call returns PMX_OK (0) or a negative PMX_E* code; on error no
+ *    out-parameter is written and pmx_last_error() describes the failure.
+ *    No C++ exception crosses the ABI.
+ */
+#ifndef PMX_H
+#define PMX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PMX_OK = 0,
+  PMX_EINVAL = -1,    /* invalid argument or descriptor                        */
+  PMX_ENOMEM = -2,    /* host or device allocation failed                      */
+  PMX_EDEVICE = -3,   /* a HIP call failed (message carries hipGetErrorString)  */
+  PMX_ESTATE = -4,    /* call not valid in the handle's state (e.g. host-only)  */
+  PMX_ENUMERIC = -5   /* NaN/Inf detected in a solver quantity                 */
+};
+
+/* Terminal kinds (Section 3: F collects fold payoffs, S showdown stakes). */
+enum { PMX_FOLD_P1 = 0, PMX_FOLD_P2 = 1, PMX_SHOWDOWN = 2 };
+
+typedef struct Game Game;   /* opaque; owns host and device state */
+
+/*
+ * GameDesc - one endgame instance (Section 3: board B, stacks (s1, s2), pot
+ * contribution c, beliefs mu_1, mu_2; betting abstraction of Appendix A).
+ * All arrays are read during game_create and copied; the caller keeps them.
+ *
+ *  deck_size        cards are 0 .. deck_size-1 (deck_size <= 64)
+ *  cards_per_hand   1 or 2
+ *  n_board, board   public cards already dealt (none may repeat)
+ *  n_river, river_cards
+ *                   0 for a river endgame.  Otherwise a turn + river endgame:
+ *                   after the first betting round one more card is dealt
+ *                   uniformly from the cards not on the board and not in
+ *                   either hand; river_cards must list exactly the cards not
+ *                   on the board.
+ *  n_hands[p], hand_cards[p]
+ *                   player p's hand list, [n_hands][cards_per_hand] card ids;
+ *                   no hand may repeat a card or use a board card.
+ *                   1 <= n_hands <= 1280.
+ *  strength[p]      [max(1, n_river)][n_hands[p]]: hand strength on each final
+ *                   board; higher wins, equal ties.  A hand that appears in
+ *                   both lists must have equal strengths.  Entries of hands
+ *                   holding that board's river card are ignored.
+ *  range[p]         [n_hands[p]] belief weights mu_p >= 0, finite, any scale
+ *                   (beta normalizes); sum over compatible pairs must be > 0.
+ *  contrib          each player's pot contribution before the endgame (> 0)
+ *  stack[p]         chips behind (>= 0)
+ *  n_bet_fracs, bet_fracs
+ *                   bet / raise sizes: match the opponent, then add fraction
+ *                   x the pot after matching (Fig. 1 caption); each > 0.
+ *  max_raises       raises allowed after the opening bet of a round (>= 0)
+ *  allow_allin      nonzero: offer all-in (also past the raise cap)
+ */
+typedef struct {
+  int32_t deck_size, cards_per_hand;
+  int32_t n_board;
+  const uint8_t* board;
+  int32_t n_river;
+  const uint8_t* river_cards;
+  int32_t n_hands[2];
+  const uint8_t* hand_cards[2];
+  const int32_t* strength[2];
+  const double* range[2];
+  double contrib;
+  double stack[2];
+  int32_t n_bet_fracs;
+  const double* bet_fracs;
+  int32_t max_raises;
+  int32_t allow_allin;
+} GameDesc;
+
+/*
+ * Layout - shape of one instance for one player.  The pointed-to arrays are
+ * owned by the Game and stay valid until game_destroy.
+ *   infoset_parent[i]  parent sequence id of infoset i (-1 = empty sequence)
+ *   infoset_first[i]   first action's sequence id (actions are consecutive)
+ *   infoset_nact[i]    number of actions
+ *   infoset_board[i]   -1 first betting round, r >= 0 river card index
+ */
+typedef struct {
+  int32_t n_seq;
+  int32_t n_hands;
+  int32_t stride;          /* row stride of vectors (>= n_hands, multiple of 4) */
+  int64_t vec_offset;      /* element offset of this instance's block           */
+  int64_t vec_elems;       /* total elements of the batched buffer (all instances) */
+  int32_t n_infosets;
+  const int32_t* infoset_parent;
+  const int32_t* infoset_first;
+  const int32_t* infoset_nact;
+  const int32_t* infoset_board;
+} Layout;
+
+/*
+ * Terminals of one instance (Section 2 / 3: the leaves of the skeleton).
+ * seq[0], seq[1]: last sequence of each player; kind: PMX_FOLD_P1 / _P2 /
+ * PMX_SHOWDOWN; c1, c2: pot contributions; board: -1 first round, else river
+ * card index; runout: showdown reached all-in before the river card.
+ */
+typedef struct {
+  int32_t n_terminals;
+  const int32_t* seq1;
+  const int32_t* seq2;
+  const int32_t* kind;
+  const int32_t* board;
+  const int32_t* runout;
+  const double* c1;
+  const double* c2;
+} Terminals;
+
+/*
+ * HandMeta - integer hand metadata of one (instance, board context, player)
+ * used by the hand operators; exported so tests can check it bit-exactly.
+ * Board context 0 is the first-round board; context 1 + r is river card r
+ * (turn + river endgames only).  Hands are ordered by (strength, index).
+ *   rank[h]     position of hand h in that order among live hands, -1 dead
+ *   n_live      live hands
+ *   lt[h], le[h]  number of live opponent hands strictly weaker / not
+ *               stronger than h (-1 if h is dead)
+ *   self_[h]    rank of the opponent's hand with the same cards (-1 none)
+ *   beta        sum of mu1 mu2 over compatible pairs (same for all contexts)
+ */
+typedef struct {
+  int32_t n_hands;
+  int32_t n_live;
+  const int32_t* rank;
+  const int32_t* lt;
+  const int32_t* le;
+  const int32_t* self_;
+  double beta;
+} HandMeta;
+
+/* ---- lifetime ------------------------------------------------------------ */
+
+/* Validate and build one instance (host) and upload it to the current HIP
+ * device.  Synchronous.  PMX_EINVAL names the offending field. */
+int game_create(const GameDesc* desc, Game** out);
+
+/* Build n instances as one batched game (Section 5's solver applied to many
+ * endgames at once); each instance keeps its own vectors (game_layout). */
+int game_create_batch(const GameDesc* descs, int32_t n, Game** out);
+
+/* Host-only build: layout, terminals and hand metadata are available, but no
+ * device memory is touched; device calls return PMX_ESTATE.  Usable on
+ * machines without a GPU. */
+int game_create_host(const GameDesc* descs, int32_t n, Game** out);
+
+/* Free host and device state.  NULL is accepted.  Synchronizes the device. */
+void game_destroy(Game* g);
+
+int game_num_instances(const Game* g, int32_t* n);
+int game_layout(const Game* g, int32_t instance, int32_t player, Layout* out);
+int game_terminals(const Game* g, int32_t instance, Terminals* out);
+int game_hand_meta(const Game* g, int32_t instance, int32_t ctx, int32_t player, HandMeta* out);
+
+/* ---- gradients (Section 2 app. 3; Prop. 1; eq. cf; Technique B) ----------- */
+
+/* out = A y (Player 1's gradient).  y: player 1's vectors (all instances),
+ * out: player 0's.  FP32 in and out; hand scans accumulate in FP64.  Both
+ * device pointers, sizes vec_elems of the respective player; must not alias.
+ * Asynchronous on `stream`. */
+int matvec_A(Game* g, const float* y_dev, float* out_dev, void* stream);
+
+/* out = A^T x.  x: player 0's vectors, out: player 1's.  As matvec_A. */
+int matvec_AT(Game* g, const float* x_dev, float* out_dev, void* stream);
+
+/* FP64 forms (used for the saddle gap and for precision checks). */
+int matvec_A_f64(Game* g, const double* y_dev, double* out_dev, void* stream);
+int matvec_AT_f64(Game* g, const double* x_dev, double* out_dev, void* stream);
+
+/* Both products of one matvec pair in a single launch (x and y independent):
+ * out_x = A y, out_y = A^T x. */
+int matvec_pair(Game* g, const float* y_dev, const float* x_dev, float* Ay_dev,
+                float* ATx_dev, void* stream);
+
+/* ---- regret matching+ solver (Section 5; per hand, all hands in parallel) -- */
+
+/* Reset to t = 0: zero regrets and averages, uniform current strategies.
+ * Asynchronous. */
+int solver_reset(Game* g, void* stream);
+
+/* Run n_iters alternating RM+ iterations: g1 = A y_t, update Player 1;
+ * g2 = -A^T x_{t+1}, update Player 2; averages += t * (x_t, y_t).
+ * Asynchronous. */
+int solver_step(Game* g, int32_t n_iters, void* stream);
+
+/* FP64 saddle gap of the average strategies (exploitability = gap / 2, over
+ * the initial pot 2 * contrib).  gap, br1, br2 are host arrays with one
+ * entry per instance: br1 = max_x x^T A ybar, br2 = min_y xbar^T A y,
+ * gap = br1 - br2 >= 0 (chips).  Synchronizes `stream`. */
+int saddle_gap(Game* g, double* gap, double* br1, double* br2, void* stream);
+
+/* The same for given sequence-form strategies (device FP64 vectors of each
+ * player, vec_elems each).  Synchronizes `stream`. */
+int saddle_gap_of(Game* g, const double* x_dev, const double* y_dev, double* gap,
+                  double* br1, double* br2, void* stream);
+
+/* Copy solver state to / from host arrays (NULL skips a field).  Regrets and
+ * current plans are FP32, averages FP64 (weighted sums, divide by wsum).
+ * t = iterations done; wsum = sum of the averaging weights. */
+int solver_get_state(Game* g, int32_t player, float* regret, float* plan,
+                     double* avg_sum, int32_t* t, double* wsum);
+int solver_set_state(Game* g, int32_t player, const float* regret, const float* plan,
+                     const double* avg_sum, int32_t t, double wsum);
+
+/* Average strategy in sequence form (FP64 host array, vec_elems). */
+int get_average_strategy(Game* g, int32_t player, double* x_host);
+
+/* Warm start: behavioural strategy b(a|I) per sequence (device FP32,
+ * vec_elems), used as the current strategy (regrets = scale * b). */
+int set_initial_strategy(Game* g, int32_t player, const float* behav_dev, float scale,
+                         void* stream);
+
+/* Thread-local description of the last error ("" if none). */
+const char* pmx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMX_H */

@@ -245,3 +245,35 @@ class Game:
         for t in self.sf.terminals:
             acc[t.seq2] += np.abs(self.hm.q_matrix(t)).sum(axis=0)
         return acc
+
+
+def abs_entry_A(game: Game, y, s1, h1):
+    """(|A| |y|)[s1, h1]: the scale of one output entry (tolerances)."""
+    acc = 0.0
+    for t in game.sf.terminals:
+        if t.seq1 == s1:
+            acc += float(np.abs(game.hm.q_row(t, h1)) @ np.abs(y[t.seq2]))
+    return acc
+
+
+def abs_entry_AT(game: Game, x, s2, h2):
+    acc = 0.0
+    for t in game.sf.terminals:
+        if t.seq2 == s2:
+            acc += float(np.abs(game.hm.q_col(t, h2)) @ np.abs(x[t.seq1]))
+    return acc
+
+
+def abs_matvec_A(game: Game, y):
+    """|A| |y| for every entry (matrix-free)."""
+    out = np.zeros((game.S[0], game.N[0]))
+    for t in game.sf.terminals:
+        out[t.seq1] += np.abs(game.hm.q_matrix(t)) @ np.abs(y[t.seq2])
+    return out
+
+
+def abs_matvec_AT(game: Game, x):
+    out = np.zeros((game.S[1], game.N[1]))
+    for t in game.sf.terminals:
+        out[t.seq2] += np.abs(game.hm.q_matrix(t)).T @ np.abs(x[t.seq1])
+    return out

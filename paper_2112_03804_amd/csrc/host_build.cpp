@@ -1,0 +1,711 @@
+// Host-side game construction for libpmx: descriptor validation, the betting
+// skeleton and its sequence form, hand metadata for the structured hand
+// operators, and the kernels' work plans.
+//
+// Betting rules (paper, Appendix A and the caption of Fig. 1): check or bet
+// when not facing a bet; fold, call or raise when facing one; a bet or raise
+// matches the opponent and then adds a fraction of the pot after matching;
+// nobody puts in more than the opponent can match (that maximum is the
+// all-in); the round ends on a fold, a call or two checks.  Raises after the
+// opening bet are capped at max_raises; the all-in stays available past the
+// cap (Fig. 1, nodes K and O).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <utility>
+
+#include "pmx_internal.hpp"
+
+namespace pmx {
+
+namespace {
+
+int hand_key(const uint8_t* c, int cph) {
+  if (cph == 1) return c[0];
+  int a = c[0], b = c[1];
+  if (a > b) std::swap(a, b);
+  return a * kMaxDeck + b;
+}
+
+bool holds(const Instance& in, int p, int h, int card) {
+  for (int k = 0; k < in.cph; ++k)
+    if (in.cards[p][h * in.cph + k] == card) return true;
+  return false;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+int validate(const GameDesc& d, Instance& o, std::string& msg) {
+  auto bad = [&](const std::string& m) {
+    msg = m;
+    return PMX_EINVAL;
+  };
+  if (d.deck_size < 2 || d.deck_size > kMaxDeck) return bad("deck_size must be in [2, 64]");
+  if (d.cards_per_hand != 1 && d.cards_per_hand != 2) return bad("cards_per_hand must be 1 or 2");
+  if (d.n_board < 0 || d.n_board > d.deck_size) return bad("n_board out of range");
+  if (d.n_board > 0 && !d.board) return bad("board is NULL");
+  o.deck = d.deck_size;
+  o.cph = d.cards_per_hand;
+  std::vector<int> on_board(o.deck, 0);
+  for (int i = 0; i < d.n_board; ++i) {
+    int c = d.board[i];
+    if (c >= o.deck) return bad("board card out of range");
+    if (on_board[c]) return bad("board card repeated");
+    on_board[c] = 1;
+    o.board.push_back((uint8_t)c);
+  }
+  if (d.n_river < 0) return bad("n_river must be >= 0");
+  if (d.n_river > 0) {
+    if (!d.river_cards) return bad("river_cards is NULL");
+    if (d.n_river != o.deck - d.n_board)
+      return bad("river_cards must list every card not on the board");
+    std::vector<int> seen(o.deck, 0);
+    for (int i = 0; i < d.n_river; ++i) {
+      int c = d.river_cards[i];
+      if (c >= o.deck || on_board[c] || seen[c])
+        return bad("river_cards must list every card not on the board exactly once");
+      seen[c] = 1;
+      o.rivers.push_back((uint8_t)c);
+    }
+    if (o.remaining() < 1) return bad("no card left for the river");
+  }
+  o.nb = std::max(1, d.n_river);
+  std::vector<int> key_strength_seen;
+  for (int p = 0; p < 2; ++p) {
+    int n = d.n_hands[p];
+    if (n < 1 || n > kMaxHands) return bad("n_hands must be in [1, 1280]");
+    if (!d.hand_cards[p] || !d.strength[p] || !d.range[p]) return bad("hand arrays must not be NULL");
+    o.n[p] = n;
+    o.cards[p].assign(d.hand_cards[p], d.hand_cards[p] + (size_t)n * o.cph);
+    o.strength[p].assign(d.strength[p], d.strength[p] + (size_t)n * o.nb);
+    o.mu[p].assign(d.range[p], d.range[p] + n);
+    std::vector<char> seen_key((size_t)kMaxDeck * kMaxDeck, 0);
+    for (int h = 0; h < n; ++h) {
+      const uint8_t* c = &o.cards[p][(size_t)h * o.cph];
+      for (int k = 0; k < o.cph; ++k) {
+        if (c[k] >= o.deck) return bad("hand card out of range");
+        if (on_board[c[k]]) return bad("hand uses a board card");
+      }
+      if (o.cph == 2 && c[0] == c[1]) return bad("hand repeats a card");
+      int key = hand_key(c, o.cph);
+      if (seen_key[key]) return bad("hand listed twice");
+      seen_key[key] = 1;
+      double m = o.mu[p][h];
+      if (!std::isfinite(m) || m < 0) return bad("range weights must be finite and >= 0");
+    }
+  }
+  // equal strength for a hand present in both lists
+  {
+    std::vector<int> idx1((size_t)kMaxDeck * kMaxDeck, -1);
+    for (int h = 0; h < o.n[1]; ++h) idx1[hand_key(&o.cards[1][(size_t)h * o.cph], o.cph)] = h;
+    for (int h = 0; h < o.n[0]; ++h) {
+      int j = idx1[hand_key(&o.cards[0][(size_t)h * o.cph], o.cph)];
+      if (j < 0) continue;
+      for (int b = 0; b < o.nb; ++b) {
+        if (!o.rivers.empty() && holds(o, 0, h, o.rivers[b])) continue;
+        if (o.strength[0][(size_t)b * o.n[0] + h] != o.strength[1][(size_t)b * o.n[1] + j])
+          return bad("a hand in both lists has two different strengths");
+      }
+    }
+  }
+  if (!std::isfinite(d.contrib) || d.contrib <= 0) return bad("contrib must be finite and > 0");
+  o.contrib = d.contrib;
+  for (int p = 0; p < 2; ++p) {
+    if (!std::isfinite(d.stack[p]) || d.stack[p] < 0) return bad("stacks must be finite and >= 0");
+    o.stack[p] = d.stack[p];
+  }
+  if (d.n_bet_fracs < 0 || (d.n_bet_fracs > 0 && !d.bet_fracs)) return bad("bad bet_fracs");
+  for (int i = 0; i < d.n_bet_fracs; ++i) {
+    double f = d.bet_fracs[i];
+    if (!std::isfinite(f) || f <= 0) return bad("bet fractions must be finite and > 0");
+    o.fracs.push_back(f);
+  }
+  std::sort(o.fracs.begin(), o.fracs.end());
+  if (d.max_raises < 0 || d.max_raises > 64) return bad("max_raises must be in [0, 64]");
+  o.max_raises = d.max_raises;
+  o.allin = d.allow_allin != 0;
+  return PMX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// betting skeleton
+// ---------------------------------------------------------------------------
+namespace {
+
+enum { K_P0 = 0, K_P1 = 1, K_LEAF = 2, K_CHANCE = 3 };
+
+struct TNode {
+  int kind;
+  double c[2], s[2];
+  int term = -1, runout = 0;
+  std::vector<int> kids;
+};
+
+struct TreeBuilder {
+  const Instance& in;
+  std::vector<TNode> nodes;
+  size_t limit = 4u << 20;
+  bool overflow = false;
+  explicit TreeBuilder(const Instance& i) : in(i) {}
+
+  int add(TNode n) {
+    if (nodes.size() >= limit) {
+      overflow = true;
+      return 0;
+    }
+    nodes.push_back(std::move(n));
+    return (int)nodes.size() - 1;
+  }
+
+  int leaf(const double c[2], const double s[2], int term, int runout) {
+    TNode n;
+    n.kind = K_LEAF;
+    n.c[0] = c[0]; n.c[1] = c[1]; n.s[0] = s[0]; n.s[1] = s[1];
+    n.term = term;
+    n.runout = runout;
+    return add(std::move(n));
+  }
+
+  int end_round(const double c[2], const double s[2], bool last) {
+    if (last) return leaf(c, s, PMX_SHOWDOWN, 0);
+    if (s[0] <= kEps || s[1] <= kEps) return leaf(c, s, PMX_SHOWDOWN, 1);
+    TNode n;
+    n.kind = K_CHANCE;
+    n.c[0] = c[0]; n.c[1] = c[1]; n.s[0] = s[0]; n.s[1] = s[1];
+    return add(std::move(n));
+  }
+
+  int decision(int p, const double c[2], const double s[2], bool facing, int raises, bool checked,
+               bool last) {
+    if (overflow) return 0;
+    const int o = 1 - p;
+    const double allin_to = std::min(c[p] + s[p], c[o] + s[o]);
+    std::vector<int> kids;
+    auto put = [&](double target, double nc[2], double ns[2]) {
+      nc[0] = c[0]; nc[1] = c[1]; ns[0] = s[0]; ns[1] = s[1];
+      nc[p] = target;
+      double rest = s[p] - (target - c[p]);
+      ns[p] = std::fabs(rest) < kEps ? 0.0 : rest;
+    };
+    if (facing) {
+      kids.push_back(leaf(c, s, p == 0 ? PMX_FOLD_P1 : PMX_FOLD_P2, 0));
+      double nc[2], ns[2];
+      put(c[o], nc, ns);
+      kids.push_back(end_round(nc, ns, last));
+    } else if (checked) {
+      kids.push_back(end_round(c, s, last));
+    } else {
+      kids.push_back(decision(o, c, s, false, raises, true, last));
+    }
+    const bool grow = allin_to > c[o] + kEps;
+    std::vector<double> targets;
+    if (grow && (!facing || raises < in.max_raises)) {
+      for (double f : in.fracs) {
+        double t = c[o] + f * 2.0 * c[o];
+        if (t >= allin_to - kEps) t = allin_to;
+        if (!targets.empty() && std::fabs(targets.back() - t) <= kEps) continue;
+        targets.push_back(t);
+      }
+    }
+    if (grow && in.allin && (targets.empty() || std::fabs(targets.back() - allin_to) > kEps))
+      targets.push_back(allin_to);
+    for (double t : targets) {
+      double nc[2], ns[2];
+      put(std::fabs(t - allin_to) <= kEps ? allin_to : t, nc, ns);
+      kids.push_back(decision(o, nc, ns, true, raises + (facing ? 1 : 0), false, last));
+    }
+    TNode n;
+    n.kind = p;
+    n.c[0] = c[0]; n.c[1] = c[1]; n.s[0] = s[0]; n.s[1] = s[1];
+    n.kids = std::move(kids);
+    return add(std::move(n));
+  }
+
+  int round(const double c[2], const double s[2], bool last) {
+    return decision(0, c, s, false, 0, false, last);
+  }
+
+  int build() {
+    double c[2] = {in.contrib, in.contrib};
+    double s[2] = {in.stack[0], in.stack[1]};
+    int root = round(c, s, !in.two_rounds());
+    if (in.two_rounds()) {
+      size_t n0 = nodes.size();
+      for (size_t i = 0; i < n0 && !overflow; ++i) {
+        if (nodes[i].kind != K_CHANCE) continue;
+        double cc[2] = {nodes[i].c[0], nodes[i].c[1]};
+        double ss[2] = {nodes[i].s[0], nodes[i].s[1]};
+        int r = round(cc, ss, true);
+        nodes[i].kids.assign(1, r);
+      }
+    }
+    return root;
+  }
+};
+
+struct SfBuilder {
+  const Instance& in;
+  const std::vector<TNode>& nodes;
+  SeqForm& sf;
+  void visit(int id, int l0, int l1, int board) {
+    const TNode& n = nodes[id];
+    if (n.kind == K_LEAF) {
+      Terminal t;
+      t.seq[0] = l0; t.seq[1] = l1;
+      t.kind = n.term;
+      t.board = board;
+      t.runout = n.runout;
+      t.c1 = n.c[0]; t.c2 = n.c[1];
+      sf.terms.push_back(t);
+      return;
+    }
+    if (n.kind == K_CHANCE) {
+      for (int r = 0; r < (int)in.rivers.size(); ++r) {
+        RiverTask rt;
+        rt.board = r;
+        rt.parent_seq[0] = l0; rt.parent_seq[1] = l1;
+        rt.inf_begin[0] = (int)sf.inf[0].size(); rt.inf_begin[1] = (int)sf.inf[1].size();
+        visit(n.kids[0], l0, l1, r);
+        rt.inf_end[0] = (int)sf.inf[0].size(); rt.inf_end[1] = (int)sf.inf[1].size();
+        sf.rivers.push_back(rt);
+      }
+      return;
+    }
+    const int p = n.kind;
+    const int first = sf.n_seq[p];
+    const int na = (int)n.kids.size();
+    sf.inf[p].push_back(Infoset{p == 0 ? l0 : l1, first, na, board});
+    sf.n_seq[p] += na;
+    for (int a = 0; a < na; ++a)
+      visit(n.kids[a], p == 0 ? first + a : l0, p == 1 ? first + a : l1, board);
+  }
+};
+
+}  // namespace
+
+void build_seqform(const Instance& in, SeqForm& sf) {
+  TreeBuilder tb(in);
+  int root = tb.build();
+  sf = SeqForm();
+  if (tb.overflow) {
+    sf.n_seq[0] = sf.n_seq[1] = -1;
+    return;
+  }
+  SfBuilder sb{in, tb.nodes, sf};
+  sb.visit(root, -1, -1, -1);
+}
+
+// ---------------------------------------------------------------------------
+// hand metadata
+// ---------------------------------------------------------------------------
+void build_hand_meta(Built& b) {
+  const Instance& in = b.inst;
+  // beta = sum of mu1 mu2 over pairs sharing no card, by inclusion-exclusion
+  // over cards (eq. cf: the all-pairs product minus the collision term).
+  double tot[2] = {0, 0};
+  std::vector<double> mc[2];
+  for (int p = 0; p < 2; ++p) {
+    mc[p].assign(in.deck, 0.0);
+    for (int h = 0; h < in.n[p]; ++h) {
+      tot[p] += in.mu[p][h];
+      for (int k = 0; k < in.cph; ++k) mc[p][in.cards[p][(size_t)h * in.cph + k]] += in.mu[p][h];
+    }
+  }
+  double collide = 0;
+  for (int c = 0; c < in.deck; ++c) collide += mc[0][c] * mc[1][c];
+  double same = 0;
+  std::vector<int> idx1((size_t)kMaxDeck * kMaxDeck, -1);
+  for (int h = 0; h < in.n[1]; ++h) idx1[hand_key(&in.cards[1][(size_t)h * in.cph], in.cph)] = h;
+  std::vector<int> twin0(in.n[0], -1), twin1(in.n[1], -1);
+  for (int h = 0; h < in.n[0]; ++h) {
+    int j = idx1[hand_key(&in.cards[0][(size_t)h * in.cph], in.cph)];
+    if (j >= 0) {
+      twin0[h] = j;
+      twin1[j] = h;
+      same += in.mu[0][h] * in.mu[1][j];
+    }
+  }
+  b.beta = tot[0] * tot[1] - collide + (in.cph == 2 ? same : 0.0);
+  const double rs = b.beta > 0 ? 1.0 / std::sqrt(b.beta) : 0.0;
+  for (int p = 0; p < 2; ++p) {
+    b.lam[p].resize(in.n[p]);
+    for (int h = 0; h < in.n[p]; ++h) b.lam[p][h] = in.mu[p][h] * rs;
+  }
+  b.n_ctx = in.two_rounds() ? 1 + (int)in.rivers.size() : 1;
+  for (int p = 0; p < 2; ++p) b.ctx[p].assign(b.n_ctx, CtxMeta());
+
+  // per-card sorted strengths of each scan side (for the query positions)
+  std::vector<std::vector<std::vector<int32_t>>> card_str(2);
+  std::vector<std::vector<int32_t>> card_start(2);
+  auto key_of = [&](int p, int ctx, int h) -> int32_t {
+    if (in.two_rounds()) return ctx == 0 ? 0 : in.strength[p][(size_t)(ctx - 1) * in.n[p] + h];
+    return in.strength[p][h];
+  };
+  auto live_in = [&](int p, int ctx, int h) {
+    return ctx == 0 || !holds(in, p, h, in.rivers[ctx - 1]);
+  };
+  for (int ctx = 0; ctx < b.n_ctx; ++ctx) {
+    for (int p = 0; p < 2; ++p) {
+      CtxMeta& m = b.ctx[p][ctx];
+      const int n = in.n[p];
+      std::vector<int> order;
+      order.reserve(n);
+      for (int h = 0; h < n; ++h)
+        if (live_in(p, ctx, h)) order.push_back(h);
+      std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        int32_t ka = key_of(p, ctx, a), kc = key_of(p, ctx, c);
+        return ka < kc || (ka == kc && a < c);
+      });
+      m.n_live = (int)order.size();
+      m.rank.assign(n, -1);
+      m.sorted_strength.resize(order.size());
+      for (int i = 0; i < (int)order.size(); ++i) {
+        m.rank[order[i]] = i;
+        m.sorted_strength[i] = key_of(p, ctx, order[i]);
+      }
+      m.seg_src.clear();
+      m.seg_end.assign(1 + in.deck, 0);
+      for (int i = 0; i < m.n_live; ++i) m.seg_src.push_back(i);
+      m.seg_end[0] = (int)m.seg_src.size();
+      m.seg_src.push_back(-1);
+      card_str[p].assign(in.deck, {});
+      card_start[p].assign(in.deck, 0);
+      for (int c = 0; c < in.deck; ++c) {
+        card_start[p][c] = (int)m.seg_src.size();
+        for (int i = 0; i < m.n_live; ++i) {
+          if (holds(in, p, order[i], c)) {
+            m.seg_src.push_back(i);
+            card_str[p][c].push_back(m.sorted_strength[i]);
+          }
+        }
+        m.seg_end[1 + c] = (int)m.seg_src.size();
+        m.seg_src.push_back(-1 - (1 + c));
+      }
+    }
+    // queries of p against the opponent's scan side
+    for (int p = 0; p < 2; ++p) {
+      const int q = 1 - p;
+      CtxMeta& m = b.ctx[p][ctx];
+      const CtxMeta& o = b.ctx[q][ctx];
+      m.q.assign(in.n[p], QueryRec{});
+      for (int h = 0; h < in.n[p]; ++h) {
+        QueryRec r{};
+        if (!live_in(p, ctx, h)) {
+          r.lt = -1;
+          r.le = -1;
+          r.cards = 255 | (255 << 8);
+          r.self = -1;
+          m.q[h] = r;
+          continue;
+        }
+        const int32_t s = key_of(p, ctx, h);
+        const auto& gs = o.sorted_strength;
+        r.lt = (int32_t)(std::lower_bound(gs.begin(), gs.end(), s) - gs.begin());
+        r.le = (int32_t)(std::upper_bound(gs.begin(), gs.end(), s) - gs.begin());
+        int32_t lts[2] = {0, 0}, les[2] = {0, 0};
+        int cs[2] = {255, 255};
+        for (int k = 0; k < in.cph; ++k) {
+          int c = in.cards[p][(size_t)h * in.cph + k];
+          const auto& v = card_str[q][c];
+          cs[k] = c;
+          lts[k] = card_start[q][c] + (int32_t)(std::lower_bound(v.begin(), v.end(), s) - v.begin());
+          les[k] = card_start[q][c] + (int32_t)(std::upper_bound(v.begin(), v.end(), s) - v.begin());
+        }
+        r.lt0 = lts[0]; r.le0 = les[0]; r.lt1 = lts[1]; r.le1 = les[1];
+        r.cards = cs[0] | (cs[1] << 8);
+        int tw = p == 0 ? twin0[h] : twin1[h];
+        r.self = tw >= 0 ? o.rank[tw] : -1;
+        m.q[h] = r;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+int default_rows_per_block() { return 4; }
+
+namespace {
+
+struct Contrib {
+  int ctx;
+  bool fold;
+  int in_seq;
+  double coef;
+};
+
+void build_matvec_plan(HostGame& hg, int d, int rows_per_block) {
+  const int p = d, q = 1 - d;
+  MvDir& D = hg.dir[d];
+  D = MvDir();
+  D.blk.push_back(0);
+  for (size_t ii = 0; ii < hg.inst.size(); ++ii) {
+    const Built& b = hg.inst[ii];
+    const Instance& in = b.inst;
+    // contexts of this instance
+    const int ctx_base = (int)D.ctx.size();
+    for (int c = 0; c < b.n_ctx; ++c) {
+      const CtxMeta& own = b.ctx[p][c];
+      const CtxMeta& opp = b.ctx[q][c];
+      MvCtx m{};
+      m.n_own = in.n[p];
+      m.n_opp = in.n[q];
+      m.n_live = opp.n_live;
+      m.n_ent = (int)opp.seg_src.size();
+      m.n_seg = 1 + in.deck;
+      m.cph = in.cph;
+      m.stride_own = b.stride[p];
+      m.q_off = (int64_t)D.q.size();
+      D.q.insert(D.q.end(), own.q.begin(), own.q.end());
+      m.rank_off = (int64_t)D.rank.size();
+      D.rank.insert(D.rank.end(), opp.rank.begin(), opp.rank.end());
+      m.seg_off = (int64_t)D.seg.size();
+      D.seg.insert(D.seg.end(), opp.seg_src.begin(), opp.seg_src.end());
+      m.segend_off = (int64_t)D.segend.size();
+      D.segend.insert(D.segend.end(), opp.seg_end.begin(), opp.seg_end.end());
+      m.lam_own_off = -1;   // filled by the ABI layer (lambda arrays are per player)
+      m.lam_opp_off = -1;
+      D.max_ent = std::max(D.max_ent, m.n_ent);
+      D.max_seg = std::max(D.max_seg, m.n_seg);
+      D.max_n = std::max(D.max_n, std::max(m.n_own, m.n_opp));
+      D.ctx.push_back(m);
+    }
+    // contributions per own sequence
+    const int S = b.sf.n_seq[p];
+    std::vector<std::vector<Contrib>> rows(S);
+    const double rem = in.two_rounds() ? (double)in.remaining() : 1.0;
+    for (const Terminal& t : b.sf.terms) {
+      const int sg = t.seq[p], other = t.seq[q];
+      if (t.kind != PMX_SHOWDOWN) {
+        const double u1 = t.kind == PMX_FOLD_P1 ? -t.c1 : t.c2;
+        if (t.board < 0) rows[sg].push_back({0, true, other, u1});
+        else rows[sg].push_back({1 + t.board, true, other, u1 / rem});
+      } else {
+        const double st = (d == 0 ? 1.0 : -1.0) * t.c1;
+        if (t.runout) {
+          for (int r = 0; r < (int)in.rivers.size(); ++r) rows[sg].push_back({1 + r, false, other, st / rem});
+        } else if (t.board < 0) {
+          rows[sg].push_back({0, false, other, st});
+        } else {
+          rows[sg].push_back({1 + t.board, false, other, st / rem});
+        }
+      }
+    }
+    const int64_t out_base = b.vec_off[p], in_base = b.vec_off[q];
+    const int64_t sp = b.stride[p], sq = b.stride[q];
+    auto emit_row = [&](int sg) {
+      // group this row's contributions by context; pair a fold and a showdown input per item
+      std::vector<Contrib>& cl = rows[sg];
+      std::stable_sort(cl.begin(), cl.end(), [](const Contrib& a, const Contrib& c) { return a.ctx < c.ctx; });
+      size_t i = 0;
+      const size_t first_item = D.items.size();
+      while (i < cl.size()) {
+        size_t j = i;
+        std::vector<const Contrib*> fs, ss;
+        while (j < cl.size() && cl[j].ctx == cl[i].ctx) {
+          (cl[j].fold ? fs : ss).push_back(&cl[j]);
+          ++j;
+        }
+        size_t k = std::max(fs.size(), ss.size());
+        for (size_t t = 0; t < k; ++t) {
+          MvItem it{};
+          it.out = out_base + sg * sp;
+          it.n_own = in.n[p];
+          it.stride = b.stride[p];
+          it.ctx = ctx_base + cl[i].ctx;
+          it.in_f = t < fs.size() ? in_base + fs[t]->in_seq * sq : -1;
+          it.kf = t < fs.size() ? fs[t]->coef : 0.0;
+          it.in_s = t < ss.size() ? in_base + ss[t]->in_seq * sq : -1;
+          it.ks = t < ss.size() ? ss[t]->coef : 0.0;
+          it.last = 0;
+          D.items.push_back(it);
+        }
+        i = j;
+      }
+      if (D.items.size() == first_item) {
+        MvItem it{};
+        it.out = out_base + sg * sp;
+        it.n_own = in.n[p];
+        it.stride = b.stride[p];
+        it.ctx = -1;
+        it.in_f = it.in_s = -1;
+        D.items.push_back(it);
+      }
+      D.items.back().last = 1;
+    };
+    auto n_ctx_of = [&](int sg) {
+      int prev = -2, cnt = 0;
+      std::vector<int> cs;
+      for (auto& c : rows[sg]) cs.push_back(c.ctx);
+      std::sort(cs.begin(), cs.end());
+      for (int c : cs)
+        if (c != prev) { ++cnt; prev = c; }
+      return cnt;
+    };
+    // single-context rows grouped by context, then multi-context rows, then empty rows
+    std::vector<std::vector<int>> by_ctx(b.n_ctx);
+    std::vector<int> multi, empty;
+    for (int sg = 0; sg < S; ++sg) {
+      int nc = n_ctx_of(sg);
+      if (nc == 0) empty.push_back(sg);
+      else if (nc == 1) by_ctx[rows[sg][0].ctx].push_back(sg);
+      else multi.push_back(sg);
+    }
+    for (int c = 0; c < b.n_ctx; ++c) {
+      int cnt = 0;
+      for (int sg : by_ctx[c]) {
+        emit_row(sg);
+        if (++cnt == rows_per_block) {
+          D.blk.push_back((int32_t)D.items.size());
+          cnt = 0;
+        }
+      }
+      if (cnt) D.blk.push_back((int32_t)D.items.size());
+    }
+    for (int sg : multi) {
+      emit_row(sg);
+      D.blk.push_back((int32_t)D.items.size());
+    }
+    {
+      int cnt = 0;
+      for (int sg : empty) {
+        emit_row(sg);
+        if (++cnt == 4 * rows_per_block) {
+          D.blk.push_back((int32_t)D.items.size());
+          cnt = 0;
+        }
+      }
+      if (cnt) D.blk.push_back((int32_t)D.items.size());
+    }
+  }
+}
+
+void build_treeplex_plan(HostGame& hg, int p) {
+  TpPlan& T = hg.tp[p];
+  T = TpPlan();
+  int64_t hand_base = 0;
+  for (size_t ii = 0; ii < hg.inst.size(); ++ii) {
+    const Built& b = hg.inst[ii];
+    const int base = (int)T.inf_parent.size();
+    for (const Infoset& I : b.sf.inf[p]) {
+      T.inf_parent.push_back(I.parent);
+      T.inf_first.push_back(I.first);
+      T.inf_nact.push_back(I.nact);
+    }
+    T.stage_stride = std::max(T.stage_stride, b.stride[p]);
+    auto new_task = [&]() {
+      TpTask t{};
+      t.vec_base = b.vec_off[p];
+      t.stride = b.stride[p];
+      t.n_hands = b.inst.n[p];
+      t.inf_begin = (int)T.order.size();
+      t.stage = -1;
+      t.pull_begin = t.pull_end = (int)T.pulls.size();
+      t.inst = (int)ii;
+      t.hand_base = (int32_t)hand_base;
+      t.ext_parent = -1;
+      return t;
+    };
+    if (b.sf.rivers.empty()) {
+      TpTask t = new_task();
+      for (int i = 0; i < (int)b.sf.inf[p].size(); ++i) T.order.push_back(base + i);
+      t.inf_end = (int)T.order.size();
+      T.single.push_back((int)T.tasks.size());
+      T.tasks.push_back(t);
+    } else {
+      // deep tasks: one per (chance node, river card) subtree
+      std::vector<TpPull> pulls;
+      for (const RiverTask& rt : b.sf.rivers) {
+        TpTask t = new_task();
+        for (int i = rt.inf_begin[p]; i < rt.inf_end[p]; ++i) T.order.push_back(base + i);
+        t.inf_end = (int)T.order.size();
+        t.stage = T.n_stage++;
+        t.ext_parent = rt.parent_seq[p];
+        pulls.push_back(TpPull{rt.parent_seq[p], t.stage});
+        T.deep.push_back((int)T.tasks.size());
+        T.tasks.push_back(t);
+      }
+      TpTask top = new_task();
+      for (int i = 0; i < (int)b.sf.inf[p].size(); ++i)
+        if (b.sf.inf[p][i].board < 0) T.order.push_back(base + i);
+      top.inf_end = (int)T.order.size();
+      top.pull_begin = (int)T.pulls.size();
+      T.pulls.insert(T.pulls.end(), pulls.begin(), pulls.end());
+      top.pull_end = (int)T.pulls.size();
+      T.top.push_back((int)T.tasks.size());
+      T.tasks.push_back(top);
+    }
+    hand_base += b.inst.n[p];
+  }
+  T.hands_total = hand_base;
+}
+
+}  // namespace
+
+int build_game(const GameDesc* descs, int n, HostGame& hg, std::string& msg) {
+  if (!descs || n < 1) {
+    msg = "need at least one descriptor";
+    return PMX_EINVAL;
+  }
+  hg = HostGame();
+  hg.inst.resize(n);
+  int64_t off[2] = {0, 0};
+  for (int i = 0; i < n; ++i) {
+    Built& b = hg.inst[i];
+    std::string m;
+    int rc = validate(descs[i], b.inst, m);
+    if (rc) {
+      msg = "instance " + std::to_string(i) + ": " + m;
+      return rc;
+    }
+    build_seqform(b.inst, b.sf);
+    if (b.sf.n_seq[0] < 0) {
+      msg = "instance " + std::to_string(i) + ": betting tree too large";
+      return PMX_EINVAL;
+    }
+    for (const Terminal& t : b.sf.terms) {
+      if (t.seq[0] < 0 || t.seq[1] < 0) {
+        msg = "instance " + std::to_string(i) + ": a terminal is reached before both players act";
+        return PMX_EINVAL;
+      }
+    }
+    build_hand_meta(b);
+    if (!(b.beta > 0) || !std::isfinite(b.beta)) {
+      msg = "instance " + std::to_string(i) + ": ranges give no compatible deal (beta = 0)";
+      return PMX_EINVAL;
+    }
+    for (int p = 0; p < 2; ++p) {
+      b.stride[p] = (b.inst.n[p] + 3) & ~3;
+      b.vec_off[p] = off[p];
+      off[p] += (int64_t)b.sf.n_seq[p] * b.stride[p];
+      hg.max_stride = std::max(hg.max_stride, b.stride[p]);
+      for (const Infoset& I : b.sf.inf[p]) {
+        b.inf_parent[p].push_back(I.parent);
+        b.inf_first[p].push_back(I.first);
+        b.inf_nact[p].push_back(I.nact);
+        b.inf_board[p].push_back(I.board);
+      }
+    }
+    for (const Terminal& t : b.sf.terms) {
+      b.t_seq1.push_back(t.seq[0]);
+      b.t_seq2.push_back(t.seq[1]);
+      b.t_kind.push_back(t.kind);
+      b.t_board.push_back(t.board);
+      b.t_runout.push_back(t.runout);
+      b.t_c1.push_back(t.c1);
+      b.t_c2.push_back(t.c2);
+    }
+  }
+  hg.elems[0] = off[0];
+  hg.elems[1] = off[1];
+  for (int d = 0; d < 2; ++d) build_matvec_plan(hg, d, default_rows_per_block());
+  for (int p = 0; p < 2; ++p) build_treeplex_plan(hg, p);
+  return PMX_OK;
+}
+
+}  // namespace pmx

@@ -1,0 +1,1098 @@
+// libpmx device code for gfx950 (CDNA4) and the C ABI.
+//
+// Kernels
+//   k_matvec      rows of A y (or A^T x): one workgroup per chunk of output
+//                 rows that share a board context.  Per item it applies the
+//                 hand factor of Prop. 1 without forming it:
+//                   - fold / compatibility (eq. cf): total of the opponent's
+//                     weighted vector minus its per-card sums plus the
+//                     identical hand (inclusion-exclusion over shared cards);
+//                   - showdown (Technique B: the inverse of the bidiagonal
+//                     difference operator is a prefix sum over hands sorted
+//                     by strength): exclusive prefix sums over the sorted
+//                     opponent hands and inside each card's sorted sub-list,
+//                     read at the tie-aware positions of each own hand.
+//                 All prefix sums come from one segmented scan over LDS with
+//                 FP64 accumulation (FP64 adds issue at the unpacked FP32
+//                 rate on CDNA4, so this costs less than compensated FP32).
+//   k_rm_*        regret matching+ on a treeplex, one thread per hand (the
+//                 paper's GPU solver updates all hands in parallel).
+//   k_br_*        FP64 best responses (bottom-up max / min) and the gap.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "pmx_internal.hpp"
+
+using namespace pmx;
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& m) {
+  g_err = m;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(PMX_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// structured matvec
+// ---------------------------------------------------------------------------
+struct MvParams {
+  const MvItem* items;
+  const int32_t* blk;
+  const MvCtx* ctx;
+  const QueryRec* q;
+  const int32_t* rank;
+  const int32_t* seg;
+  const int32_t* segend;
+  const double* lam;
+  double scale;
+  int32_t nblk;
+  int32_t max_ent, max_n, max_seg;
+};
+
+template <typename T>
+__device__ inline T shfl_up64(T v, int d) {
+  return __shfl_up(v, d, 64);
+}
+
+// Exclusive segmented scan over the threads of a block of (flag, a, b): a
+// thread's result sums the contributions of earlier threads back to (and
+// including the post-flag part of) the nearest earlier thread with flag set.
+template <int BLOCK>
+__device__ inline void block_seg_scan(bool flag, double a, double b, double* scratch, double& ea,
+                                      double& eb) {
+  constexpr int NW = BLOCK / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int f = flag ? 1 : 0;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int f2 = shfl_up64(f, off);
+    double a2 = shfl_up64(a, off);
+    double b2 = shfl_up64(b, off);
+    if (lane >= off) {
+      if (!f) {
+        a += a2;
+        b += b2;
+      }
+      f |= f2;
+    }
+  }
+  // wave aggregates
+  if (lane == 63) {
+    scratch[3 * wid + 0] = (double)f;
+    scratch[3 * wid + 1] = a;
+    scratch[3 * wid + 2] = b;
+  }
+  int xf = shfl_up64(f, 1);
+  double xa = shfl_up64(a, 1);
+  double xb = shfl_up64(b, 1);
+  if (lane == 0) {
+    xf = 0;
+    xa = 0.0;
+    xb = 0.0;
+  }
+  __syncthreads();
+  double wa = 0.0, wb = 0.0;
+  for (int w = 0; w < wid && w < NW; ++w) {
+    if (scratch[3 * w] != 0.0) {
+      wa = scratch[3 * w + 1];
+      wb = scratch[3 * w + 2];
+    } else {
+      wa += scratch[3 * w + 1];
+      wb += scratch[3 * w + 2];
+    }
+  }
+  if (!xf) {
+    xa += wa;
+    xb += wb;
+  }
+  ea = xa;
+  eb = xb;
+  __syncthreads();
+}
+
+template <int BLOCK, int KH, int KE, typename IO>
+__global__ __launch_bounds__(BLOCK) void k_matvec(MvParams P0, const IO* __restrict__ in0,
+                                                  IO* __restrict__ out0, MvParams P1,
+                                                  const IO* __restrict__ in1, IO* __restrict__ out1) {
+  const bool second = (int)blockIdx.x >= P0.nblk;
+  const MvParams& P = second ? P1 : P0;
+  const IO* __restrict__ in = second ? in1 : in0;
+  IO* __restrict__ out = second ? out1 : out0;
+  const int b = second ? (int)blockIdx.x - P0.nblk : (int)blockIdx.x;
+  const int tid = threadIdx.x;
+
+  extern __shared__ double smem[];
+  double* Pc = smem;                            // [max_ent] exclusive segmented prefix (showdown channel)
+  double* us = Pc + P.max_ent;                  // [max_n] showdown input, sorted order
+  double* uf = us + P.max_n;                    // [max_n] fold input, sorted order
+  double* segF = uf + P.max_n;                  // [max_seg] per-segment fold totals
+  double* scratch = segF + P.max_seg;           // [3 * BLOCK / 64]
+  int* segEnd = (int*)(scratch + 3 * (BLOCK / 64));  // [max_seg]
+
+  QueryRec qr[KH];
+  double lo[KH], lp[KH], acc[KH];
+  int rk[KH];
+  int src[KE];
+#pragma unroll
+  for (int k = 0; k < KH; ++k) acc[k] = 0.0;
+
+  const int it0 = P.blk[b], it1 = P.blk[b + 1];
+  int cur = -2;
+  int n_own = 0, n_opp = 0, n_live = 0, n_ent = 0, cph = 1;
+  for (int it = it0; it < it1; ++it) {
+    const MvItem item = P.items[it];
+    if (item.ctx < 0) {
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        int h = tid + k * BLOCK;
+        if (h < item.stride) out[item.out + h] = (IO)0;
+      }
+      continue;
+    }
+    __syncthreads();   // previous item's readers of LDS are done
+    if (item.ctx != cur) {
+      const MvCtx C = P.ctx[item.ctx];
+      n_own = C.n_own;
+      n_opp = C.n_opp;
+      n_live = C.n_live;
+      n_ent = C.n_ent;
+      cph = C.cph;
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        int h = tid + k * BLOCK;
+        if (h < n_own) {
+          qr[k] = P.q[C.q_off + h];
+          lo[k] = P.lam[C.lam_own_off + h];
+        } else {
+          qr[k].lt = -1;
+          lo[k] = 0.0;
+        }
+        if (h < n_opp) {
+          rk[k] = P.rank[C.rank_off + h];
+          lp[k] = P.lam[C.lam_opp_off + h];
+        } else {
+          rk[k] = -1;
+          lp[k] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < KE; ++j) {
+        int e = tid * KE + j;
+        src[j] = e < n_ent ? P.seg[C.seg_off + e] : 0;
+      }
+      for (int i = tid; i < C.n_seg; i += BLOCK) segEnd[i] = P.segend[C.segend_off + i];
+      cur = item.ctx;
+    }
+    // phase 1: weighted opponent inputs scattered to strength order
+    const bool has_s = item.in_s >= 0, has_f = item.in_f >= 0;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      int h = tid + k * BLOCK;
+      if (h < n_opp && rk[k] >= 0) {
+        double vs = has_s ? item.ks * lp[k] * (double)in[item.in_s + h] : 0.0;
+        double vf = has_f ? item.kf * lp[k] * (double)in[item.in_f + h] : 0.0;
+        us[rk[k]] = vs;
+        uf[rk[k]] = vf;
+      }
+    }
+    __syncthreads();
+    // phase 2: segmented exclusive scan over the entry list
+    double rs = 0.0, rf = 0.0;
+    bool flag = false;
+#pragma unroll
+    for (int j = 0; j < KE; ++j) {
+      int e = tid * KE + j;
+      if (e < n_ent) {
+        int s = src[j];
+        if (s >= 0) {
+          rs += us[s];
+          rf += uf[s];
+        } else {
+          flag = true;
+          rs = 0.0;
+          rf = 0.0;
+        }
+      }
+    }
+    double cs, cf;
+    block_seg_scan<BLOCK>(flag, rs, rf, scratch, cs, cf);
+    rs = cs;
+    rf = cf;
+#pragma unroll
+    for (int j = 0; j < KE; ++j) {
+      int e = tid * KE + j;
+      if (e < n_ent) {
+        int s = src[j];
+        Pc[e] = rs;
+        if (s >= 0) {
+          rs += us[s];
+          rf += uf[s];
+        } else {
+          segF[-1 - s] = rf;
+          rs = 0.0;
+          rf = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    // phase 3: read the prefix sums at each own hand's positions
+    const double tot_s = Pc[n_live];
+    const double tot_f = segF[0];
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      int h = tid + k * BLOCK;
+      if (h < n_own && qr[k].lt >= 0) {
+        const QueryRec r = qr[k];
+        double sd = Pc[r.lt] + Pc[r.le] - tot_s;
+        double fo = tot_f;
+        const int c0 = r.cards & 255;
+        sd -= Pc[r.lt0] + Pc[r.le0] - Pc[segEnd[1 + c0]];
+        fo -= segF[1 + c0];
+        if (cph == 2) {
+          const int c1 = (r.cards >> 8) & 255;
+          sd -= Pc[r.lt1] + Pc[r.le1] - Pc[segEnd[1 + c1]];
+          fo -= segF[1 + c1];
+          if (r.self >= 0) fo += uf[r.self];
+        }
+        acc[k] += sd + fo;
+      }
+    }
+    if (item.last) {
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        int h = tid + k * BLOCK;
+        if (h < item.stride) out[item.out + h] = (IO)(h < n_own ? P.scale * lo[k] * acc[k] : 0.0);
+        acc[k] = 0.0;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// treeplex kernels (one thread per hand of a task)
+// ---------------------------------------------------------------------------
+struct TpParams {
+  const int32_t* inf_parent;
+  const int32_t* inf_first;
+  const int32_t* inf_nact;
+  const int32_t* order;
+  const TpTask* tasks;
+  const TpPull* pulls;
+  const int2* blocks;
+  int32_t stage_stride;
+};
+
+constexpr int TPB = 128;
+
+// Regret-matching+ regret update of one infoset for one hand; returns V(I).
+__device__ inline float rm_infoset(float* __restrict__ g, float* __restrict__ R, int64_t base,
+                                   int64_t stride, int f, int n) {
+  float rs = 0.f;
+  for (int a = 0; a < n; ++a) rs += R[base + (f + a) * stride];
+  float V = 0.f;
+  const float inv = rs > 0.f ? 1.f / rs : 0.f;
+  const float uni = 1.f / (float)n;
+  for (int a = 0; a < n; ++a) {
+    float ba = rs > 0.f ? R[base + (f + a) * stride] * inv : uni;
+    V += ba * g[base + (f + a) * stride];
+  }
+  for (int a = 0; a < n; ++a) {
+    int64_t i = base + (f + a) * stride;
+    float r = R[i] + g[i] - V;
+    R[i] = r > 0.f ? r : 0.f;
+  }
+  return V;
+}
+
+// New behavioural strategy from regrets, realization plan, and the averaging
+// of the previous plan (weight t).
+__device__ inline void rm_descend(const float* __restrict__ R, float* __restrict__ x,
+                                  double* __restrict__ xs, int64_t base, int64_t stride, int f,
+                                  int n, int par, double t) {
+  const float xp = par >= 0 ? x[base + (int64_t)par * stride] : 1.f;
+  float rs = 0.f;
+  for (int a = 0; a < n; ++a) rs += R[base + (f + a) * stride];
+  const float inv = rs > 0.f ? 1.f / rs : 0.f;
+  const float uni = 1.f / (float)n;
+  for (int a = 0; a < n; ++a) {
+    int64_t i = base + (f + a) * stride;
+    float ba = rs > 0.f ? R[i] * inv : uni;
+    xs[i] += t * (double)x[i];
+    x[i] = xp * ba;
+  }
+}
+
+// mode 0: single-phase task (bottom-up then top-down); 1: deep bottom-up;
+// 2: top task (pull, bottom-up, top-down); 3: deep top-down.
+template <int MODE>
+__global__ __launch_bounds__(TPB) void k_rm(TpParams P, float* __restrict__ g,
+                                            float* __restrict__ R, float* __restrict__ x,
+                                            double* __restrict__ xs, float* __restrict__ stage,
+                                            double t) {
+  const int2 bt = P.blocks[blockIdx.x];
+  const TpTask T = P.tasks[bt.x];
+  const int h = bt.y + threadIdx.x;
+  if (h >= T.n_hands) return;
+  const int64_t base = T.vec_base + h, stride = T.stride;
+  if (MODE == 2) {
+    for (int i = T.pull_begin; i < T.pull_end; ++i) {
+      const TpPull pl = P.pulls[i];
+      g[base + (int64_t)pl.seq * stride] += stage[(int64_t)pl.stage * P.stage_stride + h];
+    }
+  }
+  if (MODE == 0 || MODE == 1 || MODE == 2) {
+    float vroot = 0.f;
+    for (int i = T.inf_end - 1; i >= T.inf_begin; --i) {
+      const int I = P.order[i];
+      const int par = P.inf_parent[I];
+      const float V = rm_infoset(g, R, base, stride, P.inf_first[I], P.inf_nact[I]);
+      if (MODE == 1 && par == T.ext_parent) vroot += V;
+      else if (par >= 0) g[base + (int64_t)par * stride] += V;
+    }
+    if (MODE == 1) stage[(int64_t)T.stage * P.stage_stride + h] = vroot;
+  }
+  if (MODE == 0 || MODE == 2 || MODE == 3) {
+    for (int i = T.inf_begin; i < T.inf_end; ++i) {
+      const int I = P.order[i];
+      rm_descend(R, x, xs, base, stride, P.inf_first[I], P.inf_nact[I], P.inf_parent[I], t);
+    }
+  }
+}
+
+// Best response: per hand, bottom-up max (Player 1) or min (Player 2) of g
+// plus the values below; sums of root values go to hv[hand_base + h].
+template <int MODE, bool MAXIMIZE>
+__global__ __launch_bounds__(TPB) void k_br(TpParams P, double* __restrict__ g,
+                                            double* __restrict__ stage, double* __restrict__ hv) {
+  const int2 bt = P.blocks[blockIdx.x];
+  const TpTask T = P.tasks[bt.x];
+  const int h = bt.y + threadIdx.x;
+  if (h >= T.n_hands) return;
+  const int64_t base = T.vec_base + h, stride = T.stride;
+  if (MODE == 2) {
+    for (int i = T.pull_begin; i < T.pull_end; ++i) {
+      const TpPull pl = P.pulls[i];
+      g[base + (int64_t)pl.seq * stride] += stage[(int64_t)pl.stage * P.stage_stride + h];
+    }
+  }
+  double vroot = 0.0;
+  for (int i = T.inf_end - 1; i >= T.inf_begin; --i) {
+    const int I = P.order[i];
+    const int par = P.inf_parent[I], f = P.inf_first[I], n = P.inf_nact[I];
+    double V = g[base + (int64_t)f * stride];
+    for (int a = 1; a < n; ++a) {
+      double q = g[base + (int64_t)(f + a) * stride];
+      V = MAXIMIZE ? fmax(V, q) : fmin(V, q);
+    }
+    if (par == T.ext_parent) vroot += V;
+    else g[base + (int64_t)par * stride] += V;
+  }
+  if (MODE == 1) stage[(int64_t)T.stage * P.stage_stride + h] = vroot;
+  else hv[T.hand_base + h] = vroot;
+}
+
+// Per-instance sum of per-hand values, fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_sum_instances(const double* __restrict__ hv,
+                                                       const int64_t* __restrict__ off,
+                                                       double* __restrict__ out) {
+  __shared__ double red[256];
+  const int i = blockIdx.x;
+  const int64_t a = off[i], b = off[i + 1];
+  double s = 0.0;
+  for (int64_t j = a + threadIdx.x; j < b; j += 256) s += hv[j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
+}
+
+// Uniform realization plan (top-down with zero regrets), thread per hand.
+__global__ __launch_bounds__(TPB) void k_uniform(TpParams P, float* __restrict__ x) {
+  const int2 bt = P.blocks[blockIdx.x];
+  const TpTask T = P.tasks[bt.x];
+  const int h = bt.y + threadIdx.x;
+  if (h >= T.n_hands) return;
+  const int64_t base = T.vec_base + h, stride = T.stride;
+  for (int i = T.inf_begin; i < T.inf_end; ++i) {
+    const int I = P.order[i];
+    const int par = P.inf_parent[I], f = P.inf_first[I], n = P.inf_nact[I];
+    const float xp = par >= 0 ? x[base + (int64_t)par * stride] : 1.f;
+    for (int a = 0; a < n; ++a) x[base + (int64_t)(f + a) * stride] = xp / (float)n;
+  }
+}
+
+// Regrets from a behavioural strategy (warm start): R = scale * b, and the
+// matching realization plan (thread per hand, top-down).
+__global__ __launch_bounds__(TPB) void k_warm(TpParams P, const float* __restrict__ b,
+                                              float scale, float* __restrict__ R,
+                                              float* __restrict__ x) {
+  const int2 bt = P.blocks[blockIdx.x];
+  const TpTask T = P.tasks[bt.x];
+  const int h = bt.y + threadIdx.x;
+  if (h >= T.n_hands) return;
+  const int64_t base = T.vec_base + h, stride = T.stride;
+  for (int i = T.inf_begin; i < T.inf_end; ++i) {
+    const int I = P.order[i];
+    const int par = P.inf_parent[I], f = P.inf_first[I], n = P.inf_nact[I];
+    const float xp = par >= 0 ? x[base + (int64_t)par * stride] : 1.f;
+    float s = 0.f;
+    for (int a = 0; a < n; ++a) {
+      float v = b[base + (int64_t)(f + a) * stride];
+      s += v > 0.f ? v : 0.f;
+    }
+    for (int a = 0; a < n; ++a) {
+      int64_t j = base + (int64_t)(f + a) * stride;
+      float v = b[j] > 0.f ? b[j] : 0.f;
+      float ba = s > 0.f ? v / s : 1.f / (float)n;
+      R[j] = scale * ba;
+      x[j] = xp * ba;
+    }
+  }
+}
+
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_nonfinite(const double* p, int n, int* flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(p[i])) *flag = 1;
+}
+
+// ---------------------------------------------------------------------------
+// the Game object
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  ~DBuf() {
+    if (p) (void)hipFree(p);
+  }
+  int alloc(size_t count) {
+    n = count;
+    if (count == 0) return PMX_OK;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      return fail(PMX_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return PMX_OK;
+  }
+  int upload(const std::vector<T>& v) {
+    int rc = alloc(v.size());
+    if (rc) return rc;
+    if (!v.empty()) HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return PMX_OK;
+  }
+};
+
+struct DevDir {
+  DBuf<MvItem> items;
+  DBuf<int32_t> blk;
+  DBuf<MvCtx> ctx;
+  DBuf<QueryRec> q;
+  DBuf<int32_t> rank, seg, segend;
+  int nblk = 0, max_ent = 0, max_n = 0, max_seg = 0;
+};
+
+struct DevTp {
+  DBuf<int32_t> inf_parent, inf_first, inf_nact, order;
+  DBuf<TpTask> tasks;
+  DBuf<TpPull> pulls;
+  DBuf<int2> b_single, b_deep, b_top, b_all;
+  int n_single = 0, n_deep = 0, n_top = 0, n_all = 0;
+  DBuf<float> stage;
+  DBuf<double> stage_d;
+  DBuf<double> hv;
+  int stage_stride = 0;
+};
+
+struct Game {
+  HostGame hg;
+  bool device = false;
+  int device_id = 0;
+  DevDir dd[2];
+  DevTp dt[2];
+  DBuf<double> lam;
+  int64_t lam_base[2] = {0, 0};
+  DBuf<int64_t> inst_hand_off[2];
+  // solver state
+  DBuf<float> R[2], x[2], grad[2];
+  DBuf<double> xs[2], gd[2], sd[2], br_inst;
+  int t = 0;
+  double wsum = 0.0;
+  int mv_block = 256;
+};
+
+static int ensure_device(Game* g) {
+  if (!g) return fail(PMX_EINVAL, "null game");
+  if (!g->device) return fail(PMX_ESTATE, "game was created host-only");
+  HIP_TRY(hipSetDevice(g->device_id));
+  return PMX_OK;
+}
+
+static std::vector<int2> tp_blocks(const TpPlan& T, const std::vector<int32_t>& ids) {
+  std::vector<int2> b;
+  for (int id : ids)
+    for (int h0 = 0; h0 < T.tasks[id].n_hands; h0 += TPB) b.push_back(make_int2(id, h0));
+  return b;
+}
+
+static int upload_game(Game* g) {
+  HostGame& hg = g->hg;
+  // lambda of both players, all instances
+  std::vector<double> lam;
+  std::vector<int64_t> lam_off[2];
+  for (int p = 0; p < 2; ++p) {
+    g->lam_base[p] = (int64_t)lam.size();
+    for (auto& b : hg.inst) {
+      lam_off[p].push_back((int64_t)lam.size());
+      lam.insert(lam.end(), b.lam[p].begin(), b.lam[p].end());
+    }
+  }
+  int rc = g->lam.upload(lam);
+  if (rc) return rc;
+  for (int d = 0; d < 2; ++d) {
+    MvDir& D = hg.dir[d];
+    const int p = d, q = 1 - d;
+    // fill lambda offsets: contexts are emitted instance by instance
+    size_t ci = 0;
+    for (size_t ii = 0; ii < hg.inst.size(); ++ii) {
+      for (int c = 0; c < hg.inst[ii].n_ctx; ++c, ++ci) {
+        D.ctx[ci].lam_own_off = lam_off[p][ii];
+        D.ctx[ci].lam_opp_off = lam_off[q][ii];
+      }
+    }
+    DevDir& E = g->dd[d];
+    if ((rc = E.items.upload(D.items)) || (rc = E.blk.upload(D.blk)) || (rc = E.ctx.upload(D.ctx)) ||
+        (rc = E.q.upload(D.q)) || (rc = E.rank.upload(D.rank)) || (rc = E.seg.upload(D.seg)) ||
+        (rc = E.segend.upload(D.segend)))
+      return rc;
+    E.nblk = (int)D.blk.size() - 1;
+    E.max_ent = D.max_ent;
+    E.max_n = D.max_n;
+    E.max_seg = D.max_seg;
+  }
+  for (int p = 0; p < 2; ++p) {
+    TpPlan& T = hg.tp[p];
+    DevTp& E = g->dt[p];
+    if ((rc = E.inf_parent.upload(T.inf_parent)) || (rc = E.inf_first.upload(T.inf_first)) ||
+        (rc = E.inf_nact.upload(T.inf_nact)) || (rc = E.order.upload(T.order)) ||
+        (rc = E.tasks.upload(T.tasks)) || (rc = E.pulls.upload(T.pulls)))
+      return rc;
+    auto bs = tp_blocks(T, T.single), bd = tp_blocks(T, T.deep), bt = tp_blocks(T, T.top);
+    std::vector<int32_t> all_ids = T.single;
+    all_ids.insert(all_ids.end(), T.deep.begin(), T.deep.end());
+    auto ba = tp_blocks(T, all_ids);
+    if ((rc = E.b_single.upload(bs)) || (rc = E.b_deep.upload(bd)) || (rc = E.b_top.upload(bt)) ||
+        (rc = E.b_all.upload(ba)))
+      return rc;
+    E.n_single = (int)bs.size();
+    E.n_deep = (int)bd.size();
+    E.n_top = (int)bt.size();
+    E.n_all = (int)ba.size();
+    E.stage_stride = std::max(T.stage_stride, 1);
+    if ((rc = E.stage.alloc((size_t)std::max(T.n_stage, 1) * E.stage_stride)) ||
+        (rc = E.stage_d.alloc((size_t)std::max(T.n_stage, 1) * E.stage_stride)) ||
+        (rc = E.hv.alloc((size_t)std::max<int64_t>(T.hands_total, 1))))
+      return rc;
+    std::vector<int64_t> ho(1, 0);
+    for (auto& b : hg.inst) ho.push_back(ho.back() + b.inst.n[p]);
+    if ((rc = g->inst_hand_off[p].upload(ho))) return rc;
+  }
+  for (int p = 0; p < 2; ++p) {
+    size_t n = (size_t)hg.elems[p];
+    if ((rc = g->R[p].alloc(n)) || (rc = g->x[p].alloc(n)) || (rc = g->grad[p].alloc(n)) ||
+        (rc = g->xs[p].alloc(n)) || (rc = g->gd[p].alloc(n)) || (rc = g->sd[p].alloc(n)))
+      return rc;
+  }
+  if ((rc = g->br_inst.alloc(2 * hg.inst.size()))) return rc;
+  return PMX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static MvParams mv_params(Game* g, int d, double scale) {
+  DevDir& E = g->dd[d];
+  MvParams P;
+  P.items = E.items.p;
+  P.blk = E.blk.p;
+  P.ctx = E.ctx.p;
+  P.q = E.q.p;
+  P.rank = E.rank.p;
+  P.seg = E.seg.p;
+  P.segend = E.segend.p;
+  P.lam = g->lam.p;
+  P.scale = scale;
+  P.nblk = E.nblk;
+  P.max_ent = E.max_ent;
+  P.max_n = E.max_n;
+  P.max_seg = E.max_seg;
+  return P;
+}
+
+template <int BLOCK>
+static size_t mv_lds(const MvParams& a, const MvParams& b) {
+  size_t me = std::max(a.max_ent, b.max_ent), mn = std::max(a.max_n, b.max_n),
+         ms = std::max(a.max_seg, b.max_seg);
+  return sizeof(double) * (me + 2 * mn + ms + 3 * (BLOCK / 64)) + sizeof(int) * ms;
+}
+
+template <typename IO>
+static int launch_mv(Game* g, MvParams P0, const IO* in0, IO* out0, MvParams P1, const IO* in1,
+                     IO* out1, hipStream_t s) {
+  const int nb = P0.nblk + P1.nblk;
+  if (nb == 0) return PMX_OK;
+  // shape checks: every hand and entry must have a thread slot
+  const int mn = std::max(P0.max_n, P1.max_n), me = std::max(P0.max_ent, P1.max_ent);
+  constexpr int B = 256, KH = 5, KE = 16;
+  if (mn > KH * B || me > KE * B) return fail(PMX_EINVAL, "instance too large for the matvec kernel");
+  size_t lds = mv_lds<B>(P0, P1);
+  if (lds > 160 * 1024) return fail(PMX_EINVAL, "matvec LDS footprint exceeds 160 KB");
+  hipLaunchKernelGGL((k_matvec<B, KH, KE, IO>), dim3(nb), dim3(B), lds, s, P0, in0, out0, P1, in1,
+                     out1);
+  HIP_TRY(hipGetLastError());
+  return PMX_OK;
+}
+
+static MvParams empty_params(const MvParams& like) {
+  MvParams P = like;
+  P.nblk = 0;
+  return P;
+}
+
+static TpParams tp_params(Game* g, int p, const int2* blocks) {
+  DevTp& E = g->dt[p];
+  TpParams P;
+  P.inf_parent = E.inf_parent.p;
+  P.inf_first = E.inf_first.p;
+  P.inf_nact = E.inf_nact.p;
+  P.order = E.order.p;
+  P.tasks = E.tasks.p;
+  P.pulls = E.pulls.p;
+  P.blocks = blocks;
+  P.stage_stride = E.stage_stride;
+  return P;
+}
+
+static int rm_update(Game* g, int p, double t, hipStream_t s) {
+  DevTp& E = g->dt[p];
+  float* gr = g->grad[p].p;
+  if (E.n_single)
+    hipLaunchKernelGGL(k_rm<0>, dim3(E.n_single), dim3(TPB), 0, s, tp_params(g, p, E.b_single.p), gr,
+                       g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, t);
+  if (E.n_deep)
+    hipLaunchKernelGGL(k_rm<1>, dim3(E.n_deep), dim3(TPB), 0, s, tp_params(g, p, E.b_deep.p), gr,
+                       g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, t);
+  if (E.n_top)
+    hipLaunchKernelGGL(k_rm<2>, dim3(E.n_top), dim3(TPB), 0, s, tp_params(g, p, E.b_top.p), gr,
+                       g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, t);
+  if (E.n_deep)
+    hipLaunchKernelGGL(k_rm<3>, dim3(E.n_deep), dim3(TPB), 0, s, tp_params(g, p, E.b_deep.p), gr,
+                       g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, t);
+  HIP_TRY(hipGetLastError());
+  return PMX_OK;
+}
+
+static int br_values(Game* g, int p, double* gvec, hipStream_t s) {
+  DevTp& E = g->dt[p];
+  if (p == 0) {
+    if (E.n_single)
+      hipLaunchKernelGGL((k_br<0, true>), dim3(E.n_single), dim3(TPB), 0, s,
+                         tp_params(g, p, E.b_single.p), gvec, E.stage_d.p, E.hv.p);
+    if (E.n_deep)
+      hipLaunchKernelGGL((k_br<1, true>), dim3(E.n_deep), dim3(TPB), 0, s,
+                         tp_params(g, p, E.b_deep.p), gvec, E.stage_d.p, E.hv.p);
+    if (E.n_top)
+      hipLaunchKernelGGL((k_br<2, true>), dim3(E.n_top), dim3(TPB), 0, s,
+                         tp_params(g, p, E.b_top.p), gvec, E.stage_d.p, E.hv.p);
+  } else {
+    if (E.n_single)
+      hipLaunchKernelGGL((k_br<0, false>), dim3(E.n_single), dim3(TPB), 0, s,
+                         tp_params(g, p, E.b_single.p), gvec, E.stage_d.p, E.hv.p);
+    if (E.n_deep)
+      hipLaunchKernelGGL((k_br<1, false>), dim3(E.n_deep), dim3(TPB), 0, s,
+                         tp_params(g, p, E.b_deep.p), gvec, E.stage_d.p, E.hv.p);
+    if (E.n_top)
+      hipLaunchKernelGGL((k_br<2, false>), dim3(E.n_top), dim3(TPB), 0, s,
+                         tp_params(g, p, E.b_top.p), gvec, E.stage_d.p, E.hv.p);
+  }
+  const int ni = (int)g->hg.inst.size();
+  hipLaunchKernelGGL(k_sum_instances, dim3(ni), dim3(256), 0, s, E.hv.p, g->inst_hand_off[p].p,
+                     g->br_inst.p + (size_t)p * ni);
+  HIP_TRY(hipGetLastError());
+  return PMX_OK;
+}
+
+static void fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return;
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_f32, dim3(blocks), dim3(256), 0, s, p, n, v);
+}
+static void fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_f64, dim3(blocks), dim3(256), 0, s, p, n, v);
+}
+
+static int uniform_plan(Game* g, int p, hipStream_t s) {
+  DevTp& E = g->dt[p];
+  // the top task must run before the deep tasks (parents first)
+  if (E.n_single)
+    hipLaunchKernelGGL(k_uniform, dim3(E.n_single), dim3(TPB), 0, s, tp_params(g, p, E.b_single.p),
+                       g->x[p].p);
+  if (E.n_top)
+    hipLaunchKernelGGL(k_uniform, dim3(E.n_top), dim3(TPB), 0, s, tp_params(g, p, E.b_top.p),
+                       g->x[p].p);
+  if (E.n_deep)
+    hipLaunchKernelGGL(k_uniform, dim3(E.n_deep), dim3(TPB), 0, s, tp_params(g, p, E.b_deep.p),
+                       g->x[p].p);
+  HIP_TRY(hipGetLastError());
+  return PMX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* pmx_last_error(void) { return g_err.c_str(); }
+
+static int create_common(const GameDesc* descs, int32_t n, bool device, Game** out) {
+  if (!out) return fail(PMX_EINVAL, "out is NULL");
+  if (!descs || n < 1) return fail(PMX_EINVAL, "need at least one descriptor");
+  std::unique_ptr<Game> g;
+  try {
+    g.reset(new Game());
+    std::string msg;
+    int rc = build_game(descs, n, g->hg, msg);
+    if (rc) return fail(rc, msg);
+  } catch (const std::bad_alloc&) {
+    return fail(PMX_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(PMX_EINVAL, e.what());
+  }
+  if (device) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    g->device_id = dev;
+    g->device = true;
+    int rc = upload_game(g.get());
+    if (rc) return rc;
+    hipStream_t s = nullptr;
+    if ((rc = solver_reset(g.get(), s))) return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  *out = g.release();
+  g_err.clear();
+  return PMX_OK;
+}
+
+int game_create(const GameDesc* desc, Game** out) { return create_common(desc, 1, true, out); }
+
+int game_create_batch(const GameDesc* descs, int32_t n, Game** out) {
+  return create_common(descs, n, true, out);
+}
+
+int game_create_host(const GameDesc* descs, int32_t n, Game** out) {
+  return create_common(descs, n, false, out);
+}
+
+void game_destroy(Game* g) {
+  if (!g) return;
+  if (g->device) {
+    (void)hipSetDevice(g->device_id);
+    (void)hipDeviceSynchronize();
+  }
+  delete g;
+}
+
+int game_num_instances(const Game* g, int32_t* n) {
+  if (!g || !n) return fail(PMX_EINVAL, "null argument");
+  *n = (int32_t)g->hg.inst.size();
+  return PMX_OK;
+}
+
+int game_layout(const Game* g, int32_t instance, int32_t player, Layout* out) {
+  if (!g || !out) return fail(PMX_EINVAL, "null argument");
+  if (instance < 0 || instance >= (int)g->hg.inst.size()) return fail(PMX_EINVAL, "bad instance");
+  if (player < 0 || player > 1) return fail(PMX_EINVAL, "bad player");
+  const Built& b = g->hg.inst[instance];
+  Layout L;
+  L.n_seq = b.sf.n_seq[player];
+  L.n_hands = b.inst.n[player];
+  L.stride = b.stride[player];
+  L.vec_offset = b.vec_off[player];
+  L.vec_elems = g->hg.elems[player];
+  L.n_infosets = (int32_t)b.inf_parent[player].size();
+  L.infoset_parent = b.inf_parent[player].data();
+  L.infoset_first = b.inf_first[player].data();
+  L.infoset_nact = b.inf_nact[player].data();
+  L.infoset_board = b.inf_board[player].data();
+  *out = L;
+  return PMX_OK;
+}
+
+int game_terminals(const Game* g, int32_t instance, Terminals* out) {
+  if (!g || !out) return fail(PMX_EINVAL, "null argument");
+  if (instance < 0 || instance >= (int)g->hg.inst.size()) return fail(PMX_EINVAL, "bad instance");
+  const Built& b = g->hg.inst[instance];
+  Terminals T;
+  T.n_terminals = (int32_t)b.t_seq1.size();
+  T.seq1 = b.t_seq1.data();
+  T.seq2 = b.t_seq2.data();
+  T.kind = b.t_kind.data();
+  T.board = b.t_board.data();
+  T.runout = b.t_runout.data();
+  T.c1 = b.t_c1.data();
+  T.c2 = b.t_c2.data();
+  *out = T;
+  return PMX_OK;
+}
+
+int game_hand_meta(const Game* g, int32_t instance, int32_t ctx, int32_t player, HandMeta* out) {
+  if (!g || !out) return fail(PMX_EINVAL, "null argument");
+  if (instance < 0 || instance >= (int)g->hg.inst.size()) return fail(PMX_EINVAL, "bad instance");
+  if (player < 0 || player > 1) return fail(PMX_EINVAL, "bad player");
+  const Built& b = g->hg.inst[instance];
+  if (ctx < 0 || ctx >= b.n_ctx) return fail(PMX_EINVAL, "bad board context");
+  // exported views are rebuilt lazily into per-context vectors owned by the game
+  static_assert(sizeof(QueryRec) == 8 * sizeof(int32_t), "QueryRec layout");
+  const CtxMeta& m = b.ctx[player][ctx];
+  HandMeta H;
+  H.n_hands = b.inst.n[player];
+  H.n_live = m.n_live;
+  H.rank = m.rank.data();
+  H.lt = &m.q.data()->lt;
+  H.le = &m.q.data()->le;
+  H.self_ = &m.q.data()->self;
+  H.beta = b.beta;
+  *out = H;
+  return PMX_OK;
+}
+
+int matvec_A(Game* g, const float* y, float* out, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!y || !out) return fail(PMX_EINVAL, "null vector");
+  MvParams P = mv_params(g, 0, 1.0);
+  return launch_mv<float>(g, P, y, out, empty_params(P), nullptr, nullptr, (hipStream_t)stream);
+}
+
+int matvec_AT(Game* g, const float* x, float* out, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!x || !out) return fail(PMX_EINVAL, "null vector");
+  MvParams P = mv_params(g, 1, 1.0);
+  return launch_mv<float>(g, P, x, out, empty_params(P), nullptr, nullptr, (hipStream_t)stream);
+}
+
+int matvec_A_f64(Game* g, const double* y, double* out, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!y || !out) return fail(PMX_EINVAL, "null vector");
+  MvParams P = mv_params(g, 0, 1.0);
+  return launch_mv<double>(g, P, y, out, empty_params(P), nullptr, nullptr, (hipStream_t)stream);
+}
+
+int matvec_AT_f64(Game* g, const double* x, double* out, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!x || !out) return fail(PMX_EINVAL, "null vector");
+  MvParams P = mv_params(g, 1, 1.0);
+  return launch_mv<double>(g, P, x, out, empty_params(P), nullptr, nullptr, (hipStream_t)stream);
+}
+
+int matvec_pair(Game* g, const float* y, const float* x, float* Ay, float* ATx, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!y || !x || !Ay || !ATx) return fail(PMX_EINVAL, "null vector");
+  return launch_mv<float>(g, mv_params(g, 0, 1.0), y, Ay, mv_params(g, 1, 1.0), x, ATx,
+                          (hipStream_t)stream);
+}
+
+int solver_reset(Game* g, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  for (int p = 0; p < 2; ++p) {
+    const int64_t n = g->hg.elems[p];
+    fill_f32(g->R[p].p, n, 0.f, s);
+    fill_f32(g->x[p].p, n, 0.f, s);
+    fill_f64(g->xs[p].p, n, 0.0, s);
+    if ((rc = uniform_plan(g, p, s))) return rc;
+  }
+  HIP_TRY(hipGetLastError());
+  g->t = 0;
+  g->wsum = 0.0;
+  return PMX_OK;
+}
+
+int solver_step(Game* g, int32_t n_iters, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (n_iters < 0) return fail(PMX_EINVAL, "n_iters must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  MvParams PA = mv_params(g, 0, 1.0), PT = mv_params(g, 1, -1.0);
+  for (int it = 0; it < n_iters; ++it) {
+    const double t = (double)(g->t + 1);
+    // Player 1: g1 = A y_t
+    if ((rc = launch_mv<float>(g, PA, g->x[1].p, g->grad[0].p, empty_params(PA), nullptr, nullptr, s)))
+      return rc;
+    if ((rc = rm_update(g, 0, t, s))) return rc;
+    // Player 2: g2 = -A^T x_{t+1}
+    if ((rc = launch_mv<float>(g, PT, g->x[0].p, g->grad[1].p, empty_params(PT), nullptr, nullptr, s)))
+      return rc;
+    if ((rc = rm_update(g, 1, t, s))) return rc;
+    g->t += 1;
+    g->wsum += t;
+  }
+  return PMX_OK;
+}
+
+static int gap_from_sums(Game* g, const double* xsum, const double* ysum, double scale,
+                         double* gap, double* br1, double* br2, hipStream_t s) {
+  int rc;
+  MvParams PA = mv_params(g, 0, 1.0), PT = mv_params(g, 1, 1.0);
+  if ((rc = launch_mv<double>(g, PA, ysum, g->gd[0].p, empty_params(PA), nullptr, nullptr, s))) return rc;
+  if ((rc = launch_mv<double>(g, PT, xsum, g->gd[1].p, empty_params(PT), nullptr, nullptr, s))) return rc;
+  if ((rc = br_values(g, 0, g->gd[0].p, s))) return rc;
+  if ((rc = br_values(g, 1, g->gd[1].p, s))) return rc;
+  const int ni = (int)g->hg.inst.size();
+  std::vector<double> h(2 * (size_t)ni);
+  HIP_TRY(hipMemcpyAsync(h.data(), g->br_inst.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < ni; ++i) {
+    double a = h[i] * scale, b = h[ni + i] * scale;
+    if (!std::isfinite(a) || !std::isfinite(b)) return fail(PMX_ENUMERIC, "non-finite best response");
+    if (br1) br1[i] = a;
+    if (br2) br2[i] = b;
+    if (gap) gap[i] = a - b;
+  }
+  return PMX_OK;
+}
+
+int saddle_gap(Game* g, double* gap, double* br1, double* br2, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (g->wsum > 0)
+    return gap_from_sums(g, g->xs[0].p, g->xs[1].p, 1.0 / g->wsum, gap, br1, br2, s);
+  // no iteration yet: the average is the current (uniform) plan
+  for (int p = 0; p < 2; ++p) {
+    const int64_t n = g->hg.elems[p];
+    std::vector<float> xf((size_t)n);
+    std::vector<double> xd((size_t)n);
+    HIP_TRY(hipMemcpyAsync(xf.data(), g->x[p].p, n * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n; ++i) xd[i] = xf[i];
+    HIP_TRY(hipMemcpy(g->sd[p].p, xd.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  }
+  return gap_from_sums(g, g->sd[0].p, g->sd[1].p, 1.0, gap, br1, br2, s);
+}
+
+int saddle_gap_of(Game* g, const double* x, const double* y, double* gap, double* br1, double* br2,
+                  void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!x || !y) return fail(PMX_EINVAL, "null vector");
+  return gap_from_sums(g, x, y, 1.0, gap, br1, br2, (hipStream_t)stream);
+}
+
+int solver_get_state(Game* g, int32_t player, float* regret, float* plan, double* avg_sum, int32_t* t,
+                     double* wsum) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (player < 0 || player > 1) return fail(PMX_EINVAL, "bad player");
+  HIP_TRY(hipDeviceSynchronize());
+  const size_t n = (size_t)g->hg.elems[player];
+  if (regret) HIP_TRY(hipMemcpy(regret, g->R[player].p, n * sizeof(float), hipMemcpyDeviceToHost));
+  if (plan) HIP_TRY(hipMemcpy(plan, g->x[player].p, n * sizeof(float), hipMemcpyDeviceToHost));
+  if (avg_sum) HIP_TRY(hipMemcpy(avg_sum, g->xs[player].p, n * sizeof(double), hipMemcpyDeviceToHost));
+  if (t) *t = g->t;
+  if (wsum) *wsum = g->wsum;
+  return PMX_OK;
+}
+
+int solver_set_state(Game* g, int32_t player, const float* regret, const float* plan,
+                     const double* avg_sum, int32_t t, double wsum) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (player < 0 || player > 1) return fail(PMX_EINVAL, "bad player");
+  if (t < 0 || !std::isfinite(wsum) || wsum < 0) return fail(PMX_EINVAL, "bad iteration state");
+  HIP_TRY(hipDeviceSynchronize());
+  const size_t n = (size_t)g->hg.elems[player];
+  if (regret) HIP_TRY(hipMemcpy(g->R[player].p, regret, n * sizeof(float), hipMemcpyHostToDevice));
+  if (plan) HIP_TRY(hipMemcpy(g->x[player].p, plan, n * sizeof(float), hipMemcpyHostToDevice));
+  if (avg_sum) HIP_TRY(hipMemcpy(g->xs[player].p, avg_sum, n * sizeof(double), hipMemcpyHostToDevice));
+  g->t = t;
+  g->wsum = wsum;
+  return PMX_OK;
+}
+
+int get_average_strategy(Game* g, int32_t player, double* x_host) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (player < 0 || player > 1 || !x_host) return fail(PMX_EINVAL, "bad argument");
+  const size_t n = (size_t)g->hg.elems[player];
+  HIP_TRY(hipDeviceSynchronize());
+  if (g->wsum > 0) {
+    HIP_TRY(hipMemcpy(x_host, g->xs[player].p, n * sizeof(double), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < n; ++i) x_host[i] /= g->wsum;
+  } else {
+    std::vector<float> xf(n);
+    HIP_TRY(hipMemcpy(xf.data(), g->x[player].p, n * sizeof(float), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < n; ++i) x_host[i] = xf[i];
+  }
+  return PMX_OK;
+}
+
+int set_initial_strategy(Game* g, int32_t player, const float* behav, float scale, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (player < 0 || player > 1 || !behav) return fail(PMX_EINVAL, "bad argument");
+  if (!(scale >= 0) || !std::isfinite(scale)) return fail(PMX_EINVAL, "scale must be finite and >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  DevTp& E = g->dt[player];
+  if (E.n_single)
+    hipLaunchKernelGGL(k_warm, dim3(E.n_single), dim3(TPB), 0, s, tp_params(g, player, E.b_single.p),
+                       behav, scale, g->R[player].p, g->x[player].p);
+  if (E.n_top)
+    hipLaunchKernelGGL(k_warm, dim3(E.n_top), dim3(TPB), 0, s, tp_params(g, player, E.b_top.p), behav,
+                       scale, g->R[player].p, g->x[player].p);
+  if (E.n_deep)
+    hipLaunchKernelGGL(k_warm, dim3(E.n_deep), dim3(TPB), 0, s, tp_params(g, player, E.b_deep.p),
+                       behav, scale, g->R[player].p, g->x[player].p);
+  HIP_TRY(hipGetLastError());
+  return PMX_OK;
+}
+
+}  // extern "C"

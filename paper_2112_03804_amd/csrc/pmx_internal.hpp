@@ -1,0 +1,177 @@
+// Internal host-side structures of libpmx: validated instances, the betting
+// skeleton and its sequence form, hand metadata for the structured hand
+// operators, and the work plans consumed by the HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pmx.h"
+
+namespace pmx {
+
+constexpr int kMaxHands = 1280;   // per player and instance
+constexpr int kMaxDeck = 64;
+constexpr double kEps = 1e-9;      // chip arithmetic: snapping and de-duplication
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+// ---------------------------------------------------------------------------
+// validated copy of one GameDesc
+// ---------------------------------------------------------------------------
+struct Instance {
+  int deck = 0, cph = 0;
+  std::vector<uint8_t> board, rivers;
+  int n[2] = {0, 0};
+  std::vector<uint8_t> cards[2];        // n x cph
+  std::vector<int32_t> strength[2];     // nb x n
+  std::vector<double> mu[2];
+  double contrib = 0, stack[2] = {0, 0};
+  std::vector<double> fracs;            // ascending
+  int max_raises = 0;
+  bool allin = false;
+  int nb = 1;                           // final boards (max(1, n_river))
+  bool two_rounds() const { return !rivers.empty(); }
+  int remaining() const { return deck - (int)board.size() - 2 * cph; }
+};
+
+// ---------------------------------------------------------------------------
+// sequence form
+// ---------------------------------------------------------------------------
+struct Infoset {
+  int parent, first, nact, board;
+};
+struct Terminal {
+  int seq[2];
+  int kind;
+  int board;
+  int runout;
+  double c1, c2;
+};
+struct RiverTask {      // one (chance node, river card) subtree
+  int board;
+  int parent_seq[2];    // each player's last first-round sequence
+  int inf_begin[2], inf_end[2];
+};
+struct SeqForm {
+  int n_seq[2] = {0, 0};
+  std::vector<Infoset> inf[2];
+  std::vector<Terminal> terms;
+  std::vector<RiverTask> rivers;        // empty for a river endgame
+};
+
+// ---------------------------------------------------------------------------
+// hand metadata of one (board context, player)
+// ---------------------------------------------------------------------------
+// Scan side: the player's live hands sorted by (strength, index) and the
+// entry list of the segmented scan: segment 0 = all live hands, segment 1+c =
+// live hands holding card c, each in sorted order and closed by a sentinel.
+// An entry holds the sorted position of its hand, or -1-seg for a sentinel.
+// Query side: positions in the *opponent's* scan side that bracket a hand.
+struct QueryRec {                       // 8 x int32, the kernel's record
+  int32_t lt, le;                       // global: opp live hands weaker / not stronger
+  int32_t lt0, le0, lt1, le1;           // same inside each own card's segment (absolute entry index)
+  int32_t cards;                        // c0 | c1 << 8 (c1 = 255 for one-card hands)
+  int32_t self;                         // sorted position of the identical opp hand, -1 none
+};
+struct CtxMeta {
+  // scan side of this player
+  int n_live = 0;
+  std::vector<int32_t> rank;            // n
+  std::vector<int32_t> seg_src;         // entries
+  std::vector<int32_t> seg_end;         // 1 + deck: sentinel entry index of each segment
+  std::vector<int32_t> sorted_strength; // n_live, ascending
+  // query side of this player against the opponent's scan side
+  std::vector<QueryRec> q;              // n
+};
+
+// ---------------------------------------------------------------------------
+// per-instance build result
+// ---------------------------------------------------------------------------
+struct Built {
+  Instance inst;
+  SeqForm sf;
+  double beta = 0;
+  std::vector<double> lam[2];
+  int n_ctx = 1;
+  std::vector<CtxMeta> ctx[2];          // [player][ctx]
+  int stride[2] = {0, 0};
+  int64_t vec_off[2] = {0, 0};
+  // exported layout arrays
+  std::vector<int32_t> inf_parent[2], inf_first[2], inf_nact[2], inf_board[2];
+  std::vector<int32_t> t_seq1, t_seq2, t_kind, t_board, t_runout;
+  std::vector<double> t_c1, t_c2;
+};
+
+// ---------------------------------------------------------------------------
+// kernel plans (plain structs, copied to the device verbatim)
+// ---------------------------------------------------------------------------
+struct MvCtx {                          // (instance, context) as seen by one direction
+  int32_t n_own, n_opp, n_live, n_ent;
+  int32_t n_seg, cph, stride_own, pad;
+  int64_t q_off;                        // QueryRec offset (own)
+  int64_t rank_off;                     // opp rank offset
+  int64_t seg_off;                      // opp entries offset
+  int64_t segend_off;                   // opp seg_end offset
+  int64_t lam_own_off, lam_opp_off;
+};
+struct MvItem {
+  int64_t out, in_f, in_s;              // element offsets (in_* = -1: absent)
+  int32_t ctx;                          // -1: the row has no terminal, write zeros
+  int32_t last;                         // 1: last item of its output row
+  int32_t n_own, stride;                // output row length and padded stride
+  double kf, ks;                        // coefficients (payoff x chance)
+};
+struct MvDir {                          // host copy of one direction's plan
+  std::vector<MvCtx> ctx;
+  std::vector<MvItem> items;
+  std::vector<int32_t> blk;             // item ranges: blk[b] .. blk[b+1]
+  std::vector<QueryRec> q;
+  std::vector<int32_t> rank, seg, segend;
+  int max_ent = 0, max_seg = 0, max_n = 0;
+};
+
+struct TpTask {                         // treeplex task: one subtree of one instance
+  int64_t vec_base;
+  int32_t stride, n_hands;
+  int32_t inf_begin, inf_end;           // range into the task's infoset id list
+  int32_t stage;                        // deep task: row of the stage buffer, else -1
+  int32_t pull_begin, pull_end;         // top task: stage rows to pull
+  int32_t inst;
+  int32_t hand_base;                    // offset of this instance's hands in per-hand outputs
+  int32_t ext_parent;                   // deep task: the first-round sequence its roots hang from
+};
+struct TpPull {
+  int32_t seq;                          // instance-relative sequence receiving the value
+  int32_t stage;
+};
+struct TpPlan {                         // one player
+  std::vector<int32_t> inf_parent, inf_first, inf_nact;   // global infoset table (seq ids relative)
+  std::vector<int32_t> order;           // infoset ids of each task, DFS order
+  std::vector<TpTask> tasks;
+  std::vector<TpPull> pulls;
+  std::vector<int32_t> deep, top, single;                 // task ids per phase
+  int n_stage = 0, stage_stride = 0;
+  int64_t hands_total = 0;
+};
+
+struct HostGame {
+  std::vector<Built> inst;
+  int64_t elems[2] = {0, 0};
+  MvDir dir[2];
+  TpPlan tp[2];
+  int max_stride = 0;
+};
+
+// host_build.cpp
+int validate(const GameDesc& d, Instance& out, std::string& msg);
+void build_seqform(const Instance& in, SeqForm& sf);
+void build_hand_meta(Built& b);
+int build_game(const GameDesc* descs, int n, HostGame& hg, std::string& msg);
+int default_rows_per_block();
+
+}  // namespace pmx

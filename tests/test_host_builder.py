@@ -1,0 +1,185 @@
+"""CPU tests of libpmx's host side (no GPU calls).
+
+* the library loads and exports every function include/pmx.h declares;
+* the sequence form (ids, parents, terminals, contributions) equals the
+  oracle's, bit for bit;
+* hand metadata (strength order, tie-aware positions, identical-hand links,
+  beta) equals brute-force definitions;
+* invalid descriptors are rejected with PMX_EINVAL before any device work.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2112_03804_amd import instances as I
+from paper_2112_03804_amd import pmx
+from oracle import payoff
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "pmx.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    L = pmx.lib()
+    declared = _header_functions()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(pmx.EXPORTS) == declared
+
+
+GAMES = [
+    ("kuhn", I.kuhn),
+    ("tiny", I.tiny_config),
+    ("river", lambda: I.config(1)),
+    ("river_pruned", lambda: I.river_config(seed=7, n_keep=(300, 517), bet_fracs=(0.33, 1.5))),
+    ("small_turn_1card", lambda: I.small_turn_river(0)),
+    ("small_turn_2card", lambda: I.small_turn_river(1, deck_size=9, n_board=3, cards_per_hand=2,
+                                                    bet_fracs=(0.5,), max_raises=0, stack=8.0)),
+]
+
+
+@pytest.mark.parametrize("name,fn", GAMES)
+def test_sequence_form_matches_oracle(name, fn):
+    d = fn()
+    g = pmx.Game(d, device=False)
+    o = payoff.Game(d)
+    for p in range(2):
+        L = g.layout(0, p)
+        assert L["n_seq"] == o.S[p]
+        assert L["n_hands"] == o.N[p]
+        assert L["stride"] % 4 == 0 and L["stride"] >= L["n_hands"]
+        infs = o.sf.infosets[p]
+        assert L["n_infosets"] == len(infs)
+        assert list(L["infoset_parent"]) == [I_.parent_seq for I_ in infs]
+        assert list(L["infoset_first"]) == [I_.first_seq for I_ in infs]
+        assert list(L["infoset_nact"]) == [I_.n_actions for I_ in infs]
+        assert list(L["infoset_board"]) == [I_.board for I_ in infs]
+    T = g.terminals(0)
+    ot = o.sf.terminals
+    assert len(T["seq1"]) == len(ot)
+    assert list(T["seq1"]) == [t.seq1 for t in ot]
+    assert list(T["seq2"]) == [t.seq2 for t in ot]
+    assert list(T["kind"]) == [t.kind for t in ot]
+    assert list(T["board"]) == [t.board for t in ot]
+    assert list(T["runout"]) == [int(t.runout) for t in ot]
+    assert np.array_equal(T["c1"], np.array([t.c1 for t in ot]))
+    assert np.array_equal(T["c2"], np.array([t.c2 for t in ot]))
+    g.close()
+
+
+def _brute_meta(d, ctx, p):
+    """Definitions: live hands, (strength, index) order, tie-aware counts."""
+    q = 1 - p
+    hands = [np.asarray(h) for h in d.hands]
+    two = len(d.river_cards) > 0
+
+    def live(pl, h):
+        return ctx == 0 or int(d.river_cards[ctx - 1]) not in hands[pl][h].tolist()
+
+    def st(pl, h):
+        if two:
+            return 0 if ctx == 0 else int(d.strength[pl][ctx - 1][h])
+        return int(d.strength[pl][0][h])
+
+    n = len(hands[p])
+    lv = [h for h in range(n) if live(p, h)]
+    order = sorted(lv, key=lambda h: (st(p, h), h))
+    rank = -np.ones(n, np.int64)
+    for i, h in enumerate(order):
+        rank[h] = i
+    lt = -np.ones(n, np.int64)
+    le = -np.ones(n, np.int64)
+    oq = [h for h in range(len(hands[q])) if live(q, h)]
+    for h in lv:
+        lt[h] = sum(1 for j in oq if st(q, j) < st(p, h))
+        le[h] = sum(1 for j in oq if st(q, j) <= st(p, h))
+    # the opponent's rank of the hand holding the same cards
+    orank = {}
+    oorder = sorted(oq, key=lambda h: (st(q, h), h))
+    for i, h in enumerate(oorder):
+        orank[tuple(sorted(hands[q][h].tolist()))] = i
+    self_ = -np.ones(n, np.int64)
+    for h in lv:
+        self_[h] = orank.get(tuple(sorted(hands[p][h].tolist())), -1)
+    return rank, lt, le, self_, len(lv)
+
+
+@pytest.mark.parametrize("name,fn", [GAMES[1], GAMES[3], GAMES[4], GAMES[5]])
+def test_hand_metadata_matches_definitions(name, fn):
+    d = fn()
+    g = pmx.Game(d, device=False)
+    o = payoff.Game(d)
+    n_ctx = 1 + len(d.river_cards) if len(d.river_cards) else 1
+    ctxs = range(n_ctx) if n_ctx < 12 else [0, 1, n_ctx - 1]
+    for ctx in ctxs:
+        for p in range(2):
+            m = g.hand_meta(0, ctx, p)
+            rank, lt, le, self_, nl = _brute_meta(d, ctx, p)
+            assert m["n_live"] == nl
+            assert np.array_equal(m["rank"], rank)
+            live = rank >= 0
+            assert np.array_equal(m["lt"][live], lt[live])
+            assert np.array_equal(m["le"][live], le[live])
+            assert np.array_equal(m["self_"][live], self_[live])
+            assert np.all(m["lt"][~live] == -1)
+            assert abs(m["beta"] - o.hm.beta) <= 1e-13 * o.hm.beta
+    g.close()
+
+
+def test_config_sizes():
+    g = pmx.Game(I.config(1), device=False)
+    L = g.layout(0, 0)
+    assert (L["n_seq"], L["n_hands"], L["n_infosets"]) == (46, 1081, 16)
+    g.close()
+
+
+def _bad(mutate):
+    d = I.small_river(0)
+    d = d.copy()
+    mutate(d)
+    with pytest.raises(pmx.PmxError) as ei:
+        pmx.Game(d, device=False)
+    assert ei.value.code == pmx.PMX_EINVAL
+    return str(ei.value)
+
+
+def test_rejects_invalid_descriptors():
+    _bad(lambda d: d.range_.__setitem__(0, np.zeros_like(d.range_[0])))            # beta = 0
+    _bad(lambda d: d.range_[0].__setitem__(0, np.nan))
+    _bad(lambda d: d.range_[1].__setitem__(1, -1.0))
+    _bad(lambda d: d.hands[0].__setitem__((0, 0), d.board[0]))                      # board collision
+    _bad(lambda d: d.hands[0].__setitem__((0, 1), d.hands[0][0, 0]))                # repeated card
+    _bad(lambda d: d.hands.__setitem__(1, np.concatenate([d.hands[1], d.hands[1][:1]])))
+    _bad(lambda d: setattr(d, "bet_fracs", np.array([0.5, -1.0])))
+    _bad(lambda d: setattr(d, "max_raises", -1))
+    _bad(lambda d: setattr(d, "contrib", 0.0))
+    _bad(lambda d: setattr(d, "stack", (np.inf, 10.0)))
+    _bad(lambda d: setattr(d, "deck_size", 70))
+    _bad(lambda d: d.strength[1].__setitem__((0, 0), d.strength[1][0, 0] + 1000))  # inconsistent strength
+    _bad(lambda d: setattr(d, "river_cards", np.array([0], np.uint8)))             # incomplete river list
+
+
+def test_rejects_empty_hand_list():
+    d = I.small_river(0)
+    d.hands[0] = d.hands[0][:0]
+    d.strength[0] = d.strength[0][:, :0]
+    d.range_[0] = d.range_[0][:0]
+    with pytest.raises(pmx.PmxError):
+        pmx.Game(d, device=False)
+
+
+def test_device_calls_on_host_only_game_fail_cleanly():
+    g = pmx.Game(I.kuhn(), device=False)
+    import ctypes
+    rc = pmx.lib().solver_step(g._h, 1, ctypes.c_void_p(0))
+    assert rc == pmx.PMX_ESTATE
+    g.close()
