@@ -428,7 +428,13 @@ void build_hand_meta(Built& b) {
 // ---------------------------------------------------------------------------
 // plans
 // ---------------------------------------------------------------------------
-int default_rows_per_block() { return 4; }
+// One output row per workgroup while rows are few (latency: every row in
+// flight at once); more rows per workgroup once the grid has several
+// workgroups per compute unit, so context metadata is loaded once per chunk.
+int default_rows_per_block(int64_t rows) {
+  if (rows <= 8192) return 1;
+  return (int)std::min<int64_t>(8, rows / 4096);
+}
 
 namespace {
 
@@ -438,6 +444,8 @@ struct Contrib {
   int in_seq;
   double coef;
 };
+
+}  // namespace
 
 void build_matvec_plan(HostGame& hg, int d, int rows_per_block) {
   const int p = d, q = 1 - d;
@@ -461,11 +469,24 @@ void build_matvec_plan(HostGame& hg, int d, int rows_per_block) {
       m.cph = in.cph;
       m.stride_own = b.stride[p];
       m.q_off = (int64_t)D.q.size();
-      D.q.insert(D.q.end(), own.q.begin(), own.q.end());
+      for (const QueryRec& r : own.q) {
+        auto lohi = [](int32_t lo, int32_t hi) {
+          return (uint32_t)(uint16_t)(int16_t)lo | ((uint32_t)(uint16_t)(int16_t)hi << 16);
+        };
+        QueryRec16 k;
+        k.x = lohi(r.lt, r.le);
+        k.y = lohi(r.lt0, r.le0);
+        k.z = lohi(r.lt1, r.le1);
+        k.w = (uint32_t)(r.cards & 0xffff) | ((uint32_t)(uint16_t)(int16_t)r.self << 16);
+        D.q.push_back(k);
+      }
       m.rank_off = (int64_t)D.rank.size();
-      D.rank.insert(D.rank.end(), opp.rank.begin(), opp.rank.end());
+      for (int32_t v : opp.rank) D.rank.push_back((int16_t)v);
       m.seg_off = (int64_t)D.seg.size();
-      D.seg.insert(D.seg.end(), opp.seg_src.begin(), opp.seg_src.end());
+      for (int32_t v : opp.seg_src) D.seg.push_back((int16_t)v);
+      // pad each context's entry list to a multiple of 8 (aligned vector loads)
+      while (D.seg.size() % 8) D.seg.push_back(0);
+      while (D.rank.size() % 8) D.rank.push_back(-1);
       m.segend_off = (int64_t)D.segend.size();
       D.segend.insert(D.segend.end(), opp.seg_end.begin(), opp.seg_end.end());
       m.lam_own_off = -1;   // filled by the ABI layer (lambda arrays are per player)
@@ -585,6 +606,8 @@ void build_matvec_plan(HostGame& hg, int d, int rows_per_block) {
   }
 }
 
+namespace {
+
 void build_treeplex_plan(HostGame& hg, int p) {
   TpPlan& T = hg.tp[p];
   T = TpPlan();
@@ -609,12 +632,27 @@ void build_treeplex_plan(HostGame& hg, int p) {
       t.inst = (int)ii;
       t.hand_base = (int32_t)hand_base;
       t.ext_parent = -1;
+      t.seq_begin = t.seq_end = -1;
       return t;
+    };
+    auto seq_range = [&](TpTask& t) {
+      int lo = 1 << 30, hi = -1, cnt = 0;
+      for (int k = t.inf_begin; k < t.inf_end; ++k) {
+        int I = T.order[k] - base;
+        lo = std::min(lo, b.sf.inf[p][I].first);
+        hi = std::max(hi, b.sf.inf[p][I].first + b.sf.inf[p][I].nact);
+        cnt += b.sf.inf[p][I].nact;
+      }
+      if (hi >= 0 && cnt == hi - lo) {
+        t.seq_begin = lo;
+        t.seq_end = hi;
+      }
     };
     if (b.sf.rivers.empty()) {
       TpTask t = new_task();
       for (int i = 0; i < (int)b.sf.inf[p].size(); ++i) T.order.push_back(base + i);
       t.inf_end = (int)T.order.size();
+      seq_range(t);
       T.single.push_back((int)T.tasks.size());
       T.tasks.push_back(t);
     } else {
@@ -624,6 +662,7 @@ void build_treeplex_plan(HostGame& hg, int p) {
         TpTask t = new_task();
         for (int i = rt.inf_begin[p]; i < rt.inf_end[p]; ++i) T.order.push_back(base + i);
         t.inf_end = (int)T.order.size();
+        seq_range(t);
         t.stage = T.n_stage++;
         t.ext_parent = rt.parent_seq[p];
         pulls.push_back(TpPull{rt.parent_seq[p], t.stage});
@@ -703,7 +742,12 @@ int build_game(const GameDesc* descs, int n, HostGame& hg, std::string& msg) {
   }
   hg.elems[0] = off[0];
   hg.elems[1] = off[1];
-  for (int d = 0; d < 2; ++d) build_matvec_plan(hg, d, default_rows_per_block());
+  {
+    int64_t rows = 0;
+    for (auto& b : hg.inst) rows += std::max(b.sf.n_seq[0], b.sf.n_seq[1]);
+    hg.rows_per_block = default_rows_per_block(rows);
+  }
+  for (int d = 0; d < 2; ++d) build_matvec_plan(hg, d, hg.rows_per_block);
   for (int p = 0; p < 2; ++p) build_treeplex_plan(hg, p);
   return PMX_OK;
 }

@@ -56,15 +56,20 @@ struct MvParams {
   const MvItem* items;
   const int32_t* blk;
   const MvCtx* ctx;
-  const QueryRec* q;
-  const int32_t* rank;
-  const int32_t* seg;
+  const uint4* q;
+  const int16_t* rank;
+  const int16_t* seg;
   const int32_t* segend;
   const double* lam;
+  const float* lamf;
   double scale;
   int32_t nblk;
   int32_t max_ent, max_n, max_seg;
 };
+
+// LDS index with one spare double every 16: a thread's contiguous chunk of 16
+// entries then starts on a different bank than its neighbour's.
+__host__ __device__ inline int pd(int i) { return i + (i >> 4); }
 
 template <typename T>
 __device__ inline T shfl_up64(T v, int d) {
@@ -127,29 +132,50 @@ __device__ inline void block_seg_scan(bool flag, double a, double b, double* scr
   __syncthreads();
 }
 
+__device__ inline int lo16(uint32_t v) { return (int)(int16_t)(v & 0xffffu); }
+__device__ inline int hi16(uint32_t v) { return (int)(int16_t)(v >> 16); }
+
+template <typename IO>
+__device__ inline const IO* lam_of(const MvParams& P);
+template <>
+__device__ inline const float* lam_of<float>(const MvParams& P) { return P.lamf; }
+template <>
+__device__ inline const double* lam_of<double>(const MvParams& P) { return P.lam; }
+
+// One workgroup processes a chunk of items (output rows x board contexts).
+// KH own/opponent hands and KE scan entries per thread; metadata of the
+// current context stays in registers across the chunk's rows.
 template <int BLOCK, int KH, int KE, typename IO>
-__global__ __launch_bounds__(BLOCK) void k_matvec(MvParams P0, const IO* __restrict__ in0,
+__global__ __launch_bounds__(BLOCK, 4) void k_matvec(MvParams P0, const IO* __restrict__ in0,
                                                   IO* __restrict__ out0, MvParams P1,
-                                                  const IO* __restrict__ in1, IO* __restrict__ out1) {
+                                                  const IO* __restrict__ in1, IO* __restrict__ out1,
+                                                  double* __restrict__ tick) {
+  static_assert(KE % 2 == 0, "entries are packed in pairs");
+  if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1.0;
   const bool second = (int)blockIdx.x >= P0.nblk;
   const MvParams& P = second ? P1 : P0;
   const IO* __restrict__ in = second ? in1 : in0;
   IO* __restrict__ out = second ? out1 : out0;
+  const IO* __restrict__ lam = lam_of<IO>(P);
   const int b = second ? (int)blockIdx.x - P0.nblk : (int)blockIdx.x;
   const int tid = threadIdx.x;
 
   extern __shared__ double smem[];
-  double* Pc = smem;                            // [max_ent] exclusive segmented prefix (showdown channel)
-  double* us = Pc + P.max_ent;                  // [max_n] showdown input, sorted order
-  double* uf = us + P.max_n;                    // [max_n] fold input, sorted order
-  double* segF = uf + P.max_n;                  // [max_seg] per-segment fold totals
-  double* scratch = segF + P.max_seg;           // [3 * BLOCK / 64]
-  int* segEnd = (int*)(scratch + 3 * (BLOCK / 64));  // [max_seg]
+  const int me = pd(P0.max_ent > P1.max_ent ? P0.max_ent : P1.max_ent) + 1;
+  const int mn = pd(P0.max_n > P1.max_n ? P0.max_n : P1.max_n) + 1;
+  const int ms = P0.max_seg > P1.max_seg ? P0.max_seg : P1.max_seg;
+  double* Pc = smem;                            // [me] exclusive segmented prefix (showdown channel)
+  double* segF = Pc + me;                       // [ms] per-segment fold totals
+  double* scratch = segF + ms;                  // [3 * BLOCK / 64]
+  IO* us = (IO*)(scratch + 3 * (BLOCK / 64));   // [mn] showdown input, sorted order
+  IO* uf = us + mn;                             // [mn] fold input, sorted order
+  int* segEnd = (int*)(uf + mn);                // [ms]
 
-  QueryRec qr[KH];
-  double lo[KH], lp[KH], acc[KH];
-  int rk[KH];
-  int src[KE];
+  uint4 qr[KH];
+  IO lo[KH], lp[KH];
+  double acc[KH];
+  uint32_t rkp[(KH + 1) / 2];
+  uint32_t srcp[KE / 2];
 #pragma unroll
   for (int k = 0; k < KH; ++k) acc[k] = 0.0;
 
@@ -176,54 +202,54 @@ __global__ __launch_bounds__(BLOCK) void k_matvec(MvParams P0, const IO* __restr
       cph = C.cph;
 #pragma unroll
       for (int k = 0; k < KH; ++k) {
-        int h = tid + k * BLOCK;
+        const int h = tid + k * BLOCK;
         if (h < n_own) {
           qr[k] = P.q[C.q_off + h];
-          lo[k] = P.lam[C.lam_own_off + h];
+          lo[k] = lam[C.lam_own_off + h];
         } else {
-          qr[k].lt = -1;
-          lo[k] = 0.0;
+          qr[k] = make_uint4(0xffffu, 0, 0, 0);   // lt = -1: no output
+          lo[k] = (IO)0;
         }
-        if (h < n_opp) {
-          rk[k] = P.rank[C.rank_off + h];
-          lp[k] = P.lam[C.lam_opp_off + h];
-        } else {
-          rk[k] = -1;
-          lp[k] = 0.0;
-        }
+        const int rv = h < n_opp ? (int)P.rank[C.rank_off + h] : -1;
+        lp[k] = h < n_opp ? lam[C.lam_opp_off + h] : (IO)0;
+        if (k & 1) rkp[k >> 1] |= (uint32_t)(uint16_t)(int16_t)rv << 16;
+        else rkp[k >> 1] = (uint32_t)(uint16_t)(int16_t)rv;
       }
 #pragma unroll
-      for (int j = 0; j < KE; ++j) {
-        int e = tid * KE + j;
-        src[j] = e < n_ent ? P.seg[C.seg_off + e] : 0;
+      for (int j = 0; j < KE; j += 2) {
+        const int e = tid * KE + j;
+        const int v0 = e < n_ent ? (int)P.seg[C.seg_off + e] : 0;
+        const int v1 = e + 1 < n_ent ? (int)P.seg[C.seg_off + e + 1] : 0;
+        srcp[j >> 1] = (uint32_t)(uint16_t)(int16_t)v0 | ((uint32_t)(uint16_t)(int16_t)v1 << 16);
       }
       for (int i = tid; i < C.n_seg; i += BLOCK) segEnd[i] = P.segend[C.segend_off + i];
       cur = item.ctx;
     }
     // phase 1: weighted opponent inputs scattered to strength order
     const bool has_s = item.in_s >= 0, has_f = item.in_f >= 0;
+    const IO ks = (IO)item.ks, kf = (IO)item.kf;
 #pragma unroll
     for (int k = 0; k < KH; ++k) {
-      int h = tid + k * BLOCK;
-      if (h < n_opp && rk[k] >= 0) {
-        double vs = has_s ? item.ks * lp[k] * (double)in[item.in_s + h] : 0.0;
-        double vf = has_f ? item.kf * lp[k] * (double)in[item.in_f + h] : 0.0;
-        us[rk[k]] = vs;
-        uf[rk[k]] = vf;
+      const int h = tid + k * BLOCK;
+      const int rk = (k & 1) ? hi16(rkp[k >> 1]) : lo16(rkp[k >> 1]);
+      if (h < n_opp && rk >= 0) {
+        const IO w = lp[k];
+        us[pd(rk)] = has_s ? ks * w * in[item.in_s + h] : (IO)0;
+        uf[pd(rk)] = has_f ? kf * w * in[item.in_f + h] : (IO)0;
       }
     }
     __syncthreads();
-    // phase 2: segmented exclusive scan over the entry list
+    // phase 2: segmented exclusive scan over the entry list (FP64 sums)
     double rs = 0.0, rf = 0.0;
     bool flag = false;
 #pragma unroll
     for (int j = 0; j < KE; ++j) {
-      int e = tid * KE + j;
+      const int e = tid * KE + j;
       if (e < n_ent) {
-        int s = src[j];
+        const int s = (j & 1) ? hi16(srcp[j >> 1]) : lo16(srcp[j >> 1]);
         if (s >= 0) {
-          rs += us[s];
-          rf += uf[s];
+          rs += (double)us[pd(s)];
+          rf += (double)uf[pd(s)];
         } else {
           flag = true;
           rs = 0.0;
@@ -237,13 +263,13 @@ __global__ __launch_bounds__(BLOCK) void k_matvec(MvParams P0, const IO* __restr
     rf = cf;
 #pragma unroll
     for (int j = 0; j < KE; ++j) {
-      int e = tid * KE + j;
+      const int e = tid * KE + j;
       if (e < n_ent) {
-        int s = src[j];
-        Pc[e] = rs;
+        const int s = (j & 1) ? hi16(srcp[j >> 1]) : lo16(srcp[j >> 1]);
+        Pc[pd(e)] = rs;
         if (s >= 0) {
-          rs += us[s];
-          rf += uf[s];
+          rs += (double)us[pd(s)];
+          rf += (double)uf[pd(s)];
         } else {
           segF[-1 - s] = rf;
           rs = 0.0;
@@ -253,23 +279,24 @@ __global__ __launch_bounds__(BLOCK) void k_matvec(MvParams P0, const IO* __restr
     }
     __syncthreads();
     // phase 3: read the prefix sums at each own hand's positions
-    const double tot_s = Pc[n_live];
+    const double tot_s = Pc[pd(n_live)];
     const double tot_f = segF[0];
 #pragma unroll
     for (int k = 0; k < KH; ++k) {
-      int h = tid + k * BLOCK;
-      if (h < n_own && qr[k].lt >= 0) {
-        const QueryRec r = qr[k];
-        double sd = Pc[r.lt] + Pc[r.le] - tot_s;
+      const uint4 r = qr[k];
+      const int lt = lo16(r.x);
+      if (lt >= 0) {
+        double sd = Pc[pd(lt)] + Pc[pd(hi16(r.x))] - tot_s;
         double fo = tot_f;
-        const int c0 = r.cards & 255;
-        sd -= Pc[r.lt0] + Pc[r.le0] - Pc[segEnd[1 + c0]];
+        const int c0 = r.w & 255;
+        sd -= Pc[pd(lo16(r.y))] + Pc[pd(hi16(r.y))] - Pc[pd(segEnd[1 + c0])];
         fo -= segF[1 + c0];
         if (cph == 2) {
-          const int c1 = (r.cards >> 8) & 255;
-          sd -= Pc[r.lt1] + Pc[r.le1] - Pc[segEnd[1 + c1]];
+          const int c1 = (r.w >> 8) & 255;
+          sd -= Pc[pd(lo16(r.z))] + Pc[pd(hi16(r.z))] - Pc[pd(segEnd[1 + c1])];
           fo -= segF[1 + c1];
-          if (r.self >= 0) fo += uf[r.self];
+          const int self = hi16(r.w);
+          if (self >= 0) fo += (double)uf[pd(self)];
         }
         acc[k] += sd + fo;
       }
@@ -277,8 +304,9 @@ __global__ __launch_bounds__(BLOCK) void k_matvec(MvParams P0, const IO* __restr
     if (item.last) {
 #pragma unroll
       for (int k = 0; k < KH; ++k) {
-        int h = tid + k * BLOCK;
-        if (h < item.stride) out[item.out + h] = (IO)(h < n_own ? P.scale * lo[k] * acc[k] : 0.0);
+        const int h = tid + k * BLOCK;
+        if (h < item.stride)
+          out[item.out + h] = (IO)(h < n_own ? P.scale * (double)lo[k] * acc[k] : 0.0);
         acc[k] = 0.0;
       }
     }
@@ -345,7 +373,8 @@ template <int MODE>
 __global__ __launch_bounds__(TPB) void k_rm(TpParams P, float* __restrict__ g,
                                             float* __restrict__ R, float* __restrict__ x,
                                             double* __restrict__ xs, float* __restrict__ stage,
-                                            double t) {
+                                            const double* __restrict__ tdev) {
+  const double t = *tdev;
   const int2 bt = P.blocks[blockIdx.x];
   const TpTask T = P.tasks[bt.x];
   const int h = bt.y + threadIdx.x;
@@ -375,6 +404,114 @@ __global__ __launch_bounds__(TPB) void k_rm(TpParams P, float* __restrict__ g,
     }
   }
 }
+
+// The same update with the block's slab of the task (its contiguous
+// sequences x 64 hands of g, R and x) and its infoset table staged in LDS, so
+// the serial walk over infosets touches LDS only.  One wavefront per block.
+// MODE 0: single-phase task; 1: deep bottom-up; 3: deep top-down.
+constexpr int STB = 64;
+
+template <int MODE>
+__global__ __launch_bounds__(STB) void k_rm_st(TpParams P, float* __restrict__ g,
+                                               float* __restrict__ R, float* __restrict__ x,
+                                               double* __restrict__ xs, float* __restrict__ stage,
+                                               const double* __restrict__ tdev, int ninf_max) {
+  extern __shared__ float stsm[];
+  const int2 bt = P.blocks[blockIdx.x];
+  const TpTask T = P.tasks[bt.x];
+  const int lane = threadIdx.x;
+  const int h = bt.y + lane;
+  const bool act = h < T.n_hands;
+  const int S0 = T.seq_begin, SL = T.seq_end - T.seq_begin, ninf = T.inf_end - T.inf_begin;
+  int* iPar = (int*)stsm;
+  int* iF = iPar + ninf_max;
+  int* iN = iF + ninf_max;
+  float* gL = (float*)(iN + ninf_max);
+  float* RL = gL + (size_t)SL * STB;
+  float* xL = RL + (size_t)SL * STB;
+  const int64_t base = T.vec_base + h, stride = T.stride;
+  const double t = *tdev;
+  for (int i = lane; i < ninf; i += STB) {
+    const int I = P.order[T.inf_begin + i];
+    iPar[i] = P.inf_parent[I];
+    iF[i] = P.inf_first[I] - S0;
+    iN[i] = P.inf_nact[I];
+  }
+  // rows are loaded 8 at a time so their global loads are in flight together
+  for (int r0 = 0; r0 < SL; r0 += 8) {
+    float gv[8], rv[8], xv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int r = r0 + k;
+      gv[k] = rv[k] = xv[k] = 0.f;
+      if (act && r < SL) {
+        const int64_t idx = base + (int64_t)(S0 + r) * stride;
+        if (MODE != 3) gv[k] = g[idx];
+        rv[k] = R[idx];
+        if (MODE != 1) xv[k] = x[idx];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int r = r0 + k;
+      if (r < SL) {
+        gL[r * STB + lane] = gv[k];
+        RL[r * STB + lane] = rv[k];
+        xL[r * STB + lane] = xv[k];
+        if (MODE != 1 && act) {
+          const int64_t idx = base + (int64_t)(S0 + r) * stride;
+          xs[idx] += t * (double)xv[k];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (MODE == 0 || MODE == 1) {
+    float vroot = 0.f;
+    for (int i = ninf - 1; i >= 0; --i) {
+      const int par = iPar[i], f = iF[i], n = iN[i];
+      float rs = 0.f;
+      for (int a = 0; a < n; ++a) rs += RL[(f + a) * STB + lane];
+      const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
+      float V = 0.f;
+      for (int a = 0; a < n; ++a) {
+        const float ba = rs > 0.f ? RL[(f + a) * STB + lane] * inv : uni;
+        V += ba * gL[(f + a) * STB + lane];
+      }
+      for (int a = 0; a < n; ++a) {
+        const float r = RL[(f + a) * STB + lane] + gL[(f + a) * STB + lane] - V;
+        RL[(f + a) * STB + lane] = r > 0.f ? r : 0.f;
+      }
+      if (MODE == 1 && par == T.ext_parent) vroot += V;
+      else if (par >= 0) gL[(par - S0) * STB + lane] += V;
+    }
+    if (MODE == 1 && act) stage[(int64_t)T.stage * P.stage_stride + h] = vroot;
+  }
+  if (MODE == 0 || MODE == 3) {
+    for (int i = 0; i < ninf; ++i) {
+      const int par = iPar[i], f = iF[i], n = iN[i];
+      float xp = 1.f;
+      if (par >= S0 && par < S0 + SL) xp = xL[(par - S0) * STB + lane];
+      else if (par >= 0) xp = act ? x[base + (int64_t)par * stride] : 0.f;
+      float rs = 0.f;
+      for (int a = 0; a < n; ++a) rs += RL[(f + a) * STB + lane];
+      const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
+      for (int a = 0; a < n; ++a) {
+        const float ba = rs > 0.f ? RL[(f + a) * STB + lane] * inv : uni;
+        xL[(f + a) * STB + lane] = xp * ba;
+      }
+    }
+  }
+  if (act) {
+    for (int r = 0; r < SL; ++r) {
+      const int64_t idx = base + (int64_t)(S0 + r) * stride;
+      if (MODE != 3) R[idx] = RL[r * STB + lane];
+      if (MODE != 1) x[idx] = xL[r * STB + lane];
+    }
+  }
+}
+
+__global__ void k_set1(double* tdev, double v) { tdev[0] = v; }
 
 // Best response: per hand, bottom-up max (Player 1) or min (Player 2) of g
 // plus the values below; sums of root values go to hv[hand_base + h].
@@ -517,8 +654,9 @@ struct DevDir {
   DBuf<MvItem> items;
   DBuf<int32_t> blk;
   DBuf<MvCtx> ctx;
-  DBuf<QueryRec> q;
-  DBuf<int32_t> rank, seg, segend;
+  DBuf<QueryRec16> q;
+  DBuf<int16_t> rank, seg;
+  DBuf<int32_t> segend;
   int nblk = 0, max_ent = 0, max_n = 0, max_seg = 0;
 };
 
@@ -528,6 +666,11 @@ struct DevTp {
   DBuf<TpPull> pulls;
   DBuf<int2> b_single, b_deep, b_top, b_all;
   int n_single = 0, n_deep = 0, n_top = 0, n_all = 0;
+  // solver path: LDS-staged tasks (64 hands per block) and global-walk tasks
+  DBuf<int2> b_single_st, b_deep_st, b_single_gl, b_deep_gl;
+  int n_single_st = 0, n_deep_st = 0, n_single_gl = 0, n_deep_gl = 0;
+  int st_ninf[2] = {0, 0};          // [single, deep] max infosets of staged tasks
+  size_t st_lds[2] = {0, 0};        // dynamic LDS bytes of the staged launches
   DBuf<float> stage;
   DBuf<double> stage_d;
   DBuf<double> hv;
@@ -541,6 +684,7 @@ struct Game {
   DevDir dd[2];
   DevTp dt[2];
   DBuf<double> lam;
+  DBuf<float> lamf;
   int64_t lam_base[2] = {0, 0};
   DBuf<int64_t> inst_hand_off[2];
   // solver state
@@ -549,6 +693,18 @@ struct Game {
   int t = 0;
   double wsum = 0.0;
   int mv_block = 256;
+  DBuf<double> tdev;                // iteration index of the next step (device)
+  // solver iterations captured as a graph
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_iters = 0;
+  bool use_graph = true;
+  ~Game() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
 
 static int ensure_device(Game* g) {
@@ -558,12 +714,19 @@ static int ensure_device(Game* g) {
   return PMX_OK;
 }
 
-static std::vector<int2> tp_blocks(const TpPlan& T, const std::vector<int32_t>& ids) {
+static std::vector<int2> tp_blocks(const TpPlan& T, const std::vector<int32_t>& ids, int per = TPB) {
   std::vector<int2> b;
   for (int id : ids)
-    for (int h0 = 0; h0 < T.tasks[id].n_hands; h0 += TPB) b.push_back(make_int2(id, h0));
+    for (int h0 = 0; h0 < T.tasks[id].n_hands; h0 += per) b.push_back(make_int2(id, h0));
   return b;
 }
+
+// LDS bytes a staged task needs (infoset table + three slabs of 64 hands).
+static size_t staged_bytes(const TpTask& t, int ninf_max, int sl) {
+  (void)t;
+  return (size_t)3 * ninf_max * sizeof(int) + (size_t)3 * sl * STB * sizeof(float);
+}
+constexpr size_t kStagedLdsMax = 60 * 1024;
 
 static int upload_game(Game* g) {
   HostGame& hg = g->hg;
@@ -579,6 +742,8 @@ static int upload_game(Game* g) {
   }
   int rc = g->lam.upload(lam);
   if (rc) return rc;
+  std::vector<float> lamf(lam.begin(), lam.end());
+  if ((rc = g->lamf.upload(lamf))) return rc;
   for (int d = 0; d < 2; ++d) {
     MvDir& D = hg.dir[d];
     const int p = d, q = 1 - d;
@@ -618,6 +783,52 @@ static int upload_game(Game* g) {
     E.n_deep = (int)bd.size();
     E.n_top = (int)bt.size();
     E.n_all = (int)ba.size();
+    // staged (LDS) or global-walk path per task
+    for (int ph = 0; ph < 2; ++ph) {
+      const std::vector<int32_t>& ids = ph == 0 ? T.single : T.deep;
+      std::vector<int32_t> st, gl;
+      int ninf_max = 0, sl_max = 0;
+      for (int id : ids) {
+        const TpTask& t = T.tasks[id];
+        const int ninf = t.inf_end - t.inf_begin, sl = t.seq_end - t.seq_begin;
+        if (t.seq_begin >= 0 && staged_bytes(t, ninf, sl) <= kStagedLdsMax) {
+          st.push_back(id);
+          ninf_max = std::max(ninf_max, ninf);
+          sl_max = std::max(sl_max, sl);
+        } else {
+          gl.push_back(id);
+        }
+      }
+      // the launch uses the maxima of its tasks; drop the largest until it fits
+      while (!st.empty() && staged_bytes(T.tasks[st[0]], ninf_max, sl_max) > kStagedLdsMax) {
+        size_t worst = 0;
+        for (size_t k = 1; k < st.size(); ++k) {
+          const TpTask& a = T.tasks[st[k]];
+          const TpTask& w = T.tasks[st[worst]];
+          if (a.seq_end - a.seq_begin > w.seq_end - w.seq_begin) worst = k;
+        }
+        gl.push_back(st[worst]);
+        st.erase(st.begin() + worst);
+        ninf_max = sl_max = 0;
+        for (int id : st) {
+          const TpTask& t = T.tasks[id];
+          ninf_max = std::max(ninf_max, t.inf_end - t.inf_begin);
+          sl_max = std::max(sl_max, t.seq_end - t.seq_begin);
+        }
+      }
+      E.st_ninf[ph] = ninf_max;
+      E.st_lds[ph] = st.empty() ? 0 : staged_bytes(T.tasks[st[0]], ninf_max, sl_max);
+      auto bst = tp_blocks(T, st, STB), bgl = tp_blocks(T, gl, TPB);
+      if (ph == 0) {
+        if ((rc = E.b_single_st.upload(bst)) || (rc = E.b_single_gl.upload(bgl))) return rc;
+        E.n_single_st = (int)bst.size();
+        E.n_single_gl = (int)bgl.size();
+      } else {
+        if ((rc = E.b_deep_st.upload(bst)) || (rc = E.b_deep_gl.upload(bgl))) return rc;
+        E.n_deep_st = (int)bst.size();
+        E.n_deep_gl = (int)bgl.size();
+      }
+    }
     E.stage_stride = std::max(T.stage_stride, 1);
     if ((rc = E.stage.alloc((size_t)std::max(T.n_stage, 1) * E.stage_stride)) ||
         (rc = E.stage_d.alloc((size_t)std::max(T.n_stage, 1) * E.stage_stride)) ||
@@ -634,6 +845,7 @@ static int upload_game(Game* g) {
       return rc;
   }
   if ((rc = g->br_inst.alloc(2 * hg.inst.size()))) return rc;
+  if ((rc = g->tdev.alloc(1))) return rc;
   return PMX_OK;
 }
 
@@ -646,11 +858,12 @@ static MvParams mv_params(Game* g, int d, double scale) {
   P.items = E.items.p;
   P.blk = E.blk.p;
   P.ctx = E.ctx.p;
-  P.q = E.q.p;
+  P.q = (const uint4*)E.q.p;
   P.rank = E.rank.p;
   P.seg = E.seg.p;
   P.segend = E.segend.p;
   P.lam = g->lam.p;
+  P.lamf = g->lamf.p;
   P.scale = scale;
   P.nblk = E.nblk;
   P.max_ent = E.max_ent;
@@ -659,26 +872,26 @@ static MvParams mv_params(Game* g, int d, double scale) {
   return P;
 }
 
-template <int BLOCK>
+template <int BLOCK, typename IO>
 static size_t mv_lds(const MvParams& a, const MvParams& b) {
-  size_t me = std::max(a.max_ent, b.max_ent), mn = std::max(a.max_n, b.max_n),
+  size_t me = pd(std::max(a.max_ent, b.max_ent)) + 1, mn = pd(std::max(a.max_n, b.max_n)) + 1,
          ms = std::max(a.max_seg, b.max_seg);
-  return sizeof(double) * (me + 2 * mn + ms + 3 * (BLOCK / 64)) + sizeof(int) * ms;
+  return sizeof(double) * (me + ms + 3 * (BLOCK / 64)) + 2 * mn * sizeof(IO) + sizeof(int) * ms;
 }
 
 template <typename IO>
 static int launch_mv(Game* g, MvParams P0, const IO* in0, IO* out0, MvParams P1, const IO* in1,
-                     IO* out1, hipStream_t s) {
+                     IO* out1, hipStream_t s, double* tick = nullptr) {
   const int nb = P0.nblk + P1.nblk;
   if (nb == 0) return PMX_OK;
   // shape checks: every hand and entry must have a thread slot
   const int mn = std::max(P0.max_n, P1.max_n), me = std::max(P0.max_ent, P1.max_ent);
-  constexpr int B = 256, KH = 5, KE = 16;
+  constexpr int B = 512, KH = 3, KE = 8;
   if (mn > KH * B || me > KE * B) return fail(PMX_EINVAL, "instance too large for the matvec kernel");
-  size_t lds = mv_lds<B>(P0, P1);
+  size_t lds = mv_lds<B, IO>(P0, P1);
   if (lds > 160 * 1024) return fail(PMX_EINVAL, "matvec LDS footprint exceeds 160 KB");
   hipLaunchKernelGGL((k_matvec<B, KH, KE, IO>), dim3(nb), dim3(B), lds, s, P0, in0, out0, P1, in1,
-                     out1);
+                     out1, tick);
   HIP_TRY(hipGetLastError());
   return PMX_OK;
 }
@@ -703,21 +916,34 @@ static TpParams tp_params(Game* g, int p, const int2* blocks) {
   return P;
 }
 
-static int rm_update(Game* g, int p, double t, hipStream_t s) {
+static int rm_update(Game* g, int p, hipStream_t s) {
   DevTp& E = g->dt[p];
   float* gr = g->grad[p].p;
-  if (E.n_single)
-    hipLaunchKernelGGL(k_rm<0>, dim3(E.n_single), dim3(TPB), 0, s, tp_params(g, p, E.b_single.p), gr,
-                       g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, t);
-  if (E.n_deep)
-    hipLaunchKernelGGL(k_rm<1>, dim3(E.n_deep), dim3(TPB), 0, s, tp_params(g, p, E.b_deep.p), gr,
-                       g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, t);
+  const double* td = g->tdev.p;
+  if (E.n_single_st)
+    hipLaunchKernelGGL(k_rm_st<0>, dim3(E.n_single_st), dim3(STB), E.st_lds[0], s,
+                       tp_params(g, p, E.b_single_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
+                       E.stage.p, td, E.st_ninf[0]);
+  if (E.n_single_gl)
+    hipLaunchKernelGGL(k_rm<0>, dim3(E.n_single_gl), dim3(TPB), 0, s, tp_params(g, p, E.b_single_gl.p),
+                       gr, g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
+  if (E.n_deep_st)
+    hipLaunchKernelGGL(k_rm_st<1>, dim3(E.n_deep_st), dim3(STB), E.st_lds[1], s,
+                       tp_params(g, p, E.b_deep_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
+                       E.stage.p, td, E.st_ninf[1]);
+  if (E.n_deep_gl)
+    hipLaunchKernelGGL(k_rm<1>, dim3(E.n_deep_gl), dim3(TPB), 0, s, tp_params(g, p, E.b_deep_gl.p),
+                       gr, g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
   if (E.n_top)
     hipLaunchKernelGGL(k_rm<2>, dim3(E.n_top), dim3(TPB), 0, s, tp_params(g, p, E.b_top.p), gr,
-                       g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, t);
-  if (E.n_deep)
-    hipLaunchKernelGGL(k_rm<3>, dim3(E.n_deep), dim3(TPB), 0, s, tp_params(g, p, E.b_deep.p), gr,
-                       g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, t);
+                       g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
+  if (E.n_deep_st)
+    hipLaunchKernelGGL(k_rm_st<3>, dim3(E.n_deep_st), dim3(STB), E.st_lds[1], s,
+                       tp_params(g, p, E.b_deep_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
+                       E.stage.p, td, E.st_ninf[1]);
+  if (E.n_deep_gl)
+    hipLaunchKernelGGL(k_rm<3>, dim3(E.n_deep_gl), dim3(TPB), 0, s, tp_params(g, p, E.b_deep_gl.p),
+                       gr, g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
   HIP_TRY(hipGetLastError());
   return PMX_OK;
 }
@@ -950,9 +1176,53 @@ int solver_reset(Game* g, void* stream) {
     fill_f64(g->xs[p].p, n, 0.0, s);
     if ((rc = uniform_plan(g, p, s))) return rc;
   }
+  hipLaunchKernelGGL(k_set1, dim3(1), dim3(1), 0, s, g->tdev.p, 0.0);
   HIP_TRY(hipGetLastError());
   g->t = 0;
   g->wsum = 0.0;
+  return PMX_OK;
+}
+
+// One alternating RM+ iteration, enqueued on s: g1 = A y_t (its launch also
+// advances the device iteration index t, read by the updates as the
+// averaging weight, so a captured sequence of iterations replays correctly)
+// and Player 1's update, then g2 = -A^T x_{t+1} and Player 2's update.
+static int enqueue_iteration(Game* g, hipStream_t s) {
+  int rc;
+  MvParams PA = mv_params(g, 0, 1.0), PT = mv_params(g, 1, -1.0);
+  if ((rc = launch_mv<float>(g, PA, g->x[1].p, g->grad[0].p, empty_params(PA), nullptr, nullptr, s,
+                             g->tdev.p)))
+    return rc;
+  if ((rc = rm_update(g, 0, s))) return rc;
+  if ((rc = launch_mv<float>(g, PT, g->x[0].p, g->grad[1].p, empty_params(PT), nullptr, nullptr, s)))
+    return rc;
+  if ((rc = rm_update(g, 1, s))) return rc;
+  return PMX_OK;
+}
+
+static constexpr int kGraphIters = 32;
+
+static int capture_graph(Game* g) {
+  if (g->graph_exec) return PMX_OK;
+  if (!g->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeRelaxed));
+  int rc = PMX_OK;
+  for (int i = 0; i < kGraphIters && rc == PMX_OK; ++i) rc = enqueue_iteration(g, g->cap_stream);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(g->cap_stream, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(PMX_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    g->graph_exec = nullptr;
+    return fail(PMX_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  g->graph = graph;
+  g->graph_iters = kGraphIters;
   return PMX_OK;
 }
 
@@ -961,19 +1231,19 @@ int solver_step(Game* g, int32_t n_iters, void* stream) {
   if (rc) return rc;
   if (n_iters < 0) return fail(PMX_EINVAL, "n_iters must be >= 0");
   hipStream_t s = (hipStream_t)stream;
-  MvParams PA = mv_params(g, 0, 1.0), PT = mv_params(g, 1, -1.0);
-  for (int it = 0; it < n_iters; ++it) {
-    const double t = (double)(g->t + 1);
-    // Player 1: g1 = A y_t
-    if ((rc = launch_mv<float>(g, PA, g->x[1].p, g->grad[0].p, empty_params(PA), nullptr, nullptr, s)))
-      return rc;
-    if ((rc = rm_update(g, 0, t, s))) return rc;
-    // Player 2: g2 = -A^T x_{t+1}
-    if ((rc = launch_mv<float>(g, PT, g->x[0].p, g->grad[1].p, empty_params(PT), nullptr, nullptr, s)))
-      return rc;
-    if ((rc = rm_update(g, 1, t, s))) return rc;
+  int left = n_iters;
+  if (g->use_graph && left >= kGraphIters) {
+    if ((rc = capture_graph(g))) return rc;
+    while (left >= g->graph_iters) {
+      HIP_TRY(hipGraphLaunch(g->graph_exec, s));
+      left -= g->graph_iters;
+    }
+  }
+  for (int i = 0; i < left; ++i)
+    if ((rc = enqueue_iteration(g, s))) return rc;
+  for (int i = 0; i < n_iters; ++i) {
     g->t += 1;
-    g->wsum += t;
+    g->wsum += (double)g->t;
   }
   return PMX_OK;
 }
@@ -1055,6 +1325,8 @@ int solver_set_state(Game* g, int32_t player, const float* regret, const float* 
   if (avg_sum) HIP_TRY(hipMemcpy(g->xs[player].p, avg_sum, n * sizeof(double), hipMemcpyHostToDevice));
   g->t = t;
   g->wsum = wsum;
+  const double cur = (double)t;   // the next iteration's first launch makes it t + 1
+  HIP_TRY(hipMemcpy(g->tdev.p, &cur, sizeof(double), hipMemcpyHostToDevice));
   return PMX_OK;
 }
 

@@ -78,6 +78,11 @@ struct QueryRec {                       // 8 x int32, the kernel's record
   int32_t cards;                        // c0 | c1 << 8 (c1 = 255 for one-card hands)
   int32_t self;                         // sorted position of the identical opp hand, -1 none
 };
+// The kernel's packed form of a QueryRec (16 bytes): x = lt | le << 16,
+// y = lt0 | le0 << 16, z = lt1 | le1 << 16, w = c0 | c1 << 8 | self << 16.
+struct QueryRec16 {
+  uint32_t x, y, z, w;
+};
 struct CtxMeta {
   // scan side of this player
   int n_live = 0;
@@ -130,8 +135,9 @@ struct MvDir {                          // host copy of one direction's plan
   std::vector<MvCtx> ctx;
   std::vector<MvItem> items;
   std::vector<int32_t> blk;             // item ranges: blk[b] .. blk[b+1]
-  std::vector<QueryRec> q;
-  std::vector<int32_t> rank, seg, segend;
+  std::vector<QueryRec16> q;
+  std::vector<int16_t> rank, seg;
+  std::vector<int32_t> segend;
   int max_ent = 0, max_seg = 0, max_n = 0;
 };
 
@@ -144,6 +150,7 @@ struct TpTask {                         // treeplex task: one subtree of one ins
   int32_t inst;
   int32_t hand_base;                    // offset of this instance's hands in per-hand outputs
   int32_t ext_parent;                   // deep task: the first-round sequence its roots hang from
+  int32_t seq_begin, seq_end;           // contiguous sequences owned by the task (-1: not contiguous)
 };
 struct TpPull {
   int32_t seq;                          // instance-relative sequence receiving the value
@@ -162,6 +169,7 @@ struct TpPlan {                         // one player
 struct HostGame {
   std::vector<Built> inst;
   int64_t elems[2] = {0, 0};
+  int rows_per_block = 1;
   MvDir dir[2];
   TpPlan tp[2];
   int max_stride = 0;
@@ -172,6 +180,7 @@ int validate(const GameDesc& d, Instance& out, std::string& msg);
 void build_seqform(const Instance& in, SeqForm& sf);
 void build_hand_meta(Built& b);
 int build_game(const GameDesc* descs, int n, HostGame& hg, std::string& msg);
-int default_rows_per_block();
+int default_rows_per_block(int64_t rows);
+void build_matvec_plan(HostGame& hg, int d, int rows_per_block);
 
 }  // namespace pmx
