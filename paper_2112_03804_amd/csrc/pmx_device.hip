@@ -407,19 +407,25 @@ __global__ __launch_bounds__(TPB) void k_rm(TpParams P, float* __restrict__ g,
 
 // The same update with the block's slab of the task (its contiguous
 // sequences x 64 hands of g, R and x) and its infoset table staged in LDS, so
-// the serial walk over infosets touches LDS only.  One wavefront per block.
+// the serial walk over infosets touches LDS only.  Four wavefronts load and
+// store the slab (rows interleaved, all loads in flight); wavefront 0 walks
+// the tree for the block's 64 hands, reading each infoset's actions once.
 // MODE 0: single-phase task; 1: deep bottom-up; 3: deep top-down.
-constexpr int STB = 64;
+constexpr int STB = 64;       // hands per block
+constexpr int STW = 4;        // wavefronts per block
+constexpr int STR = 16;       // rows per thread per load round
+constexpr int MAXA = 8;       // actions handled in registers
 
 template <int MODE>
-__global__ __launch_bounds__(STB) void k_rm_st(TpParams P, float* __restrict__ g,
-                                               float* __restrict__ R, float* __restrict__ x,
-                                               double* __restrict__ xs, float* __restrict__ stage,
-                                               const double* __restrict__ tdev, int ninf_max) {
+__global__ __launch_bounds__(STB * STW) void k_rm_st(TpParams P, float* __restrict__ g,
+                                                     float* __restrict__ R, float* __restrict__ x,
+                                                     double* __restrict__ xs,
+                                                     float* __restrict__ stage,
+                                                     const double* __restrict__ tdev, int ninf_max) {
   extern __shared__ float stsm[];
   const int2 bt = P.blocks[blockIdx.x];
   const TpTask T = P.tasks[bt.x];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (STB - 1), wv = threadIdx.x / STB;
   const int h = bt.y + lane;
   const bool act = h < T.n_hands;
   const int S0 = T.seq_begin, SL = T.seq_end - T.seq_begin, ninf = T.inf_end - T.inf_begin;
@@ -431,18 +437,17 @@ __global__ __launch_bounds__(STB) void k_rm_st(TpParams P, float* __restrict__ g
   float* xL = RL + (size_t)SL * STB;
   const int64_t base = T.vec_base + h, stride = T.stride;
   const double t = *tdev;
-  for (int i = lane; i < ninf; i += STB) {
+  for (int i = threadIdx.x; i < ninf; i += STB * STW) {
     const int I = P.order[T.inf_begin + i];
     iPar[i] = P.inf_parent[I];
     iF[i] = P.inf_first[I] - S0;
     iN[i] = P.inf_nact[I];
   }
-  // rows are loaded 8 at a time so their global loads are in flight together
-  for (int r0 = 0; r0 < SL; r0 += 8) {
-    float gv[8], rv[8], xv[8];
+  for (int r0 = wv; r0 < SL; r0 += STW * STR) {
+    float gv[STR], rv[STR], xv[STR];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int r = r0 + k;
+    for (int k = 0; k < STR; ++k) {
+      const int r = r0 + k * STW;
       gv[k] = rv[k] = xv[k] = 0.f;
       if (act && r < SL) {
         const int64_t idx = base + (int64_t)(S0 + r) * stride;
@@ -451,59 +456,99 @@ __global__ __launch_bounds__(STB) void k_rm_st(TpParams P, float* __restrict__ g
         if (MODE != 1) xv[k] = x[idx];
       }
     }
+    double xo[STR];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int r = r0 + k;
+    for (int k = 0; k < STR; ++k) {
+      const int r = r0 + k * STW;
+      xo[k] = 0.0;
+      if (MODE != 1 && act && r < SL) xo[k] = xs[base + (int64_t)(S0 + r) * stride];
+    }
+#pragma unroll
+    for (int k = 0; k < STR; ++k) {
+      const int r = r0 + k * STW;
       if (r < SL) {
         gL[r * STB + lane] = gv[k];
         RL[r * STB + lane] = rv[k];
         xL[r * STB + lane] = xv[k];
-        if (MODE != 1 && act) {
-          const int64_t idx = base + (int64_t)(S0 + r) * stride;
-          xs[idx] += t * (double)xv[k];
+        if (MODE != 1 && act) xs[base + (int64_t)(S0 + r) * stride] = xo[k] + t * (double)xv[k];
+      }
+    }
+  }
+  __syncthreads();
+  if (wv == 0) {
+    if (MODE == 0 || MODE == 1) {
+      float vroot = 0.f;
+      for (int i = ninf - 1; i >= 0; --i) {
+        const int par = iPar[i], f = iF[i], n = iN[i];
+        float V;
+        if (n <= MAXA) {
+          float rr[MAXA], gg[MAXA];
+          float rs = 0.f;
+#pragma unroll
+          for (int a = 0; a < MAXA; ++a) {
+            rr[a] = a < n ? RL[(f + a) * STB + lane] : 0.f;
+            gg[a] = a < n ? gL[(f + a) * STB + lane] : 0.f;
+            rs += rr[a];
+          }
+          const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
+          V = 0.f;
+#pragma unroll
+          for (int a = 0; a < MAXA; ++a)
+            if (a < n) V += (rs > 0.f ? rr[a] * inv : uni) * gg[a];
+#pragma unroll
+          for (int a = 0; a < MAXA; ++a)
+            if (a < n) {
+              const float r = rr[a] + gg[a] - V;
+              RL[(f + a) * STB + lane] = r > 0.f ? r : 0.f;
+            }
+        } else {
+          float rs = 0.f;
+          for (int a = 0; a < n; ++a) rs += RL[(f + a) * STB + lane];
+          const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
+          V = 0.f;
+          for (int a = 0; a < n; ++a)
+            V += (rs > 0.f ? RL[(f + a) * STB + lane] * inv : uni) * gL[(f + a) * STB + lane];
+          for (int a = 0; a < n; ++a) {
+            const float r = RL[(f + a) * STB + lane] + gL[(f + a) * STB + lane] - V;
+            RL[(f + a) * STB + lane] = r > 0.f ? r : 0.f;
+          }
+        }
+        if (MODE == 1 && par == T.ext_parent) vroot += V;
+        else if (par >= 0) gL[(par - S0) * STB + lane] += V;
+      }
+      if (MODE == 1 && act) stage[(int64_t)T.stage * P.stage_stride + h] = vroot;
+    }
+    if (MODE == 0 || MODE == 3) {
+      for (int i = 0; i < ninf; ++i) {
+        const int par = iPar[i], f = iF[i], n = iN[i];
+        float xp = 1.f;
+        if (par >= S0 && par < S0 + SL) xp = xL[(par - S0) * STB + lane];
+        else if (par >= 0) xp = act ? x[base + (int64_t)par * stride] : 0.f;
+        if (n <= MAXA) {
+          float rr[MAXA];
+          float rs = 0.f;
+#pragma unroll
+          for (int a = 0; a < MAXA; ++a) {
+            rr[a] = a < n ? RL[(f + a) * STB + lane] : 0.f;
+            rs += rr[a];
+          }
+          const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
+#pragma unroll
+          for (int a = 0; a < MAXA; ++a)
+            if (a < n) xL[(f + a) * STB + lane] = xp * (rs > 0.f ? rr[a] * inv : uni);
+        } else {
+          float rs = 0.f;
+          for (int a = 0; a < n; ++a) rs += RL[(f + a) * STB + lane];
+          const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
+          for (int a = 0; a < n; ++a)
+            xL[(f + a) * STB + lane] = xp * (rs > 0.f ? RL[(f + a) * STB + lane] * inv : uni);
         }
       }
     }
   }
   __syncthreads();
-  if (MODE == 0 || MODE == 1) {
-    float vroot = 0.f;
-    for (int i = ninf - 1; i >= 0; --i) {
-      const int par = iPar[i], f = iF[i], n = iN[i];
-      float rs = 0.f;
-      for (int a = 0; a < n; ++a) rs += RL[(f + a) * STB + lane];
-      const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
-      float V = 0.f;
-      for (int a = 0; a < n; ++a) {
-        const float ba = rs > 0.f ? RL[(f + a) * STB + lane] * inv : uni;
-        V += ba * gL[(f + a) * STB + lane];
-      }
-      for (int a = 0; a < n; ++a) {
-        const float r = RL[(f + a) * STB + lane] + gL[(f + a) * STB + lane] - V;
-        RL[(f + a) * STB + lane] = r > 0.f ? r : 0.f;
-      }
-      if (MODE == 1 && par == T.ext_parent) vroot += V;
-      else if (par >= 0) gL[(par - S0) * STB + lane] += V;
-    }
-    if (MODE == 1 && act) stage[(int64_t)T.stage * P.stage_stride + h] = vroot;
-  }
-  if (MODE == 0 || MODE == 3) {
-    for (int i = 0; i < ninf; ++i) {
-      const int par = iPar[i], f = iF[i], n = iN[i];
-      float xp = 1.f;
-      if (par >= S0 && par < S0 + SL) xp = xL[(par - S0) * STB + lane];
-      else if (par >= 0) xp = act ? x[base + (int64_t)par * stride] : 0.f;
-      float rs = 0.f;
-      for (int a = 0; a < n; ++a) rs += RL[(f + a) * STB + lane];
-      const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
-      for (int a = 0; a < n; ++a) {
-        const float ba = rs > 0.f ? RL[(f + a) * STB + lane] * inv : uni;
-        xL[(f + a) * STB + lane] = xp * ba;
-      }
-    }
-  }
   if (act) {
-    for (int r = 0; r < SL; ++r) {
+    for (int r = wv; r < SL; r += STW) {
       const int64_t idx = base + (int64_t)(S0 + r) * stride;
       if (MODE != 3) R[idx] = RL[r * STB + lane];
       if (MODE != 1) x[idx] = xL[r * STB + lane];
@@ -921,14 +966,14 @@ static int rm_update(Game* g, int p, hipStream_t s) {
   float* gr = g->grad[p].p;
   const double* td = g->tdev.p;
   if (E.n_single_st)
-    hipLaunchKernelGGL(k_rm_st<0>, dim3(E.n_single_st), dim3(STB), E.st_lds[0], s,
+    hipLaunchKernelGGL(k_rm_st<0>, dim3(E.n_single_st), dim3(STB * STW), E.st_lds[0], s,
                        tp_params(g, p, E.b_single_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
                        E.stage.p, td, E.st_ninf[0]);
   if (E.n_single_gl)
     hipLaunchKernelGGL(k_rm<0>, dim3(E.n_single_gl), dim3(TPB), 0, s, tp_params(g, p, E.b_single_gl.p),
                        gr, g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
   if (E.n_deep_st)
-    hipLaunchKernelGGL(k_rm_st<1>, dim3(E.n_deep_st), dim3(STB), E.st_lds[1], s,
+    hipLaunchKernelGGL(k_rm_st<1>, dim3(E.n_deep_st), dim3(STB * STW), E.st_lds[1], s,
                        tp_params(g, p, E.b_deep_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
                        E.stage.p, td, E.st_ninf[1]);
   if (E.n_deep_gl)
@@ -938,7 +983,7 @@ static int rm_update(Game* g, int p, hipStream_t s) {
     hipLaunchKernelGGL(k_rm<2>, dim3(E.n_top), dim3(TPB), 0, s, tp_params(g, p, E.b_top.p), gr,
                        g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
   if (E.n_deep_st)
-    hipLaunchKernelGGL(k_rm_st<3>, dim3(E.n_deep_st), dim3(STB), E.st_lds[1], s,
+    hipLaunchKernelGGL(k_rm_st<3>, dim3(E.n_deep_st), dim3(STB * STW), E.st_lds[1], s,
                        tp_params(g, p, E.b_deep_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
                        E.stage.p, td, E.st_ninf[1]);
   if (E.n_deep_gl)
