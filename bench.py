@@ -66,6 +66,104 @@ def cpu_baseline(desc, budget_s=15.0):
                       f"61 terminals x 1081 x 1081 hand pairs), {dt:.1f} s"}
 
 
+def batched_leg(args, stream):
+    """Configuration of 512 uneven river endgames in one game: matvec-pair
+    throughput and roofline over the batch, batched time to 1e-4 * pot for
+    every instance, and the plain single-instance solver on a sample of the
+    same instances for comparison."""
+    import torch
+    from paper_2112_03804_amd import instances as I
+    from paper_2112_03804_amd import pmx
+
+    descs = I.batched_configs(args.batch)
+    t_create = time.perf_counter()
+    g = pmx.Game(descs)
+    t_create = time.perf_counter() - t_create
+    L = g.layouts
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # solver iterations over the whole batch
+    g.solver_reset()
+    g.solver_step(64)
+    torch.cuda.synchronize()
+    K = args.batch_steps
+    e0.record(stream)
+    g.solver_step(K)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    it_ms = e0.elapsed_time(e1) / K
+    # the matvec pair alone
+    rng = np.random.default_rng(2)
+    y = torch.from_numpy(rng.random(g.elems[1]).astype(np.float32)).cuda()
+    x = torch.from_numpy(rng.random(g.elems[0]).astype(np.float32)).cuda()
+    Ay = torch.empty(g.elems[0], dtype=torch.float32, device="cuda")
+    ATx = torch.empty(g.elems[1], dtype=torch.float32, device="cuda")
+    for _ in range(10):
+        g.matvec_pair(y, x, Ay, ATx)
+    reps = 200
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        g.matvec_pair(y, x, Ay, ATx)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    pair_us = e0.elapsed_time(e1) * 1e3 / reps
+    bytes_pair = algorithmic_bytes_pair(L)
+    achieved = bytes_pair / (pair_us * 1e-6) / 1e9
+    # batched time to gap: every instance at or below 1e-4 of its pot
+    pots = np.array([2 * d.contrib for d in descs])
+    g.solver_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, done_at = 0, np.full(len(descs), -1)
+    while iters < args.max_iters:
+        g.solver_step(32)
+        iters += 32
+        gap = g.saddle_gap()[0]
+        newly = (gap <= 1e-4 * pots) & (done_at < 0)
+        done_at[newly] = iters
+        if (done_at >= 0).all():
+            break
+    ttg_batched = time.perf_counter() - t0
+    g.close()
+    # plain single-instance solver on a sample of the same instances
+    sample = list(range(0, len(descs), max(1, len(descs) // args.plain_sample)))[:args.plain_sample]
+    plain_s, plain_it = [], []
+    for i in sample:
+        gi = pmx.Game(descs[i])
+        pot = 2 * descs[i].contrib
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it = 0
+        while it < args.max_iters:
+            gi.solver_step(32)
+            it += 32
+            if gi.saddle_gap()[0][0] <= 1e-4 * pot:
+                break
+        plain_s.append(time.perf_counter() - t0)
+        plain_it.append(it)
+        gi.close()
+    plain_total_est = float(np.mean(plain_s)) * len(descs)
+    return {
+        "workload": f"{len(descs)} river endgames, hands U[200,1081] per player, 1-3 bet sizes, "
+                    "raise caps 2-4, pots U[20,400], stack/pot U[1,10]",
+        "game_create_s": t_create,
+        "iteration_ms": it_ms,
+        "matvec_pairs_per_s": len(descs) / (it_ms * 1e-3),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "kernel": "k_matvec (matvec_pair launch)",
+                     "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair},
+        "time_to_gap_batched_s": ttg_batched,
+        "iterations_batched": iters,
+        "instances_reached": int((done_at >= 0).sum()),
+        "iterations_per_instance_p50_p90_max": [float(np.percentile(done_at[done_at > 0], q))
+                                                for q in (50, 90, 100)] if (done_at > 0).any() else None,
+        "plain_single_instance_sample": {"instances": len(sample), "mean_s": float(np.mean(plain_s)),
+                                         "mean_iterations": float(np.mean(plain_it)),
+                                         "sum_over_batch_extrapolated_s": plain_total_est},
+        "speedup_batched_vs_plain": plain_total_est / ttg_batched,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +171,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=256)
+    ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--max-iters", type=int, default=100000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -167,9 +270,11 @@ def main():
                         "FP64 gap checked every 25 iterations"},
         "game_create_s": t_create,
     }
+    g.close()
+    if not args.no_batched:
+        out["batched"] = batched_leg(args, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(desc, args.cpu_budget)
-    g.close()
     print(json.dumps(out), flush=True)
 
 

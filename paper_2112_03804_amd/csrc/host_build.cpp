@@ -436,6 +436,10 @@ int default_rows_per_block(int64_t rows) {
   return (int)std::min<int64_t>(8, rows / 4096);
 }
 
+// Few rows: a workgroup per row (every row in flight at once, short scans).
+// Many rows: a wavefront per row chunk, so more rows are in flight per CU.
+int default_mv_kernel(int64_t rows) { return rows > 2048 ? 1 : 0; }
+
 namespace {
 
 struct Contrib {
@@ -606,6 +610,33 @@ void build_matvec_plan(HostGame& hg, int d, int rows_per_block) {
   }
 }
 
+// Group the row chunks of one direction by hand-count class.
+void classify_chunks(MvDir& D) {
+  for (int c = 0; c < MvDir::kClasses; ++c) {
+    D.cls_chunks[c].clear();
+    D.cls_ent[c] = D.cls_n[c] = 0;
+  }
+  const int nch = (int)D.blk.size() - 1;
+  for (int b = 0; b < nch; ++b) {
+    int nmax = 0, emax = 0;
+    for (int it = D.blk[b]; it < D.blk[b + 1]; ++it) {
+      const MvItem& m = D.items[it];
+      if (m.ctx < 0) {
+        nmax = std::max(nmax, m.n_own);
+        continue;
+      }
+      const MvCtx& c = D.ctx[m.ctx];
+      nmax = std::max(nmax, std::max(c.n_own, c.n_opp));
+      emax = std::max(emax, c.n_ent);
+    }
+    int c = 0;
+    while (c < MvDir::kClasses - 1 && nmax > kClassN[c]) ++c;
+    D.cls_chunks[c].push_back(b);
+    D.cls_ent[c] = std::max(D.cls_ent[c], emax);
+    D.cls_n[c] = std::max(D.cls_n[c], nmax);
+  }
+}
+
 namespace {
 
 void build_treeplex_plan(HostGame& hg, int p) {
@@ -747,7 +778,16 @@ int build_game(const GameDesc* descs, int n, HostGame& hg, std::string& msg) {
     for (auto& b : hg.inst) rows += std::max(b.sf.n_seq[0], b.sf.n_seq[1]);
     hg.rows_per_block = default_rows_per_block(rows);
   }
-  for (int d = 0; d < 2; ++d) build_matvec_plan(hg, d, hg.rows_per_block);
+  {
+    int64_t rows = 0;
+    for (auto& b : hg.inst) rows += std::max(b.sf.n_seq[0], b.sf.n_seq[1]);
+    hg.mv_kernel = default_mv_kernel(rows);
+    if (hg.mv_kernel == 1) hg.rows_per_block = rows > 16384 ? 2 : 1;
+  }
+  for (int d = 0; d < 2; ++d) {
+    build_matvec_plan(hg, d, hg.rows_per_block);
+    classify_chunks(hg.dir[d]);
+  }
   for (int p = 0; p < 2; ++p) build_treeplex_plan(hg, p);
   return PMX_OK;
 }

@@ -65,6 +65,7 @@ struct MvParams {
   double scale;
   int32_t nblk;
   int32_t max_ent, max_n, max_seg;
+  int32_t dir;
 };
 
 // LDS index with one spare double every 16: a thread's contiguous chunk of 16
@@ -307,6 +308,177 @@ __global__ __launch_bounds__(BLOCK, 4) void k_matvec(MvParams P0, const IO* __re
         const int h = tid + k * BLOCK;
         if (h < item.stride)
           out[item.out + h] = (IO)(h < n_own ? P.scale * (double)lo[k] * acc[k] : 0.0);
+        acc[k] = 0.0;
+      }
+    }
+  }
+}
+
+// Exclusive segmented scan over the 64 lanes of a wavefront (see
+// block_seg_scan).
+__device__ inline void wave_seg_scan(bool flag, double a, double b, double& ea, double& eb) {
+  const int lane = threadIdx.x & 63;
+  int f = flag ? 1 : 0;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int f2 = shfl_up64(f, off);
+    double a2 = shfl_up64(a, off);
+    double b2 = shfl_up64(b, off);
+    if (lane >= off) {
+      if (!f) {
+        a += a2;
+        b += b2;
+      }
+      f |= f2;
+    }
+  }
+  double xa = shfl_up64(a, 1);
+  double xb = shfl_up64(b, 1);
+  ea = lane == 0 ? 0.0 : xa;
+  eb = lane == 0 ? 0.0 : xb;
+}
+
+// Wavefront-per-chunk form of k_matvec: a workgroup is one wavefront that owns
+// a chunk of output rows, so no row waits on another wavefront's barrier and
+// a CU keeps as many rows in flight as its LDS holds.  KH own/opponent hands
+// and KE scan entries per lane (the chunk's hand-count class bounds them).
+// Context metadata is read from global memory (L2-resident) per row.
+template <int KH, int KE, typename IO>
+__global__ __launch_bounds__(64) void k_matvec_w(MvParams P, const int32_t* __restrict__ chunks,
+                                                 const IO* __restrict__ in, IO* __restrict__ out,
+                                                 double* __restrict__ tick, int me, int mn, int ms) {
+  static_assert(KE % 2 == 0, "entries are packed in pairs");
+  if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1.0;
+  const int lane = threadIdx.x;
+  const int ch = chunks[blockIdx.x];
+  const IO* __restrict__ lam = lam_of<IO>(P);
+  extern __shared__ double smem[];
+  double* Pc = smem;                      // [me]
+  double* segF = Pc + me;                 // [ms]
+  IO* us = (IO*)(segF + ms);              // [mn]
+  IO* uf = us + mn;                       // [mn]
+  int* segEnd = (int*)(uf + mn);          // [ms]
+
+  double acc[KH];
+#pragma unroll
+  for (int k = 0; k < KH; ++k) acc[k] = 0.0;
+  uint32_t srcp[KE / 2];
+  MvCtx C;
+  int cur = -2;
+  const int it0 = P.blk[ch], it1 = P.blk[ch + 1];
+  for (int it = it0; it < it1; ++it) {
+    const MvItem item = P.items[it];
+    if (item.ctx < 0) {
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int h = lane + 64 * k;
+        if (h < item.stride) out[item.out + h] = (IO)0;
+      }
+      continue;
+    }
+    __syncthreads();
+    if (item.ctx != cur) {
+      C = P.ctx[item.ctx];
+#pragma unroll
+      for (int j = 0; j < KE; j += 2) {
+        const int e = lane * KE + j;
+        const int v0 = e < C.n_ent ? (int)P.seg[C.seg_off + e] : 0;
+        const int v1 = e + 1 < C.n_ent ? (int)P.seg[C.seg_off + e + 1] : 0;
+        srcp[j >> 1] = (uint32_t)(uint16_t)(int16_t)v0 | ((uint32_t)(uint16_t)(int16_t)v1 << 16);
+      }
+      for (int i = lane; i < C.n_seg; i += 64) segEnd[i] = P.segend[C.segend_off + i];
+      cur = item.ctx;
+    }
+    // phase 1: weighted opponent inputs scattered to strength order
+    const bool has_s = item.in_s >= 0, has_f = item.in_f >= 0;
+    const IO ks = (IO)item.ks, kf = (IO)item.kf;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int h = lane + 64 * k;
+      if (h < C.n_opp) {
+        const int rk = (int)P.rank[C.rank_off + h];
+        if (rk >= 0) {
+          const IO w = lam[C.lam_opp_off + h];
+          us[pd(rk)] = has_s ? ks * w * in[item.in_s + h] : (IO)0;
+          uf[pd(rk)] = has_f ? kf * w * in[item.in_f + h] : (IO)0;
+        }
+      }
+    }
+    __syncthreads();
+    // phase 2: segmented exclusive scan over the entry list (FP64 sums)
+    double rs = 0.0, rf = 0.0;
+    bool flag = false;
+#pragma unroll
+    for (int j = 0; j < KE; ++j) {
+      const int e = lane * KE + j;
+      if (e < C.n_ent) {
+        const int sidx = (j & 1) ? hi16(srcp[j >> 1]) : lo16(srcp[j >> 1]);
+        if (sidx >= 0) {
+          rs += (double)us[pd(sidx)];
+          rf += (double)uf[pd(sidx)];
+        } else {
+          flag = true;
+          rs = 0.0;
+          rf = 0.0;
+        }
+      }
+    }
+    double cs, cf;
+    wave_seg_scan(flag, rs, rf, cs, cf);
+    rs = cs;
+    rf = cf;
+#pragma unroll
+    for (int j = 0; j < KE; ++j) {
+      const int e = lane * KE + j;
+      if (e < C.n_ent) {
+        const int sidx = (j & 1) ? hi16(srcp[j >> 1]) : lo16(srcp[j >> 1]);
+        Pc[pd(e)] = rs;
+        if (sidx >= 0) {
+          rs += (double)us[pd(sidx)];
+          rf += (double)uf[pd(sidx)];
+        } else {
+          segF[-1 - sidx] = rf;
+          rs = 0.0;
+          rf = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    // phase 3
+    const double tot_s = Pc[pd(C.n_live)];
+    const double tot_f = segF[0];
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int h = lane + 64 * k;
+      if (h < C.n_own) {
+        const uint4 r = P.q[C.q_off + h];
+        const int lt = lo16(r.x);
+        if (lt >= 0) {
+          double sd = Pc[pd(lt)] + Pc[pd(hi16(r.x))] - tot_s;
+          double fo = tot_f;
+          const int c0 = r.w & 255;
+          sd -= Pc[pd(lo16(r.y))] + Pc[pd(hi16(r.y))] - Pc[pd(segEnd[1 + c0])];
+          fo -= segF[1 + c0];
+          if (C.cph == 2) {
+            const int c1 = (r.w >> 8) & 255;
+            sd -= Pc[pd(lo16(r.z))] + Pc[pd(hi16(r.z))] - Pc[pd(segEnd[1 + c1])];
+            fo -= segF[1 + c1];
+            const int self = hi16(r.w);
+            if (self >= 0) fo += (double)uf[pd(self)];
+          }
+          acc[k] += sd + fo;
+        }
+      }
+    }
+    if (item.last) {
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int h = lane + 64 * k;
+        if (h < item.stride) {
+          double v = 0.0;
+          if (h < C.n_own) v = P.scale * (double)lam[C.lam_own_off + h] * acc[k];
+          out[item.out + h] = (IO)v;
+        }
         acc[k] = 0.0;
       }
     }
@@ -678,6 +850,10 @@ struct DBuf {
     if (p) (void)hipFree(p);
   }
   int alloc(size_t count) {
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+    }
     n = count;
     if (count == 0) return PMX_OK;
     hipError_t e = hipMalloc(&p, count * sizeof(T));
@@ -703,6 +879,9 @@ struct DevDir {
   DBuf<int16_t> rank, seg;
   DBuf<int32_t> segend;
   int nblk = 0, max_ent = 0, max_n = 0, max_seg = 0;
+  DBuf<int32_t> cls_chunks[MvDir::kClasses];
+  int cls_count[MvDir::kClasses] = {0, 0, 0};
+  int cls_ent[MvDir::kClasses] = {0, 0, 0}, cls_n[MvDir::kClasses] = {0, 0, 0};
 };
 
 struct DevTp {
@@ -731,6 +910,7 @@ struct Game {
   DBuf<double> lam;
   DBuf<float> lamf;
   int64_t lam_base[2] = {0, 0};
+  std::vector<int64_t> lam_off[2];   // per player: offset of each instance's lambdas
   DBuf<int64_t> inst_hand_off[2];
   // solver state
   DBuf<float> R[2], x[2], grad[2];
@@ -773,25 +953,13 @@ static size_t staged_bytes(const TpTask& t, int ninf_max, int sl) {
 }
 constexpr size_t kStagedLdsMax = 60 * 1024;
 
-static int upload_game(Game* g) {
+static int upload_dir(Game* g, int d) {
+  int rc;
   HostGame& hg = g->hg;
-  // lambda of both players, all instances
-  std::vector<double> lam;
-  std::vector<int64_t> lam_off[2];
-  for (int p = 0; p < 2; ++p) {
-    g->lam_base[p] = (int64_t)lam.size();
-    for (auto& b : hg.inst) {
-      lam_off[p].push_back((int64_t)lam.size());
-      lam.insert(lam.end(), b.lam[p].begin(), b.lam[p].end());
-    }
-  }
-  int rc = g->lam.upload(lam);
-  if (rc) return rc;
-  std::vector<float> lamf(lam.begin(), lam.end());
-  if ((rc = g->lamf.upload(lamf))) return rc;
-  for (int d = 0; d < 2; ++d) {
+  {
     MvDir& D = hg.dir[d];
     const int p = d, q = 1 - d;
+    const std::vector<int64_t>* lam_off = g->lam_off;
     // fill lambda offsets: contexts are emitted instance by instance
     size_t ci = 0;
     for (size_t ii = 0; ii < hg.inst.size(); ++ii) {
@@ -809,7 +977,36 @@ static int upload_game(Game* g) {
     E.max_ent = D.max_ent;
     E.max_n = D.max_n;
     E.max_seg = D.max_seg;
+    for (int c = 0; c < MvDir::kClasses; ++c) {
+      if ((rc = E.cls_chunks[c].upload(D.cls_chunks[c]))) return rc;
+      E.cls_count[c] = (int)D.cls_chunks[c].size();
+      E.cls_ent[c] = D.cls_ent[c];
+      E.cls_n[c] = D.cls_n[c];
+    }
   }
+  return PMX_OK;
+}
+
+static int upload_game(Game* g) {
+  HostGame& hg = g->hg;
+  // lambda of both players, all instances
+  std::vector<double> lam;
+  std::vector<int64_t> lam_off[2];
+  for (int p = 0; p < 2; ++p) {
+    g->lam_base[p] = (int64_t)lam.size();
+    for (auto& b : hg.inst) {
+      lam_off[p].push_back((int64_t)lam.size());
+      lam.insert(lam.end(), b.lam[p].begin(), b.lam[p].end());
+    }
+  }
+  int rc = g->lam.upload(lam);
+  if (rc) return rc;
+  std::vector<float> lamf(lam.begin(), lam.end());
+  if ((rc = g->lamf.upload(lamf))) return rc;
+  g->lam_off[0] = lam_off[0];
+  g->lam_off[1] = lam_off[1];
+  for (int d = 0; d < 2; ++d)
+    if ((rc = upload_dir(g, d))) return rc;
   for (int p = 0; p < 2; ++p) {
     TpPlan& T = hg.tp[p];
     DevTp& E = g->dt[p];
@@ -910,6 +1107,7 @@ static MvParams mv_params(Game* g, int d, double scale) {
   P.lam = g->lam.p;
   P.lamf = g->lamf.p;
   P.scale = scale;
+  P.dir = d;
   P.nblk = E.nblk;
   P.max_ent = E.max_ent;
   P.max_n = E.max_n;
@@ -924,17 +1122,52 @@ static size_t mv_lds(const MvParams& a, const MvParams& b) {
   return sizeof(double) * (me + ms + 3 * (BLOCK / 64)) + 2 * mn * sizeof(IO) + sizeof(int) * ms;
 }
 
+template <int KH, int KE, typename IO>
+static int launch_mv_w_class(Game* g, const MvParams& P, int c, const IO* in, IO* out, hipStream_t s,
+                             double* tick) {
+  DevDir& E = g->dd[P.dir];
+  if (E.cls_count[c] == 0) return PMX_OK;
+  if (E.cls_ent[c] > KE * 64 || E.cls_n[c] > KH * 64)
+    return fail(PMX_EINVAL, "row chunk exceeds its size class");
+  const int me = pd(std::max(E.cls_ent[c], 1)) + 1, mn = pd(std::max(E.cls_n[c], 1)) + 1, ms = E.max_seg;
+  const size_t lds = sizeof(double) * (me + ms) + 2 * sizeof(IO) * mn + sizeof(int) * ms;
+  if (lds > 64 * 1024) return fail(PMX_EINVAL, "wave matvec LDS footprint exceeds 64 KB");
+  hipLaunchKernelGGL((k_matvec_w<KH, KE, IO>), dim3(E.cls_count[c]), dim3(64), lds, s, P,
+                     E.cls_chunks[c].p, in, out, tick, me, mn, ms);
+  HIP_TRY(hipGetLastError());
+  return PMX_OK;
+}
+
+template <typename IO>
+static int launch_mv_w(Game* g, const MvParams& P, const IO* in, IO* out, hipStream_t s,
+                       double* tick) {
+  int rc;
+  // the iteration tick belongs to the first launch only
+  if ((rc = launch_mv_w_class<8, 26, IO>(g, P, 0, in, out, s, tick))) return rc;
+  if (g->dd[P.dir].cls_count[0]) tick = nullptr;
+  if ((rc = launch_mv_w_class<16, 50, IO>(g, P, 1, in, out, s, tick))) return rc;
+  if (g->dd[P.dir].cls_count[1]) tick = nullptr;
+  return launch_mv_w_class<20, 62, IO>(g, P, 2, in, out, s, tick);
+}
+
 template <typename IO>
 static int launch_mv(Game* g, MvParams P0, const IO* in0, IO* out0, MvParams P1, const IO* in1,
                      IO* out1, hipStream_t s, double* tick = nullptr) {
   const int nb = P0.nblk + P1.nblk;
   if (nb == 0) return PMX_OK;
+  if (g->hg.mv_kernel == 1) {
+    int rc;
+    if (P0.nblk && (rc = launch_mv_w<IO>(g, P0, in0, out0, s, tick))) return rc;
+    if (P0.nblk) tick = nullptr;
+    if (P1.nblk && (rc = launch_mv_w<IO>(g, P1, in1, out1, s, tick))) return rc;
+    return PMX_OK;
+  }
   // shape checks: every hand and entry must have a thread slot
   const int mn = std::max(P0.max_n, P1.max_n), me = std::max(P0.max_ent, P1.max_ent);
   constexpr int B = 512, KH = 3, KE = 8;
   if (mn > KH * B || me > KE * B) return fail(PMX_EINVAL, "instance too large for the matvec kernel");
   size_t lds = mv_lds<B, IO>(P0, P1);
-  if (lds > 160 * 1024) return fail(PMX_EINVAL, "matvec LDS footprint exceeds 160 KB");
+  if (lds > 64 * 1024) return fail(PMX_EINVAL, "matvec LDS footprint exceeds 64 KB");
   hipLaunchKernelGGL((k_matvec<B, KH, KE, IO>), dim3(nb), dim3(B), lds, s, P0, in0, out0, P1, in1,
                      out1, tick);
   HIP_TRY(hipGetLastError());
@@ -1167,6 +1400,37 @@ int game_hand_meta(const Game* g, int32_t instance, int32_t ctx, int32_t player,
   H.self_ = &m.q.data()->self;
   H.beta = b.beta;
   *out = H;
+  return PMX_OK;
+}
+
+int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (kernel < 0 || kernel > 1) return fail(PMX_EINVAL, "kernel must be 0 or 1");
+  if (rows_per_chunk < 1 || rows_per_chunk > 64) return fail(PMX_EINVAL, "rows_per_chunk must be in [1, 64]");
+  HIP_TRY(hipDeviceSynchronize());
+  if (g->graph_exec) {
+    (void)hipGraphExecDestroy(g->graph_exec);
+    g->graph_exec = nullptr;
+  }
+  if (g->graph) {
+    (void)hipGraphDestroy(g->graph);
+    g->graph = nullptr;
+  }
+  g->hg.mv_kernel = kernel;
+  g->hg.rows_per_block = rows_per_chunk;
+  for (int d = 0; d < 2; ++d) {
+    build_matvec_plan(g->hg, d, rows_per_chunk);
+    classify_chunks(g->hg.dir[d]);
+    if ((rc = upload_dir(g, d))) return rc;
+  }
+  return PMX_OK;
+}
+
+int game_get_tuning(const Game* g, int32_t* kernel, int32_t* rows_per_chunk) {
+  if (!g || !kernel || !rows_per_chunk) return fail(PMX_EINVAL, "null argument");
+  *kernel = g->hg.mv_kernel;
+  *rows_per_chunk = g->hg.rows_per_block;
   return PMX_OK;
 }
 

@@ -139,7 +139,12 @@ struct MvDir {                          // host copy of one direction's plan
   std::vector<int16_t> rank, seg;
   std::vector<int32_t> segend;
   int max_ent = 0, max_seg = 0, max_n = 0;
+  // wave kernel: chunks grouped by hand-count class (LDS sized per class)
+  static constexpr int kClasses = 3;
+  std::vector<int32_t> cls_chunks[kClasses];
+  int cls_ent[kClasses] = {0, 0, 0}, cls_n[kClasses] = {0, 0, 0};
 };
+constexpr int kClassN[MvDir::kClasses] = {512, 1024, 1280};   // hands per player, upper bounds
 
 struct TpTask {                         // treeplex task: one subtree of one instance
   int64_t vec_base;
@@ -170,6 +175,7 @@ struct HostGame {
   std::vector<Built> inst;
   int64_t elems[2] = {0, 0};
   int rows_per_block = 1;
+  int mv_kernel = 0;                    // 0: workgroup per row chunk, 1: wavefront per row chunk
   MvDir dir[2];
   TpPlan tp[2];
   int max_stride = 0;
@@ -181,6 +187,8 @@ void build_seqform(const Instance& in, SeqForm& sf);
 void build_hand_meta(Built& b);
 int build_game(const GameDesc* descs, int n, HostGame& hg, std::string& msg);
 int default_rows_per_block(int64_t rows);
+int default_mv_kernel(int64_t rows);
+void classify_chunks(MvDir& D);
 void build_matvec_plan(HostGame& hg, int d, int rows_per_block);
 
 }  // namespace pmx

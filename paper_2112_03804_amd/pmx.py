@@ -75,7 +75,7 @@ EXPORTS = [
     "matvec_A", "matvec_AT", "matvec_A_f64", "matvec_AT_f64", "matvec_pair",
     "solver_reset", "solver_step", "saddle_gap", "saddle_gap_of",
     "solver_get_state", "solver_set_state", "get_average_strategy",
-    "set_initial_strategy", "pmx_last_error",
+    "set_initial_strategy", "pmx_last_error", "game_tune", "game_get_tuning",
 ]
 
 
@@ -110,6 +110,8 @@ def lib():
                                    ctypes.c_double]
     L.get_average_strategy.argtypes = [vp, ctypes.c_int32, _c_f64p]
     L.set_initial_strategy.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_float, vp]
+    L.game_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.game_get_tuning.argtypes = [vp, _c_i32p, _c_i32p]
     L.pmx_last_error.argtypes = []
     L.pmx_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -244,6 +246,14 @@ class Game:
         rec = np.ctypeslib.as_array(ctypes.cast(H.lt, _c_i32p), shape=(n * 8,)).reshape(n, 8).copy()
         return dict(n_live=H.n_live, rank=rank, lt=rec[:, 0], le=rec[:, 1], self_=rec[:, 7],
                     beta=H.beta)
+
+    def game_tune(self, kernel: int, rows_per_chunk: int):
+        _check(lib().game_tune(self._h, int(kernel), int(rows_per_chunk)))
+
+    def game_get_tuning(self):
+        k, r = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().game_get_tuning(self._h, ctypes.byref(k), ctypes.byref(r)))
+        return k.value, r.value
 
     # -- vector packing (host numpy <-> flat padded layout) ------------------
     def pack(self, player: int, per_instance: List[np.ndarray], dtype=np.float32) -> np.ndarray:
