@@ -75,11 +75,14 @@ def batched_leg(args, stream):
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
 
+    from paper_2112_03804_amd import autotune
     descs = I.batched_configs(args.batch)
     t_create = time.perf_counter()
     g = pmx.Game(descs)
     t_create = time.perf_counter() - t_create
     L = g.layouts
+    default_sched = g.game_get_tuning()
+    sched, sched_us = autotune.tune(g, use_cache=False)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     # solver iterations over the whole batch
     g.solver_reset()
@@ -147,6 +150,8 @@ def batched_leg(args, stream):
         "workload": f"{len(descs)} river endgames, hands U[200,1081] per player, 1-3 bet sizes, "
                     "raise caps 2-4, pots U[20,400], stack/pot U[1,10]",
         "game_create_s": t_create,
+        "schedule": {"default": list(default_sched), "tuned": list(sched),
+                     "us_per_pair_by_schedule": sched_us},
         "iteration_ms": it_ms,
         "matvec_pairs_per_s": len(descs) / (it_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -271,6 +271,61 @@ int get_average_strategy(Game* g, int32_t player, double* x_host);
 int set_initial_strategy(Game* g, int32_t player, const float* behav_dev, float scale,
                          void* stream);
 
+/* ---- learned warm start (not in the paper; a prior for the solver) -------- */
+/* The network sees one row per (infoset I, hand h) of a player, rows ordered
+ * instance by instance, infosets in layout order, hands in list order.  Row
+ * features (64, BF16): 59 betting features of I (pot, stacks and amount to
+ * call relative to the pot, raises, depth, round, and per action slot its
+ * kind and added chips; 8 slots) followed by 5 range features of h (belief
+ * weight relative to the mean, strength quantile, share of the opponent's
+ * range it blocks, compatible opponent mass it beats / loses to).  Infosets
+ * with more than 8 actions make the warm start unavailable (PMX_EINVAL). */
+int warm_num_rows(const Game* g, int32_t player, int64_t* rows);
+/* x_dev: device BF16 [rows][64]. Asynchronous. */
+int warm_features(Game* g, int32_t player, uint16_t* x_dev, void* stream);
+/* Training targets from the solver's average strategy: target_dev [rows][8]
+ * holds xbar[Ia] / xbar[parent(I)] for valid slots (uniform if unreached) and
+ * -1 for invalid slots; weight_dev [rows] = relative belief weight x average
+ * reach of I.  Needs at least one solver iteration.  Asynchronous. */
+int warm_targets(Game* g, int32_t player, float* target_dev, float* weight_dev, void* stream);
+/* Reset the solver to the prior given by network logits (device FP32
+ * [rows][ldz] per player): masked softmax per row -> behavioural prior b0;
+ * regrets = regret_scale * lambda(h) * pot * b0 (the units of that hand's
+ * gradients), current plans = realization of b0, averages
+ * seeded as avg_weight iterations of b0.  Asynchronous. */
+int warm_apply(Game* g, const float* logits0_dev, const float* logits1_dev, int32_t ldz,
+               float regret_scale, double avg_weight, void* stream);
+
+/* ---- network kernels (device buffers, asynchronous) ----------------------- */
+/* C[M x N] = op(A) op(B) on the BF16 matrix cores with FP32 accumulation;
+ * op(A)(m,k) = transA ? A[k*lda + m] : A[m*lda + k], op(B)(k,n) = transB ?
+ * B[n*ldb + k] : B[k*ldb + n].  Epilogue: + bias[n] (if bias), ReLU (if relu),
+ * zero where mask[m*ldm + n] <= 0 (if mask); stored as FP32 C and / or BF16 Cb
+ * (either may be NULL, not both). */
+int mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t lda, int32_t transA,
+                  const uint16_t* B, int32_t ldb, int32_t transB, const float* bias, int32_t relu,
+                  const float* mask, int32_t ldm, float* C, int32_t ldc, uint16_t* Cb, int32_t ldcb,
+                  void* stream);
+/* Masked softmax cross-entropy over K <= 64 slots (target < 0 = invalid):
+ * dlogits[r][a] = weight[r] (softmax - target) (FP32 and / or BF16, stride K);
+ * loss_partial[b] = sum of weight[r] * cross-entropy over block b's 256 rows. */
+int mlp_softmax_xent(int32_t rows, int32_t K, const float* logits, int32_t ldl, const float* target,
+                     const float* weight, float* dlogits, uint16_t* dlogits_bf16, float* loss_partial,
+                     void* stream);
+/* db[n] = sum_m dz[m][n] (bias gradient). */
+int mlp_colsum(int32_t rows, int32_t cols, const float* dz, float* db, void* stream);
+/* Adam with bias correction and decoupled-free L2 weight decay; writes the
+ * BF16 copy of the weights when w_bf16 is not NULL. */
+int mlp_adam(int64_t n, float* w, const float* g, float* m, float* v, uint16_t* w_bf16, float lr,
+             float beta1, float beta2, float eps, float weight_decay, int32_t step, void* stream);
+/* dst[i][:] = src[idx[i]][:] for rows of `width` elements. */
+int mlp_gather_bf16(int64_t n, int32_t width, const int64_t* idx, const uint16_t* src, uint16_t* dst,
+                    void* stream);
+int mlp_gather_f32(int64_t n, int32_t width, const int64_t* idx, const float* src, float* dst,
+                   void* stream);
+/* dst = BF16(src), round to nearest even. */
+int mlp_cast_bf16(int64_t n, const float* src, uint16_t* dst, void* stream);
+
 /* Thread-local description of the last error ("" if none). */
 const char* pmx_last_error(void);
 

@@ -1,0 +1,91 @@
+"""Schedule autotuner for the structured matvec.
+
+For a game it times every candidate schedule (``game_tune(kernel, rows)``:
+kernel 0 = workgroup per row chunk, 1 = wavefront per row chunk launched per
+hand-count class; rows = output rows per chunk) on the matvec-pair launch with
+HIP events, keeps the fastest, and remembers the choice in a JSON cache keyed
+by GPU architecture and a size class of the game (instances, rows, largest
+hand count), so later games of the same class are tuned without timing.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Iterable, Optional, Tuple
+
+import numpy as np
+
+DEFAULT_CANDIDATES = [(0, 1), (0, 2), (0, 4), (0, 8), (1, 1), (1, 2), (1, 4)]
+CACHE_ENV = "PMX_TUNE_CACHE"
+
+
+def _bucket(v: int, edges: Iterable[int]) -> int:
+    for i, e in enumerate(edges):
+        if v <= e:
+            return i
+    return len(list(edges))
+
+
+def signature(game) -> str:
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "cpu"
+    rows = sum(max(L[0]["n_seq"], L[1]["n_seq"]) for L in game.layouts)
+    nmax = max(max(L[0]["n_hands"], L[1]["n_hands"]) for L in game.layouts)
+    return "|".join([arch, f"inst{_bucket(game.n_instances, (1, 16, 128, 1024))}",
+                     f"rows{_bucket(rows, (256, 2048, 16384, 65536))}",
+                     f"hands{_bucket(nmax, (512, 1024, 1280))}"])
+
+
+def _load(path: str) -> Dict[str, list]:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def time_schedule(game, kernel: int, rows: int, reps: int = 20) -> float:
+    """Average microseconds of one matvec-pair launch under a schedule."""
+    import torch
+    game.game_tune(kernel, rows)
+    rng = np.random.default_rng(0)
+    y = torch.from_numpy(rng.random(game.elems[1]).astype(np.float32)).cuda()
+    x = torch.from_numpy(rng.random(game.elems[0]).astype(np.float32)).cuda()
+    Ay = torch.empty(game.elems[0], dtype=torch.float32, device="cuda")
+    ATx = torch.empty(game.elems[1], dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        game.matvec_pair(y, x, Ay, ATx)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        game.matvec_pair(y, x, Ay, ATx)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
+def tune(game, candidates=None, reps: int = 20, cache_path: Optional[str] = None,
+         use_cache: bool = True) -> Tuple[Tuple[int, int], Dict[str, float]]:
+    """Pick and apply the fastest schedule.  Returns ((kernel, rows), timings)."""
+    cache_path = cache_path or os.environ.get(CACHE_ENV)
+    key = signature(game)
+    cache = _load(cache_path) if cache_path else {}
+    if use_cache and key in cache:
+        k, r = cache[key]
+        game.game_tune(int(k), int(r))
+        return (int(k), int(r)), {}
+    timings = {}
+    for k, r in (candidates or DEFAULT_CANDIDATES):
+        timings[f"{k}:{r}"] = time_schedule(game, k, r, reps)
+    best = min(timings, key=timings.get)
+    k, r = (int(v) for v in best.split(":"))
+    game.game_tune(k, r)
+    if cache_path:
+        cache[key] = [k, r]
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
+    return (k, r), timings

@@ -142,6 +142,7 @@ struct TNode {
   int kind;
   double c[2], s[2];
   int term = -1, runout = 0;
+  int raises = 0, facing = 0;
   std::vector<int> kids;
 };
 
@@ -221,6 +222,8 @@ struct TreeBuilder {
     TNode n;
     n.kind = p;
     n.c[0] = c[0]; n.c[1] = c[1]; n.s[0] = s[0]; n.s[1] = s[1];
+    n.raises = raises;
+    n.facing = facing ? 1 : 0;
     n.kids = std::move(kids);
     return add(std::move(n));
   }
@@ -251,7 +254,42 @@ struct SfBuilder {
   const Instance& in;
   const std::vector<TNode>& nodes;
   SeqForm& sf;
-  void visit(int id, int l0, int l1, int board) {
+  // Betting features of a decision node (inputs of the warm-start network):
+  // pot and stacks relative to the pot, the amount to call, raise count,
+  // depth, round, and per action slot its kind and the chips it adds.
+  void infoset_features(const TNode& n, int p, int depth, int board) {
+    const int o = 1 - p;
+    const double pot = n.c[0] + n.c[1];
+    float f[kInfFeat] = {0};
+    f[0] = (float)p;
+    f[1] = (float)(pot / (2.0 * in.contrib));
+    f[2] = (float)(n.c[p] / pot);
+    f[3] = (float)((n.c[o] - n.c[p]) / pot);
+    f[4] = (float)(std::min(n.s[p] / pot, 20.0) / 20.0);
+    f[5] = (float)(std::min(n.s[o] / pot, 20.0) / 20.0);
+    f[6] = (float)n.facing;
+    f[7] = (float)n.raises / 4.f;
+    f[8] = (float)n.kids.size() / (float)kWarmActions;
+    f[9] = (float)depth / 8.f;
+    f[10] = board >= 0 ? 1.f : 0.f;
+    for (int a = 0; a < (int)n.kids.size() && a < kWarmActions; ++a) {
+      const TNode& k = nodes[n.kids[a]];
+      float* q = f + 11 + 6 * a;
+      q[0] = 1.f;
+      if (a == 0 && n.facing) {
+        q[1] = 1.f;                                   // fold
+      } else if (a == 0 || (a == 1 && n.facing)) {
+        q[2] = 1.f;                                   // check / call
+      } else {
+        q[3] = 1.f;                                   // bet / raise
+        if (k.s[p] <= kEps) q[4] = 1.f;               // all-in
+      }
+      q[5] = (float)((k.c[p] - n.c[p]) / pot);
+    }
+    sf.inf_feat[p].insert(sf.inf_feat[p].end(), f, f + kInfFeat);
+  }
+
+  void visit(int id, int l0, int l1, int board, int depth = 0) {
     const TNode& n = nodes[id];
     if (n.kind == K_LEAF) {
       Terminal t;
@@ -269,7 +307,7 @@ struct SfBuilder {
         rt.board = r;
         rt.parent_seq[0] = l0; rt.parent_seq[1] = l1;
         rt.inf_begin[0] = (int)sf.inf[0].size(); rt.inf_begin[1] = (int)sf.inf[1].size();
-        visit(n.kids[0], l0, l1, r);
+        visit(n.kids[0], l0, l1, r, depth + 1);
         rt.inf_end[0] = (int)sf.inf[0].size(); rt.inf_end[1] = (int)sf.inf[1].size();
         sf.rivers.push_back(rt);
       }
@@ -279,9 +317,10 @@ struct SfBuilder {
     const int first = sf.n_seq[p];
     const int na = (int)n.kids.size();
     sf.inf[p].push_back(Infoset{p == 0 ? l0 : l1, first, na, board});
+    infoset_features(n, p, depth, board);
     sf.n_seq[p] += na;
     for (int a = 0; a < na; ++a)
-      visit(n.kids[a], p == 0 ? first + a : l0, p == 1 ? first + a : l1, board);
+      visit(n.kids[a], p == 0 ? first + a : l0, p == 1 ? first + a : l1, board, depth + 1);
   }
 };
 
@@ -420,6 +459,57 @@ void build_hand_meta(Built& b) {
         int tw = p == 0 ? twin0[h] : twin1[h];
         r.self = tw >= 0 ? o.rank[tw] : -1;
         m.q[h] = r;
+      }
+    }
+  }
+  // Range features of each hand on the first board context (warm-start
+  // inputs): belief weight relative to the mean, strength quantile, share of
+  // the opponent's range it blocks, and the compatible opponent mass it beats
+  // and loses to (prefix sums over the sorted opponent list with per-card
+  // inclusion-exclusion, the hand operators of eq. cf and Technique B).
+  for (int p = 0; p < 2; ++p) {
+    const int q = 1 - p;
+    const CtxMeta& own = b.ctx[p][0];
+    const CtxMeta& opp = b.ctx[q][0];
+    std::vector<double> pre(opp.seg_src.size() + 1, 0.0);   // exclusive prefix of mu_q per entry
+    {
+      std::vector<int> order(opp.n_live);
+      for (int h = 0; h < in.n[q]; ++h)
+        if (opp.rank[h] >= 0) order[opp.rank[h]] = h;
+      double run = 0.0;
+      for (size_t e = 0; e < opp.seg_src.size(); ++e) {
+        pre[e] = run;
+        int sidx = opp.seg_src[e];
+        if (sidx >= 0) run += in.mu[q][order[sidx]];
+        else run = 0.0;
+      }
+    }
+    const double T = pre[opp.seg_end[0]];
+    double meanp = 0;
+    for (int h = 0; h < in.n[p]; ++h) meanp += in.mu[p][h];
+    meanp = meanp > 0 ? meanp / in.n[p] : 1.0;
+    b.hand_feat[p].assign((size_t)in.n[p] * kHandFeat, 0.f);
+    for (int h = 0; h < in.n[p]; ++h) {
+      float* f = &b.hand_feat[p][(size_t)h * kHandFeat];
+      f[0] = (float)(std::min(in.mu[p][h] / meanp, 8.0) / 8.0);
+      const QueryRec& r = own.q[h];
+      if (r.lt < 0 || !(T > 0)) continue;
+      f[1] = own.n_live > 1 ? (float)own.rank[h] / (float)(own.n_live - 1) : 0.5f;
+      double blocked = 0, weaker = pre[r.lt], stronger = T - pre[r.le];
+      for (int k = 0; k < in.cph; ++k) {
+        const int c = in.cards[p][(size_t)h * in.cph + k];
+        const double tc = pre[opp.seg_end[1 + c]];
+        blocked += tc;
+        weaker -= pre[k == 0 ? r.lt0 : r.lt1];
+        stronger -= tc - pre[k == 0 ? r.le0 : r.le1];
+      }
+      const int tw = p == 0 ? twin0[h] : twin1[h];
+      if (in.cph == 2 && tw >= 0) blocked -= in.mu[q][tw];
+      const double compat = T - blocked;
+      f[2] = (float)(blocked / T);
+      if (compat > 0) {
+        f[3] = (float)(weaker / compat);
+        f[4] = (float)(stronger / compat);
       }
     }
   }

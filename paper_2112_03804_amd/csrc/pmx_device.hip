@@ -42,6 +42,8 @@ static int fail(int code, const std::string& m) {
   return code;
 }
 
+void pmx_set_error(const char* m) { g_err = m; }
+
 #define HIP_TRY(expr)                                                                 \
   do {                                                                                \
     hipError_t e_ = (expr);                                                           \
@@ -840,6 +842,100 @@ __global__ void k_nonfinite(const double* p, int n, int* flag) {
 }
 
 // ---------------------------------------------------------------------------
+// warm start: rows = (infoset, hand) pairs of one player, instance by instance
+// ---------------------------------------------------------------------------
+struct WarmSeg {
+  int64_t row_base;        // first row of this infoset
+  int64_t vec_base;        // instance's vector block
+  int32_t stride, n_hands, hand_base, first;
+  int32_t nact, parent, pad0, pad1;
+};
+
+__device__ inline uint16_t dev_f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// X[row] = betting features of the infoset ++ range features of the hand (BF16)
+__global__ __launch_bounds__(256) void k_warm_features(const WarmSeg* __restrict__ segs,
+                                                       const int2* __restrict__ blocks,
+                                                       const float* __restrict__ inf_feat,
+                                                       const float* __restrict__ hand_feat,
+                                                       uint16_t* __restrict__ X) {
+  const int2 bt = blocks[blockIdx.x];
+  const WarmSeg S = segs[bt.x];
+  const int h = bt.y + threadIdx.x;
+  if (h >= S.n_hands) return;
+  uint16_t* xr = X + (S.row_base + h) * kWarmIn;
+  const float* fi = inf_feat + (int64_t)bt.x * kInfFeat;
+  const float* fh = hand_feat + (int64_t)(S.hand_base + h) * kHandFeat;
+  for (int j = 0; j < kInfFeat; ++j) xr[j] = dev_f2bf(fi[j]);
+  for (int j = 0; j < kHandFeat; ++j) xr[kInfFeat + j] = dev_f2bf(fh[j]);
+}
+
+// Targets from the solver's average: b*(a|I,h) = xbar[Ia] / xbar[parent]
+// (uniform where the parent is unreached); invalid action slots get -1.
+// Weight = belief weight relative to the mean x average reach of the infoset.
+__global__ __launch_bounds__(256) void k_warm_targets(const WarmSeg* __restrict__ segs,
+                                                      const int2* __restrict__ blocks,
+                                                      const double* __restrict__ xs, double wsum,
+                                                      const float* __restrict__ hand_feat,
+                                                      float* __restrict__ T, float* __restrict__ W) {
+  const int2 bt = blocks[blockIdx.x];
+  const WarmSeg S = segs[bt.x];
+  const int h = bt.y + threadIdx.x;
+  if (h >= S.n_hands) return;
+  const int64_t base = S.vec_base + h, row = S.row_base + h;
+  double tot = 0.0;
+  for (int a = 0; a < S.nact; ++a) tot += xs[base + (int64_t)(S.first + a) * S.stride];
+  float* tr = T + row * kWarmActions;
+  for (int a = 0; a < kWarmActions; ++a) {
+    float v = -1.f;
+    if (a < S.nact)
+      v = tot > 0.0 ? (float)(xs[base + (int64_t)(S.first + a) * S.stride] / tot) : 1.f / (float)S.nact;
+    tr[a] = v;
+  }
+  const double reach = wsum > 0.0 ? tot / wsum : 0.0;
+  W[row] = (float)(8.0 * hand_feat[(int64_t)(S.hand_base + h) * kHandFeat] * reach);
+}
+
+// Prior from network logits: masked softmax per row, regrets = scale * prior,
+// plan = its realization (top-down), averages seeded with weight avg_w.
+__global__ __launch_bounds__(TPB) void k_warm_apply(TpParams P, const int64_t* __restrict__ row_base,
+                                                    const float* __restrict__ Z, int ldz, float scale,
+                                                    double avg_w, const double* __restrict__ lam,
+                                                    const int64_t* __restrict__ lam_off,
+                                                    const double* __restrict__ pot, float* __restrict__ R,
+                                                    float* __restrict__ x, double* __restrict__ xs) {
+  const int2 bt = P.blocks[blockIdx.x];
+  const TpTask T = P.tasks[bt.x];
+  const int h = bt.y + threadIdx.x;
+  if (h >= T.n_hands) return;
+  const int64_t base = T.vec_base + h, stride = T.stride;
+  // regrets in the units of this hand's gradients: lambda(h) x pot
+  const float rs = scale * (float)(lam[lam_off[T.inst] + h] * pot[T.inst]);
+  for (int i = T.inf_begin; i < T.inf_end; ++i) {
+    const int I = P.order[i];
+    const int par = P.inf_parent[I], f = P.inf_first[I], n = P.inf_nact[I];
+    const float* zr = Z + (row_base[I] + h) * ldz;
+    float mx = -INFINITY;
+    for (int a = 0; a < n; ++a) mx = fmaxf(mx, zr[a]);
+    float se = 0.f;
+    for (int a = 0; a < n; ++a) se += __expf(zr[a] - mx);
+    const float xp = par >= 0 ? x[base + (int64_t)par * stride] : 1.f;
+    for (int a = 0; a < n; ++a) {
+      const int64_t j = base + (int64_t)(f + a) * stride;
+      float pa = __expf(zr[a] - mx) / se;
+      if (!(pa >= 0.f)) pa = 1.f / (float)n;   // NaN guard: uniform
+      R[j] = rs * pa;
+      x[j] = xp * pa;
+      xs[j] = avg_w * (double)(xp * pa);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // the Game object
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -919,6 +1015,16 @@ struct Game {
   double wsum = 0.0;
   int mv_block = 256;
   DBuf<double> tdev;                // iteration index of the next step (device)
+  // warm start: per player infoset segments, their blocks, features
+  DBuf<WarmSeg> wseg[2];
+  DBuf<int2> wblk[2];
+  DBuf<int64_t> wrow_base[2];
+  DBuf<float> winf[2], whand[2];
+  DBuf<int64_t> lam_inst[2];
+  DBuf<double> pot_inst;
+  int64_t wrows[2] = {0, 0};
+  int wn_blk[2] = {0, 0};
+  bool warm_ok = true;
   // solver iterations captured as a graph
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -1088,6 +1194,45 @@ static int upload_game(Game* g) {
   }
   if ((rc = g->br_inst.alloc(2 * hg.inst.size()))) return rc;
   if ((rc = g->tdev.alloc(1))) return rc;
+  for (int p = 0; p < 2; ++p) {
+    std::vector<WarmSeg> segs;
+    std::vector<int2> blks;
+    std::vector<int64_t> rb;
+    std::vector<float> fi, fh;
+    int64_t row = 0;
+    int32_t hand_base = 0;
+    for (auto& b : hg.inst) {
+      for (size_t k = 0; k < b.sf.inf[p].size(); ++k) {
+        const Infoset& I = b.sf.inf[p][k];
+        if (I.nact > kWarmActions) g->warm_ok = false;
+        WarmSeg S{};
+        S.row_base = row;
+        S.vec_base = b.vec_off[p];
+        S.stride = b.stride[p];
+        S.n_hands = b.inst.n[p];
+        S.hand_base = hand_base;
+        S.first = I.first;
+        S.nact = I.nact;
+        S.parent = I.parent;
+        for (int h0 = 0; h0 < S.n_hands; h0 += 256) blks.push_back(make_int2((int)segs.size(), h0));
+        segs.push_back(S);
+        rb.push_back(row);
+        row += b.inst.n[p];
+      }
+      fi.insert(fi.end(), b.sf.inf_feat[p].begin(), b.sf.inf_feat[p].end());
+      fh.insert(fh.end(), b.hand_feat[p].begin(), b.hand_feat[p].end());
+      hand_base += b.inst.n[p];
+    }
+    if ((rc = g->wseg[p].upload(segs)) || (rc = g->wblk[p].upload(blks)) || (rc = g->wrow_base[p].upload(rb)) ||
+        (rc = g->winf[p].upload(fi)) || (rc = g->whand[p].upload(fh)))
+      return rc;
+    g->wrows[p] = row;
+    g->wn_blk[p] = (int)blks.size();
+    if ((rc = g->lam_inst[p].upload(g->lam_off[p]))) return rc;
+  }
+  std::vector<double> pots;
+  for (auto& b : hg.inst) pots.push_back(2.0 * b.inst.contrib);
+  if ((rc = g->pot_inst.upload(pots))) return rc;
   return PMX_OK;
 }
 
@@ -1673,6 +1818,71 @@ int set_initial_strategy(Game* g, int32_t player, const float* behav, float scal
     hipLaunchKernelGGL(k_warm, dim3(E.n_deep), dim3(TPB), 0, s, tp_params(g, player, E.b_deep.p),
                        behav, scale, g->R[player].p, g->x[player].p);
   HIP_TRY(hipGetLastError());
+  return PMX_OK;
+}
+
+int warm_num_rows(const Game* g, int32_t player, int64_t* rows) {
+  if (!g || !rows || player < 0 || player > 1) return fail(PMX_EINVAL, "bad argument");
+  if (!g->device) return fail(PMX_ESTATE, "game was created host-only");
+  *rows = g->wrows[player];
+  return PMX_OK;
+}
+
+int warm_features(Game* g, int32_t player, uint16_t* x_dev, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (player < 0 || player > 1 || !x_dev) return fail(PMX_EINVAL, "bad argument");
+  if (g->wn_blk[player])
+    hipLaunchKernelGGL(k_warm_features, dim3(g->wn_blk[player]), dim3(256), 0, (hipStream_t)stream,
+                       g->wseg[player].p, g->wblk[player].p, g->winf[player].p, g->whand[player].p, x_dev);
+  HIP_TRY(hipGetLastError());
+  return PMX_OK;
+}
+
+int warm_targets(Game* g, int32_t player, float* target_dev, float* weight_dev, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (player < 0 || player > 1 || !target_dev || !weight_dev) return fail(PMX_EINVAL, "bad argument");
+  if (!g->warm_ok) return fail(PMX_EINVAL, "an infoset has more actions than the network's slots");
+  if (!(g->wsum > 0)) return fail(PMX_ESTATE, "no solver iterations to take targets from");
+  if (g->wn_blk[player])
+    hipLaunchKernelGGL(k_warm_targets, dim3(g->wn_blk[player]), dim3(256), 0, (hipStream_t)stream,
+                       g->wseg[player].p, g->wblk[player].p, g->xs[player].p, g->wsum, g->whand[player].p,
+                       target_dev, weight_dev);
+  HIP_TRY(hipGetLastError());
+  return PMX_OK;
+}
+
+int warm_apply(Game* g, const float* logits0_dev, const float* logits1_dev, int32_t ldz, float regret_scale,
+               double avg_weight, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!logits0_dev || !logits1_dev || ldz < kWarmActions) return fail(PMX_EINVAL, "bad argument");
+  if (!g->warm_ok) return fail(PMX_EINVAL, "an infoset has more actions than the network's slots");
+  if (!(regret_scale >= 0) || !std::isfinite(regret_scale) || !(avg_weight >= 0) || !std::isfinite(avg_weight))
+    return fail(PMX_EINVAL, "scale and weight must be finite and >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = solver_reset(g, s))) return rc;
+  for (int p = 0; p < 2; ++p) {
+    DevTp& E = g->dt[p];
+    const float* Z = p == 0 ? logits0_dev : logits1_dev;
+    // parents before children: single, then top, then deep tasks
+    if (E.n_single)
+      hipLaunchKernelGGL(k_warm_apply, dim3(E.n_single), dim3(TPB), 0, s, tp_params(g, p, E.b_single.p),
+                         g->wrow_base[p].p, Z, ldz, regret_scale, avg_weight, g->lam.p, g->lam_inst[p].p,
+                         g->pot_inst.p, g->R[p].p, g->x[p].p, g->xs[p].p);
+    if (E.n_top)
+      hipLaunchKernelGGL(k_warm_apply, dim3(E.n_top), dim3(TPB), 0, s, tp_params(g, p, E.b_top.p),
+                         g->wrow_base[p].p, Z, ldz, regret_scale, avg_weight, g->lam.p, g->lam_inst[p].p,
+                         g->pot_inst.p, g->R[p].p, g->x[p].p, g->xs[p].p);
+    if (E.n_deep)
+      hipLaunchKernelGGL(k_warm_apply, dim3(E.n_deep), dim3(TPB), 0, s, tp_params(g, p, E.b_deep.p),
+                         g->wrow_base[p].p, Z, ldz, regret_scale, avg_weight, g->lam.p, g->lam_inst[p].p,
+                         g->pot_inst.p, g->R[p].p, g->x[p].p, g->xs[p].p);
+  }
+  HIP_TRY(hipGetLastError());
+  g->t = 0;
+  g->wsum = avg_weight;
   return PMX_OK;
 }
 

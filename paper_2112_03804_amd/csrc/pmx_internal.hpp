@@ -57,11 +57,17 @@ struct RiverTask {      // one (chance node, river card) subtree
   int parent_seq[2];    // each player's last first-round sequence
   int inf_begin[2], inf_end[2];
 };
+constexpr int kWarmActions = 8;        // action slots of the warm-start network
+constexpr int kInfFeat = 11 + 6 * kWarmActions;   // betting features per infoset (59)
+constexpr int kHandFeat = 5;           // range features per hand
+constexpr int kWarmIn = 64;            // network input width (kInfFeat + kHandFeat)
+
 struct SeqForm {
   int n_seq[2] = {0, 0};
   std::vector<Infoset> inf[2];
   std::vector<Terminal> terms;
   std::vector<RiverTask> rivers;        // empty for a river endgame
+  std::vector<float> inf_feat[2];       // kInfFeat per infoset (warm-start inputs)
 };
 
 // ---------------------------------------------------------------------------
@@ -110,6 +116,7 @@ struct Built {
   std::vector<int32_t> inf_parent[2], inf_first[2], inf_nact[2], inf_board[2];
   std::vector<int32_t> t_seq1, t_seq2, t_kind, t_board, t_runout;
   std::vector<double> t_c1, t_c2;
+  std::vector<float> hand_feat[2];      // kHandFeat per hand (warm-start inputs)
 };
 
 // ---------------------------------------------------------------------------

@@ -76,6 +76,9 @@ EXPORTS = [
     "solver_reset", "solver_step", "saddle_gap", "saddle_gap_of",
     "solver_get_state", "solver_set_state", "get_average_strategy",
     "set_initial_strategy", "pmx_last_error", "game_tune", "game_get_tuning",
+    "warm_num_rows", "warm_features", "warm_targets", "warm_apply",
+    "mlp_gemm_bf16", "mlp_softmax_xent", "mlp_colsum", "mlp_adam", "mlp_gather_bf16",
+    "mlp_gather_f32", "mlp_cast_bf16",
 ]
 
 
@@ -112,6 +115,19 @@ def lib():
     L.set_initial_strategy.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_float, vp]
     L.game_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     L.game_get_tuning.argtypes = [vp, _c_i32p, _c_i32p]
+    i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    L.warm_num_rows.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    L.warm_features.argtypes = [vp, i32, vp, vp]
+    L.warm_targets.argtypes = [vp, i32, vp, vp, vp]
+    L.warm_apply.argtypes = [vp, vp, vp, i32, f32, ctypes.c_double, vp]
+    L.mlp_gemm_bf16.argtypes = [i32, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, vp, i32, vp, i32,
+                                vp, i32, vp]
+    L.mlp_softmax_xent.argtypes = [i32, i32, vp, i32, vp, vp, vp, vp, vp, vp]
+    L.mlp_colsum.argtypes = [i32, i32, vp, vp, vp]
+    L.mlp_adam.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, f32, i32, vp]
+    L.mlp_gather_bf16.argtypes = [i64, i32, vp, vp, vp, vp]
+    L.mlp_gather_f32.argtypes = [i64, i32, vp, vp, vp, vp]
+    L.mlp_cast_bf16.argtypes = [i64, vp, vp, vp]
     L.pmx_last_error.argtypes = []
     L.pmx_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -141,7 +157,21 @@ def _stream(stream):
 
 
 def _dptr(t):
-    return ctypes.c_void_p(t.data_ptr())
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def check(rc):
+    """Raise PmxError for a nonzero return code of a libpmx call."""
+    _check(rc)
+
+
+def dptr(t):
+    """Device pointer of a torch tensor (NULL for None)."""
+    return _dptr(t)
+
+
+def stream_ptr(stream=None):
+    return _stream(stream)
 
 
 class _DescPack:
@@ -333,6 +363,21 @@ class Game:
         out = np.zeros(self.elems[player], np.float64)
         _check(lib().get_average_strategy(self._h, player, _ptr(out, ctypes.c_double)))
         return out
+
+    def warm_num_rows(self, player: int) -> int:
+        n = ctypes.c_int64()
+        _check(lib().warm_num_rows(self._h, player, ctypes.byref(n)))
+        return n.value
+
+    def warm_features(self, player: int, x_bf16, stream=None):
+        _check(lib().warm_features(self._h, player, _dptr(x_bf16), _stream(stream)))
+
+    def warm_targets(self, player: int, target, weight, stream=None):
+        _check(lib().warm_targets(self._h, player, _dptr(target), _dptr(weight), _stream(stream)))
+
+    def warm_apply(self, logits0, logits1, ldz: int, regret_scale: float, avg_weight: float, stream=None):
+        _check(lib().warm_apply(self._h, _dptr(logits0), _dptr(logits1), int(ldz), float(regret_scale),
+                                float(avg_weight), _stream(stream)))
 
     def set_initial_strategy(self, player: int, behav, scale: float = 1.0, stream=None):
         _check(lib().set_initial_strategy(self._h, player, _dptr(behav), float(scale), _stream(stream)))
