@@ -112,21 +112,14 @@ def batched_leg(args, stream):
     pair_us = e0.elapsed_time(e1) * 1e3 / reps
     bytes_pair = algorithmic_bytes_pair(L)
     achieved = bytes_pair / (pair_us * 1e-6) / 1e9
-    # batched time to gap: every instance at or below 1e-4 of its pot
-    pots = np.array([2 * d.contrib for d in descs])
+    # batched time to gap: every instance at or below 1e-4 of its pot; solved
+    # instances are retired from the iteration
+    from paper_2112_03804_amd import warmstart as ws
     g.solver_reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters, done_at = 0, np.full(len(descs), -1)
-    while iters < args.max_iters:
-        g.solver_step(32)
-        iters += 32
-        gap = g.saddle_gap()[0]
-        newly = (gap <= 1e-4 * pots) & (done_at < 0)
-        done_at[newly] = iters
-        if (done_at >= 0).all():
-            break
-    ttg_batched = time.perf_counter() - t0
+    ttg_batched, iters, done_at = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters)
+    g.solver_reset()
+    ttg_noretire, iters_nr, _ = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters,
+                                                retire=False)
     g.close()
     # plain single-instance solver on a sample of the same instances
     sample = list(range(0, len(descs), max(1, len(descs) // args.plain_sample)))[:args.plain_sample]
@@ -158,6 +151,7 @@ def batched_leg(args, stream):
                      "frac": achieved / HBM_PEAK_GBS, "kernel": "k_matvec (matvec_pair launch)",
                      "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair},
         "time_to_gap_batched_s": ttg_batched,
+        "time_to_gap_batched_no_retirement_s": ttg_noretire,
         "iterations_batched": iters,
         "instances_reached": int((done_at >= 0).sum()),
         "iterations_per_instance_p50_p90_max": [float(np.percentile(done_at[done_at > 0], q))
@@ -167,6 +161,130 @@ def batched_leg(args, stream):
                                          "sum_over_batch_extrapolated_s": plain_total_est},
         "speedup_batched_vs_plain": plain_total_est / ttg_batched,
     }
+
+
+def turn_river_leg(args, stream):
+    """The turn + river endgame: one instance of 19,480 sequences x 1128 hands
+    per player (352 MB per matvec pair): tuned matvec-pair roofline, solver
+    iteration time, and the FP64 gap after a fixed number of iterations."""
+    import torch
+    from paper_2112_03804_amd import autotune
+    from paper_2112_03804_amd import instances as I
+    from paper_2112_03804_amd import pmx
+
+    desc = I.config(2)
+    t_create = time.perf_counter()
+    g = pmx.Game(desc)
+    t_create = time.perf_counter() - t_create
+    sched, sched_us = autotune.tune(g, candidates=[(0, 1), (0, 4), (0, 8), (1, 2)], reps=10,
+                                    use_cache=False)
+    bytes_pair = algorithmic_bytes_pair(g.layouts)
+    pair_us = min(sched_us.values())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g.solver_reset()
+    g.solver_step(4)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    g.solver_step(args.turn_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    it_ms = e0.elapsed_time(e1) / args.turn_steps
+    gap = float(g.saddle_gap()[0][0])
+    out = {"workload": "turn + river endgame: 4-card board, 48 river cards, 1128 hands/player, "
+                       "bets {0.33,0.75,1.5}xpot + all-in, max 3 raises per street, pot 100, stacks 400",
+           "game_create_s": t_create,
+           "schedule": {"tuned": list(sched), "us_per_pair_by_schedule": sched_us},
+           "roofline": {"bound": "hbm", "achieved": bytes_pair / (pair_us * 1e-6) / 1e9,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": bytes_pair / (pair_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                        "kernel": "k_matvec (matvec_pair launch)", "us_per_launch": pair_us,
+                        "algorithmic_bytes_per_launch": bytes_pair},
+           "matvec_pairs_per_s": 1e6 / pair_us,
+           "iteration_ms": it_ms,
+           "gap_over_pot_after": {"iterations": 4 + args.turn_steps, "gap_over_pot": gap / (2 * desc.contrib)}}
+    g.close()
+    return out
+
+
+def warm_leg(args, stream, batched):
+    """Learned warm start on the batched workload: label instances with the
+    plain batched solver, train the BF16 network on the GPU, then solve the
+    512 held-out instances (the batched workload) from the network's prior."""
+    import torch
+    from paper_2112_03804_amd import instances as I
+    from paper_2112_03804_amd import pmx
+    from paper_2112_03804_amd import warmstart as ws
+
+    t0 = time.perf_counter()
+    train_descs = I.batched_configs(args.warm_train, seed=11)
+    ds = ws.make_dataset(train_descs, iters=args.warm_label_iters, batch=512)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = ws.WarmMLP(seed=0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = ws.train(net, ds, steps=args.warm_steps, batch_rows=8192, lr=1e-3,
+                    log_every=max(1, args.warm_steps // 10))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    rows_trained = args.warm_steps * 8192
+    flops_per_row = 2 * (64 * 512 + 512 * 512 + 512 * 8) * 3     # forward + backward
+    n_rows = ds.rows
+    del ds
+    descs = I.batched_configs(args.batch)
+    g = pmx.Game(descs)
+    g.game_tune(*batched["schedule"]["tuned"])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ws.apply_prior(g, net, args.warm_scale, args.warm_avg)
+    sec, iters, done = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters)
+    t_warm = time.perf_counter() - t2
+    g.close()
+    plain_total = batched["plain_single_instance_sample"]["sum_over_batch_extrapolated_s"]
+    return {"train_instances": len(train_descs), "label_iterations": args.warm_label_iters,
+            "dataset_rows": n_rows, "data_s": t_data,
+            "train_steps": args.warm_steps, "train_s": t_train, "loss_history": hist,
+            "train_tflops": rows_trained * flops_per_row / t_train / 1e12,
+            "prior": {"regret_scale": args.warm_scale, "avg_weight": args.warm_avg},
+            "time_to_gap_warm_batched_s": t_warm,
+            "iterations": iters,
+            "iterations_per_instance_p50_p90_max": [float(np.percentile(done[done >= 0], q))
+                                                    for q in (50, 90, 100)] if (done >= 0).any() else None,
+            "instances_reached": int((done >= 0).sum()),
+            "speedup_vs_plain_single_instance": plain_total / t_warm,
+            "speedup_vs_batched_uniform": batched["time_to_gap_batched_s"] / t_warm}
+
+
+def pmc_probe(args):
+    """Launches for hardware-counter runs (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE):
+    a plain 256 MiB device-to-device copy (known bytes: calibrates the counters),
+    then matvec-pair launches on the river endgame and on the batch."""
+    import torch
+    from paper_2112_03804_amd import instances as I
+    from paper_2112_03804_amd import pmx
+    n = 64 << 20
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    games = [("river", pmx.Game(I.config(1)))]
+    if not args.no_batched:
+        gb = pmx.Game(I.batched_configs(args.batch))
+        gb.game_tune(0, 8)
+        games.append(("batch", gb))
+    for name, g in games:
+        rng = np.random.default_rng(0)
+        y = torch.from_numpy(rng.random(g.elems[1]).astype(np.float32)).cuda()
+        x = torch.from_numpy(rng.random(g.elems[0]).astype(np.float32)).cuda()
+        Ay = torch.empty(g.elems[0], dtype=torch.float32, device="cuda")
+        ATx = torch.empty(g.elems[1], dtype=torch.float32, device="cuda")
+        for _ in range(10):
+            g.matvec_pair(y, x, Ay, ATx)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": name, "algorithmic_bytes_per_launch": algorithmic_bytes_pair(g.layouts),
+                          "copy_bytes_each_way": 4 * n}), flush=True)
+        g.close()
 
 
 def main():
@@ -181,6 +299,16 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=256)
     ap.add_argument("--plain-sample", type=int, default=16)
     ap.add_argument("--max-iters", type=int, default=100000)
+    ap.add_argument("--no-turn", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only run the launches profiled for HBM traffic counters")
+    ap.add_argument("--turn-steps", type=int, default=20)
+    ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--warm-train", type=int, default=1024)
+    ap.add_argument("--warm-label-iters", type=int, default=3072)
+    ap.add_argument("--warm-steps", type=int, default=2000)
+    ap.add_argument("--warm-scale", type=float, default=0.5)
+    ap.add_argument("--warm-avg", type=float, default=0.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -193,6 +321,9 @@ def main():
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
 
+    if args.pmc_probe:
+        pmc_probe(args)
+        return
     desc = I.config(1)
     pot = 2 * desc.contrib
     stream = torch.cuda.current_stream()
@@ -234,19 +365,23 @@ def main():
     achieved = bytes_pair / (pair_us * 1e-6) / 1e9
 
     # ---- time to gap 1e-4 * pot from a uniform start -----------------------
-    target = 1e-4 * pot
-    g.solver_reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = 0
-    gap = float("inf")
-    while iters < 200000:
-        g.solver_step(25)
-        iters += 25
-        gap = float(g.saddle_gap()[0][0])
-        if gap <= target:
-            break
-    ttg = time.perf_counter() - t0
+    def time_to_gap(kind):
+        g.solver_set_params(kind)
+        g.solver_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters, gap = 0, float("inf")
+        while iters < 200000:
+            g.solver_step(25)
+            iters += 25
+            gap = float(g.saddle_gap()[0][0])
+            if gap <= 1e-4 * pot:
+                break
+        return time.perf_counter() - t0, iters, gap
+
+    ttg, iters, gap = time_to_gap("rm+")
+    ttg_d, iters_d, gap_d = time_to_gap("dcfr")
+    g.solver_set_params("rm+")
 
     out = {
         "metric": "matvec pairs/s (A·y+Aᵀx) & time to gap 1e-4·pot: plain vs batched/warm-start",
@@ -272,12 +407,18 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_pair},
         "time_to_gap": {"target": "1e-4*pot", "seconds": ttg, "iterations": iters,
                         "gap_over_pot": gap / pot, "solver": "plain RM+, uniform start, "
-                        "FP64 gap checked every 25 iterations"},
+                        "FP64 gap checked every 25 iterations",
+                        "dcfr": {"seconds": ttg_d, "iterations": iters_d, "gap_over_pot": gap_d / pot,
+                                 "params": "alpha 1.5, beta 0, gamma 2"}},
         "game_create_s": t_create,
     }
     g.close()
     if not args.no_batched:
         out["batched"] = batched_leg(args, stream)
+        if not args.no_warm:
+            out["warm_start"] = warm_leg(args, stream, out["batched"])
+    if not args.no_turn:
+        out["turn_river"] = turn_river_leg(args, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(desc, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -239,10 +239,26 @@ int matvec_pair(Game* g, const float* y_dev, const float* x_dev, float* Ay_dev,
  * Asynchronous. */
 int solver_reset(Game* g, void* stream);
 
+/* Solver rule: kind 0 = regret matching+ (default); kind 1 = discounted CFR,
+ * the family of the paper's GPU solver (Section 5): regrets scaled by
+ * t^alpha/(t^alpha+1) when positive and t^beta/(t^beta+1) otherwise before
+ * the instantaneous regret is added, strategies from the positive part, and
+ * iterate t weighted t^gamma in the average (gamma in {1, 2, 3}).  Takes
+ * effect from the next iteration; averages already accumulated are kept.
+ * Synchronizes the device. */
+int solver_set_params(Game* g, int32_t kind, double alpha, double beta, int32_t gamma);
+
 /* Run n_iters alternating RM+ iterations: g1 = A y_t, update Player 1;
  * g2 = -A^T x_{t+1}, update Player 2; averages += t * (x_t, y_t).
  * Asynchronous. */
 int solver_step(Game* g, int32_t n_iters, void* stream);
+
+/* Retire or revive instances of a batch: active_host[i] = 0 makes
+ * solver_step skip instance i (its regrets, plans and averages stay frozen
+ * and its iteration count no longer advances with the others); saddle_gap
+ * still reports every instance.  solver_reset revives all.  Synchronizes
+ * `stream`. */
+int solver_set_active(Game* g, const int32_t* active_host, void* stream);
 
 /* FP64 saddle gap of the average strategies (exploitability = gap / 2, over
  * the initial pot 2 * contrib).  gap, br1, br2 are host arrays with one

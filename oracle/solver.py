@@ -68,6 +68,23 @@ class Treeplex:
                 q[par] += V
         return R
 
+    def dcfr_update(self, R, g, t, alpha, beta):
+        """Discounted CFR regret update at iteration t: positive regrets are
+        scaled by t^a/(t^a+1), the others by t^b/(t^b+1), then the
+        instantaneous regret q - V is added (no floor)."""
+        b = self.behaviour_from_regret(R)
+        q = np.array(g, dtype=np.float64, copy=True)
+        R = R.copy()
+        dp = t ** alpha / (t ** alpha + 1.0)
+        dn = t ** beta / (t ** beta + 1.0)
+        for par, f, n in reversed(self.inf):
+            V = (b[f:f + n] * q[f:f + n]).sum(axis=0)
+            r = R[f:f + n]
+            R[f:f + n] = r * np.where(r > 0, dp, dn) + q[f:f + n] - V[None, :]
+            if par >= 0:
+                q[par] += V
+        return R
+
     def best_value(self, g, maximize=True):
         """Per-hand best-response value: sum over root infosets of the
         bottom-up max (or min) of g plus the values below."""
@@ -88,9 +105,13 @@ class Treeplex:
 
 
 class RMPlus:
-    """Plain FP64 alternating RM+ with linear averaging."""
+    """Plain FP64 alternating RM+ with linear averaging; with kind="dcfr",
+    Discounted CFR (the solver of the paper's GPU experiments): discounted
+    regrets (alpha, beta) and averages weighted t^gamma."""
 
-    def __init__(self, game: Game, matvec_A=None, matvec_AT=None):
+    def __init__(self, game: Game, matvec_A=None, matvec_AT=None, kind="rm+", alpha=1.5, beta=0.0,
+                 gamma=2):
+        self.kind, self.alpha, self.beta, self.gamma = kind, alpha, beta, gamma
         self.g = game
         self.tp = [Treeplex(game, 0), Treeplex(game, 1)]
         self.A = matvec_A or game.matvec_A
@@ -101,17 +122,23 @@ class RMPlus:
         self.wsum = 0.0
         self.t = 0
 
+    def _update(self, p, g):
+        if self.kind == "dcfr":
+            return self.tp[p].dcfr_update(self.R[p], g, float(self.t), self.alpha, self.beta)
+        return self.tp[p].rmplus_update(self.R[p], g)
+
     def step(self):
         self.t += 1
         t = float(self.t)
+        w = t ** self.gamma if self.kind == "dcfr" else t
         for p in range(2):
-            self.sum[p] += t * self.x[p]
-        self.wsum += t
+            self.sum[p] += w * self.x[p]
+        self.wsum += w
         g1 = self.A(self.x[1])
-        self.R[0] = self.tp[0].rmplus_update(self.R[0], g1)
+        self.R[0] = self._update(0, g1)
         self.x[0] = self.tp[0].realization(self.tp[0].behaviour_from_regret(self.R[0]))
         g2 = -self.AT(self.x[0])
-        self.R[1] = self.tp[1].rmplus_update(self.R[1], g2)
+        self.R[1] = self._update(1, g2)
         self.x[1] = self.tp[1].realization(self.tp[1].behaviour_from_regret(self.R[1]))
 
     def average(self, p):

@@ -676,26 +676,26 @@ void build_matvec_plan(HostGame& hg, int d, int rows_per_block) {
       for (int sg : by_ctx[c]) {
         emit_row(sg);
         if (++cnt == rows_per_block) {
-          D.blk.push_back((int32_t)D.items.size());
+          { D.blk.push_back((int32_t)D.items.size()); D.blk_inst.push_back((int32_t)ii); }
           cnt = 0;
         }
       }
-      if (cnt) D.blk.push_back((int32_t)D.items.size());
+      if (cnt) { D.blk.push_back((int32_t)D.items.size()); D.blk_inst.push_back((int32_t)ii); }
     }
     for (int sg : multi) {
       emit_row(sg);
-      D.blk.push_back((int32_t)D.items.size());
+      { D.blk.push_back((int32_t)D.items.size()); D.blk_inst.push_back((int32_t)ii); }
     }
     {
       int cnt = 0;
       for (int sg : empty) {
         emit_row(sg);
         if (++cnt == 4 * rows_per_block) {
-          D.blk.push_back((int32_t)D.items.size());
+          { D.blk.push_back((int32_t)D.items.size()); D.blk_inst.push_back((int32_t)ii); }
           cnt = 0;
         }
       }
-      if (cnt) D.blk.push_back((int32_t)D.items.size());
+      if (cnt) { D.blk.push_back((int32_t)D.items.size()); D.blk_inst.push_back((int32_t)ii); }
     }
   }
 }

@@ -68,6 +68,8 @@ struct MvParams {
   int32_t nblk;
   int32_t max_ent, max_n, max_seg;
   int32_t dir;
+  const int32_t* blk_inst;   // instance of each row chunk
+  const int32_t* active;     // per-instance flag (NULL: all); inactive chunks are skipped
 };
 
 // LDS index with one spare double every 16: a thread's contiguous chunk of 16
@@ -82,6 +84,7 @@ __device__ inline T shfl_up64(T v, int d) {
 // Exclusive segmented scan over the threads of a block of (flag, a, b): a
 // thread's result sums the contributions of earlier threads back to (and
 // including the post-flag part of) the nearest earlier thread with flag set.
+// One barrier; the caller alternates `scratch` between consecutive scans.
 template <int BLOCK>
 __device__ inline void block_seg_scan(bool flag, double a, double b, double* scratch, double& ea,
                                       double& eb) {
@@ -132,7 +135,6 @@ __device__ inline void block_seg_scan(bool flag, double a, double b, double* scr
   }
   ea = xa;
   eb = xb;
-  __syncthreads();
 }
 
 __device__ inline int lo16(uint32_t v) { return (int)(int16_t)(v & 0xffffu); }
@@ -149,11 +151,15 @@ __device__ inline const double* lam_of<double>(const MvParams& P) { return P.lam
 // KH own/opponent hands and KE scan entries per thread; metadata of the
 // current context stays in registers across the chunk's rows.
 template <int BLOCK, int KH, int KE, typename IO>
-__global__ __launch_bounds__(BLOCK, 4) void k_matvec(MvParams P0, const IO* __restrict__ in0,
-                                                  IO* __restrict__ out0, MvParams P1,
-                                                  const IO* __restrict__ in1, IO* __restrict__ out1,
-                                                  double* __restrict__ tick) {
+__global__ __launch_bounds__(BLOCK, sizeof(IO) == 4 ? 4 : 3) void k_matvec(MvParams P0, const IO* __restrict__ in0,
+                                                     IO* __restrict__ out0, MvParams P1,
+                                                     const IO* __restrict__ in1, IO* __restrict__ out1,
+                                                     double* __restrict__ tick) {
   static_assert(KE % 2 == 0, "entries are packed in pairs");
+  constexpr int NW = BLOCK / 64;
+  // FP32 rows double-buffer their inputs in LDS (no barrier between rows);
+  // FP64 rows would not fit twice, so they take one barrier instead.
+  constexpr bool DB = sizeof(IO) == 4;
   if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1.0;
   const bool second = (int)blockIdx.x >= P0.nblk;
   const MvParams& P = second ? P1 : P0;
@@ -162,31 +168,52 @@ __global__ __launch_bounds__(BLOCK, 4) void k_matvec(MvParams P0, const IO* __re
   const IO* __restrict__ lam = lam_of<IO>(P);
   const int b = second ? (int)blockIdx.x - P0.nblk : (int)blockIdx.x;
   const int tid = threadIdx.x;
+  if (P.active && !P.active[P.blk_inst[b]]) return;   // retired instance
 
+  // LDS: prefix sums, fold totals, two scan scratch buffers, two input buffers
   extern __shared__ double smem[];
   const int me = pd(P0.max_ent > P1.max_ent ? P0.max_ent : P1.max_ent) + 1;
   const int mn = pd(P0.max_n > P1.max_n ? P0.max_n : P1.max_n) + 1;
   const int ms = P0.max_seg > P1.max_seg ? P0.max_seg : P1.max_seg;
   double* Pc = smem;                            // [me] exclusive segmented prefix (showdown channel)
   double* segF = Pc + me;                       // [ms] per-segment fold totals
-  double* scratch = segF + ms;                  // [3 * BLOCK / 64]
-  IO* us = (IO*)(scratch + 3 * (BLOCK / 64));   // [mn] showdown input, sorted order
-  IO* uf = us + mn;                             // [mn] fold input, sorted order
-  int* segEnd = (int*)(uf + mn);                // [ms]
+  double* scratch = segF + ms;                  // [2][3 * NW]
+  IO* usb = (IO*)(scratch + 6 * NW);            // [1 or 2][mn] showdown input, sorted order
+  IO* ufb = usb + (DB ? 2 : 1) * mn;            // [1 or 2][mn] fold input, sorted order
+  int* segEnd = (int*)(ufb + (DB ? 2 : 1) * mn);  // [ms]
 
   uint4 qr[KH];
   IO lo[KH], lp[KH];
   double acc[KH];
   uint32_t rkp[(KH + 1) / 2];
   uint32_t srcp[KE / 2];
+  IO nxs[KH], nxf[KH];                          // raw inputs of the next row (prefetched)
 #pragma unroll
   for (int k = 0; k < KH; ++k) acc[k] = 0.0;
 
   const int it0 = P.blk[b], it1 = P.blk[b + 1];
-  int cur = -2;
+  auto fetch = [&](int it) {
+    const MvItem nx = P.items[it];
+    const int nopp = nx.ctx >= 0 ? P.ctx[nx.ctx].n_opp : 0;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int h = tid + k * BLOCK;
+      nxs[k] = (h < nopp && nx.in_s >= 0) ? in[nx.in_s + h] : (IO)0;
+      nxf[k] = (h < nopp && nx.in_f >= 0) ? in[nx.in_f + h] : (IO)0;
+    }
+  };
+  if (it0 < it1) fetch(it0);
+  int cur = -2, par = 0;
   int n_own = 0, n_opp = 0, n_live = 0, n_ent = 0, cph = 1;
   for (int it = it0; it < it1; ++it) {
     const MvItem item = P.items[it];
+    IO cs_in[KH], cf_in[KH];
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      cs_in[k] = nxs[k];
+      cf_in[k] = nxf[k];
+    }
+    if (it + 1 < it1) fetch(it + 1);
     if (item.ctx < 0) {
 #pragma unroll
       for (int k = 0; k < KH; ++k) {
@@ -195,7 +222,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_matvec(MvParams P0, const IO* __re
       }
       continue;
     }
-    __syncthreads();   // previous item's readers of LDS are done
+    if (item.ctx != cur || !DB) __syncthreads();   // previous rows no longer read segEnd / inputs
     if (item.ctx != cur) {
       const MvCtx C = P.ctx[item.ctx];
       n_own = C.n_own;
@@ -228,8 +255,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_matvec(MvParams P0, const IO* __re
       for (int i = tid; i < C.n_seg; i += BLOCK) segEnd[i] = P.segend[C.segend_off + i];
       cur = item.ctx;
     }
+    IO* us = usb + par * mn;
+    IO* uf = ufb + par * mn;
+    double* scr = scratch + par * 3 * NW;
     // phase 1: weighted opponent inputs scattered to strength order
-    const bool has_s = item.in_s >= 0, has_f = item.in_f >= 0;
     const IO ks = (IO)item.ks, kf = (IO)item.kf;
 #pragma unroll
     for (int k = 0; k < KH; ++k) {
@@ -237,8 +266,8 @@ __global__ __launch_bounds__(BLOCK, 4) void k_matvec(MvParams P0, const IO* __re
       const int rk = (k & 1) ? hi16(rkp[k >> 1]) : lo16(rkp[k >> 1]);
       if (h < n_opp && rk >= 0) {
         const IO w = lp[k];
-        us[pd(rk)] = has_s ? ks * w * in[item.in_s + h] : (IO)0;
-        uf[pd(rk)] = has_f ? kf * w * in[item.in_f + h] : (IO)0;
+        us[pd(rk)] = ks * w * cs_in[k];
+        uf[pd(rk)] = kf * w * cf_in[k];
       }
     }
     __syncthreads();
@@ -249,10 +278,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_matvec(MvParams P0, const IO* __re
     for (int j = 0; j < KE; ++j) {
       const int e = tid * KE + j;
       if (e < n_ent) {
-        const int s = (j & 1) ? hi16(srcp[j >> 1]) : lo16(srcp[j >> 1]);
-        if (s >= 0) {
-          rs += (double)us[pd(s)];
-          rf += (double)uf[pd(s)];
+        const int sidx = (j & 1) ? hi16(srcp[j >> 1]) : lo16(srcp[j >> 1]);
+        if (sidx >= 0) {
+          rs += (double)us[pd(sidx)];
+          rf += (double)uf[pd(sidx)];
         } else {
           flag = true;
           rs = 0.0;
@@ -261,20 +290,20 @@ __global__ __launch_bounds__(BLOCK, 4) void k_matvec(MvParams P0, const IO* __re
       }
     }
     double cs, cf;
-    block_seg_scan<BLOCK>(flag, rs, rf, scratch, cs, cf);
+    block_seg_scan<BLOCK>(flag, rs, rf, scr, cs, cf);
     rs = cs;
     rf = cf;
 #pragma unroll
     for (int j = 0; j < KE; ++j) {
       const int e = tid * KE + j;
       if (e < n_ent) {
-        const int s = (j & 1) ? hi16(srcp[j >> 1]) : lo16(srcp[j >> 1]);
+        const int sidx = (j & 1) ? hi16(srcp[j >> 1]) : lo16(srcp[j >> 1]);
         Pc[pd(e)] = rs;
-        if (s >= 0) {
-          rs += (double)us[pd(s)];
-          rf += (double)uf[pd(s)];
+        if (sidx >= 0) {
+          rs += (double)us[pd(sidx)];
+          rf += (double)uf[pd(sidx)];
         } else {
-          segF[-1 - s] = rf;
+          segF[-1 - sidx] = rf;
           rs = 0.0;
           rf = 0.0;
         }
@@ -313,6 +342,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_matvec(MvParams P0, const IO* __re
         acc[k] = 0.0;
       }
     }
+    if (DB) par ^= 1;
   }
 }
 
@@ -353,6 +383,7 @@ __global__ __launch_bounds__(64) void k_matvec_w(MvParams P, const int32_t* __re
   if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1.0;
   const int lane = threadIdx.x;
   const int ch = chunks[blockIdx.x];
+  if (P.active && !P.active[P.blk_inst[ch]]) return;   // retired instance
   const IO* __restrict__ lam = lam_of<IO>(P);
   extern __shared__ double smem[];
   double* Pc = smem;                      // [me]
@@ -499,26 +530,54 @@ struct TpParams {
   const TpPull* pulls;
   const int2* blocks;
   int32_t stage_stride;
+  const int32_t* active;     // per-instance flag (NULL: all); inactive tasks are skipped
+  int32_t dcfr;              // 0: regret matching+, 1: discounted CFR
+  int32_t gamma;             // averaging weight t^gamma (1 for RM+)
+  float alpha, beta;         // DCFR regret discounts
 };
+
+// Per-iteration constants of the regret update and the averaging weight.
+struct RmStep {
+  double w;                  // weight of this iteration's plan in the average
+  float dp, dn;              // factors for positive / other regrets
+  bool floor;                // RM+: clip regrets at 0
+};
+__device__ inline RmStep rm_step(const TpParams& P, double t) {
+  RmStep r;
+  r.w = P.gamma == 1 ? t : (P.gamma == 2 ? t * t : t * t * t);
+  r.dp = 1.f;
+  r.dn = 1.f;
+  r.floor = !P.dcfr;
+  if (P.dcfr) {
+    const float tf = (float)t;
+    const float ta = powf(tf, P.alpha), tb = powf(tf, P.beta);
+    r.dp = ta / (ta + 1.f);
+    r.dn = tb / (tb + 1.f);
+  }
+  return r;
+}
+__device__ inline float rm_new(float r, float inst, const RmStep& k) {
+  const float v = r * (r > 0.f ? k.dp : k.dn) + inst;
+  return (k.floor && v < 0.f) ? 0.f : v;
+}
 
 constexpr int TPB = 128;
 
 // Regret-matching+ regret update of one infoset for one hand; returns V(I).
 __device__ inline float rm_infoset(float* __restrict__ g, float* __restrict__ R, int64_t base,
-                                   int64_t stride, int f, int n) {
+                                   int64_t stride, int f, int n, const RmStep& k) {
   float rs = 0.f;
-  for (int a = 0; a < n; ++a) rs += R[base + (f + a) * stride];
+  for (int a = 0; a < n; ++a) rs += fmaxf(R[base + (f + a) * stride], 0.f);
   float V = 0.f;
   const float inv = rs > 0.f ? 1.f / rs : 0.f;
   const float uni = 1.f / (float)n;
   for (int a = 0; a < n; ++a) {
-    float ba = rs > 0.f ? R[base + (f + a) * stride] * inv : uni;
+    float ba = rs > 0.f ? fmaxf(R[base + (f + a) * stride], 0.f) * inv : uni;
     V += ba * g[base + (f + a) * stride];
   }
   for (int a = 0; a < n; ++a) {
     int64_t i = base + (f + a) * stride;
-    float r = R[i] + g[i] - V;
-    R[i] = r > 0.f ? r : 0.f;
+    R[i] = rm_new(R[i], g[i] - V, k);
   }
   return V;
 }
@@ -530,12 +589,12 @@ __device__ inline void rm_descend(const float* __restrict__ R, float* __restrict
                                   int n, int par, double t) {
   const float xp = par >= 0 ? x[base + (int64_t)par * stride] : 1.f;
   float rs = 0.f;
-  for (int a = 0; a < n; ++a) rs += R[base + (f + a) * stride];
+  for (int a = 0; a < n; ++a) rs += fmaxf(R[base + (f + a) * stride], 0.f);
   const float inv = rs > 0.f ? 1.f / rs : 0.f;
   const float uni = 1.f / (float)n;
   for (int a = 0; a < n; ++a) {
     int64_t i = base + (f + a) * stride;
-    float ba = rs > 0.f ? R[i] * inv : uni;
+    float ba = rs > 0.f ? fmaxf(R[i], 0.f) * inv : uni;
     xs[i] += t * (double)x[i];
     x[i] = xp * ba;
   }
@@ -548,9 +607,11 @@ __global__ __launch_bounds__(TPB) void k_rm(TpParams P, float* __restrict__ g,
                                             float* __restrict__ R, float* __restrict__ x,
                                             double* __restrict__ xs, float* __restrict__ stage,
                                             const double* __restrict__ tdev) {
-  const double t = *tdev;
+  const RmStep K = rm_step(P, *tdev);
+  const double t = K.w;
   const int2 bt = P.blocks[blockIdx.x];
   const TpTask T = P.tasks[bt.x];
+  if (P.active && !P.active[T.inst]) return;
   const int h = bt.y + threadIdx.x;
   if (h >= T.n_hands) return;
   const int64_t base = T.vec_base + h, stride = T.stride;
@@ -565,7 +626,7 @@ __global__ __launch_bounds__(TPB) void k_rm(TpParams P, float* __restrict__ g,
     for (int i = T.inf_end - 1; i >= T.inf_begin; --i) {
       const int I = P.order[i];
       const int par = P.inf_parent[I];
-      const float V = rm_infoset(g, R, base, stride, P.inf_first[I], P.inf_nact[I]);
+      const float V = rm_infoset(g, R, base, stride, P.inf_first[I], P.inf_nact[I], K);
       if (MODE == 1 && par == T.ext_parent) vroot += V;
       else if (par >= 0) g[base + (int64_t)par * stride] += V;
     }
@@ -599,6 +660,7 @@ __global__ __launch_bounds__(STB * STW) void k_rm_st(TpParams P, float* __restri
   extern __shared__ float stsm[];
   const int2 bt = P.blocks[blockIdx.x];
   const TpTask T = P.tasks[bt.x];
+  if (P.active && !P.active[T.inst]) return;   // whole block: T is uniform
   const int lane = threadIdx.x & (STB - 1), wv = threadIdx.x / STB;
   const int h = bt.y + lane;
   const bool act = h < T.n_hands;
@@ -610,7 +672,8 @@ __global__ __launch_bounds__(STB * STW) void k_rm_st(TpParams P, float* __restri
   float* RL = gL + (size_t)SL * STB;
   float* xL = RL + (size_t)SL * STB;
   const int64_t base = T.vec_base + h, stride = T.stride;
-  const double t = *tdev;
+  const RmStep K = rm_step(P, *tdev);
+  const double t = K.w;
   for (int i = threadIdx.x; i < ninf; i += STB * STW) {
     const int I = P.order[T.inf_begin + i];
     iPar[i] = P.inf_parent[I];
@@ -662,30 +725,25 @@ __global__ __launch_bounds__(STB * STW) void k_rm_st(TpParams P, float* __restri
           for (int a = 0; a < MAXA; ++a) {
             rr[a] = a < n ? RL[(f + a) * STB + lane] : 0.f;
             gg[a] = a < n ? gL[(f + a) * STB + lane] : 0.f;
-            rs += rr[a];
+            rs += fmaxf(rr[a], 0.f);
           }
           const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
           V = 0.f;
 #pragma unroll
           for (int a = 0; a < MAXA; ++a)
-            if (a < n) V += (rs > 0.f ? rr[a] * inv : uni) * gg[a];
+            if (a < n) V += (rs > 0.f ? fmaxf(rr[a], 0.f) * inv : uni) * gg[a];
 #pragma unroll
           for (int a = 0; a < MAXA; ++a)
-            if (a < n) {
-              const float r = rr[a] + gg[a] - V;
-              RL[(f + a) * STB + lane] = r > 0.f ? r : 0.f;
-            }
+            if (a < n) RL[(f + a) * STB + lane] = rm_new(rr[a], gg[a] - V, K);
         } else {
           float rs = 0.f;
-          for (int a = 0; a < n; ++a) rs += RL[(f + a) * STB + lane];
+          for (int a = 0; a < n; ++a) rs += fmaxf(RL[(f + a) * STB + lane], 0.f);
           const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
           V = 0.f;
           for (int a = 0; a < n; ++a)
-            V += (rs > 0.f ? RL[(f + a) * STB + lane] * inv : uni) * gL[(f + a) * STB + lane];
-          for (int a = 0; a < n; ++a) {
-            const float r = RL[(f + a) * STB + lane] + gL[(f + a) * STB + lane] - V;
-            RL[(f + a) * STB + lane] = r > 0.f ? r : 0.f;
-          }
+            V += (rs > 0.f ? fmaxf(RL[(f + a) * STB + lane], 0.f) * inv : uni) * gL[(f + a) * STB + lane];
+          for (int a = 0; a < n; ++a)
+            RL[(f + a) * STB + lane] = rm_new(RL[(f + a) * STB + lane], gL[(f + a) * STB + lane] - V, K);
         }
         if (MODE == 1 && par == T.ext_parent) vroot += V;
         else if (par >= 0) gL[(par - S0) * STB + lane] += V;
@@ -703,7 +761,7 @@ __global__ __launch_bounds__(STB * STW) void k_rm_st(TpParams P, float* __restri
           float rs = 0.f;
 #pragma unroll
           for (int a = 0; a < MAXA; ++a) {
-            rr[a] = a < n ? RL[(f + a) * STB + lane] : 0.f;
+            rr[a] = a < n ? fmaxf(RL[(f + a) * STB + lane], 0.f) : 0.f;
             rs += rr[a];
           }
           const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
@@ -712,10 +770,10 @@ __global__ __launch_bounds__(STB * STW) void k_rm_st(TpParams P, float* __restri
             if (a < n) xL[(f + a) * STB + lane] = xp * (rs > 0.f ? rr[a] * inv : uni);
         } else {
           float rs = 0.f;
-          for (int a = 0; a < n; ++a) rs += RL[(f + a) * STB + lane];
+          for (int a = 0; a < n; ++a) rs += fmaxf(RL[(f + a) * STB + lane], 0.f);
           const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
           for (int a = 0; a < n; ++a)
-            xL[(f + a) * STB + lane] = xp * (rs > 0.f ? RL[(f + a) * STB + lane] * inv : uni);
+            xL[(f + a) * STB + lane] = xp * (rs > 0.f ? fmaxf(RL[(f + a) * STB + lane], 0.f) * inv : uni);
         }
       }
     }
@@ -835,6 +893,9 @@ __global__ void k_fill_f64(double* p, int64_t n, double v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
+}
+__global__ void k_fill_i32(int* p, int n, int v) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
 __global__ void k_nonfinite(const double* p, int n, int* flag) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -969,7 +1030,7 @@ struct DBuf {
 
 struct DevDir {
   DBuf<MvItem> items;
-  DBuf<int32_t> blk;
+  DBuf<int32_t> blk, blk_inst;
   DBuf<MvCtx> ctx;
   DBuf<QueryRec16> q;
   DBuf<int16_t> rank, seg;
@@ -1015,6 +1076,9 @@ struct Game {
   double wsum = 0.0;
   int mv_block = 256;
   DBuf<double> tdev;                // iteration index of the next step (device)
+  DBuf<int32_t> active;             // per-instance: 1 = iterated by solver_step
+  int dcfr = 0, gamma = 1;          // solver rule (see solver_set_params)
+  double alpha = 1.5, beta = 0.0;
   // warm start: per player infoset segments, their blocks, features
   DBuf<WarmSeg> wseg[2];
   DBuf<int2> wblk[2];
@@ -1075,7 +1139,8 @@ static int upload_dir(Game* g, int d) {
       }
     }
     DevDir& E = g->dd[d];
-    if ((rc = E.items.upload(D.items)) || (rc = E.blk.upload(D.blk)) || (rc = E.ctx.upload(D.ctx)) ||
+    if ((rc = E.items.upload(D.items)) || (rc = E.blk.upload(D.blk)) || (rc = E.blk_inst.upload(D.blk_inst)) ||
+        (rc = E.ctx.upload(D.ctx)) ||
         (rc = E.q.upload(D.q)) || (rc = E.rank.upload(D.rank)) || (rc = E.seg.upload(D.seg)) ||
         (rc = E.segend.upload(D.segend)))
       return rc;
@@ -1194,6 +1259,7 @@ static int upload_game(Game* g) {
   }
   if ((rc = g->br_inst.alloc(2 * hg.inst.size()))) return rc;
   if ((rc = g->tdev.alloc(1))) return rc;
+  if ((rc = g->active.upload(std::vector<int32_t>(hg.inst.size(), 1)))) return rc;
   for (int p = 0; p < 2; ++p) {
     std::vector<WarmSeg> segs;
     std::vector<int2> blks;
@@ -1253,6 +1319,8 @@ static MvParams mv_params(Game* g, int d, double scale) {
   P.lamf = g->lamf.p;
   P.scale = scale;
   P.dir = d;
+  P.blk_inst = E.blk_inst.p;
+  P.active = nullptr;
   P.nblk = E.nblk;
   P.max_ent = E.max_ent;
   P.max_n = E.max_n;
@@ -1264,7 +1332,8 @@ template <int BLOCK, typename IO>
 static size_t mv_lds(const MvParams& a, const MvParams& b) {
   size_t me = pd(std::max(a.max_ent, b.max_ent)) + 1, mn = pd(std::max(a.max_n, b.max_n)) + 1,
          ms = std::max(a.max_seg, b.max_seg);
-  return sizeof(double) * (me + ms + 3 * (BLOCK / 64)) + 2 * mn * sizeof(IO) + sizeof(int) * ms;
+  const size_t bufs = sizeof(IO) == 4 ? 2 : 1;
+  return sizeof(double) * (me + ms + 6 * (BLOCK / 64)) + 2 * bufs * mn * sizeof(IO) + sizeof(int) * ms;
 }
 
 template <int KH, int KE, typename IO>
@@ -1336,6 +1405,21 @@ static TpParams tp_params(Game* g, int p, const int2* blocks) {
   P.pulls = E.pulls.p;
   P.blocks = blocks;
   P.stage_stride = E.stage_stride;
+  P.active = nullptr;
+  P.dcfr = 0;
+  P.gamma = 1;
+  P.alpha = 1.f;
+  P.beta = 1.f;
+  return P;
+}
+
+static TpParams tp_active(Game* g, int p, const int2* blocks) {
+  TpParams P = tp_params(g, p, blocks);
+  P.active = g->active.p;
+  P.dcfr = g->dcfr;
+  P.gamma = g->gamma;
+  P.alpha = (float)g->alpha;
+  P.beta = (float)g->beta;
   return P;
 }
 
@@ -1345,27 +1429,27 @@ static int rm_update(Game* g, int p, hipStream_t s) {
   const double* td = g->tdev.p;
   if (E.n_single_st)
     hipLaunchKernelGGL(k_rm_st<0>, dim3(E.n_single_st), dim3(STB * STW), E.st_lds[0], s,
-                       tp_params(g, p, E.b_single_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
+                       tp_active(g, p, E.b_single_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
                        E.stage.p, td, E.st_ninf[0]);
   if (E.n_single_gl)
-    hipLaunchKernelGGL(k_rm<0>, dim3(E.n_single_gl), dim3(TPB), 0, s, tp_params(g, p, E.b_single_gl.p),
+    hipLaunchKernelGGL(k_rm<0>, dim3(E.n_single_gl), dim3(TPB), 0, s, tp_active(g, p, E.b_single_gl.p),
                        gr, g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
   if (E.n_deep_st)
     hipLaunchKernelGGL(k_rm_st<1>, dim3(E.n_deep_st), dim3(STB * STW), E.st_lds[1], s,
-                       tp_params(g, p, E.b_deep_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
+                       tp_active(g, p, E.b_deep_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
                        E.stage.p, td, E.st_ninf[1]);
   if (E.n_deep_gl)
-    hipLaunchKernelGGL(k_rm<1>, dim3(E.n_deep_gl), dim3(TPB), 0, s, tp_params(g, p, E.b_deep_gl.p),
+    hipLaunchKernelGGL(k_rm<1>, dim3(E.n_deep_gl), dim3(TPB), 0, s, tp_active(g, p, E.b_deep_gl.p),
                        gr, g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
   if (E.n_top)
-    hipLaunchKernelGGL(k_rm<2>, dim3(E.n_top), dim3(TPB), 0, s, tp_params(g, p, E.b_top.p), gr,
+    hipLaunchKernelGGL(k_rm<2>, dim3(E.n_top), dim3(TPB), 0, s, tp_active(g, p, E.b_top.p), gr,
                        g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
   if (E.n_deep_st)
     hipLaunchKernelGGL(k_rm_st<3>, dim3(E.n_deep_st), dim3(STB * STW), E.st_lds[1], s,
-                       tp_params(g, p, E.b_deep_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
+                       tp_active(g, p, E.b_deep_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
                        E.stage.p, td, E.st_ninf[1]);
   if (E.n_deep_gl)
-    hipLaunchKernelGGL(k_rm<3>, dim3(E.n_deep_gl), dim3(TPB), 0, s, tp_params(g, p, E.b_deep_gl.p),
+    hipLaunchKernelGGL(k_rm<3>, dim3(E.n_deep_gl), dim3(TPB), 0, s, tp_active(g, p, E.b_deep_gl.p),
                        gr, g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
   HIP_TRY(hipGetLastError());
   return PMX_OK;
@@ -1631,9 +1715,23 @@ int solver_reset(Game* g, void* stream) {
     if ((rc = uniform_plan(g, p, s))) return rc;
   }
   hipLaunchKernelGGL(k_set1, dim3(1), dim3(1), 0, s, g->tdev.p, 0.0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, g->active.p, (int)g->hg.inst.size(), 1);
   HIP_TRY(hipGetLastError());
   g->t = 0;
   g->wsum = 0.0;
+  return PMX_OK;
+}
+
+int solver_set_active(Game* g, const int32_t* active_host, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!active_host) return fail(PMX_EINVAL, "null argument");
+  const size_t n = g->hg.inst.size();
+  std::vector<int32_t> a(active_host, active_host + n);
+  for (auto& v : a) v = v ? 1 : 0;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(g->active.p, a.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
   return PMX_OK;
 }
 
@@ -1644,6 +1742,7 @@ int solver_reset(Game* g, void* stream) {
 static int enqueue_iteration(Game* g, hipStream_t s) {
   int rc;
   MvParams PA = mv_params(g, 0, 1.0), PT = mv_params(g, 1, -1.0);
+  PA.active = PT.active = g->active.p;
   if ((rc = launch_mv<float>(g, PA, g->x[1].p, g->grad[0].p, empty_params(PA), nullptr, nullptr, s,
                              g->tdev.p)))
     return rc;
@@ -1697,7 +1796,30 @@ int solver_step(Game* g, int32_t n_iters, void* stream) {
     if ((rc = enqueue_iteration(g, s))) return rc;
   for (int i = 0; i < n_iters; ++i) {
     g->t += 1;
-    g->wsum += (double)g->t;
+    const double t = (double)g->t;
+    g->wsum += g->gamma == 1 ? t : (g->gamma == 2 ? t * t : t * t * t);
+  }
+  return PMX_OK;
+}
+
+int solver_set_params(Game* g, int32_t kind, double alpha, double beta, int32_t gamma) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (kind != 0 && kind != 1) return fail(PMX_EINVAL, "kind must be 0 (RM+) or 1 (DCFR)");
+  if (kind == 1 && (gamma < 1 || gamma > 3 || !std::isfinite(alpha) || !std::isfinite(beta)))
+    return fail(PMX_EINVAL, "DCFR needs finite alpha, beta and gamma in {1, 2, 3}");
+  HIP_TRY(hipDeviceSynchronize());
+  g->dcfr = kind;
+  g->gamma = kind == 1 ? gamma : 1;
+  g->alpha = alpha;
+  g->beta = beta;
+  if (g->graph_exec) {
+    (void)hipGraphExecDestroy(g->graph_exec);
+    g->graph_exec = nullptr;
+  }
+  if (g->graph) {
+    (void)hipGraphDestroy(g->graph);
+    g->graph = nullptr;
   }
   return PMX_OK;
 }

@@ -142,6 +142,7 @@ struct MvDir {                          // host copy of one direction's plan
   std::vector<MvCtx> ctx;
   std::vector<MvItem> items;
   std::vector<int32_t> blk;             // item ranges: blk[b] .. blk[b+1]
+  std::vector<int32_t> blk_inst;        // instance of each chunk
   std::vector<QueryRec16> q;
   std::vector<int16_t> rank, seg;
   std::vector<int32_t> segend;

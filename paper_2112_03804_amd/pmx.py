@@ -78,7 +78,7 @@ EXPORTS = [
     "set_initial_strategy", "pmx_last_error", "game_tune", "game_get_tuning",
     "warm_num_rows", "warm_features", "warm_targets", "warm_apply",
     "mlp_gemm_bf16", "mlp_softmax_xent", "mlp_colsum", "mlp_adam", "mlp_gather_bf16",
-    "mlp_gather_f32", "mlp_cast_bf16",
+    "mlp_gather_f32", "mlp_cast_bf16", "solver_set_active", "solver_set_params",
 ]
 
 
@@ -106,6 +106,8 @@ def lib():
     L.matvec_pair.argtypes = [vp, vp, vp, vp, vp, vp]
     L.solver_reset.argtypes = [vp, vp]
     L.solver_step.argtypes = [vp, ctypes.c_int32, vp]
+    L.solver_set_active.argtypes = [vp, _c_i32p, vp]
+    L.solver_set_params.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32]
     L.saddle_gap.argtypes = [vp, _c_f64p, _c_f64p, _c_f64p, vp]
     L.saddle_gap_of.argtypes = [vp, vp, vp, _c_f64p, _c_f64p, _c_f64p, vp]
     L.solver_get_state.argtypes = [vp, ctypes.c_int32, _c_f32p, _c_f32p, _c_f64p, _c_i32p, _c_f64p]
@@ -325,6 +327,16 @@ class Game:
 
     def solver_step(self, n_iters: int, stream=None):
         _check(lib().solver_step(self._h, int(n_iters), _stream(stream)))
+
+    def solver_set_params(self, kind: str = "rm+", alpha: float = 1.5, beta: float = 0.0, gamma: int = 2):
+        k = {"rm+": 0, "dcfr": 1}[kind]
+        _check(lib().solver_set_params(self._h, k, float(alpha), float(beta), int(gamma)))
+
+    def solver_set_active(self, active, stream=None):
+        a = np.ascontiguousarray(active, dtype=np.int32)
+        if a.shape != (self.n_instances,):
+            raise ValueError("one flag per instance")
+        _check(lib().solver_set_active(self._h, _ptr(a, ctypes.c_int32), _stream(stream)))
 
     def saddle_gap(self, stream=None):
         n = self.n_instances

@@ -225,9 +225,11 @@ def apply_prior(game, mlp: WarmMLP, regret_scale: float, avg_weight: float):
     return logits
 
 
-def solve_to_gap(game, target_rel: float, check_every: int = 32, max_iters: int = 100000):
-    """Iterate until every instance's gap <= target_rel * its pot; returns
-    (seconds, iterations, per-instance first iteration at target)."""
+def solve_to_gap(game, target_rel: float, check_every: int = 32, max_iters: int = 100000,
+                 retire: bool = True):
+    """Iterate until every instance's gap <= target_rel * its pot, retiring
+    instances (``solver_set_active``) as they reach it; returns (seconds,
+    iterations, per-instance first iteration at target)."""
     torch = _torch()
     pots = np.array([2 * d.contrib for d in game.descs])
     done = np.full(game.n_instances, -1)
@@ -236,10 +238,14 @@ def solve_to_gap(game, target_rel: float, check_every: int = 32, max_iters: int 
     it = 0
     gap = game.saddle_gap()[0]
     done[gap <= target_rel * pots] = 0
+    if retire:
+        game.solver_set_active(done < 0)
     while (done < 0).any() and it < max_iters:
         game.solver_step(check_every)
         it += check_every
         gap = game.saddle_gap()[0]
         newly = (gap <= target_rel * pots) & (done < 0)
         done[newly] = it
+        if retire and newly.any():
+            game.solver_set_active(done < 0)
     return time.perf_counter() - t0, it, done

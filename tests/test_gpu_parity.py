@@ -390,3 +390,83 @@ def test_matvec_schedules_agree(kernel, rows):
     gap = g.saddle_gap()[0]
     assert np.all(gap >= 0)
     g.close()
+
+
+def test_retired_instances_stay_frozen():
+    pmx = _need_gpu()
+    descs = [I.river_config(seed=900 + i, n_keep=(120, 140), bet_fracs=(0.5, 1.0), max_raises=2,
+                            pot=40.0, stack=120.0) for i in range(3)]
+    _say("retirement")
+    g = pmx.Game(descs)
+    g.solver_step(40)
+    before = [g.unpack(p, g.solver_get_state(p)["avg_sum"]) for p in range(2)]
+    gap0 = g.saddle_gap()[0]
+    g.solver_set_active([1, 0, 1])
+    g.solver_step(40)
+    after = [g.unpack(p, g.solver_get_state(p)["avg_sum"]) for p in range(2)]
+    for p in range(2):
+        assert np.array_equal(before[p][1], after[p][1])
+        assert not np.array_equal(before[p][0], after[p][0])
+        assert not np.array_equal(before[p][2], after[p][2])
+    g.solver_reset()
+    g.solver_step(8)
+    assert all(np.abs(a).sum() > 0 for a in g.unpack(0, g.solver_get_state(0)["avg_sum"]))
+    assert gap0.shape == (3,)
+    g.close()
+
+
+@pytest.mark.parametrize("name,fn", [SMALL[2], SMALL[6], ("river", lambda: I.config(1))])
+def test_dcfr_single_step_from_given_state(name, fn):
+    pmx = _need_gpu()
+    d = fn()
+    _say("DCFR step parity", name)
+    o = payoff.Game(d)
+    g = pmx.Game(d)
+    g.solver_set_params("dcfr", alpha=1.5, beta=0.0, gamma=2)
+    rng = np.random.default_rng(13)
+    ref = solver.RMPlus(o, kind="dcfr", alpha=1.5, beta=0.0, gamma=2)
+    t0, w0 = 7, 140.0
+    for p in range(2):
+        R = ((rng.random((o.S[p], o.N[p])) - 0.3) * 3.0).astype(np.float32).astype(np.float64)
+        x = ref.tp[p].realization(ref.tp[p].behaviour_from_regret(R)).astype(np.float32).astype(np.float64)
+        s = rng.random((o.S[p], o.N[p]))
+        ref.R[p], ref.x[p], ref.sum[p] = R, x, s.copy()
+        g.solver_set_state(p, regret=g.pack(p, [R]), plan=g.pack(p, [x]),
+                           avg_sum=g.pack(p, [s], np.float64), t=t0, wsum=w0)
+    ref.t, ref.wsum = t0, w0
+    g.solver_step(1)
+    torch.cuda.synchronize()
+    ref.step()
+    for p in range(2):
+        st = g.solver_get_state(p)
+        R = g.unpack(p, st["regret"])[0]
+        x = g.unpack(p, st["plan"])[0]
+        s = g.unpack(p, st["avg_sum"])[0]
+        scale = max(1.0, np.abs(ref.R[p]).max())
+        assert np.abs(R - ref.R[p]).max() <= 1e-5 * scale, p
+        assert np.abs(x - ref.x[p]).max() <= 1e-5, p
+        assert np.abs(s - ref.sum[p]).max() <= 1e-6 * max(1.0, np.abs(ref.sum[p]).max()), p
+        assert st["wsum"] == w0 + (t0 + 1) ** 2
+    g.close()
+
+
+def test_dcfr_solve_river_certified():
+    pmx = _need_gpu()
+    d = I.config(1)
+    _say("DCFR solve river")
+    o = payoff.Game(d)
+    g = pmx.Game(d)
+    g.solver_set_params("dcfr")
+    pot = 2 * d.contrib
+    gap = np.inf
+    for _ in range(100):
+        g.solver_step(64)
+        gap = g.saddle_gap()[0][0]
+        if gap <= 1e-4 * pot:
+            break
+    assert gap <= 1e-4 * pot
+    x = g.unpack(0, g.get_average_strategy(0))[0]
+    y = g.unpack(1, g.get_average_strategy(1))[0]
+    rgap, _, _ = solver.saddle_gap(o, x, y)
+    assert abs(rgap - gap) <= 1e-9 * pot
+    g.close()

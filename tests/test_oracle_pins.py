@@ -313,3 +313,31 @@ def test_single_entries_match_matrix_free_product():
         assert abs(g.entry_A(y, s, h) - Ay[s, h]) < 1e-12
         s, h = rng.integers(g.S[1]), rng.integers(g.N[1])
         assert abs(g.entry_AT(x, s, h) - ATx[s, h]) < 1e-12
+
+
+def test_dcfr_reaches_lp_value_and_beats_rmplus_on_tiny():
+    """Discounted CFR (alpha 1.5, beta 0, gamma 2) converges to the LP value."""
+    g = payoff.Game(I.tiny_config())
+    v, _ = solver.lp_value(g)
+    s = solver.RMPlus(g, kind="dcfr")
+    for _ in range(2000):
+        s.step()
+    gap, br1, br2 = s.gap()
+    assert gap >= -1e-12 and br2 - 1e-9 <= v <= br1 + 1e-9
+    assert gap < 1e-4 * g.pot
+
+
+def test_dcfr_single_update_closed_form():
+    """Regrets (2, -2) at t = 1 discount to (1, -1) (factors 1/2 each), then
+    the instantaneous regrets of values (1, 3) under strategy (1, 0) add
+    (0, 2): (1, 1)."""
+    g = payoff.Game(I.kuhn())
+    tp = solver.Treeplex(g, 0)
+    tp.N = 1
+    f = tp.inf[tp.roots[0]][1]
+    gvec = np.zeros((g.S[0], 1))
+    gvec[f, 0], gvec[f + 1, 0] = 1.0, 3.0
+    R = np.zeros((g.S[0], 1))
+    R[f, 0], R[f + 1, 0] = 2.0, -2.0
+    Rn = tp.dcfr_update(R, gvec, 1.0, 1.5, 0.0)
+    assert Rn[f, 0] == 1.0 and Rn[f + 1, 0] == 1.0
