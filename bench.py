@@ -287,6 +287,28 @@ def pmc_probe(args):
         g.close()
 
 
+def trace_probe(args):
+    """Launches for a kernel trace of the solver iteration on the batch and on
+    the turn + river game: each at its tuned schedule, a few graph-captured
+    iterations after a warm-up."""
+    import torch
+    from paper_2112_03804_amd import instances as I
+    from paper_2112_03804_amd import pmx
+    for name, make, sched, iters in (("batch", lambda: pmx.Game(I.batched_configs(args.batch)), (0, 8), 64),
+                                     ("turn_river", lambda: pmx.Game(I.config(2)), (0, 8), 32)):
+        g = make()
+        g.game_tune(*sched)
+        g.solver_reset()
+        g.solver_step(32)
+        torch.cuda.synchronize()
+        g.solver_step(iters)
+        torch.cuda.synchronize()
+        g.saddle_gap()
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": name, "iterations": 32 + iters}), flush=True)
+        g.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +324,8 @@ def main():
     ap.add_argument("--no-turn", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run the launches profiled for HBM traffic counters")
+    ap.add_argument("--trace-probe", action="store_true",
+                    help="only run solver iterations on the batch and the turn + river game")
     ap.add_argument("--turn-steps", type=int, default=20)
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--warm-train", type=int, default=1024)
@@ -323,6 +347,9 @@ def main():
 
     if args.pmc_probe:
         pmc_probe(args)
+        return
+    if args.trace_probe:
+        trace_probe(args)
         return
     desc = I.config(1)
     pot = 2 * desc.contrib

@@ -213,6 +213,15 @@ int game_hand_meta(const Game* g, int32_t instance, int32_t ctx, int32_t player,
 int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk);
 int game_get_tuning(const Game* g, int32_t* kernel, int32_t* rows_per_chunk);
 
+/* Regret-update schedule: each player's treeplex is cut into pieces of at
+ * most `rows` sequences (default and maximum 64) whose rows stay in LDS for
+ * 64 hands at a time; pieces hanging below other pieces exchange root values
+ * and parent weights through a stage buffer.  Results do not depend on the
+ * cut (same arithmetic per infoset).  PMX_EINVAL if rows is outside [1, 64]
+ * or below the largest action count of an infoset (the previous cut stays).
+ * Synchronizes the device; drops the captured solver graph. */
+int solver_set_task_rows(Game* g, int32_t rows);
+
 /* ---- gradients (Section 2 app. 3; Prop. 1; eq. cf; Technique B) ----------- */
 
 /* out = A y (Player 1's gradient).  y: player 1's vectors (all instances),

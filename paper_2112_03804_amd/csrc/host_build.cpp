@@ -727,6 +727,187 @@ void classify_chunks(MvDir& D) {
   }
 }
 
+// Cut one player's treeplex of every instance into regret-update pieces of
+// at most `cap` rows.  Repeatedly: take the maximal infoset subtrees of the
+// remaining treeplex that have at most `cap` rows, pack consecutive ones
+// (depth-first order) into pieces, and remove them; once what remains fits,
+// it becomes the last piece.  Pieces made earlier hang below pieces made
+// later, so the bottom-up pass runs them in creation order and the top-down
+// pass in reverse; `depth` groups pieces that can run in one launch.
+int build_rm_plan(HostGame& hg, int p, int cap, std::string& msg) {
+  RmPlan& P = hg.rm[p];
+  P = RmPlan();
+  if (cap < 1 || cap > kTaskRowsMax) {
+    msg = "task_rows must be in [1, " + std::to_string(kTaskRowsMax) + "]";
+    return PMX_EINVAL;
+  }
+  std::vector<int32_t> depth_of;        // per task
+  for (size_t ii = 0; ii < hg.inst.size(); ++ii) {
+    const Built& b = hg.inst[ii];
+    const std::vector<Infoset>& inf = b.sf.inf[p];
+    const int ni = (int)inf.size(), S = b.sf.n_seq[p];
+    P.stage_stride = std::max(P.stage_stride, b.stride[p]);
+    std::vector<int> owner(S, -1);
+    for (int i = 0; i < ni; ++i) {
+      if (inf[i].nact > cap) {
+        msg = "an infoset has more actions than task_rows";
+        return PMX_EINVAL;
+      }
+      for (int a = 0; a < inf[i].nact; ++a) owner[inf[i].first + a] = i;
+    }
+    std::vector<std::vector<int>> kids(S);   // child infosets of each sequence
+    for (int i = 0; i < ni; ++i)
+      if (inf[i].parent >= 0) kids[inf[i].parent].push_back(i);
+    std::vector<char> alive(ni, 1);
+    std::vector<int> rows(ni, 0);
+    std::vector<std::vector<int32_t>> pending(S);   // stage rows waiting for the piece holding seq
+    const int first_task = (int)P.tasks.size();
+    auto count_rows = [&]() {
+      int64_t total = 0;
+      for (int i = ni - 1; i >= 0; --i) {
+        if (!alive[i]) continue;
+        int r = inf[i].nact;
+        for (int a = 0; a < inf[i].nact; ++a)
+          for (int j : kids[inf[i].first + a])
+            if (alive[j]) r += rows[j];
+        rows[i] = r;
+        if (inf[i].parent < 0) total += r;
+      }
+      return total;
+    };
+    // emit one piece from a list of infosets (depth-first order)
+    auto emit = [&](std::vector<int>& members) {
+      std::sort(members.begin(), members.end());
+      RmTask t{};
+      t.vec_base = b.vec_off[p];
+      t.stride = b.stride[p];
+      t.n_hands = b.inst.n[p];
+      t.inst = (int32_t)ii;
+      t.depth = 0;
+      std::vector<int32_t> seqs;
+      for (int i : members)
+        for (int a = 0; a < inf[i].nact; ++a) seqs.push_back(inf[i].first + a);
+      std::sort(seqs.begin(), seqs.end());
+      auto local = [&](int s) {
+        auto it = std::lower_bound(seqs.begin(), seqs.end(), s);
+        return (it != seqs.end() && *it == s) ? (int)(it - seqs.begin()) : -1;
+      };
+      t.rows_off = (int32_t)P.rows.size();
+      t.n_rows = (int32_t)seqs.size();
+      P.rows.insert(P.rows.end(), seqs.begin(), seqs.end());
+      std::vector<int32_t> ext;
+      t.inf_off = (int32_t)P.infs.size();
+      t.n_inf = (int32_t)members.size();
+      for (int i : members) {
+        int par;
+        if (inf[i].parent < 0) {
+          par = -1;
+        } else if (local(inf[i].parent) >= 0) {
+          par = local(inf[i].parent);
+        } else {
+          auto it = std::find(ext.begin(), ext.end(), inf[i].parent);
+          int k = (int)(it - ext.begin());
+          if (it == ext.end()) ext.push_back(inf[i].parent);
+          par = -2 - k;
+        }
+        const int f = local(inf[i].first);
+        P.infs.push_back((int32_t)((uint32_t)f | ((uint32_t)inf[i].nact << 8) | ((uint32_t)(uint16_t)(int16_t)par << 16)));
+      }
+      t.ext_off = (int32_t)P.ext_seq.size();
+      t.n_ext = (int32_t)ext.size();
+      for (int e : ext) {
+        P.ext_seq.push_back(e);
+        P.ext_slot.push_back(P.n_slot);
+        pending[e].push_back(P.n_slot);
+        ++P.n_slot;
+      }
+      t.pull_off = (int32_t)P.pulls.size();
+      for (int r = 0; r < (int)seqs.size(); ++r) {
+        for (int32_t slot : pending[seqs[r]]) P.pulls.push_back((int32_t)((uint32_t)r | ((uint32_t)slot << 8)));
+        pending[seqs[r]].clear();
+      }
+      t.n_pull = (int32_t)P.pulls.size() - t.pull_off;
+      for (int i : members) alive[i] = 0;
+      P.tasks.push_back(t);
+    };
+    int64_t total = count_rows();
+    while (total > cap) {
+      // maximal subtrees that fit, in depth-first order
+      std::vector<int> roots;
+      for (int i = 0; i < ni; ++i) {
+        if (!alive[i] || rows[i] > cap) continue;
+        const int par = inf[i].parent;
+        if (par < 0 || rows[owner[par]] > cap) roots.push_back(i);
+      }
+      if (roots.empty()) {
+        msg = "treeplex cannot be cut into pieces of task_rows";
+        return PMX_EINVAL;
+      }
+      std::vector<int> members, exts;
+      int r_sum = 0;
+      auto collect = [&](int root, std::vector<int>& out) {
+        std::vector<int> st{root};
+        while (!st.empty()) {
+          int i = st.back();
+          st.pop_back();
+          out.push_back(i);
+          for (int a = 0; a < inf[i].nact; ++a)
+            for (int j : kids[inf[i].first + a])
+              if (alive[j]) st.push_back(j);
+        }
+      };
+      for (int i : roots) {
+        const int par = inf[i].parent;
+        const bool new_ext = par >= 0 && std::find(exts.begin(), exts.end(), par) == exts.end();
+        if (!members.empty() && (r_sum + rows[i] > cap || (new_ext && (int)exts.size() >= kTaskExtMax))) {
+          emit(members);
+          members.clear();
+          exts.clear();
+          r_sum = 0;
+        }
+        collect(i, members);
+        r_sum += rows[i];
+        if (par >= 0 && std::find(exts.begin(), exts.end(), par) == exts.end()) exts.push_back(par);
+      }
+      if (!members.empty()) emit(members);
+      total = count_rows();
+    }
+    if (total > 0) {
+      std::vector<int> members;
+      for (int i = 0; i < ni; ++i)
+        if (alive[i]) members.push_back(i);
+      emit(members);
+    }
+    // depth: pieces with no external parent run in the fused launch (0);
+    // the others sit one below the deepest piece holding a parent sequence
+    std::vector<int> task_of_seq(S, -1);
+    for (int t = first_task; t < (int)P.tasks.size(); ++t)
+      for (int r = 0; r < P.tasks[t].n_rows; ++r) task_of_seq[P.rows[P.tasks[t].rows_off + r]] = t;
+    for (int t = (int)P.tasks.size() - 1; t >= first_task; --t) {
+      RmTask& T = P.tasks[t];
+      int d = 0;
+      for (int k = 0; k < T.n_ext; ++k) d = std::max(d, 1 + P.tasks[task_of_seq[P.ext_seq[T.ext_off + k]]].depth);
+      T.depth = d;
+    }
+    for (int s = 0; s < S; ++s)
+      if (!pending[s].empty()) {
+        msg = "internal: a stage row has no receiving piece";
+        return PMX_EINVAL;
+      }
+  }
+  int max_depth = 0;
+  for (const RmTask& t : P.tasks) max_depth = std::max(max_depth, (int)t.depth);
+  P.by_depth.assign(max_depth + 1, {});
+  for (int t = 0; t < (int)P.tasks.size(); ++t) {
+    const RmTask& T = P.tasks[t];
+    P.by_depth[T.depth].push_back(t);
+    const int k = T.depth == 0 ? 0 : 1;
+    P.max_rows[k] = std::max(P.max_rows[k], (int)T.n_rows);
+    P.max_ext[k] = std::max(P.max_ext[k], (int)T.n_ext);
+  }
+  return PMX_OK;
+}
+
 namespace {
 
 void build_treeplex_plan(HostGame& hg, int p) {
@@ -879,6 +1060,10 @@ int build_game(const GameDesc* descs, int n, HostGame& hg, std::string& msg) {
     classify_chunks(hg.dir[d]);
   }
   for (int p = 0; p < 2; ++p) build_treeplex_plan(hg, p);
+  for (int p = 0; p < 2; ++p) {
+    int rc = build_rm_plan(hg, p, hg.task_rows, msg);
+    if (rc) return rc;
+  }
   return PMX_OK;
 }
 

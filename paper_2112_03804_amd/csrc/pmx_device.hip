@@ -15,8 +15,10 @@
 //                 All prefix sums come from one segmented scan over LDS with
 //                 FP64 accumulation (FP64 adds issue at the unpacked FP32
 //                 rate on CDNA4, so this costs less than compensated FP32).
-//   k_rm_*        regret matching+ on a treeplex, one thread per hand (the
-//                 paper's GPU solver updates all hands in parallel).
+//   k_rmp         regret matching+ (or discounted CFR) on pieces of a
+//                 treeplex of at most 64 sequences, one lane per hand (the
+//                 paper's GPU solver updates all hands in parallel), the
+//                 piece's rows resident in LDS during the walk.
 //   k_br_*        FP64 best responses (bottom-up max / min) and the gap.
 #include <hip/hip_runtime.h>
 
@@ -542,19 +544,22 @@ struct RmStep {
   float dp, dn;              // factors for positive / other regrets
   bool floor;                // RM+: clip regrets at 0
 };
-__device__ inline RmStep rm_step(const TpParams& P, double t) {
+__device__ inline RmStep rm_step(int dcfr, int gamma, float alpha, float beta, double t) {
   RmStep r;
-  r.w = P.gamma == 1 ? t : (P.gamma == 2 ? t * t : t * t * t);
+  r.w = gamma == 1 ? t : (gamma == 2 ? t * t : t * t * t);
   r.dp = 1.f;
   r.dn = 1.f;
-  r.floor = !P.dcfr;
-  if (P.dcfr) {
+  r.floor = !dcfr;
+  if (dcfr) {
     const float tf = (float)t;
-    const float ta = powf(tf, P.alpha), tb = powf(tf, P.beta);
+    const float ta = powf(tf, alpha), tb = powf(tf, beta);
     r.dp = ta / (ta + 1.f);
     r.dn = tb / (tb + 1.f);
   }
   return r;
+}
+__device__ inline RmStep rm_step(const TpParams& P, double t) {
+  return rm_step(P.dcfr, P.gamma, P.alpha, P.beta, t);
 }
 __device__ inline float rm_new(float r, float inst, const RmStep& k) {
   const float v = r * (r > 0.f ? k.dp : k.dn) + inst;
@@ -563,232 +568,244 @@ __device__ inline float rm_new(float r, float inst, const RmStep& k) {
 
 constexpr int TPB = 128;
 
-// Regret-matching+ regret update of one infoset for one hand; returns V(I).
-__device__ inline float rm_infoset(float* __restrict__ g, float* __restrict__ R, int64_t base,
-                                   int64_t stride, int f, int n, const RmStep& k) {
+constexpr int MAXA = 8;       // actions handled in registers by the walks
+
+__global__ void k_set1(double* tdev, double v) { tdev[0] = v; }
+
+// ---------------------------------------------------------------------------
+// regret update on treeplex pieces (RmTask): the piece's rows of g, R and x
+// for 64 hands live in LDS; every wavefront of the block loads and stores a
+// quarter of the rows (all loads in flight at once), wavefront 0 walks the
+// piece's infosets.  Row, infoset, pull and external-parent tables are held
+// one entry per lane and read with readlane, so the walk touches LDS only
+// for the slab itself.
+// ---------------------------------------------------------------------------
+struct RmParams {
+  const RmTask* tasks;
+  const int2* blocks;           // (task, first hand)
+  const int32_t* rows;
+  const int32_t* infs;
+  const int32_t* pulls;
+  const int32_t* ext_seq;
+  const int32_t* ext_slot;
+  const int32_t* active;        // per-instance flag (NULL: all)
+  int32_t stage_stride;
+  int32_t max_rows, max_ext;    // LDS layout of the launch
+  int32_t dcfr, gamma;
+  float alpha, beta;
+};
+constexpr int RMW = 4;                      // wavefronts per block
+constexpr int RMR = kTaskRowsMax / RMW;     // rows loaded per wavefront
+
+__device__ inline int rl(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
+
+// Bottom-up step of one infoset with N actions for one hand (LDS rows, 64
+// lanes apart): V(I) from the current behaviour, the regret update from
+// q = A (g plus the values below), and V added into the parent's slot `pp`
+// (a row of Al, an external-root accumulator, or a sink row for roots).  All LDS reads of
+// the step, the parent's included, issue together; the action count is a
+// template constant so the step has no branch per action.
+template <int N>
+__device__ inline void rmp_up_n(float* __restrict__ Al, float* __restrict__ Rl, float* pp, int f, int lane,
+                                const RmStep& K) {
+  float rr[N], gg[N];
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    rr[a] = Rl[(f + a) * 64 + lane];
+    gg[a] = Al[(f + a) * 64 + lane];
+  }
+  const float pv = *pp;
+  float rs = 0.f, dot = 0.f, gs = 0.f;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    const float r = fmaxf(rr[a], 0.f);
+    rs += r;
+    dot += r * gg[a];
+    gs += gg[a];
+  }
+  const float V = rs > 0.f ? dot / rs : gs * (1.f / (float)N);
+#pragma unroll
+  for (int a = 0; a < N; ++a) Rl[(f + a) * 64 + lane] = rm_new(rr[a], gg[a] - V, K);
+  *pp = pv + V;
+}
+
+// Top-down step: the new behaviour from the regrets times the parent's
+// realization weight *xpp (a row holding 1 for roots), into the rows of Al.
+template <int N>
+__device__ inline void rmp_down_n(float* __restrict__ Al, const float* __restrict__ Rl, const float* xpp,
+                                  int f, int lane) {
+  float rr[N];
+#pragma unroll
+  for (int a = 0; a < N; ++a) rr[a] = fmaxf(Rl[(f + a) * 64 + lane], 0.f);
+  const float xp = *xpp;
   float rs = 0.f;
-  for (int a = 0; a < n; ++a) rs += fmaxf(R[base + (f + a) * stride], 0.f);
-  float V = 0.f;
-  const float inv = rs > 0.f ? 1.f / rs : 0.f;
-  const float uni = 1.f / (float)n;
-  for (int a = 0; a < n; ++a) {
-    float ba = rs > 0.f ? fmaxf(R[base + (f + a) * stride], 0.f) * inv : uni;
-    V += ba * g[base + (f + a) * stride];
-  }
-  for (int a = 0; a < n; ++a) {
-    int64_t i = base + (f + a) * stride;
-    R[i] = rm_new(R[i], g[i] - V, k);
-  }
-  return V;
+#pragma unroll
+  for (int a = 0; a < N; ++a) rs += rr[a];
+  const float inv = rs > 0.f ? xp / rs : 0.f, uni = xp * (1.f / (float)N);
+#pragma unroll
+  for (int a = 0; a < N; ++a) Al[(f + a) * 64 + lane] = rs > 0.f ? rr[a] * inv : uni;
 }
 
-// New behavioural strategy from regrets, realization plan, and the averaging
-// of the previous plan (weight t).
-__device__ inline void rm_descend(const float* __restrict__ R, float* __restrict__ x,
-                                  double* __restrict__ xs, int64_t base, int64_t stride, int f,
-                                  int n, int par, double t) {
-  const float xp = par >= 0 ? x[base + (int64_t)par * stride] : 1.f;
+// Any action count (beyond the specialized ones).
+__device__ inline void rmp_up_any(float* __restrict__ Al, float* __restrict__ Rl, float* pp, int f, int n,
+                                  int lane, const RmStep& K) {
+  float rs = 0.f, dot = 0.f, gs = 0.f;
+  for (int a = 0; a < n; ++a) {
+    const float r = fmaxf(Rl[(f + a) * 64 + lane], 0.f), gv = Al[(f + a) * 64 + lane];
+    rs += r;
+    dot += r * gv;
+    gs += gv;
+  }
+  const float V = rs > 0.f ? dot / rs : gs / (float)n;
+  for (int a = 0; a < n; ++a)
+    Rl[(f + a) * 64 + lane] = rm_new(Rl[(f + a) * 64 + lane], Al[(f + a) * 64 + lane] - V, K);
+  *pp += V;
+}
+__device__ inline void rmp_down_any(float* __restrict__ Al, const float* __restrict__ Rl, const float* xpp,
+                                    int f, int n, int lane) {
+  const float xp = *xpp;
   float rs = 0.f;
-  for (int a = 0; a < n; ++a) rs += fmaxf(R[base + (f + a) * stride], 0.f);
-  const float inv = rs > 0.f ? 1.f / rs : 0.f;
-  const float uni = 1.f / (float)n;
-  for (int a = 0; a < n; ++a) {
-    int64_t i = base + (f + a) * stride;
-    float ba = rs > 0.f ? fmaxf(R[i], 0.f) * inv : uni;
-    xs[i] += t * (double)x[i];
-    x[i] = xp * ba;
+  for (int a = 0; a < n; ++a) rs += fmaxf(Rl[(f + a) * 64 + lane], 0.f);
+  const float inv = rs > 0.f ? xp / rs : 0.f, uni = xp / (float)n;
+  for (int a = 0; a < n; ++a)
+    Al[(f + a) * 64 + lane] = rs > 0.f ? fmaxf(Rl[(f + a) * 64 + lane], 0.f) * inv : uni;
+}
+
+__device__ inline void rmp_up(float* Al, float* Rl, float* pp, int f, int n, int lane, const RmStep& K) {
+  switch (n) {
+    case 1: rmp_up_n<1>(Al, Rl, pp, f, lane, K); break;
+    case 2: rmp_up_n<2>(Al, Rl, pp, f, lane, K); break;
+    case 3: rmp_up_n<3>(Al, Rl, pp, f, lane, K); break;
+    case 4: rmp_up_n<4>(Al, Rl, pp, f, lane, K); break;
+    case 5: rmp_up_n<5>(Al, Rl, pp, f, lane, K); break;
+    case 6: rmp_up_n<6>(Al, Rl, pp, f, lane, K); break;
+    case 7: rmp_up_n<7>(Al, Rl, pp, f, lane, K); break;
+    case 8: rmp_up_n<8>(Al, Rl, pp, f, lane, K); break;
+    default: rmp_up_any(Al, Rl, pp, f, n, lane, K);
+  }
+}
+__device__ inline void rmp_down(float* Al, const float* Rl, const float* xpp, int f, int n, int lane) {
+  switch (n) {
+    case 1: rmp_down_n<1>(Al, Rl, xpp, f, lane); break;
+    case 2: rmp_down_n<2>(Al, Rl, xpp, f, lane); break;
+    case 3: rmp_down_n<3>(Al, Rl, xpp, f, lane); break;
+    case 4: rmp_down_n<4>(Al, Rl, xpp, f, lane); break;
+    case 5: rmp_down_n<5>(Al, Rl, xpp, f, lane); break;
+    case 6: rmp_down_n<6>(Al, Rl, xpp, f, lane); break;
+    case 7: rmp_down_n<7>(Al, Rl, xpp, f, lane); break;
+    case 8: rmp_down_n<8>(Al, Rl, xpp, f, lane); break;
+    default: rmp_down_any(Al, Rl, xpp, f, n, lane);
   }
 }
 
-// mode 0: single-phase task (bottom-up then top-down); 1: deep bottom-up;
-// 2: top task (pull, bottom-up, top-down); 3: deep top-down.
+// MODE 0: bottom-up and top-down of a piece with no external parent (pulls
+// from deeper pieces first); 1: bottom-up of a deep piece (root values to the
+// stage buffer); 2: top-down of a deep piece (parent weights from x).  The
+// running average takes the previous plan (weight K.w) in the pass that
+// overwrites x.
 template <int MODE>
-__global__ __launch_bounds__(TPB) void k_rm(TpParams P, float* __restrict__ g,
-                                            float* __restrict__ R, float* __restrict__ x,
-                                            double* __restrict__ xs, float* __restrict__ stage,
-                                            const double* __restrict__ tdev) {
-  const RmStep K = rm_step(P, *tdev);
-  const double t = K.w;
+__global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict__ g, float* __restrict__ R,
+                                                  float* __restrict__ x, double* __restrict__ xs,
+                                                  float* __restrict__ stage, const double* __restrict__ tdev) {
+  extern __shared__ float rsm[];
   const int2 bt = P.blocks[blockIdx.x];
-  const TpTask T = P.tasks[bt.x];
-  if (P.active && !P.active[T.inst]) return;
-  const int h = bt.y + threadIdx.x;
-  if (h >= T.n_hands) return;
-  const int64_t base = T.vec_base + h, stride = T.stride;
-  if (MODE == 2) {
-    for (int i = T.pull_begin; i < T.pull_end; ++i) {
-      const TpPull pl = P.pulls[i];
-      g[base + (int64_t)pl.seq * stride] += stage[(int64_t)pl.stage * P.stage_stride + h];
-    }
-  }
-  if (MODE == 0 || MODE == 1 || MODE == 2) {
-    float vroot = 0.f;
-    for (int i = T.inf_end - 1; i >= T.inf_begin; --i) {
-      const int I = P.order[i];
-      const int par = P.inf_parent[I];
-      const float V = rm_infoset(g, R, base, stride, P.inf_first[I], P.inf_nact[I], K);
-      if (MODE == 1 && par == T.ext_parent) vroot += V;
-      else if (par >= 0) g[base + (int64_t)par * stride] += V;
-    }
-    if (MODE == 1) stage[(int64_t)T.stage * P.stage_stride + h] = vroot;
-  }
-  if (MODE == 0 || MODE == 2 || MODE == 3) {
-    for (int i = T.inf_begin; i < T.inf_end; ++i) {
-      const int I = P.order[i];
-      rm_descend(R, x, xs, base, stride, P.inf_first[I], P.inf_nact[I], P.inf_parent[I], t);
-    }
-  }
-}
-
-// The same update with the block's slab of the task (its contiguous
-// sequences x 64 hands of g, R and x) and its infoset table staged in LDS, so
-// the serial walk over infosets touches LDS only.  Four wavefronts load and
-// store the slab (rows interleaved, all loads in flight); wavefront 0 walks
-// the tree for the block's 64 hands, reading each infoset's actions once.
-// MODE 0: single-phase task; 1: deep bottom-up; 3: deep top-down.
-constexpr int STB = 64;       // hands per block
-constexpr int STW = 4;        // wavefronts per block
-constexpr int STR = 16;       // rows per thread per load round
-constexpr int MAXA = 8;       // actions handled in registers
-
-template <int MODE>
-__global__ __launch_bounds__(STB * STW) void k_rm_st(TpParams P, float* __restrict__ g,
-                                                     float* __restrict__ R, float* __restrict__ x,
-                                                     double* __restrict__ xs,
-                                                     float* __restrict__ stage,
-                                                     const double* __restrict__ tdev, int ninf_max) {
-  extern __shared__ float stsm[];
-  const int2 bt = P.blocks[blockIdx.x];
-  const TpTask T = P.tasks[bt.x];
+  const RmTask T = P.tasks[bt.x];
   if (P.active && !P.active[T.inst]) return;   // whole block: T is uniform
-  const int lane = threadIdx.x & (STB - 1), wv = threadIdx.x / STB;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int h = bt.y + lane;
   const bool act = h < T.n_hands;
-  const int S0 = T.seq_begin, SL = T.seq_end - T.seq_begin, ninf = T.inf_end - T.inf_begin;
-  int* iPar = (int*)stsm;
-  int* iF = iPar + ninf_max;
-  int* iN = iF + ninf_max;
-  float* gL = (float*)(iN + ninf_max);
-  float* RL = gL + (size_t)SL * STB;
-  float* xL = RL + (size_t)SL * STB;
+  const int SL = T.n_rows;
+  float* Al = rsm;                          // [max_rows][64]: g, then the new x
+  float* Rl = rsm + P.max_rows * 64;        // [max_rows][64]
+  float* Xl = Rl + P.max_rows * 64;         // [max_ext][64]: root values / parent weights
+  float* One = Xl + P.max_ext * 64;         // [64]: sink of root values, then 1 (root weight)
   const int64_t base = T.vec_base + h, stride = T.stride;
-  const RmStep K = rm_step(P, *tdev);
-  const double t = K.w;
-  for (int i = threadIdx.x; i < ninf; i += STB * STW) {
-    const int I = P.order[T.inf_begin + i];
-    iPar[i] = P.inf_parent[I];
-    iF[i] = P.inf_first[I] - S0;
-    iN[i] = P.inf_nact[I];
-  }
-  for (int r0 = wv; r0 < SL; r0 += STW * STR) {
-    float gv[STR], rv[STR], xv[STR];
+  const RmStep K = rm_step(P.dcfr, P.gamma, P.alpha, P.beta, *tdev);
+  const int rowv = lane < SL ? P.rows[T.rows_off + lane] : 0;
+  const int infv = (wv == 0 && lane < T.n_inf) ? P.infs[T.inf_off + lane] : 0;
+  const int extv = (MODE != 0 && wv == 0 && lane < T.n_ext)
+                       ? (MODE == 1 ? P.ext_slot[T.ext_off + lane] : P.ext_seq[T.ext_off + lane]) : 0;
+  {
+    // unconditional loads at clamped (in-bounds) rows and hands, so that all
+    // of them issue before the first is waited for
+    float a[RMR], b[RMR], c[RMR];
+    double d[RMR];
+    const int64_t cbase = T.vec_base + (act ? h : T.n_hands - 1);
 #pragma unroll
-    for (int k = 0; k < STR; ++k) {
-      const int r = r0 + k * STW;
-      gv[k] = rv[k] = xv[k] = 0.f;
-      if (act && r < SL) {
-        const int64_t idx = base + (int64_t)(S0 + r) * stride;
-        if (MODE != 3) gv[k] = g[idx];
-        rv[k] = R[idx];
-        if (MODE != 1) xv[k] = x[idx];
+    for (int k = 0; k < RMR; ++k) {
+      const int r = min(wv + RMW * k, SL - 1);
+      const int64_t idx = cbase + (int64_t)rl(rowv, r) * stride;
+      if (MODE != 2) a[k] = g[idx];
+      b[k] = R[idx];
+      if (MODE != 1) {
+        c[k] = x[idx];
+        d[k] = xs[idx];
       }
     }
-    double xo[STR];
+    if (MODE == 2 && wv == 0)
+      for (int k = 0; k < T.n_ext; ++k)
+        Xl[k * 64 + lane] = act ? x[base + (int64_t)rl(extv, k) * stride] : 0.f;
 #pragma unroll
-    for (int k = 0; k < STR; ++k) {
-      const int r = r0 + k * STW;
-      xo[k] = 0.0;
-      if (MODE != 1 && act && r < SL) xo[k] = xs[base + (int64_t)(S0 + r) * stride];
-    }
-#pragma unroll
-    for (int k = 0; k < STR; ++k) {
-      const int r = r0 + k * STW;
+    for (int k = 0; k < RMR; ++k) {
+      const int r = wv + RMW * k;
       if (r < SL) {
-        gL[r * STB + lane] = gv[k];
-        RL[r * STB + lane] = rv[k];
-        xL[r * STB + lane] = xv[k];
-        if (MODE != 1 && act) xs[base + (int64_t)(S0 + r) * stride] = xo[k] + t * (double)xv[k];
+        if (MODE != 2) Al[r * 64 + lane] = a[k];
+        Rl[r * 64 + lane] = b[k];
+        if (MODE != 1 && act) xs[base + (int64_t)rl(rowv, r) * stride] = d[k] + K.w * (double)c[k];
+      }
+    }
+  }
+  if (MODE != 2) {
+    // values of deeper pieces into the rows they hang from (each wavefront
+    // adds into the rows it loaded)
+    for (int c0 = 0; c0 < T.n_pull; c0 += 64) {
+      const int pv = c0 + lane < T.n_pull ? P.pulls[T.pull_off + c0 + lane] : 0;
+      const int nn = min(64, T.n_pull - c0);
+      for (int j = 0; j < nn; ++j) {
+        const int v = rl(pv, j);
+        const int lr = v & 255;
+        if (lr % RMW == wv && act) Al[lr * 64 + lane] += stage[(int64_t)((uint32_t)v >> 8) * P.stage_stride + h];
       }
     }
   }
   __syncthreads();
   if (wv == 0) {
-    if (MODE == 0 || MODE == 1) {
-      float vroot = 0.f;
-      for (int i = ninf - 1; i >= 0; --i) {
-        const int par = iPar[i], f = iF[i], n = iN[i];
-        float V;
-        if (n <= MAXA) {
-          float rr[MAXA], gg[MAXA];
-          float rs = 0.f;
-#pragma unroll
-          for (int a = 0; a < MAXA; ++a) {
-            rr[a] = a < n ? RL[(f + a) * STB + lane] : 0.f;
-            gg[a] = a < n ? gL[(f + a) * STB + lane] : 0.f;
-            rs += fmaxf(rr[a], 0.f);
-          }
-          const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
-          V = 0.f;
-#pragma unroll
-          for (int a = 0; a < MAXA; ++a)
-            if (a < n) V += (rs > 0.f ? fmaxf(rr[a], 0.f) * inv : uni) * gg[a];
-#pragma unroll
-          for (int a = 0; a < MAXA; ++a)
-            if (a < n) RL[(f + a) * STB + lane] = rm_new(rr[a], gg[a] - V, K);
-        } else {
-          float rs = 0.f;
-          for (int a = 0; a < n; ++a) rs += fmaxf(RL[(f + a) * STB + lane], 0.f);
-          const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
-          V = 0.f;
-          for (int a = 0; a < n; ++a)
-            V += (rs > 0.f ? fmaxf(RL[(f + a) * STB + lane], 0.f) * inv : uni) * gL[(f + a) * STB + lane];
-          for (int a = 0; a < n; ++a)
-            RL[(f + a) * STB + lane] = rm_new(RL[(f + a) * STB + lane], gL[(f + a) * STB + lane] - V, K);
-        }
-        if (MODE == 1 && par == T.ext_parent) vroot += V;
-        else if (par >= 0) gL[(par - S0) * STB + lane] += V;
+    if (MODE != 2) {
+      for (int k = 0; k < T.n_ext; ++k) Xl[k * 64 + lane] = 0.f;
+      for (int i = T.n_inf - 1; i >= 0; --i) {
+        const int v = rl(infv, i);
+        const int par = v >> 16;
+        float* pp = par >= 0 ? &Al[par * 64 + lane] : (par <= -2 ? &Xl[(-2 - par) * 64 + lane] : &One[lane]);
+        rmp_up(Al, Rl, pp, v & 255, (v >> 8) & 255, lane, K);
       }
-      if (MODE == 1 && act) stage[(int64_t)T.stage * P.stage_stride + h] = vroot;
+      if (MODE == 1 && act)
+        for (int k = 0; k < T.n_ext; ++k)
+          stage[(int64_t)rl(extv, k) * P.stage_stride + h] = Xl[k * 64 + lane];
     }
-    if (MODE == 0 || MODE == 3) {
-      for (int i = 0; i < ninf; ++i) {
-        const int par = iPar[i], f = iF[i], n = iN[i];
-        float xp = 1.f;
-        if (par >= S0 && par < S0 + SL) xp = xL[(par - S0) * STB + lane];
-        else if (par >= 0) xp = act ? x[base + (int64_t)par * stride] : 0.f;
-        if (n <= MAXA) {
-          float rr[MAXA];
-          float rs = 0.f;
-#pragma unroll
-          for (int a = 0; a < MAXA; ++a) {
-            rr[a] = a < n ? fmaxf(RL[(f + a) * STB + lane], 0.f) : 0.f;
-            rs += rr[a];
-          }
-          const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
-#pragma unroll
-          for (int a = 0; a < MAXA; ++a)
-            if (a < n) xL[(f + a) * STB + lane] = xp * (rs > 0.f ? rr[a] * inv : uni);
-        } else {
-          float rs = 0.f;
-          for (int a = 0; a < n; ++a) rs += fmaxf(RL[(f + a) * STB + lane], 0.f);
-          const float inv = rs > 0.f ? 1.f / rs : 0.f, uni = 1.f / (float)n;
-          for (int a = 0; a < n; ++a)
-            xL[(f + a) * STB + lane] = xp * (rs > 0.f ? fmaxf(RL[(f + a) * STB + lane], 0.f) * inv : uni);
-        }
+    if (MODE != 1) {
+      One[lane] = 1.f;
+      for (int i = 0; i < T.n_inf; ++i) {
+        const int v = rl(infv, i);
+        const int par = v >> 16;
+        const float* xpp = par >= 0 ? &Al[par * 64 + lane] : (par == -1 ? &One[lane] : &Xl[(-2 - par) * 64 + lane]);
+        rmp_down(Al, Rl, xpp, v & 255, (v >> 8) & 255, lane);
       }
     }
   }
   __syncthreads();
   if (act) {
-    for (int r = wv; r < SL; r += STW) {
-      const int64_t idx = base + (int64_t)(S0 + r) * stride;
-      if (MODE != 3) R[idx] = RL[r * STB + lane];
-      if (MODE != 1) x[idx] = xL[r * STB + lane];
+#pragma unroll
+    for (int k = 0; k < RMR; ++k) {
+      const int r = wv + RMW * k;
+      if (r < SL) {
+        const int64_t idx = base + (int64_t)rl(rowv, r) * stride;
+        if (MODE != 2) R[idx] = Rl[r * 64 + lane];
+        if (MODE != 1) x[idx] = Al[r * 64 + lane];
+      }
     }
   }
 }
-
-__global__ void k_set1(double* tdev, double v) { tdev[0] = v; }
 
 // Best response: per hand, bottom-up max (Player 1) or min (Player 2) of g
 // plus the values below; sums of root values go to hv[hand_base + h].
@@ -1047,15 +1064,20 @@ struct DevTp {
   DBuf<TpPull> pulls;
   DBuf<int2> b_single, b_deep, b_top, b_all;
   int n_single = 0, n_deep = 0, n_top = 0, n_all = 0;
-  // solver path: LDS-staged tasks (64 hands per block) and global-walk tasks
-  DBuf<int2> b_single_st, b_deep_st, b_single_gl, b_deep_gl;
-  int n_single_st = 0, n_deep_st = 0, n_single_gl = 0, n_deep_gl = 0;
-  int st_ninf[2] = {0, 0};          // [single, deep] max infosets of staged tasks
-  size_t st_lds[2] = {0, 0};        // dynamic LDS bytes of the staged launches
   DBuf<float> stage;
   DBuf<double> stage_d;
   DBuf<double> hv;
   int stage_stride = 0;
+};
+
+struct DevRm {                  // regret-update pieces of one player
+  DBuf<RmTask> tasks;
+  DBuf<int32_t> rows, infs, pulls, ext_seq, ext_slot;
+  DBuf<int2> blocks;            // all depths, depth d at [blk_off[d], blk_off[d + 1])
+  std::vector<int> blk_off;
+  std::vector<int> max_rows, max_ext;   // per depth
+  DBuf<float> stage;
+  int stage_stride = 1;
 };
 
 struct Game {
@@ -1064,6 +1086,7 @@ struct Game {
   int device_id = 0;
   DevDir dd[2];
   DevTp dt[2];
+  DevRm drm[2];
   DBuf<double> lam;
   DBuf<float> lamf;
   int64_t lam_base[2] = {0, 0};
@@ -1116,13 +1139,6 @@ static std::vector<int2> tp_blocks(const TpPlan& T, const std::vector<int32_t>& 
   return b;
 }
 
-// LDS bytes a staged task needs (infoset table + three slabs of 64 hands).
-static size_t staged_bytes(const TpTask& t, int ninf_max, int sl) {
-  (void)t;
-  return (size_t)3 * ninf_max * sizeof(int) + (size_t)3 * sl * STB * sizeof(float);
-}
-constexpr size_t kStagedLdsMax = 60 * 1024;
-
 static int upload_dir(Game* g, int d) {
   int rc;
   HostGame& hg = g->hg;
@@ -1158,6 +1174,33 @@ static int upload_dir(Game* g, int d) {
   return PMX_OK;
 }
 
+static int upload_rm(Game* g, int p) {
+  const RmPlan& T = g->hg.rm[p];
+  DevRm& E = g->drm[p];
+  int rc;
+  if ((rc = E.tasks.upload(T.tasks)) || (rc = E.rows.upload(T.rows)) || (rc = E.infs.upload(T.infs)) ||
+      (rc = E.pulls.upload(T.pulls)) || (rc = E.ext_seq.upload(T.ext_seq)) || (rc = E.ext_slot.upload(T.ext_slot)))
+    return rc;
+  std::vector<int2> blocks;
+  const int D = (int)T.by_depth.size();
+  E.blk_off.assign(D + 1, 0);
+  E.max_rows.assign(D, 0);
+  E.max_ext.assign(D, 0);
+  for (int d = 0; d < D; ++d) {
+    E.blk_off[d] = (int)blocks.size();
+    for (int id : T.by_depth[d]) {
+      const RmTask& t = T.tasks[id];
+      E.max_rows[d] = std::max(E.max_rows[d], (int)t.n_rows);
+      E.max_ext[d] = std::max(E.max_ext[d], (int)t.n_ext);
+      for (int h0 = 0; h0 < t.n_hands; h0 += 64) blocks.push_back(make_int2(id, h0));
+    }
+  }
+  E.blk_off[D] = (int)blocks.size();
+  if ((rc = E.blocks.upload(blocks))) return rc;
+  E.stage_stride = std::max(T.stage_stride, 1);
+  return E.stage.alloc((size_t)std::max(T.n_slot, 1) * E.stage_stride);
+}
+
 static int upload_game(Game* g) {
   HostGame& hg = g->hg;
   // lambda of both players, all instances
@@ -1177,7 +1220,7 @@ static int upload_game(Game* g) {
   g->lam_off[0] = lam_off[0];
   g->lam_off[1] = lam_off[1];
   for (int d = 0; d < 2; ++d)
-    if ((rc = upload_dir(g, d))) return rc;
+    if ((rc = upload_dir(g, d)) || (rc = upload_rm(g, d))) return rc;
   for (int p = 0; p < 2; ++p) {
     TpPlan& T = hg.tp[p];
     DevTp& E = g->dt[p];
@@ -1196,52 +1239,6 @@ static int upload_game(Game* g) {
     E.n_deep = (int)bd.size();
     E.n_top = (int)bt.size();
     E.n_all = (int)ba.size();
-    // staged (LDS) or global-walk path per task
-    for (int ph = 0; ph < 2; ++ph) {
-      const std::vector<int32_t>& ids = ph == 0 ? T.single : T.deep;
-      std::vector<int32_t> st, gl;
-      int ninf_max = 0, sl_max = 0;
-      for (int id : ids) {
-        const TpTask& t = T.tasks[id];
-        const int ninf = t.inf_end - t.inf_begin, sl = t.seq_end - t.seq_begin;
-        if (t.seq_begin >= 0 && staged_bytes(t, ninf, sl) <= kStagedLdsMax) {
-          st.push_back(id);
-          ninf_max = std::max(ninf_max, ninf);
-          sl_max = std::max(sl_max, sl);
-        } else {
-          gl.push_back(id);
-        }
-      }
-      // the launch uses the maxima of its tasks; drop the largest until it fits
-      while (!st.empty() && staged_bytes(T.tasks[st[0]], ninf_max, sl_max) > kStagedLdsMax) {
-        size_t worst = 0;
-        for (size_t k = 1; k < st.size(); ++k) {
-          const TpTask& a = T.tasks[st[k]];
-          const TpTask& w = T.tasks[st[worst]];
-          if (a.seq_end - a.seq_begin > w.seq_end - w.seq_begin) worst = k;
-        }
-        gl.push_back(st[worst]);
-        st.erase(st.begin() + worst);
-        ninf_max = sl_max = 0;
-        for (int id : st) {
-          const TpTask& t = T.tasks[id];
-          ninf_max = std::max(ninf_max, t.inf_end - t.inf_begin);
-          sl_max = std::max(sl_max, t.seq_end - t.seq_begin);
-        }
-      }
-      E.st_ninf[ph] = ninf_max;
-      E.st_lds[ph] = st.empty() ? 0 : staged_bytes(T.tasks[st[0]], ninf_max, sl_max);
-      auto bst = tp_blocks(T, st, STB), bgl = tp_blocks(T, gl, TPB);
-      if (ph == 0) {
-        if ((rc = E.b_single_st.upload(bst)) || (rc = E.b_single_gl.upload(bgl))) return rc;
-        E.n_single_st = (int)bst.size();
-        E.n_single_gl = (int)bgl.size();
-      } else {
-        if ((rc = E.b_deep_st.upload(bst)) || (rc = E.b_deep_gl.upload(bgl))) return rc;
-        E.n_deep_st = (int)bst.size();
-        E.n_deep_gl = (int)bgl.size();
-      }
-    }
     E.stage_stride = std::max(T.stage_stride, 1);
     if ((rc = E.stage.alloc((size_t)std::max(T.n_stage, 1) * E.stage_stride)) ||
         (rc = E.stage_d.alloc((size_t)std::max(T.n_stage, 1) * E.stage_stride)) ||
@@ -1413,9 +1410,21 @@ static TpParams tp_params(Game* g, int p, const int2* blocks) {
   return P;
 }
 
-static TpParams tp_active(Game* g, int p, const int2* blocks) {
-  TpParams P = tp_params(g, p, blocks);
+
+static RmParams rm_params(Game* g, int p, int depth) {
+  DevRm& E = g->drm[p];
+  RmParams P;
+  P.tasks = E.tasks.p;
+  P.blocks = E.blocks.p + E.blk_off[depth];
+  P.rows = E.rows.p;
+  P.infs = E.infs.p;
+  P.pulls = E.pulls.p;
+  P.ext_seq = E.ext_seq.p;
+  P.ext_slot = E.ext_slot.p;
   P.active = g->active.p;
+  P.stage_stride = E.stage_stride;
+  P.max_rows = E.max_rows[depth];
+  P.max_ext = E.max_ext[depth];
   P.dcfr = g->dcfr;
   P.gamma = g->gamma;
   P.alpha = (float)g->alpha;
@@ -1423,34 +1432,32 @@ static TpParams tp_active(Game* g, int p, const int2* blocks) {
   return P;
 }
 
+// One player's regret update: bottom-up passes of the deep pieces (deepest
+// first), the pieces without external parents, then the top-down passes of
+// the deep pieces (shallowest first).
 static int rm_update(Game* g, int p, hipStream_t s) {
-  DevTp& E = g->dt[p];
+  DevRm& E = g->drm[p];
   float* gr = g->grad[p].p;
   const double* td = g->tdev.p;
-  if (E.n_single_st)
-    hipLaunchKernelGGL(k_rm_st<0>, dim3(E.n_single_st), dim3(STB * STW), E.st_lds[0], s,
-                       tp_active(g, p, E.b_single_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
-                       E.stage.p, td, E.st_ninf[0]);
-  if (E.n_single_gl)
-    hipLaunchKernelGGL(k_rm<0>, dim3(E.n_single_gl), dim3(TPB), 0, s, tp_active(g, p, E.b_single_gl.p),
-                       gr, g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
-  if (E.n_deep_st)
-    hipLaunchKernelGGL(k_rm_st<1>, dim3(E.n_deep_st), dim3(STB * STW), E.st_lds[1], s,
-                       tp_active(g, p, E.b_deep_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
-                       E.stage.p, td, E.st_ninf[1]);
-  if (E.n_deep_gl)
-    hipLaunchKernelGGL(k_rm<1>, dim3(E.n_deep_gl), dim3(TPB), 0, s, tp_active(g, p, E.b_deep_gl.p),
-                       gr, g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
-  if (E.n_top)
-    hipLaunchKernelGGL(k_rm<2>, dim3(E.n_top), dim3(TPB), 0, s, tp_active(g, p, E.b_top.p), gr,
-                       g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
-  if (E.n_deep_st)
-    hipLaunchKernelGGL(k_rm_st<3>, dim3(E.n_deep_st), dim3(STB * STW), E.st_lds[1], s,
-                       tp_active(g, p, E.b_deep_st.p), gr, g->R[p].p, g->x[p].p, g->xs[p].p,
-                       E.stage.p, td, E.st_ninf[1]);
-  if (E.n_deep_gl)
-    hipLaunchKernelGGL(k_rm<3>, dim3(E.n_deep_gl), dim3(TPB), 0, s, tp_active(g, p, E.b_deep_gl.p),
-                       gr, g->R[p].p, g->x[p].p, g->xs[p].p, E.stage.p, td);
+  const int D = (int)E.max_rows.size();
+  auto launch = [&](int mode, int d) {
+    const int nb = E.blk_off[d + 1] - E.blk_off[d];
+    if (nb == 0) return;
+    const RmParams P = rm_params(g, p, d);
+    const size_t lds = sizeof(float) * 64 * (size_t)(2 * P.max_rows + P.max_ext + 1);
+    if (mode == 0)
+      hipLaunchKernelGGL(k_rmp<0>, dim3(nb), dim3(64 * RMW), lds, s, P, gr, g->R[p].p, g->x[p].p, g->xs[p].p,
+                         E.stage.p, td);
+    else if (mode == 1)
+      hipLaunchKernelGGL(k_rmp<1>, dim3(nb), dim3(64 * RMW), lds, s, P, gr, g->R[p].p, g->x[p].p, g->xs[p].p,
+                         E.stage.p, td);
+    else
+      hipLaunchKernelGGL(k_rmp<2>, dim3(nb), dim3(64 * RMW), lds, s, P, gr, g->R[p].p, g->x[p].p, g->xs[p].p,
+                         E.stage.p, td);
+  };
+  for (int d = D - 1; d >= 1; --d) launch(1, d);
+  if (D > 0) launch(0, 0);
+  for (int d = 1; d < D; ++d) launch(2, d);
   HIP_TRY(hipGetLastError());
   return PMX_OK;
 }
@@ -1653,6 +1660,35 @@ int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk) {
     classify_chunks(g->hg.dir[d]);
     if ((rc = upload_dir(g, d))) return rc;
   }
+  return PMX_OK;
+}
+
+int solver_set_task_rows(Game* g, int32_t rows) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (rows < 1 || rows > kTaskRowsMax) return fail(PMX_EINVAL, "rows must be in [1, 64]");
+  HIP_TRY(hipDeviceSynchronize());
+  if (g->graph_exec) {
+    (void)hipGraphExecDestroy(g->graph_exec);
+    g->graph_exec = nullptr;
+  }
+  if (g->graph) {
+    (void)hipGraphDestroy(g->graph);
+    g->graph = nullptr;
+  }
+  for (int p = 0; p < 2; ++p) {
+    std::string m;
+    if ((rc = build_rm_plan(g->hg, p, rows, m))) {
+      // keep a consistent plan: rebuild the previous one
+      std::string m2;
+      for (int q = 0; q < 2; ++q) (void)build_rm_plan(g->hg, q, g->hg.task_rows, m2);
+      for (int q = 0; q < 2; ++q) (void)upload_rm(g, q);
+      return fail(rc, m);
+    }
+  }
+  g->hg.task_rows = rows;
+  for (int p = 0; p < 2; ++p)
+    if ((rc = upload_rm(g, p))) return rc;
   return PMX_OK;
 }
 

@@ -179,6 +179,35 @@ struct TpPlan {                         // one player
   int64_t hands_total = 0;
 };
 
+// Regret-update tasks.  Each player's treeplex is cut into pieces of at most
+// `task_rows` sequences, so that a piece's rows for 64 hands stay resident in
+// LDS during the bottom-up and top-down passes.  A piece is a forest of whole
+// infoset subtrees of what remains of the treeplex once the deeper pieces are
+// cut away.  A piece whose roots hang from a sequence of another piece (a
+// "deep" piece) passes its root values up through a stage buffer and reads
+// the parent sequence's realization weight back in its top-down pass.
+constexpr int kTaskRowsMax = 64;        // rows per piece (one per lane of a wavefront)
+constexpr int kTaskExtMax = 16;         // distinct external parents per piece
+struct RmTask {
+  int64_t vec_base;
+  int32_t stride, n_hands;
+  int32_t rows_off, n_rows;             // sorted instance-relative sequence ids of the piece
+  int32_t inf_off, n_inf;               // packed local infosets, depth-first order
+  int32_t pull_off, n_pull;             // stage rows added into local rows before the walk
+  int32_t ext_off, n_ext;               // external parents: sequence and stage row
+  int32_t inst, depth;
+};
+// Packed local infoset: first local row (bits 0-7) | actions (bits 8-15) |
+// parent (bits 16-31, signed): >= 0 local row, -1 empty sequence, -2-k the
+// k-th external parent.  Pull: local row (bits 0-7) | stage row << 8.
+struct RmPlan {                         // one player
+  std::vector<RmTask> tasks;
+  std::vector<int32_t> rows, infs, pulls, ext_seq, ext_slot;
+  std::vector<std::vector<int32_t>> by_depth;   // task ids per depth (0: no external parent)
+  int n_slot = 0, stage_stride = 0;
+  int max_rows[2] = {0, 0}, max_ext[2] = {0, 0};   // [depth 0, deeper] LDS sizing
+};
+
 struct HostGame {
   std::vector<Built> inst;
   int64_t elems[2] = {0, 0};
@@ -186,6 +215,8 @@ struct HostGame {
   int mv_kernel = 0;                    // 0: workgroup per row chunk, 1: wavefront per row chunk
   MvDir dir[2];
   TpPlan tp[2];
+  RmPlan rm[2];
+  int task_rows = kTaskRowsMax;
   int max_stride = 0;
 };
 
@@ -198,5 +229,6 @@ int default_rows_per_block(int64_t rows);
 int default_mv_kernel(int64_t rows);
 void classify_chunks(MvDir& D);
 void build_matvec_plan(HostGame& hg, int d, int rows_per_block);
+int build_rm_plan(HostGame& hg, int p, int task_rows, std::string& msg);
 
 }  // namespace pmx

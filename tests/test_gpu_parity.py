@@ -261,6 +261,64 @@ def test_single_solver_step_from_given_state(name, fn):
     g.close()
 
 
+BIG_TREE = ("river_big_tree", lambda: I.river_config(seed=21, n_keep=(150, 170), bet_fracs=(0.33, 0.75, 1.5),
+                                                      max_raises=4, stack=400.0))
+
+
+@pytest.mark.parametrize("kind", ["rm+", "dcfr"])
+@pytest.mark.parametrize("rows", [8, 13, 64])
+@pytest.mark.parametrize("name,fn", [SMALL[6], ("river", lambda: I.config(1)), BIG_TREE])
+def test_single_step_any_piece_size(name, fn, rows, kind):
+    """One solver step from a given state is the same whatever the cut of the
+    treeplex into regret-update pieces (small cuts give several levels of
+    pieces exchanging values through the stage buffer)."""
+    pmx = _need_gpu()
+    d = fn()
+    _say("piece-size step parity", name, rows, kind)
+    o = payoff.Game(d)
+    g = pmx.Game(d)
+    g.solver_set_task_rows(rows)
+    g.solver_set_params(kind)
+    rng = np.random.default_rng(21)
+    ref = solver.RMPlus(o, kind=kind)
+    t0, w0 = 6, 91.0
+    for p in range(2):
+        R = ((rng.random((o.S[p], o.N[p])) - 0.2) * 3.0).astype(np.float32).astype(np.float64)
+        if kind == "rm+":
+            R = np.maximum(R, 0.0)
+        x = ref.tp[p].realization(ref.tp[p].behaviour_from_regret(R)).astype(np.float32).astype(np.float64)
+        s = rng.random((o.S[p], o.N[p]))
+        ref.R[p], ref.x[p], ref.sum[p] = R, x, s.copy()
+        g.solver_set_state(p, regret=g.pack(p, [R]), plan=g.pack(p, [x]),
+                           avg_sum=g.pack(p, [s], np.float64), t=t0, wsum=w0)
+    ref.t, ref.wsum = t0, w0
+    g.solver_step(1)
+    torch.cuda.synchronize()
+    ref.step()
+    for p in range(2):
+        st = g.solver_get_state(p)
+        R = g.unpack(p, st["regret"])[0]
+        x = g.unpack(p, st["plan"])[0]
+        s = g.unpack(p, st["avg_sum"])[0]
+        scale = max(1.0, np.abs(ref.R[p]).max())
+        assert np.abs(R - ref.R[p]).max() <= 1e-5 * scale, p
+        assert np.abs(x - ref.x[p]).max() <= 1e-5, p
+        assert np.abs(s - ref.sum[p]).max() <= 1e-6 * max(1.0, np.abs(ref.sum[p]).max()), p
+    g.close()
+
+
+def test_piece_size_rejects_too_small():
+    pmx = _need_gpu()
+    g = pmx.Game(I.config(1))
+    with pytest.raises(pmx.PmxError):
+        g.solver_set_task_rows(2)      # an infoset of this tree has more actions
+    with pytest.raises(pmx.PmxError):
+        g.solver_set_task_rows(65)
+    g.solver_step(3)                   # the previous cut is still in place
+    torch.cuda.synchronize()
+    g.close()
+
+
 @pytest.mark.parametrize("name,fn,target", [("tiny", I.tiny_config, 1e-6),
                                             ("kuhn", I.kuhn, 1e-5),
                                             ("river", lambda: I.config(1), 1e-4),
