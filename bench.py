@@ -258,7 +258,8 @@ def warm_leg(args, stream, batched):
 def pmc_probe(args):
     """Launches for hardware-counter runs (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE):
     a plain 256 MiB device-to-device copy (known bytes: calibrates the counters),
-    then matvec-pair launches on the river endgame and on the batch."""
+    then matvec-pair launches on the river endgame (default schedule) and on
+    the batch (schedule 2:4)."""
     import torch
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
@@ -271,7 +272,7 @@ def pmc_probe(args):
     games = [("river", pmx.Game(I.config(1)))]
     if not args.no_batched:
         gb = pmx.Game(I.batched_configs(args.batch))
-        gb.game_tune(0, 8)
+        gb.game_tune(2, 4)
         games.append(("batch", gb))
     for name, g in games:
         rng = np.random.default_rng(0)

@@ -205,10 +205,13 @@ int game_layout(const Game* g, int32_t instance, int32_t player, Layout* out);
 int game_terminals(const Game* g, int32_t instance, Terminals* out);
 int game_hand_meta(const Game* g, int32_t instance, int32_t ctx, int32_t player, HandMeta* out);
 
-/* Matvec schedule (results are identical up to FP64 summation order):
+/* Matvec schedule (results agree to the FP32 rounding of the data):
  * kernel 0 = one workgroup per chunk of output rows, kernel 1 = one
- * wavefront per chunk (launched per hand-count class); rows_per_chunk in
- * [1, 64].  Synchronizes the device; drops the captured solver graph.  The
+ * wavefront per chunk (launched per hand-count class), both on the sentinel
+ * entry list; kernels 2 and 3 = one workgroup of 256 / 512 threads per chunk
+ * on the chunk-aligned scan layout, launched per hands-per-thread class
+ * (prefix sums accumulated in FP64 and stored once rounded to the I/O type);
+ * rows_per_chunk in [1, 64].  Synchronizes the device; drops the captured solver graph.  The
  * defaults depend on the number of rows; an autotuner may override them. */
 int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk);
 int game_get_tuning(const Game* g, int32_t* kernel, int32_t* rows_per_chunk);

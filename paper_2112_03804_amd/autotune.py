@@ -2,7 +2,9 @@
 
 For a game it times every candidate schedule (``game_tune(kernel, rows)``:
 kernel 0 = workgroup per row chunk, 1 = wavefront per row chunk launched per
-hand-count class; rows = output rows per chunk) on the matvec-pair launch with
+hand-count class, 2 / 3 = chunk-aligned scan layout with 256- / 512-thread
+workgroups launched per hands-per-thread class; rows = output rows per
+chunk) on the matvec-pair launch with
 HIP events, keeps the fastest, and remembers the choice in a JSON cache keyed
 by GPU architecture and a size class of the game (instances, rows, largest
 hand count), so later games of the same class are tuned without timing.
@@ -15,7 +17,8 @@ from typing import Dict, Iterable, Optional, Tuple
 
 import numpy as np
 
-DEFAULT_CANDIDATES = [(0, 1), (0, 2), (0, 4), (0, 8), (1, 1), (1, 2), (1, 4)]
+DEFAULT_CANDIDATES = [(0, 1), (0, 4), (0, 8), (1, 2), (2, 1), (2, 2), (2, 4), (2, 8), (3, 1), (3, 2), (3, 4),
+                      (3, 8)]
 CACHE_ENV = "PMX_TUNE_CACHE"
 
 

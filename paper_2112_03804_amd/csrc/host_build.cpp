@@ -10,6 +10,7 @@
 // opening bet are capped at max_raises; the all-in stays available past the
 // cap (Fig. 1, nodes K and O).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -521,14 +522,15 @@ void build_hand_meta(Built& b) {
 // One output row per workgroup while rows are few (latency: every row in
 // flight at once); more rows per workgroup once the grid has several
 // workgroups per compute unit, so context metadata is loaded once per chunk.
-int default_rows_per_block(int64_t rows) {
-  if (rows <= 8192) return 1;
-  return (int)std::min<int64_t>(8, rows / 4096);
+int default_rows_per_block(int64_t rows, int kernel) {
+  if (rows <= 2048) return 1;
+  return kernel == 3 ? 8 : 2;
 }
 
-// Few rows: a workgroup per row (every row in flight at once, short scans).
-// Many rows: a wavefront per row chunk, so more rows are in flight per CU.
-int default_mv_kernel(int64_t rows) { return rows > 2048 ? 1 : 0; }
+// The chunk-aligned layout: 512-thread workgroups (fewer entries per thread,
+// shorter serial passes) when instances hold many hands on average, 256-thread
+// workgroups for batches of smaller instances.
+int default_mv_kernel(int64_t mean_hands) { return mean_hands > 800 ? 3 : 2; }
 
 namespace {
 
@@ -698,6 +700,136 @@ void build_matvec_plan(HostGame& hg, int d, int rows_per_block) {
       if (cnt) { D.blk.push_back((int32_t)D.items.size()); D.blk_inst.push_back((int32_t)ii); }
     }
   }
+}
+
+// Chunk-aligned layout of one direction for workgroups of `block` threads
+// (see McCtx): slots of every opponent hand, the own hands' query slots, the
+// per-thread chunk descriptors of each context, and the row chunks grouped by
+// hands-per-thread class.  Uses the contexts and row chunks of hg.dir[d].
+int build_mc_layout(HostGame& hg, int d, int block, std::string& msg) {
+  const int p = d, q = 1 - d;
+  McDir& M = hg.mc[d];
+  M = McDir();
+  M.block = block;
+  const MvDir& D = hg.dir[d];
+  const int kh_max = block == 512 ? 3 : 5;
+  std::vector<int> inst_class(hg.inst.size(), 0);
+  auto lohi = [](int32_t lo, int32_t hi) {
+    return (uint32_t)(uint16_t)(int16_t)lo | ((uint32_t)(uint16_t)(int16_t)hi << 16);
+  };
+  size_t ci = 0;
+  for (size_t ii = 0; ii < hg.inst.size(); ++ii) {
+    const Built& b = hg.inst[ii];
+    const Instance& in = b.inst;
+    const int nmax = std::max(in.n[p], in.n[q]);
+    const int kh = std::max(1, (nmax + block - 1) / block);
+    if (kh > kh_max) {
+      msg = "instance " + std::to_string(ii) + " has too many hands for this matvec schedule";
+      return PMX_EINVAL;
+    }
+    inst_class[ii] = kh - 1;
+    const int ke = mc_ke(block, kh), sk = mc_sk(ke);
+    for (int c = 0; c < b.n_ctx; ++c, ++ci) {
+      const CtxMeta& own = b.ctx[p][c];
+      const CtxMeta& opp = b.ctx[q][c];
+      const int n_seg = 1 + in.deck;
+      // opponent scan side: sorted live hands and, per card, its holders in that order
+      std::vector<int> order(opp.n_live);
+      for (int h = 0; h < in.n[q]; ++h)
+        if (opp.rank[h] >= 0) order[opp.rank[h]] = h;
+      std::vector<int> len(n_seg, 0);
+      len[0] = opp.n_live;
+      std::vector<std::array<int, 2>> idx_in_card(in.n[q], std::array<int, 2>{-1, -1});
+      for (int i = 0; i < opp.n_live; ++i) {
+        const int h = order[i];
+        for (int k = 0; k < in.cph; ++k) {
+          const int card = in.cards[q][(size_t)h * in.cph + k];
+          idx_in_card[h][k] = len[1 + card]++;
+        }
+      }
+      std::vector<int> cstart(n_seg + 1, 0);
+      for (int sg = 0; sg < n_seg; ++sg) cstart[sg + 1] = cstart[sg] + (len[sg] + 1 + ke - 1) / ke;
+      const int n_chunk = cstart[n_seg];
+      if (n_chunk > block) {
+        msg = "instance " + std::to_string(ii) + ": scan entries exceed the workgroup";
+        return PMX_EINVAL;
+      }
+      auto slot = [&](int sg, int i) { return (cstart[sg] + i / ke) * sk + i % ke; };
+      McCtx m{};
+      m.n_own = in.n[p];
+      m.n_opp = in.n[q];
+      m.cph = in.cph;
+      m.n_chunk = n_chunk;
+      m.lam_own_off = m.lam_opp_off = -1;   // filled by the ABI layer
+      m.pos_off = (int64_t)M.pos.size() / 2;
+      for (int h = 0; h < in.n[q]; ++h) {
+        if (opp.rank[h] < 0) {
+          M.pos.push_back(0xffffffffu);
+          M.pos.push_back(0xffffffffu);
+          continue;
+        }
+        int cs[2] = {-1, -1};
+        for (int k = 0; k < in.cph; ++k) {
+          const int card = in.cards[q][(size_t)h * in.cph + k];
+          cs[k] = slot(1 + card, idx_in_card[h][k]);
+        }
+        M.pos.push_back(lohi(slot(0, opp.rank[h]), cs[0]));
+        M.pos.push_back(lohi(cs[1], -1));
+      }
+      m.meta_off = (int64_t)M.meta.size();
+      std::vector<uint32_t> meta(block, 0u);
+      for (int sg = 0; sg < n_seg; ++sg) {
+        const int nch = cstart[sg + 1] - cstart[sg];
+        for (int j = 0; j < nch; ++j) {
+          const int nv = std::max(0, std::min(ke, len[sg] - j * ke));
+          uint32_t v = (uint32_t)nv;
+          if (j == 0) v |= 1u << 8;
+          if (j == nch - 1) v |= (uint32_t)(sg + 1) << 16;
+          meta[cstart[sg] + j] = v;
+        }
+      }
+      M.meta.insert(M.meta.end(), meta.begin(), meta.end());
+      m.q_off = (int64_t)M.q.size();
+      for (int h = 0; h < in.n[p]; ++h) {
+        const QueryRec& r = own.q[h];
+        QueryRec16 k{};
+        if (r.lt < 0) {
+          k.x = lohi(-1, -1);
+          k.w = 255u | (255u << 8) | (0xffffu << 16);
+          M.q.push_back(k);
+          continue;
+        }
+        k.x = lohi(slot(0, r.lt), slot(0, r.le));
+        int cards[2] = {255, 255};
+        uint32_t cw[2] = {0, 0};
+        for (int kk = 0; kk < in.cph; ++kk) {
+          const int card = in.cards[p][(size_t)h * in.cph + kk];
+          const int base_old = opp.seg_end[card] + 1;   // old entry list: segment 1 + card starts here
+          const int lt = (kk == 0 ? r.lt0 : r.lt1) - base_old, le = (kk == 0 ? r.le0 : r.le1) - base_old;
+          cards[kk] = card;
+          cw[kk] = lohi(slot(1 + card, lt), slot(1 + card, le));
+        }
+        k.y = cw[0];
+        k.z = cw[1];
+        const int self = r.self >= 0 ? slot(0, r.self) : -1;
+        k.w = (uint32_t)cards[0] | ((uint32_t)cards[1] << 8) | ((uint32_t)(uint16_t)(int16_t)self << 16);
+        M.q.push_back(k);
+      }
+      M.ctx.push_back(m);
+    }
+  }
+  const int nch = (int)D.blk.size() - 1;
+  for (int bch = 0; bch < nch; ++bch) {
+    const int it0 = D.blk[bch], it1 = D.blk[bch + 1], ii = D.blk_inst[bch];
+    int ctx = -1;
+    for (int it = it0; it < it1 && ctx < 0; ++it) ctx = D.items[it].ctx;
+    std::vector<int32_t>& L = M.chunks[inst_class[ii]];
+    L.push_back(it0);
+    L.push_back(it1);
+    L.push_back(ii);
+    L.push_back(ctx);
+  }
+  return PMX_OK;
 }
 
 // Group the row chunks of one direction by hand-count class.
@@ -1045,15 +1177,13 @@ int build_game(const GameDesc* descs, int n, HostGame& hg, std::string& msg) {
   hg.elems[0] = off[0];
   hg.elems[1] = off[1];
   {
-    int64_t rows = 0;
-    for (auto& b : hg.inst) rows += std::max(b.sf.n_seq[0], b.sf.n_seq[1]);
-    hg.rows_per_block = default_rows_per_block(rows);
-  }
-  {
-    int64_t rows = 0;
-    for (auto& b : hg.inst) rows += std::max(b.sf.n_seq[0], b.sf.n_seq[1]);
-    hg.mv_kernel = default_mv_kernel(rows);
-    if (hg.mv_kernel == 1) hg.rows_per_block = rows > 16384 ? 2 : 1;
+    int64_t rows = 0, hands = 0;
+    for (auto& b : hg.inst) {
+      rows += std::max(b.sf.n_seq[0], b.sf.n_seq[1]);
+      hands += std::max(b.inst.n[0], b.inst.n[1]);
+    }
+    hg.mv_kernel = default_mv_kernel(hands / (int64_t)hg.inst.size());
+    hg.rows_per_block = default_rows_per_block(rows, hg.mv_kernel);
   }
   for (int d = 0; d < 2; ++d) {
     build_matvec_plan(hg, d, hg.rows_per_block);

@@ -348,6 +348,319 @@ __global__ __launch_bounds__(BLOCK, sizeof(IO) == 4 ? 4 : 3) void k_matvec(MvPar
   }
 }
 
+// ---------------------------------------------------------------------------
+// chunk-aligned matvec (kernels 2 and 3; layout in McCtx)
+// ---------------------------------------------------------------------------
+// DPP lane moves (CDNA encodings): row_shr:n = 0x110 + n, row_bcast:15 =
+// 0x142, row_bcast:31 = 0x143, wave_shr:1 = 0x138.  Lanes without a source
+// (or outside the row mask) read 0.
+template <int CTRL, int RM>
+__device__ inline int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, RM, 0xf, false);
+}
+template <int CTRL, int RM>
+__device__ inline double dpp_d(double v) {
+  const int lo = dpp_i<CTRL, RM>(__double2loint(v));
+  const int hi = dpp_i<CTRL, RM>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+// One step of an inclusive segmented scan of (flag, a, b): the element from
+// the earlier lane is added unless this lane's run already holds a flag.
+template <int CTRL, int RM>
+__device__ inline void seg_step(int& f, double& a, double& b) {
+  const int f2 = dpp_i<CTRL, RM>(f);
+  const double a2 = dpp_d<CTRL, RM>(a), b2 = dpp_d<CTRL, RM>(b);
+  if (!f) {
+    a += a2;
+    b += b2;
+  }
+  f |= f2;
+}
+
+// Exclusive segmented scan over the threads of a block: thread t receives
+// the sum of a (and b) over the threads from the nearest thread at or before
+// t - 1 whose flag is set, up to t - 1; 0 if t's own flag is set.  One
+// barrier; `scr` holds 3 doubles per wavefront and is free again after the
+// caller's next barrier.
+template <int NW>
+__device__ inline void block_seg_scan_x(int flag, double a, double b, double* scr, double& ea, double& eb) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int f = flag;
+  double ai = a, bi = b;
+  seg_step<0x111, 0xf>(f, ai, bi);
+  seg_step<0x112, 0xf>(f, ai, bi);
+  seg_step<0x114, 0xf>(f, ai, bi);
+  seg_step<0x118, 0xf>(f, ai, bi);
+  seg_step<0x142, 0xa>(f, ai, bi);
+  seg_step<0x143, 0xc>(f, ai, bi);
+  if (lane == 63) {
+    scr[3 * wid + 0] = (double)f;
+    scr[3 * wid + 1] = ai;
+    scr[3 * wid + 2] = bi;
+  }
+  __syncthreads();
+  double ca = 0.0, cb = 0.0;
+  for (int w = 0; w < wid && w < NW; ++w) {
+    if (scr[3 * w] != 0.0) {
+      ca = scr[3 * w + 1];
+      cb = scr[3 * w + 2];
+    } else {
+      ca += scr[3 * w + 1];
+      cb += scr[3 * w + 2];
+    }
+  }
+  if (!f) {
+    ai += ca;
+    bi += cb;
+  }
+  double pa = dpp_d<0x138, 0xf>(ai), pb = dpp_d<0x138, 0xf>(bi);
+  if (lane == 0) {
+    pa = ca;
+    pb = cb;
+  }
+  ea = flag ? 0.0 : pa;
+  eb = flag ? 0.0 : pb;
+}
+
+struct McParams {
+  const MvItem* items;
+  const int4* chunks;            // (first item, end item, instance, first context) per workgroup
+  const McCtx* ctx;
+  const uint4* q;
+  const uint2* pos;
+  const uint32_t* meta;
+  const double* lam;
+  const float* lamf;
+  const int32_t* active;         // per-instance flag (NULL: all)
+  double scale;
+  int32_t nchunk;
+};
+template <typename IO>
+__device__ inline const IO* mc_lam(const McParams& P);
+template <>
+__device__ inline const float* mc_lam<float>(const McParams& P) { return P.lamf; }
+template <>
+__device__ inline const double* mc_lam<double>(const McParams& P) { return P.lam; }
+
+template <typename IO>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  static constexpr int N = 4;   // values per 16-byte LDS access
+  __device__ static void ld(const float* p, float* v) {
+    const float4 t = *(const float4*)p;
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+  }
+  __device__ static void st(float* p, const float* v) { *(float4*)p = make_float4(v[0], v[1], v[2], v[3]); }
+};
+template <>
+struct Vec4<double> {
+  static constexpr int N = 2;
+  __device__ static void ld(const double* p, double* v) {
+    const double2 t = *(const double2*)p;
+    v[0] = t.x; v[1] = t.y;
+  }
+  __device__ static void st(double* p, const double* v) { *(double2*)p = make_double2(v[0], v[1]); }
+};
+
+// One workgroup per row chunk.  Per item: the weighted opponent inputs are
+// written to their three slots (global, card 0, card 1), each thread sums its
+// chunk of KE slots in FP64, a segmented block scan carries the sums across
+// chunks of a segment, each thread writes its chunk's exclusive prefix sums
+// (rounded once to IO) over the showdown channel and its segment totals, and
+// every own hand reads the prefix sums at its query slots (Technique B) and
+// the per-card fold totals (eq. cf).
+template <int BLOCK, int KH, typename IO>
+__global__ __launch_bounds__(BLOCK) void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
+                                               McParams P1, const IO* __restrict__ in1, IO* __restrict__ out1,
+                                               double* __restrict__ tick) {
+  constexpr int KE = BLOCK == 512 ? 4 * KH : 4 * KH + 4;
+  constexpr int SK = KE + (KE % 8 == 0 ? 4 : 0);
+  constexpr int NW = BLOCK / 64;
+  constexpr int NSLOT = BLOCK * SK;
+  constexpr int VN = Vec4<IO>::N;
+  static_assert(KE % 4 == 0, "chunks are read 16 bytes at a time");
+  if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1.0;
+  const bool second = (int)blockIdx.x >= P0.nchunk;
+  const McParams& P = second ? P1 : P0;
+  const IO* __restrict__ in = second ? in1 : in0;
+  IO* __restrict__ out = second ? out1 : out0;
+  const IO* __restrict__ lam = mc_lam<IO>(P);
+  const int4 cr = P.chunks[second ? (int)blockIdx.x - P0.nchunk : (int)blockIdx.x];
+  if (P.active && !P.active[cr.z]) return;   // retired instance
+  const int tid = threadIdx.x;
+  extern __shared__ double smem[];
+  double* segT = smem;                        // [2 * kMcSegMax] (showdown, fold) totals per segment
+  double* scr = segT + 2 * kMcSegMax;         // [3 * NW] scan scratch
+  IO* S = (IO*)(scr + 3 * NW);                // [NSLOT] showdown values, then exclusive prefix sums
+  IO* F = S + NSLOT;                          // [NSLOT] fold values
+
+  uint4 qr[KH];
+  uint2 ps[KH];
+  IO lo[KH], lp[KH];
+  double acc[KH];
+  IO nxs[KH], nxf[KH];
+#pragma unroll
+  for (int k = 0; k < KH; ++k) acc[k] = 0.0;
+  uint32_t cm = 0;
+  int n_own = 0, cph = 1, n_chunk = 0, cur = -2;
+
+  const int it0 = cr.x, it1 = cr.y;
+  auto fetch = [&](int it) {
+    const MvItem nx = P.items[it];
+    const int nopp = nx.ctx >= 0 ? P.ctx[nx.ctx].n_opp : 0;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int h = tid + k * BLOCK;
+      nxs[k] = (h < nopp && nx.in_s >= 0) ? in[nx.in_s + h] : (IO)0;
+      nxf[k] = (h < nopp && nx.in_f >= 0) ? in[nx.in_f + h] : (IO)0;
+    }
+  };
+  if (it0 < it1) fetch(it0);
+  for (int it = it0; it < it1; ++it) {
+    const MvItem item = P.items[it];
+    IO cs_in[KH], cf_in[KH];
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      cs_in[k] = nxs[k];
+      cf_in[k] = nxf[k];
+    }
+    if (it + 1 < it1) fetch(it + 1);
+    if (item.ctx < 0) {
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int h = tid + k * BLOCK;
+        if (h < item.stride) out[item.out + h] = (IO)0;
+      }
+      continue;
+    }
+    __syncthreads();   // the previous item's readers of S, F and segT are done
+    if (item.ctx != cur) {
+      const McCtx C = P.ctx[item.ctx];
+      n_own = C.n_own;
+      cph = C.cph;
+      n_chunk = C.n_chunk;
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int h = tid + k * BLOCK;
+        qr[k] = h < C.n_own ? P.q[C.q_off + h] : make_uint4(0xffffffffu, 0u, 0u, 0u);
+        lo[k] = h < C.n_own ? lam[C.lam_own_off + h] : (IO)0;
+        ps[k] = h < C.n_opp ? P.pos[C.pos_off + h] : make_uint2(0xffffffffu, 0xffffffffu);
+        lp[k] = h < C.n_opp ? lam[C.lam_opp_off + h] : (IO)0;
+      }
+      cm = P.meta[C.meta_off + tid];
+      cur = item.ctx;
+    }
+    const bool hs = item.in_s >= 0, hf = item.in_f >= 0;
+    // weighted opponent inputs into their slots
+    const IO ks = (IO)item.ks, kf = (IO)item.kf;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const uint2 pp = ps[k];
+      const int g = lo16(pp.x);
+      if (g >= 0) {
+        const int c0 = hi16(pp.x), c1 = lo16(pp.y);
+        if (hs) {
+          const IO v = ks * lp[k] * cs_in[k];
+          S[g] = v;
+          S[c0] = v;
+          if (c1 >= 0) S[c1] = v;
+        }
+        if (hf) {
+          const IO v = kf * lp[k] * cf_in[k];
+          F[g] = v;
+          F[c0] = v;
+          if (c1 >= 0) F[c1] = v;
+        }
+      }
+    }
+    __syncthreads();
+    // chunk sums (slots past the chunk's valid entries read as 0)
+    // Chunk sums in the I/O type (at most KE terms), carried across chunks in
+    // FP64; the chunk is read again after the scan rather than held in
+    // registers.  Wavefronts past the last chunk skip both passes.
+    const int nv = (int)(cm & 255u);
+    const bool wlive = (tid & ~63) < n_chunk;
+    IO ls = (IO)0, lf = (IO)0;
+    if (hs && wlive) {
+#pragma unroll
+      for (int j = 0; j < KE; j += VN) {
+        IO v[VN];
+        Vec4<IO>::ld(&S[tid * SK + j], v);
+#pragma unroll
+        for (int u = 0; u < VN; ++u) ls += j + u < nv ? v[u] : (IO)0;
+      }
+    }
+    if (hf && wlive) {
+#pragma unroll
+      for (int j = 0; j < KE; j += VN) {
+        IO v[VN];
+        Vec4<IO>::ld(&F[tid * SK + j], v);
+#pragma unroll
+        for (int u = 0; u < VN; ++u) lf += j + u < nv ? v[u] : (IO)0;
+      }
+    }
+    const double ts = (double)ls, tf = (double)lf;
+    double es, ef;
+    block_seg_scan_x<NW>((int)((cm >> 8) & 1u), ts, tf, scr, es, ef);
+    if (hs && wlive) {
+      IO run = (IO)0;
+#pragma unroll
+      for (int j = 0; j < KE; j += VN) {
+        IO v[VN], pc[VN];
+        Vec4<IO>::ld(&S[tid * SK + j], v);
+#pragma unroll
+        for (int u = 0; u < VN; ++u) {
+          pc[u] = (IO)(es + (double)run);
+          run += j + u < nv ? v[u] : (IO)0;
+        }
+        Vec4<IO>::st(&S[tid * SK + j], pc);
+      }
+    }
+    const int endseg = (int)((cm >> 16) & 255u);
+    if (endseg) {
+      segT[2 * (endseg - 1)] = es + ts;
+      segT[2 * (endseg - 1) + 1] = ef + tf;
+    }
+    __syncthreads();
+    // own hands: prefix sums at the query slots, fold totals per card
+    const double2* T2 = (const double2*)segT;   // (showdown, fold) total of each segment
+    const double2 T0 = T2[0];
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const uint4 r = qr[k];
+      const int lt = lo16(r.x);
+      if (lt >= 0) {
+        const int c0 = r.w & 255, c1 = (r.w >> 8) & 255;
+        const double2 Ta = T2[1 + c0];
+        const double2 Tb = cph == 2 ? T2[1 + c1] : make_double2(0.0, 0.0);
+        double v = 0.0;
+        if (hs) {
+          double sd = (double)S[lt] + (double)S[hi16(r.x)] - T0.x;
+          sd -= (double)S[lo16(r.y)] + (double)S[hi16(r.y)] - Ta.x;
+          if (cph == 2) sd -= (double)S[lo16(r.z)] + (double)S[hi16(r.z)] - Tb.x;
+          v += sd;
+        }
+        if (hf) {
+          double fo = T0.y - Ta.y - Tb.y;
+          const int self = hi16(r.w);
+          if (cph == 2 && self >= 0) fo += (double)F[self];
+          v += fo;
+        }
+        acc[k] += v;
+      }
+    }
+    if (item.last) {
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int h = tid + k * BLOCK;
+        if (h < item.stride) out[item.out + h] = (IO)(h < n_own ? P.scale * (double)lo[k] * acc[k] : 0.0);
+        acc[k] = 0.0;
+      }
+    }
+  }
+}
+
 // Exclusive segmented scan over the 64 lanes of a wavefront (see
 // block_seg_scan).
 __device__ inline void wave_seg_scan(bool flag, double a, double b, double& ea, double& eb) {
@@ -1058,6 +1371,14 @@ struct DevDir {
   int cls_ent[MvDir::kClasses] = {0, 0, 0}, cls_n[MvDir::kClasses] = {0, 0, 0};
 };
 
+struct DevMc {                  // chunk-aligned matvec layout of one direction
+  DBuf<McCtx> ctx;
+  DBuf<uint32_t> q, pos, meta;
+  DBuf<int32_t> chunks[kMcClasses];
+  int count[kMcClasses] = {0, 0, 0, 0, 0};
+  int block = 0;                // 0: not built
+};
+
 struct DevTp {
   DBuf<int32_t> inf_parent, inf_first, inf_nact, order;
   DBuf<TpTask> tasks;
@@ -1085,6 +1406,7 @@ struct Game {
   bool device = false;
   int device_id = 0;
   DevDir dd[2];
+  DevMc dm[2];
   DevTp dt[2];
   DevRm drm[2];
   DBuf<double> lam;
@@ -1098,6 +1420,7 @@ struct Game {
   int t = 0;
   double wsum = 0.0;
   int mv_block = 256;
+  int max_lds = 64 * 1024;          // dynamic LDS bytes a workgroup may use on this device
   DBuf<double> tdev;                // iteration index of the next step (device)
   DBuf<int32_t> active;             // per-instance: 1 = iterated by solver_step
   int dcfr = 0, gamma = 1;          // solver rule (see solver_set_params)
@@ -1139,6 +1462,40 @@ static std::vector<int2> tp_blocks(const TpPlan& T, const std::vector<int32_t>& 
   return b;
 }
 
+static int upload_mc(Game* g, int d) {
+  HostGame& hg = g->hg;
+  DevMc& E = g->dm[d];
+  const int block = hg.mv_kernel == 3 ? 512 : 256;
+  std::string m;
+  int rc = build_mc_layout(hg, d, block, m);
+  if (rc) return fail(rc, m);
+  McDir& M = hg.mc[d];
+  const int p = d, q = 1 - d;
+  size_t ci = 0;
+  for (size_t ii = 0; ii < hg.inst.size(); ++ii)
+    for (int c = 0; c < hg.inst[ii].n_ctx; ++c, ++ci) {
+      M.ctx[ci].lam_own_off = g->lam_off[p][ii];
+      M.ctx[ci].lam_opp_off = g->lam_off[q][ii];
+    }
+  std::vector<uint32_t> qv;
+  qv.reserve(M.q.size() * 4);
+  for (const QueryRec16& r : M.q) {
+    qv.push_back(r.x);
+    qv.push_back(r.y);
+    qv.push_back(r.z);
+    qv.push_back(r.w);
+  }
+  if ((rc = E.ctx.upload(M.ctx)) || (rc = E.q.upload(qv)) || (rc = E.pos.upload(M.pos)) ||
+      (rc = E.meta.upload(M.meta)))
+    return rc;
+  for (int c = 0; c < kMcClasses; ++c) {
+    if ((rc = E.chunks[c].upload(M.chunks[c]))) return rc;
+    E.count[c] = (int)M.chunks[c].size() / 4;
+  }
+  E.block = block;
+  return PMX_OK;
+}
+
 static int upload_dir(Game* g, int d) {
   int rc;
   HostGame& hg = g->hg;
@@ -1171,6 +1528,8 @@ static int upload_dir(Game* g, int d) {
       E.cls_n[c] = D.cls_n[c];
     }
   }
+  if (hg.mv_kernel >= 2) return upload_mc(g, d);
+  g->dm[d].block = 0;
   return PMX_OK;
 }
 
@@ -1361,11 +1720,96 @@ static int launch_mv_w(Game* g, const MvParams& P, const IO* in, IO* out, hipStr
   return launch_mv_w_class<20, 62, IO>(g, P, 2, in, out, s, tick);
 }
 
+static McParams mc_params(Game* g, int d, const MvParams& like, int c) {
+  DevMc& E = g->dm[d];
+  McParams P;
+  P.items = g->dd[d].items.p;
+  P.chunks = (const int4*)E.chunks[c].p;
+  P.ctx = E.ctx.p;
+  P.q = (const uint4*)E.q.p;
+  P.pos = (const uint2*)E.pos.p;
+  P.meta = E.meta.p;
+  P.lam = g->lam.p;
+  P.lamf = g->lamf.p;
+  P.active = like.active;
+  P.scale = like.scale;
+  P.nchunk = like.nblk > 0 ? E.count[c] : 0;
+  return P;
+}
+
+template <int BLOCK, int KH, typename IO>
+static constexpr size_t mc_lds() {
+  constexpr int KE = BLOCK == 512 ? 4 * KH : 4 * KH + 4;
+  constexpr int SK = KE + (KE % 8 == 0 ? 4 : 0);
+  return sizeof(double) * (2 * kMcSegMax + 3 * (BLOCK / 64)) + 2 * sizeof(IO) * (size_t)BLOCK * SK;
+}
+
+// LDS bytes of the largest class a launch of the chunk-aligned kernel needs.
+template <typename IO>
+static size_t mc_lds_max(Game* g) {
+  size_t m = 0;
+  for (int c = 0; c < kMcClasses; ++c) {
+    if (!g->dm[0].count[c] && !g->dm[1].count[c]) continue;
+    size_t b = 0;
+    if (g->dm[0].block == 512)
+      b = c == 0 ? mc_lds<512, 1, IO>() : c == 1 ? mc_lds<512, 2, IO>() : mc_lds<512, 3, IO>();
+    else
+      b = c == 0 ? mc_lds<256, 1, IO>() : c == 1 ? mc_lds<256, 2, IO>() : c == 2 ? mc_lds<256, 3, IO>()
+        : c == 3 ? mc_lds<256, 4, IO>() : mc_lds<256, 5, IO>();
+    m = std::max(m, b);
+  }
+  return m;
+}
+
+template <int BLOCK, int KH, typename IO>
+static void launch_mc_class(const McParams& A, const IO* in0, IO* out0, const McParams& B, const IO* in1,
+                            IO* out1, hipStream_t s, double* tick) {
+  const size_t lds = mc_lds<BLOCK, KH, IO>();
+  hipLaunchKernelGGL((k_mvc<BLOCK, KH, IO>), dim3(A.nchunk + B.nchunk), dim3(BLOCK), lds, s, A, in0, out0, B,
+                     in1, out1, tick);
+}
+
+// Kernels 2 and 3: one launch per hands-per-thread class present.
+template <typename IO>
+static int launch_mc(Game* g, const MvParams& P0, const IO* in0, IO* out0, const MvParams& P1, const IO* in1,
+                     IO* out1, hipStream_t s, double* tick) {
+  const int block = g->dm[0].block;
+  if (block == 0 || g->dm[1].block != block) return fail(PMX_ESTATE, "matvec layout not built");
+  for (int c = 0; c < kMcClasses; ++c) {
+    const McParams A = mc_params(g, P0.dir, P0, c), B = mc_params(g, P1.dir, P1, c);
+    if (A.nchunk + B.nchunk == 0) continue;
+    if (block == 512) {
+      switch (c) {
+        case 0: launch_mc_class<512, 1, IO>(A, in0, out0, B, in1, out1, s, tick); break;
+        case 1: launch_mc_class<512, 2, IO>(A, in0, out0, B, in1, out1, s, tick); break;
+        case 2: launch_mc_class<512, 3, IO>(A, in0, out0, B, in1, out1, s, tick); break;
+        default: return fail(PMX_EINVAL, "no 512-thread matvec class for this hand count");
+      }
+    } else {
+      switch (c) {
+        case 0: launch_mc_class<256, 1, IO>(A, in0, out0, B, in1, out1, s, tick); break;
+        case 1: launch_mc_class<256, 2, IO>(A, in0, out0, B, in1, out1, s, tick); break;
+        case 2: launch_mc_class<256, 3, IO>(A, in0, out0, B, in1, out1, s, tick); break;
+        case 3: launch_mc_class<256, 4, IO>(A, in0, out0, B, in1, out1, s, tick); break;
+        default: launch_mc_class<256, 5, IO>(A, in0, out0, B, in1, out1, s, tick); break;
+      }
+    }
+    tick = nullptr;   // the iteration tick belongs to the first launch
+  }
+  HIP_TRY(hipGetLastError());
+  return PMX_OK;
+}
+
 template <typename IO>
 static int launch_mv(Game* g, MvParams P0, const IO* in0, IO* out0, MvParams P1, const IO* in1,
                      IO* out1, hipStream_t s, double* tick = nullptr) {
   const int nb = P0.nblk + P1.nblk;
   if (nb == 0) return PMX_OK;
+  // the chunk-aligned layout, unless its FP64 form needs more LDS than a
+  // workgroup may take here (then the workgroup kernel on the sentinel entry
+  // list serves the call)
+  if (g->hg.mv_kernel >= 2 && mc_lds_max<IO>(g) <= (size_t)g->max_lds)
+    return launch_mc<IO>(g, P0, in0, out0, P1, in1, out1, s, tick);
   if (g->hg.mv_kernel == 1) {
     int rc;
     if (P0.nblk && (rc = launch_mv_w<IO>(g, P0, in0, out0, s, tick))) return rc;
@@ -1545,6 +1989,9 @@ static int create_common(const GameDesc* descs, int32_t n, bool device, Game** o
     HIP_TRY(hipGetDevice(&dev));
     g->device_id = dev;
     g->device = true;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+      g->max_lds = lds;
     int rc = upload_game(g.get());
     if (rc) return rc;
     hipStream_t s = nullptr;
@@ -1642,7 +2089,7 @@ int game_hand_meta(const Game* g, int32_t instance, int32_t ctx, int32_t player,
 int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk) {
   int rc = ensure_device(g);
   if (rc) return rc;
-  if (kernel < 0 || kernel > 1) return fail(PMX_EINVAL, "kernel must be 0 or 1");
+  if (kernel < 0 || kernel > 3) return fail(PMX_EINVAL, "kernel must be in [0, 3]");
   if (rows_per_chunk < 1 || rows_per_chunk > 64) return fail(PMX_EINVAL, "rows_per_chunk must be in [1, 64]");
   HIP_TRY(hipDeviceSynchronize());
   if (g->graph_exec) {

@@ -154,6 +154,36 @@ struct MvDir {                          // host copy of one direction's plan
 };
 constexpr int kClassN[MvDir::kClasses] = {512, 1024, 1280};   // hands per player, upper bounds
 
+// Chunk-aligned matvec layout (kernels 2 and 3).  The opponent's scan side
+// is laid out segment by segment (segment 0: all live hands by strength;
+// segment 1 + c: live hands holding card c), each segment starting at a
+// thread chunk of KE entries and owning ceil((len + 1) / KE) chunks, so the
+// slot after its last entry (its total) lies in its own last chunk.  Entry i
+// of a chunk sits at LDS slot chunk * SK + i (SK = KE plus padding that keeps
+// the 16-byte chunk reads of a wavefront free of bank conflicts).
+constexpr int kMcClasses = 5;            // hands per thread: 1..5
+constexpr int kMcSegMax = 1 + kMaxDeck;
+inline int mc_ke(int block, int kh) { return block == 512 ? 4 * kh : 4 * kh + 4; }
+inline int mc_sk(int ke) { return ke + (ke % 8 == 0 ? 4 : 0); }
+struct McCtx {                           // (instance, context) as seen by one direction
+  int32_t n_own, n_opp, cph, n_chunk;
+  int64_t q_off;                         // own query records (uint4)
+  int64_t pos_off;                       // opponent hands' three slots (uint2)
+  int64_t meta_off;                      // per-thread chunk descriptors (block entries)
+  int64_t lam_own_off, lam_opp_off;
+};
+// Chunk descriptor bits: 0-7 valid entries, 8 first chunk of a segment,
+// 16-23 (segment + 1) when the chunk is the last of its segment.
+struct McDir {
+  int block = 256;                       // threads per workgroup the layout is built for
+  std::vector<McCtx> ctx;                // same indexing as MvDir::ctx
+  std::vector<QueryRec16> q;             // x: lt|le (global), y: lt0|le0, z: lt1|le1 (card slots),
+                                         // w: c0 | c1 << 8 | self slot << 16
+  std::vector<uint32_t> pos;             // pairs: (global | card0 << 16, card1 | 0xffff << 16)
+  std::vector<uint32_t> meta;
+  std::vector<int32_t> chunks[kMcClasses];   // per class: 4 ints per row chunk (it0, it1, inst, ctx)
+};
+
 struct TpTask {                         // treeplex task: one subtree of one instance
   int64_t vec_base;
   int32_t stride, n_hands;
@@ -212,8 +242,10 @@ struct HostGame {
   std::vector<Built> inst;
   int64_t elems[2] = {0, 0};
   int rows_per_block = 1;
-  int mv_kernel = 0;                    // 0: workgroup per row chunk, 1: wavefront per row chunk
+  int mv_kernel = 2;                    // 0 / 1: sentinel entry list, workgroup / wavefront per row
+                                        // chunk; 2 / 3: chunk-aligned layout, 256 / 512 threads
   MvDir dir[2];
+  McDir mc[2];
   TpPlan tp[2];
   RmPlan rm[2];
   int task_rows = kTaskRowsMax;
@@ -225,10 +257,11 @@ int validate(const GameDesc& d, Instance& out, std::string& msg);
 void build_seqform(const Instance& in, SeqForm& sf);
 void build_hand_meta(Built& b);
 int build_game(const GameDesc* descs, int n, HostGame& hg, std::string& msg);
-int default_rows_per_block(int64_t rows);
-int default_mv_kernel(int64_t rows);
+int default_rows_per_block(int64_t rows, int kernel);
+int default_mv_kernel(int64_t mean_hands);
 void classify_chunks(MvDir& D);
 void build_matvec_plan(HostGame& hg, int d, int rows_per_block);
 int build_rm_plan(HostGame& hg, int p, int task_rows, std::string& msg);
+int build_mc_layout(HostGame& hg, int d, int block, std::string& msg);
 
 }  // namespace pmx

@@ -2,11 +2,12 @@
 
 Tolerances (written here, derived in the design notes):
 * FP32 matvec: |g - g_ref| <= 1e-5 * ||A||_inf * ||y||_inf (the stated bound)
-  and, stricter, elementwise <= 1e-6 * (|A| |y|) + 1e-12 * ||A||_inf ||y||_inf:
-  the kernel accumulates in FP64, so the FP32 rounding of inputs and output
-  remains, plus FP64 cancellation in the inclusion-exclusion, which is
-  relative to the whole row's scale (an entry that is exactly 0 can come out
-  as ~1e-17 of the row scale).
+  and, stricter, elementwise <= 1e-6 * (|A| |y|) + 1e-7 * ||A||_inf ||y||_inf:
+  sums are carried across chunks in FP64, but inputs, chunk partial sums (at
+  most 24 terms) and the stored prefix sums are FP32, and the
+  inclusion-exclusion subtracts prefix sums of whole segments (all opponent
+  hands, blocked ones included), so a few FP32 ulps of a segment total remain
+  on an entry whatever its own size.
 * FP64 matvec: elementwise <= 1e-12 * (|A| |y|) + 1e-15 * ||A||_inf ||y||_inf.
 * Saddle gap, best responses: |diff| <= 1e-9 * pot.
 * One RM+ step from a given state: regrets and plans within 1e-5 of their
@@ -55,6 +56,10 @@ SMALL = [
 ]
 
 
+F32_FLOOR = 1e-7     # normalized by ||A||_inf ||y||_inf
+F64_FLOOR = 1e-15
+
+
 def _rand_vectors(o, rng, p):
     v = rng.standard_normal((o.S[p], o.N[p]))
     v[:, rng.random(o.N[p]) < 0.1] = 0.0
@@ -98,9 +103,9 @@ def _check_matvecs(pmx, d, seed=0, full=True):
     got_AT = g.unpack(1, ATx.cpu().numpy())[0].astype(np.float64)
     assert np.abs(got_A - ref_A).max() <= 1e-5 * normA * np.abs(y).max()
     assert np.abs(got_AT - ref_AT).max() <= 1e-5 * o.abs_col_sums().max() * np.abs(x).max()
-    # floor: FP64 rounding of the inclusion-exclusion relative to the row scale
-    fl_A = 1e-12 * normA * np.abs(y).max()
-    fl_AT = 1e-12 * o.abs_col_sums().max() * np.abs(x).max()
+    # floor: rounding of segment totals in the inclusion-exclusion (FP32 data)
+    fl_A = F32_FLOOR * normA * np.abs(y).max()
+    fl_AT = F32_FLOOR * o.abs_col_sums().max() * np.abs(x).max()
     _assert_close(got_A, ref_A, mag_A, 1e-6, fl_A, "A y (fp32)")
     _assert_close(got_AT, ref_AT, mag_AT, 1e-6, fl_AT, "A^T x (fp32)")
     # the pair launch gives the same bits as the separate launches
@@ -112,8 +117,9 @@ def _check_matvecs(pmx, d, seed=0, full=True):
         assert np.all(blk[:, L["n_hands"]:] == 0)
     got_Ad = g.unpack(0, Ayd.cpu().numpy())[0]
     got_ATd = g.unpack(1, ATxd.cpu().numpy())[0]
-    _assert_close(got_Ad, ref_A, mag_A, 1e-12, 1e-3 * fl_A, "A y (fp64)")
-    _assert_close(got_ATd, ref_AT, mag_AT, 1e-12, 1e-3 * fl_AT, "A^T x (fp64)")
+    _assert_close(got_Ad, ref_A, mag_A, 1e-12, F64_FLOOR * normA * np.abs(y).max(), "A y (fp64)")
+    _assert_close(got_ATd, ref_AT, mag_AT, 1e-12, F64_FLOOR * o.abs_col_sums().max() * np.abs(x).max(),
+                  "A^T x (fp64)")
     g.close()
 
 
@@ -148,9 +154,9 @@ def test_matvec_batched_uneven():
     torch.cuda.synchronize()
     gA, gAT = g.unpack(0, Ay.cpu().numpy()), g.unpack(1, ATx.cpu().numpy())
     for i, o in enumerate(os_):
-        fl = 1e-12 * o.abs_row_sums().max() * np.abs(ys[i]).max()
+        fl = F32_FLOOR * o.abs_row_sums().max() * np.abs(ys[i]).max()
         _assert_close(gA[i], o.matvec_A(ys[i]), payoff.abs_matvec_A(o, ys[i]), 1e-6, fl, f"A y inst {i}")
-        fl = 1e-12 * o.abs_col_sums().max() * np.abs(xs[i]).max()
+        fl = F32_FLOOR * o.abs_col_sums().max() * np.abs(xs[i]).max()
         _assert_close(gAT[i], o.matvec_AT(xs[i]), payoff.abs_matvec_AT(o, xs[i]), 1e-6, fl,
                       f"A^T x inst {i}")
     g.close()
@@ -174,8 +180,9 @@ def test_matvec_turn_river_full_size_sampled():
     gA, gAT = g.unpack(0, Ay.cpu().numpy())[0], g.unpack(1, ATx.cpu().numpy())[0]
     gAd = g.unpack(0, Ayd.cpu().numpy())[0]
     T = g.terminals(0)
-    # absolute floor: FP64 rounding relative to the scale of a whole row of A
-    floor = 1e-12 * 2 * d.stack[0] * np.abs(y).max()
+    # absolute floors relative to the scale of a whole row of A
+    floor = F32_FLOOR * 2 * d.stack[0] * np.abs(y).max()
+    floor64 = F64_FLOOR * 2 * d.stack[0] * np.abs(y).max()
     # sample rows of every kind: runout rows, first-round fold rows, river rows
     runout_rows = sorted(set(T["seq1"][T["runout"] == 1].tolist()))[:3]
     first_rows = sorted(set(T["seq1"][(T["board"] < 0) & (T["runout"] == 0)].tolist()))[:3]
@@ -186,7 +193,7 @@ def test_matvec_turn_river_full_size_sampled():
             ref = o.entry_A(y, s, h)
             mag = payoff.abs_entry_A(o, y, s, h)
             assert abs(gA[s, h] - ref) <= 1e-6 * mag + floor, (s, h, gA[s, h], ref, mag)
-            assert abs(gAd[s, h] - ref) <= 1e-12 * mag + 1e-3 * floor, (s, h, gAd[s, h], ref, mag)
+            assert abs(gAd[s, h] - ref) <= 1e-12 * mag + floor64, (s, h, gAd[s, h], ref, mag)
     cols = sorted(set(T["seq2"][T["runout"] == 1].tolist()))[:2] + \
         [int(c) for c in rng.choice(sorted(set(T["seq2"].tolist())), size=6, replace=False)]
     for s in cols:
@@ -301,8 +308,22 @@ def test_single_step_any_piece_size(name, fn, rows, kind):
         x = g.unpack(p, st["plan"])[0]
         s = g.unpack(p, st["avg_sum"])[0]
         scale = max(1.0, np.abs(ref.R[p]).max())
+        # regrets are continuous in the inputs: compared everywhere
         assert np.abs(R - ref.R[p]).max() <= 1e-5 * scale, p
-        assert np.abs(x - ref.x[p]).max() <= 1e-5, p
+        # the plan is the realization of the device's own regrets ...
+        tp = ref.tp[p]
+        assert np.abs(x - tp.realization(tp.behaviour_from_regret(R))).max() <= 1e-5, p
+        # ... and the oracle's plan wherever it is well conditioned: where an
+        # infoset's new regrets are all 0 (all its q equal, as under a river
+        # card that blocks the hand, where the gradient is exactly 0) the
+        # behaviour is the uniform convention and FP32 noise of ~1e-8 in g
+        # may select another one, for the whole subtree below
+        ok = np.ones_like(x, dtype=bool)
+        for par, f, n in tp.inf:
+            cond = np.maximum(ref.R[p][f:f + n], 0.0).sum(axis=0) > 1e-4 * scale
+            ok[f:f + n] = (ok[par] if par >= 0 else True) & cond[None, :]
+        assert ok.mean() > 0.5
+        assert np.abs(x - ref.x[p])[ok].max() <= 1e-5, p
         assert np.abs(s - ref.sum[p]).max() <= 1e-6 * max(1.0, np.abs(ref.sum[p]).max()), p
     g.close()
 
@@ -400,11 +421,13 @@ def test_solver_state_round_trip_and_reset():
     g.close()
 
 
-@pytest.mark.parametrize("kernel,rows", [(1, 1), (1, 3), (0, 2), (0, 5)])
+@pytest.mark.parametrize("kernel,rows", [(1, 1), (1, 3), (0, 2), (0, 5), (2, 1), (2, 3), (3, 1), (3, 4)])
 def test_matvec_schedules_agree(kernel, rows):
-    """Every matvec schedule (workgroup or wavefront per row chunk, any chunk
-    length) gives the oracle's products on a batch of uneven games, including
-    a turn + river game whose rows span several board contexts."""
+    """Every matvec schedule (workgroup or wavefront per row chunk with the
+    sentinel entry list, or the chunk-aligned layout with 256- or 512-thread
+    workgroups; any chunk length) gives the oracle's products on a batch of
+    uneven games, including a turn + river game whose rows span several board
+    contexts."""
     pmx = _need_gpu()
     descs = [I.river_config(seed=500 + i, n_keep=(90 + 170 * i, 700 - 120 * i),
                             bet_fracs=((0.5,), (0.33, 1.0), (0.75, 1.5, 2.0))[i % 3],
@@ -429,12 +452,12 @@ def test_matvec_schedules_agree(kernel, rows):
     gA, gAT = g.unpack(0, Ay.cpu().numpy()), g.unpack(1, ATx.cpu().numpy())
     gAd = g.unpack(0, Ayd.cpu().numpy())
     for i, o in enumerate(os_):
-        fl = 1e-12 * o.abs_row_sums().max() * np.abs(ys[i]).max()
+        fl = F32_FLOOR * o.abs_row_sums().max() * np.abs(ys[i]).max()
         mag = payoff.abs_matvec_A(o, ys[i])
         ref = o.matvec_A(ys[i])
         _assert_close(gA[i], ref, mag, 1e-6, fl, f"A y inst {i}")
-        _assert_close(gAd[i], ref, mag, 1e-12, 1e-3 * fl, f"A y fp64 inst {i}")
-        fl = 1e-12 * o.abs_col_sums().max() * np.abs(xs[i]).max()
+        _assert_close(gAd[i], ref, mag, 1e-12, F64_FLOOR / F32_FLOOR * fl, f"A y fp64 inst {i}")
+        fl = F32_FLOOR * o.abs_col_sums().max() * np.abs(xs[i]).max()
         _assert_close(gAT[i], o.matvec_AT(xs[i]), payoff.abs_matvec_AT(o, xs[i]), 1e-6, fl,
                       f"A^T x inst {i}")
     # padding written as zero by every schedule
