@@ -700,6 +700,14 @@ void build_matvec_plan(HostGame& hg, int d, int rows_per_block) {
       if (cnt) { D.blk.push_back((int32_t)D.items.size()); D.blk_inst.push_back((int32_t)ii); }
     }
   }
+  // runs of consecutive items of a chunk that share a context
+  for (size_t b = 0; b + 1 < D.blk.size(); ++b) {
+    for (int it = D.blk[b + 1] - 1; it >= D.blk[b]; --it) {
+      MvItem& m = D.items[it];
+      const bool joins = it + 1 < D.blk[b + 1] && m.ctx >= 0 && D.items[it + 1].ctx == m.ctx;
+      m.run_end = joins ? D.items[it + 1].run_end : it + 1;
+    }
+  }
 }
 
 // Chunk-aligned layout of one direction for workgroups of `block` threads
@@ -754,7 +762,8 @@ int build_mc_layout(HostGame& hg, int d, int block, std::string& msg) {
         msg = "instance " + std::to_string(ii) + ": scan entries exceed the workgroup";
         return PMX_EINVAL;
       }
-      auto slot = [&](int sg, int i) { return (cstart[sg] + i / ke) * sk + i % ke; };
+      // byte offset of a slot for 4-byte values (the FP64 kernels double it)
+      auto slot = [&](int sg, int i) { return 4 * ((cstart[sg] + i / ke) * sk + i % ke); };
       McCtx m{};
       m.n_own = in.n[p];
       m.n_opp = in.n[q];

@@ -442,6 +442,12 @@ __device__ inline const float* mc_lam<float>(const McParams& P) { return P.lamf;
 template <>
 __device__ inline const double* mc_lam<double>(const McParams& P) { return P.lam; }
 
+// LDS value at a slot given as the byte offset of a 4-byte value.
+template <typename IO>
+__device__ inline IO& at_slot(IO* base, int off4) {
+  return *(IO*)((char*)base + (sizeof(IO) == 4 ? off4 : 2 * off4));
+}
+
 template <typename IO>
 struct Vec4;
 template <>
@@ -470,8 +476,18 @@ struct Vec4<double> {
 // (rounded once to IO) over the showdown channel and its segment totals, and
 // every own hand reads the prefix sums at its query slots (Technique B) and
 // the per-card fold totals (eq. cf).
+// Wavefronts per SIMD each FP32 class is built for: the register budget of
+// the workgroups per CU its LDS allows (4 of 256 threads for the small
+// classes, 3 and 2 for the larger ones, 2 of 512).  The FP64 forms, used for
+// the gap only, are left unconstrained.
 template <int BLOCK, int KH, typename IO>
-__global__ __launch_bounds__(BLOCK) void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
+constexpr int mc_waves_per_simd() {
+  return sizeof(IO) != 4 ? 1 : (BLOCK == 512 ? 4 : (KH <= 2 ? 4 : (KH <= 4 ? 3 : 2)));
+}
+
+template <int BLOCK, int KH, typename IO>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(mc_waves_per_simd<BLOCK, KH, IO>())))
+void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
                                                McParams P1, const IO* __restrict__ in1, IO* __restrict__ out1,
                                                double* __restrict__ tick) {
   constexpr int KE = BLOCK == 512 ? 4 * KH : 4 * KH + 4;
@@ -562,15 +578,15 @@ __global__ __launch_bounds__(BLOCK) void k_mvc(McParams P0, const IO* __restrict
         const int c0 = hi16(pp.x), c1 = lo16(pp.y);
         if (hs) {
           const IO v = ks * lp[k] * cs_in[k];
-          S[g] = v;
-          S[c0] = v;
-          if (c1 >= 0) S[c1] = v;
+          at_slot(S, g) = v;
+          at_slot(S, c0) = v;
+          if (c1 >= 0) at_slot(S, c1) = v;
         }
         if (hf) {
           const IO v = kf * lp[k] * cf_in[k];
-          F[g] = v;
-          F[c0] = v;
-          if (c1 >= 0) F[c1] = v;
+          at_slot(F, g) = v;
+          at_slot(F, c0) = v;
+          if (c1 >= 0) at_slot(F, c1) = v;
         }
       }
     }
@@ -604,15 +620,21 @@ __global__ __launch_bounds__(BLOCK) void k_mvc(McParams P0, const IO* __restrict
     double es, ef;
     block_seg_scan_x<NW>((int)((cm >> 8) & 1u), ts, tf, scr, es, ef);
     if (hs && wlive) {
-      IO run = (IO)0;
+      // FP32: the FP64 carry as a rounded head plus its remainder, so each
+      // prefix is head + (remainder + partial) in two FP32 adds.  Slots past
+      // a segment's end slot (which only sums valid entries) receive
+      // unspecified values; the first pass masks them and no query reads
+      // them.
+      const IO eh = (IO)es;
+      IO run = sizeof(IO) == 4 ? (IO)(es - (double)eh) : (IO)0;
 #pragma unroll
       for (int j = 0; j < KE; j += VN) {
         IO v[VN], pc[VN];
         Vec4<IO>::ld(&S[tid * SK + j], v);
 #pragma unroll
         for (int u = 0; u < VN; ++u) {
-          pc[u] = (IO)(es + (double)run);
-          run += j + u < nv ? v[u] : (IO)0;
+          pc[u] = eh + run;
+          run += v[u];
         }
         Vec4<IO>::st(&S[tid * SK + j], pc);
       }
@@ -636,15 +658,15 @@ __global__ __launch_bounds__(BLOCK) void k_mvc(McParams P0, const IO* __restrict
         const double2 Tb = cph == 2 ? T2[1 + c1] : make_double2(0.0, 0.0);
         double v = 0.0;
         if (hs) {
-          double sd = (double)S[lt] + (double)S[hi16(r.x)] - T0.x;
-          sd -= (double)S[lo16(r.y)] + (double)S[hi16(r.y)] - Ta.x;
-          if (cph == 2) sd -= (double)S[lo16(r.z)] + (double)S[hi16(r.z)] - Tb.x;
+          double sd = (double)at_slot(S, lt) + (double)at_slot(S, hi16(r.x)) - T0.x;
+          sd -= (double)at_slot(S, lo16(r.y)) + (double)at_slot(S, hi16(r.y)) - Ta.x;
+          if (cph == 2) sd -= (double)at_slot(S, lo16(r.z)) + (double)at_slot(S, hi16(r.z)) - Tb.x;
           v += sd;
         }
         if (hf) {
           double fo = T0.y - Ta.y - Tb.y;
           const int self = hi16(r.w);
-          if (cph == 2 && self >= 0) fo += (double)F[self];
+          if (cph == 2 && self >= 0) fo += (double)at_slot(F, self);
           v += fo;
         }
         acc[k] += v;

@@ -137,6 +137,8 @@ struct MvItem {
   int32_t last;                         // 1: last item of its output row
   int32_t n_own, stride;                // output row length and padded stride
   double kf, ks;                        // coefficients (payoff x chance)
+  int32_t run_end;                      // one past the last item of this chunk with the same ctx
+  int32_t pad;
 };
 struct MvDir {                          // host copy of one direction's plan
   std::vector<MvCtx> ctx;
@@ -174,6 +176,7 @@ struct McCtx {                           // (instance, context) as seen by one d
 };
 // Chunk descriptor bits: 0-7 valid entries, 8 first chunk of a segment,
 // 16-23 (segment + 1) when the chunk is the last of its segment.
+// Slots are stored as byte offsets of 4-byte values (int16; -1 = none).
 struct McDir {
   int block = 256;                       // threads per workgroup the layout is built for
   std::vector<McCtx> ctx;                // same indexing as MvDir::ctx
