@@ -938,21 +938,108 @@ int build_rm_plan(HostGame& hg, int p, int cap, std::string& msg) {
       P.rows.insert(P.rows.end(), seqs.begin(), seqs.end());
       std::vector<int32_t> ext;
       t.inf_off = (int32_t)P.infs.size();
-      t.n_inf = (int32_t)members.size();
-      for (int i : members) {
+      const int nm = (int)members.size();
+      t.n_inf = (int32_t)nm;
+      std::vector<int> par_of(nm), pinf(nm, -1);   // parent code; member index of the parent infoset
+      for (int m = 0; m < nm; ++m) {
+        const int i = members[m];
         int par;
         if (inf[i].parent < 0) {
           par = -1;
         } else if (local(inf[i].parent) >= 0) {
           par = local(inf[i].parent);
+          pinf[m] = (int)(std::lower_bound(members.begin(), members.end(), owner[inf[i].parent]) - members.begin());
         } else {
           auto it = std::find(ext.begin(), ext.end(), inf[i].parent);
           int k = (int)(it - ext.begin());
           if (it == ext.end()) ext.push_back(inf[i].parent);
           par = -2 - k;
         }
+        par_of[m] = par;
+      }
+      // Split the piece for the four wavefronts of a block: up to four groups
+      // of whole subtrees (largest first onto the least loaded wavefront)
+      // walked concurrently, and the top part above them walked by wavefront
+      // 0.  A group root's value goes to its wavefront's accumulator slot j
+      // (one per distinct parent target); wavefront 0 adds the slots into
+      // their targets in a fixed order before walking the top part.
+      std::vector<int> rows_t(nm, 0);
+      for (int m = nm - 1; m >= 0; --m) {
+        rows_t[m] += inf[members[m]].nact;
+        if (pinf[m] >= 0) rows_t[pinf[m]] += rows_t[m];
+      }
+      int total_rows = 0;
+      for (int m = 0; m < nm; ++m)
+        if (pinf[m] < 0) total_rows += rows_t[m];
+      std::vector<int> group(nm, -1), root_slot(nm, -1);
+      std::vector<std::vector<int>> gtargets(kRmGroups);
+      int n_groups = 0;
+      if (nm >= 8 && total_rows >= 16) {
+        const int target = std::max(4, (total_rows + kRmGroups - 1) / kRmGroups);
+        std::vector<int> cand;
+        for (int m = 0; m < nm; ++m)
+          if (rows_t[m] <= target && (pinf[m] < 0 || rows_t[pinf[m]] > target)) cand.push_back(m);
+        std::stable_sort(cand.begin(), cand.end(), [&](int a, int c) { return rows_t[a] > rows_t[c]; });
+        int load[kRmGroups] = {0, 0, 0, 0};
+        for (int m : cand) {
+          int w = 0;
+          for (int q2 = 1; q2 < kRmGroups; ++q2)
+            if (load[q2] < load[w]) w = q2;
+          auto& tg = gtargets[w];
+          auto it = std::find(tg.begin(), tg.end(), par_of[m]);
+          if (it == tg.end()) {
+            if ((int)tg.size() >= kRmGroupSlots) continue;   // stays in the top part
+            tg.push_back(par_of[m]);
+            it = tg.end() - 1;
+          }
+          root_slot[m] = (int)(it - tg.begin());
+          load[w] += rows_t[m];
+          group[m] = w;
+        }
+        // members below a group root belong to its group (depth-first order:
+        // parents come first)
+        for (int m = 0; m < nm; ++m)
+          if (group[m] < 0 && pinf[m] >= 0 && group[pinf[m]] >= 0) group[m] = group[pinf[m]];
+        for (int w = 0; w < kRmGroups; ++w)
+          if (load[w] > 0) ++n_groups;
+        if (n_groups < 2) {
+          std::fill(group.begin(), group.end(), -1);
+          std::fill(root_slot.begin(), root_slot.end(), -1);
+          for (auto& tg : gtargets) tg.clear();
+          n_groups = 0;
+        }
+      }
+      std::vector<int> order;
+      int gb[kRmGroups + 1];
+      for (int w = 0; w < kRmGroups; ++w) {
+        gb[w] = (int)order.size();
+        for (int m = 0; m < nm; ++m)
+          if (group[m] == w) order.push_back(m);
+      }
+      gb[kRmGroups] = (int)order.size();
+      for (int m = 0; m < nm; ++m)
+        if (group[m] < 0) order.push_back(m);
+      for (int m : order) {
+        const int i = members[m];
         const int f = local(inf[i].first);
-        P.infs.push_back((int32_t)((uint32_t)f | ((uint32_t)inf[i].nact << 8) | ((uint32_t)(uint16_t)(int16_t)par << 16)));
+        const uint32_t jr = root_slot[m] >= 0 ? (uint32_t)(root_slot[m] + 1) : 0u;
+        P.infs.push_back((int32_t)((uint32_t)f | ((uint32_t)inf[i].nact << 8) | (jr << 15) |
+                                   ((uint32_t)par_of[m] << 20)));
+      }
+      t.grp_off = -1;
+      if (n_groups > 0) {
+        t.grp_off = (int32_t)P.grp.size();
+        std::vector<int32_t> G(64, 0);
+        G[0] = kRmGroups;
+        for (int w = 0; w < kRmGroups; ++w) {
+          G[1 + w] = gb[w];
+          G[5 + w] = gb[w + 1];
+          G[11 + w] = (int)gtargets[w].size();
+          for (size_t j = 0; j < gtargets[w].size(); ++j) G[16 + kRmGroupSlots * w + j] = gtargets[w][j];
+        }
+        G[9] = gb[kRmGroups];
+        G[10] = nm;
+        P.grp.insert(P.grp.end(), G.begin(), G.end());
       }
       t.ext_off = (int32_t)P.ext_seq.size();
       t.n_ext = (int32_t)ext.size();

@@ -923,6 +923,7 @@ struct RmParams {
   const int32_t* pulls;
   const int32_t* ext_seq;
   const int32_t* ext_slot;
+  const int32_t* grp;           // group tables of split pieces
   const int32_t* active;        // per-instance flag (NULL: all)
   int32_t stage_stride;
   int32_t max_rows, max_ext;    // LDS layout of the launch
@@ -1055,10 +1056,13 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
   float* Rl = rsm + P.max_rows * 64;        // [max_rows][64]
   float* Xl = Rl + P.max_rows * 64;         // [max_ext][64]: root values / parent weights
   float* One = Xl + P.max_ext * 64;         // [64]: sink of root values, then 1 (root weight)
+  float* Xw = One + 64;                     // [RMW][kRmGroupSlots][64]: group-root values
   const int64_t base = T.vec_base + h, stride = T.stride;
   const RmStep K = rm_step(P.dcfr, P.gamma, P.alpha, P.beta, *tdev);
   const int rowv = lane < SL ? P.rows[T.rows_off + lane] : 0;
-  const int infv = (wv == 0 && lane < T.n_inf) ? P.infs[T.inf_off + lane] : 0;
+  const int infv = lane < T.n_inf ? P.infs[T.inf_off + lane] : 0;
+  const bool grouped = T.grp_off >= 0;
+  const int grpv = grouped ? P.grp[T.grp_off + lane] : 0;
   const int extv = (MODE != 0 && wv == 0 && lane < T.n_ext)
                        ? (MODE == 1 ? P.ext_slot[T.ext_off + lane] : P.ext_seq[T.ext_off + lane]) : 0;
   {
@@ -1104,28 +1108,63 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
       }
     }
   }
+  if (MODE != 2 && wv == 0)
+    for (int k = 0; k < T.n_ext; ++k) Xl[k * 64 + lane] = 0.f;
   __syncthreads();
-  if (wv == 0) {
-    if (MODE != 2) {
-      for (int k = 0; k < T.n_ext; ++k) Xl[k * 64 + lane] = 0.f;
-      for (int i = T.n_inf - 1; i >= 0; --i) {
+  // infoset ranges: wavefront wv's group, and the top part (all infosets when
+  // the piece is not split)
+  const int gb = grouped ? rl(grpv, 1 + wv) : 0, ge = grouped ? rl(grpv, 5 + wv) : 0;
+  const int tb = grouped ? rl(grpv, 9) : 0, te = grouped ? rl(grpv, 10) : T.n_inf;
+  if (MODE != 2) {
+    if (grouped) {
+      // groups concurrently; a group root's value goes to its slot in Xw
+      float* Xa = Xw + wv * kRmGroupSlots * 64;
+      for (int j = 0; j < rl(grpv, 11 + wv); ++j) Xa[j * 64 + lane] = 0.f;
+      for (int i = ge - 1; i >= gb; --i) {
         const int v = rl(infv, i);
-        const int par = v >> 16;
+        const int jr = (v >> 15) & 31, par = v >> 20;
+        float* pp = jr ? &Xa[(jr - 1) * 64 + lane] : &Al[par * 64 + lane];
+        rmp_up(Al, Rl, pp, v & 255, (v >> 8) & 127, lane, K);
+      }
+      __syncthreads();
+      if (wv == 0) {   // group-root values into their targets, in a fixed order
+        for (int w = 0; w < RMW; ++w)
+          for (int j = 0; j < rl(grpv, 11 + w); ++j) {
+            const int tg = rl(grpv, 16 + kRmGroupSlots * w + j);
+            const float gv = Xw[(w * kRmGroupSlots + j) * 64 + lane];
+            if (tg >= 0) Al[tg * 64 + lane] += gv;
+            else if (tg <= -2) Xl[(-2 - tg) * 64 + lane] += gv;
+          }
+      }
+    }
+    if (wv == 0) {
+      for (int i = te - 1; i >= tb; --i) {
+        const int v = rl(infv, i);
+        const int par = v >> 20;
         float* pp = par >= 0 ? &Al[par * 64 + lane] : (par <= -2 ? &Xl[(-2 - par) * 64 + lane] : &One[lane]);
-        rmp_up(Al, Rl, pp, v & 255, (v >> 8) & 255, lane, K);
+        rmp_up(Al, Rl, pp, v & 255, (v >> 8) & 127, lane, K);
       }
       if (MODE == 1 && act)
         for (int k = 0; k < T.n_ext; ++k)
           stage[(int64_t)rl(extv, k) * P.stage_stride + h] = Xl[k * 64 + lane];
     }
-    if (MODE != 1) {
-      One[lane] = 1.f;
-      for (int i = 0; i < T.n_inf; ++i) {
+  }
+  if (MODE != 1) {
+    auto down = [&](int i0, int i1) {
+      for (int i = i0; i < i1; ++i) {
         const int v = rl(infv, i);
-        const int par = v >> 16;
+        const int par = v >> 20;
         const float* xpp = par >= 0 ? &Al[par * 64 + lane] : (par == -1 ? &One[lane] : &Xl[(-2 - par) * 64 + lane]);
-        rmp_down(Al, Rl, xpp, v & 255, (v >> 8) & 255, lane);
+        rmp_down(Al, Rl, xpp, v & 255, (v >> 8) & 127, lane);
       }
+    };
+    if (wv == 0) {
+      One[lane] = 1.f;
+      down(tb, te);
+    }
+    if (grouped) {
+      __syncthreads();
+      down(gb, ge);
     }
   }
   __syncthreads();
@@ -1415,7 +1454,7 @@ struct DevTp {
 
 struct DevRm {                  // regret-update pieces of one player
   DBuf<RmTask> tasks;
-  DBuf<int32_t> rows, infs, pulls, ext_seq, ext_slot;
+  DBuf<int32_t> rows, infs, pulls, ext_seq, ext_slot, grp;
   DBuf<int2> blocks;            // all depths, depth d at [blk_off[d], blk_off[d + 1])
   std::vector<int> blk_off;
   std::vector<int> max_rows, max_ext;   // per depth
@@ -1560,7 +1599,8 @@ static int upload_rm(Game* g, int p) {
   DevRm& E = g->drm[p];
   int rc;
   if ((rc = E.tasks.upload(T.tasks)) || (rc = E.rows.upload(T.rows)) || (rc = E.infs.upload(T.infs)) ||
-      (rc = E.pulls.upload(T.pulls)) || (rc = E.ext_seq.upload(T.ext_seq)) || (rc = E.ext_slot.upload(T.ext_slot)))
+      (rc = E.pulls.upload(T.pulls)) || (rc = E.ext_seq.upload(T.ext_seq)) || (rc = E.ext_slot.upload(T.ext_slot)) ||
+      (rc = E.grp.upload(T.grp)))
     return rc;
   std::vector<int2> blocks;
   const int D = (int)T.by_depth.size();
@@ -1887,6 +1927,7 @@ static RmParams rm_params(Game* g, int p, int depth) {
   P.pulls = E.pulls.p;
   P.ext_seq = E.ext_seq.p;
   P.ext_slot = E.ext_slot.p;
+  P.grp = E.grp.p;
   P.active = g->active.p;
   P.stage_stride = E.stage_stride;
   P.max_rows = E.max_rows[depth];
@@ -1910,7 +1951,7 @@ static int rm_update(Game* g, int p, hipStream_t s) {
     const int nb = E.blk_off[d + 1] - E.blk_off[d];
     if (nb == 0) return;
     const RmParams P = rm_params(g, p, d);
-    const size_t lds = sizeof(float) * 64 * (size_t)(2 * P.max_rows + P.max_ext + 1);
+    const size_t lds = sizeof(float) * 64 * (size_t)(2 * P.max_rows + P.max_ext + 1 + RMW * kRmGroupSlots);
     if (mode == 0)
       hipLaunchKernelGGL(k_rmp<0>, dim3(nb), dim3(64 * RMW), lds, s, P, gr, g->R[p].p, g->x[p].p, g->xs[p].p,
                          E.stage.p, td);

@@ -221,6 +221,8 @@ struct TpPlan {                         // one player
 // the parent sequence's realization weight back in its top-down pass.
 constexpr int kTaskRowsMax = 64;        // rows per piece (one per lane of a wavefront)
 constexpr int kTaskExtMax = 16;         // distinct external parents per piece
+constexpr int kRmGroups = 4;            // subtree groups walked concurrently (wavefronts per block)
+constexpr int kRmGroupSlots = 4;        // distinct parent targets of one group's roots
 struct RmTask {
   int64_t vec_base;
   int32_t stride, n_hands;
@@ -229,13 +231,20 @@ struct RmTask {
   int32_t pull_off, n_pull;             // stage rows added into local rows before the walk
   int32_t ext_off, n_ext;               // external parents: sequence and stage row
   int32_t inst, depth;
+  int32_t grp_off, pad;                 // 64-int group table, -1: one wavefront walks the piece
 };
-// Packed local infoset: first local row (bits 0-7) | actions (bits 8-15) |
-// parent (bits 16-31, signed): >= 0 local row, -1 empty sequence, -2-k the
-// k-th external parent.  Pull: local row (bits 0-7) | stage row << 8.
+// Packed local infoset: first local row (bits 0-7) | actions (bits 8-14) |
+// group-root accumulator slot + 1 (bits 15-19, 0: none) | parent (bits
+// 20-31, signed): >= 0 local row, -1 empty sequence, -2-k the k-th external
+// parent.  Pull: local row (bits 0-7) | stage row << 8.  Group table:
+// [0] groups, [1 + w] / [5 + w] infoset range of group w, [9] / [10] range of
+// the top part, [11 + w] targets of group w, [16 + kRmGroupSlots w + j]
+// its target j
+// (parent code as above).  Infosets are listed group by group, then the top
+// part, each in depth-first order.
 struct RmPlan {                         // one player
   std::vector<RmTask> tasks;
-  std::vector<int32_t> rows, infs, pulls, ext_seq, ext_slot;
+  std::vector<int32_t> rows, infs, pulls, ext_seq, ext_slot, grp;
   std::vector<std::vector<int32_t>> by_depth;   // task ids per depth (0: no external parent)
   int n_slot = 0, stage_stride = 0;
   int max_rows[2] = {0, 0}, max_ext[2] = {0, 0};   // [depth 0, deeper] LDS sizing
