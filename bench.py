@@ -27,6 +27,27 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 
+# HBM bytes per matvec-pair launch from two rocprofv3 --pmc runs (FETCH_SIZE,
+# then WRITE_SIZE), each scaled by what the counter reads for a plain copy of
+# known size (profiles/matvec_pair_traffic_counters.md).  They describe the
+# kernel sources whose SHA-1 is recorded here and are reported as null for any
+# other version of those sources.
+TRAFFIC = {"sources_sha1": "cb14f1f4546c01b6fba488f8781f3cad165eca7e", "river": 1626175, "batch": 449777304}
+TRAFFIC_SOURCES = ("paper_2112_03804_amd/csrc/pmx_device.hip", "paper_2112_03804_amd/csrc/host_build.cpp")
+
+
+def sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key):
+    return TRAFFIC[key] if TRAFFIC["sources_sha1"] == sources_sha1() else None
+
 
 def algorithmic_bytes_pair(layouts):
     """Bytes one matvec pair must move: read y and x, write A y and A^T x
@@ -148,7 +169,8 @@ def batched_leg(args, stream):
         "iteration_ms": it_ms,
         "matvec_pairs_per_s": len(descs) / (it_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "kernel": "k_matvec (matvec_pair launch)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("batch"),
+                     "kernel": "k_mvc (matvec_pair launch, schedule %d:%d)" % tuple(sched),
                      "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair},
         "time_to_gap_batched_s": ttg_batched,
         "time_to_gap_batched_no_retirement_s": ttg_noretire,
@@ -166,7 +188,9 @@ def batched_leg(args, stream):
 def turn_river_leg(args, stream):
     """The turn + river endgame: one instance of 19,480 sequences x 1128 hands
     per player (352 MB per matvec pair): tuned matvec-pair roofline, solver
-    iteration time, and the FP64 gap after a fixed number of iterations."""
+    iteration time, and the precision run: discounted CFR from a uniform
+    start toward an FP64 saddle gap of 1e-8 * pot, the gap checked at doubling
+    iteration counts, within a time budget."""
     import torch
     from paper_2112_03804_amd import autotune
     from paper_2112_03804_amd import instances as I
@@ -176,7 +200,7 @@ def turn_river_leg(args, stream):
     t_create = time.perf_counter()
     g = pmx.Game(desc)
     t_create = time.perf_counter() - t_create
-    sched, sched_us = autotune.tune(g, candidates=[(0, 1), (0, 4), (0, 8), (1, 2)], reps=10,
+    sched, sched_us = autotune.tune(g, candidates=[(0, 8), (2, 4), (2, 8), (3, 4), (3, 8)], reps=10,
                                     use_cache=False)
     bytes_pair = algorithmic_bytes_pair(g.layouts)
     pair_us = min(sched_us.values())
@@ -190,6 +214,28 @@ def turn_river_leg(args, stream):
     torch.cuda.synchronize()
     it_ms = e0.elapsed_time(e1) / args.turn_steps
     gap = float(g.saddle_gap()[0][0])
+    # precision run
+    pot = 2 * desc.contrib
+    g.solver_set_params("dcfr")
+    g.solver_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it, nxt, traj, reached = 0, 256, [], False
+    while True:
+        g.solver_step(nxt - it)
+        it = nxt
+        gp = float(g.saddle_gap()[0][0]) / pot
+        el = time.perf_counter() - t0
+        traj.append([it, round(el, 3), gp])
+        if gp <= 1e-8:
+            reached = True
+            break
+        # next check: double, or what the measured rate still allows in budget
+        per_it = el / it
+        left = args.turn_budget - el
+        if left < 256 * per_it:
+            break
+        nxt = it + min(it, int(left / per_it) // 256 * 256)
     out = {"workload": "turn + river endgame: 4-card board, 48 river cards, 1128 hands/player, "
                        "bets {0.33,0.75,1.5}xpot + all-in, max 3 raises per street, pot 100, stacks 400",
            "game_create_s": t_create,
@@ -197,11 +243,16 @@ def turn_river_leg(args, stream):
            "roofline": {"bound": "hbm", "achieved": bytes_pair / (pair_us * 1e-6) / 1e9,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": bytes_pair / (pair_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
-                        "kernel": "k_matvec (matvec_pair launch)", "us_per_launch": pair_us,
-                        "algorithmic_bytes_per_launch": bytes_pair},
+                        "kernel": "k_mvc (matvec_pair launch, schedule %d:%d)" % tuple(sched),
+                        "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair},
            "matvec_pairs_per_s": 1e6 / pair_us,
            "iteration_ms": it_ms,
-           "gap_over_pot_after": {"iterations": 4 + args.turn_steps, "gap_over_pot": gap / (2 * desc.contrib)}}
+           "gap_over_pot_after": {"iterations": 4 + args.turn_steps, "gap_over_pot": gap / (2 * desc.contrib)},
+           "precision_run": {"solver": "DCFR (alpha 1.5, beta 0, gamma 2), uniform start, FP32 gradients "
+                                       "with FP64-carried scans; gap from FP64 matvecs and FP64 best responses",
+                             "target_gap_over_pot": 1e-8, "reached": reached,
+                             "iterations": it, "seconds": traj[-1][1], "gap_over_pot": traj[-1][2],
+                             "trajectory_iters_s_gap": traj, "budget_s": args.turn_budget}}
     g.close()
     return out
 
@@ -295,8 +346,8 @@ def trace_probe(args):
     import torch
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
-    for name, make, sched, iters in (("batch", lambda: pmx.Game(I.batched_configs(args.batch)), (0, 8), 64),
-                                     ("turn_river", lambda: pmx.Game(I.config(2)), (0, 8), 32)):
+    for name, make, sched, iters in (("batch", lambda: pmx.Game(I.batched_configs(args.batch)), (2, 4), 64),
+                                     ("turn_river", lambda: pmx.Game(I.config(2)), (3, 8), 32)):
         g = make()
         g.game_tune(*sched)
         g.solver_reset()
@@ -328,6 +379,8 @@ def main():
     ap.add_argument("--trace-probe", action="store_true",
                     help="only run solver iterations on the batch and the turn + river game")
     ap.add_argument("--turn-steps", type=int, default=20)
+    ap.add_argument("--turn-budget", type=float, default=90.0,
+                    help="seconds for the turn + river precision run")
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--warm-train", type=int, default=1024)
     ap.add_argument("--warm-label-iters", type=int, default=3072)
@@ -430,9 +483,9 @@ def main():
                    "n_seq": [L[0][0]["n_seq"], L[0][1]["n_seq"]],
                    "n_hands": [L[0][0]["n_hands"], L[0][1]["n_hands"]]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_matvec (matvec_pair launch)", "us_per_launch": pair_us,
-                     "algorithmic_bytes_per_launch": bytes_pair},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("river"),
+                     "kernel": "k_mvc (matvec_pair launch, schedule %d:%d)" % g.game_get_tuning(),
+                     "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair},
         "time_to_gap": {"target": "1e-4*pot", "seconds": ttg, "iterations": iters,
                         "gap_over_pot": gap / pot, "solver": "plain RM+, uniform start, "
                         "FP64 gap checked every 25 iterations",
