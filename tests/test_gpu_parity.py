@@ -136,6 +136,37 @@ def test_matvec_river_full_size():
     _check_matvecs(pmx, I.config(1), seed=3)
 
 
+@pytest.mark.parametrize("kernel", [2, 3, 0])
+def test_matvec_max_hands(kernel):
+    """The largest hand lists a game may hold (1280 per player, the top
+    hands-per-thread class of each workgroup size) on a 57-card deck."""
+    pmx = _need_gpu()
+    d = I.river_config(seed=33, deck_size=57, bet_fracs=(0.75,), max_raises=1, n_keep=(1280, 1280),
+                       name="river_max_hands")
+    _say("matvec max hands, kernel", kernel)
+    o = payoff.Game(d)
+    g = pmx.Game(d)
+    g.game_tune(kernel, 1)
+    rng = np.random.default_rng(kernel)
+    y = _rand_vectors(o, rng, 1)
+    x = _rand_vectors(o, rng, 0)
+    Ay = torch.zeros(g.elems[0], dtype=torch.float32, device="cuda")
+    ATx = torch.zeros(g.elems[1], dtype=torch.float32, device="cuda")
+    g.matvec_pair(_dev(g.pack(1, [y]), np.float32), _dev(g.pack(0, [x]), np.float32), Ay, ATx)
+    Ayd = torch.zeros(g.elems[0], dtype=torch.float64, device="cuda")
+    g.matvec_A_f64(_dev(g.pack(1, [y], np.float64), np.float64), Ayd)
+    torch.cuda.synchronize()
+    gA, gAT = g.unpack(0, Ay.cpu().numpy())[0], g.unpack(1, ATx.cpu().numpy())[0]
+    gAd = g.unpack(0, Ayd.cpu().numpy())[0]
+    normA = o.abs_row_sums().max() * np.abs(y).max()
+    normAT = o.abs_col_sums().max() * np.abs(x).max()
+    ref_A, ref_AT = o.matvec_A(y), o.matvec_AT(x)
+    _assert_close(gA, ref_A, payoff.abs_matvec_A(o, y), 1e-6, F32_FLOOR * normA, "A y (fp32)")
+    _assert_close(gAT, ref_AT, payoff.abs_matvec_AT(o, x), 1e-6, F32_FLOOR * normAT, "A^T x (fp32)")
+    _assert_close(gAd, ref_A, payoff.abs_matvec_A(o, y), 1e-12, F64_FLOOR * normA, "A y (fp64)")
+    g.close()
+
+
 def test_matvec_batched_uneven():
     pmx = _need_gpu()
     descs = [I.river_config(seed=100 + i, n_keep=(40 + 37 * i, 200 - 13 * i),
