@@ -268,7 +268,8 @@ def warm_leg(args, stream, batched):
 
     t0 = time.perf_counter()
     train_descs = I.batched_configs(args.warm_train, seed=11)
-    ds = ws.make_dataset(train_descs, iters=args.warm_label_iters, batch=512)
+    ds = ws.make_dataset(train_descs, batch=512, target=args.warm_label_gap, kind="rm+",
+                         max_iters=args.warm_label_iters)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = ws.WarmMLP(seed=0)
@@ -292,7 +293,9 @@ def warm_leg(args, stream, batched):
     t_warm = time.perf_counter() - t2
     g.close()
     plain_total = batched["plain_single_instance_sample"]["sum_over_batch_extrapolated_s"]
-    return {"train_instances": len(train_descs), "label_iterations": args.warm_label_iters,
+    return {"train_instances": len(train_descs),
+            "labels": f"average strategies of the plain batched RM+ solver run to {args.warm_label_gap:g} * pot "
+                      f"(at most {args.warm_label_iters} iterations)",
             "dataset_rows": n_rows, "data_s": t_data,
             "train_steps": args.warm_steps, "train_s": t_train, "loss_history": hist,
             "train_tflops": rows_trained * flops_per_row / t_train / 1e12,
@@ -382,10 +385,11 @@ def main():
     ap.add_argument("--turn-budget", type=float, default=90.0,
                     help="seconds for the turn + river precision run")
     ap.add_argument("--no-warm", action="store_true")
-    ap.add_argument("--warm-train", type=int, default=1024)
-    ap.add_argument("--warm-label-iters", type=int, default=3072)
-    ap.add_argument("--warm-steps", type=int, default=2000)
-    ap.add_argument("--warm-scale", type=float, default=0.5)
+    ap.add_argument("--warm-train", type=int, default=2048)
+    ap.add_argument("--warm-label-gap", type=float, default=1e-5)
+    ap.add_argument("--warm-label-iters", type=int, default=12288)
+    ap.add_argument("--warm-steps", type=int, default=4000)
+    ap.add_argument("--warm-scale", type=float, default=1.0)
     ap.add_argument("--warm-avg", type=float, default=0.0)
     args = ap.parse_args()
     if args.gpus != 1:

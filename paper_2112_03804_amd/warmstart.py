@@ -170,13 +170,20 @@ class Dataset:
         return int(self.X.shape[0])
 
 
-def make_dataset(descs: Sequence, iters: int, batch: int = 512) -> Dataset:
-    """Solve the instances with the plain batched solver for `iters`
-    iterations and collect training rows from the average strategies."""
+def make_dataset(descs: Sequence, iters: int = 0, batch: int = 512, target: float = 0.0,
+                 kind: str = "rm+", max_iters: int = 100000) -> Dataset:
+    """Solve the instances in batches and collect training rows from the
+    average strategies: for `iters` iterations of the chosen solver, or, with
+    `target` > 0, until every instance's FP64 gap is at most target * its pot
+    (instances retire as they reach it; at most `max_iters` iterations)."""
     ds = Dataset()
     for a in range(0, len(descs), batch):
         g = pmx.Game(list(descs[a:a + batch]))
-        g.solver_step(iters)
+        g.solver_set_params(kind)
+        if target > 0:
+            solve_to_gap(g, target, check_every=64, max_iters=max_iters)
+        else:
+            g.solver_step(iters)
         ds.add_game(g)
         _torch().cuda.synchronize()
         g.close()
