@@ -141,6 +141,11 @@ def batched_leg(args, stream):
     g.solver_reset()
     ttg_noretire, iters_nr, _ = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters,
                                                 retire=False)
+    # the same with discounted CFR (the paper's solver family) instead of RM+
+    g.solver_set_params("dcfr")
+    g.solver_reset()
+    ttg_dcfr, iters_dcfr, _ = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters)
+    g.solver_set_params("rm+")
     g.close()
     # plain single-instance solver on a sample of the same instances
     sample = list(range(0, len(descs), max(1, len(descs) // args.plain_sample)))[:args.plain_sample]
@@ -174,6 +179,8 @@ def batched_leg(args, stream):
                      "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair},
         "time_to_gap_batched_s": ttg_batched,
         "time_to_gap_batched_no_retirement_s": ttg_noretire,
+        "time_to_gap_batched_dcfr_s": ttg_dcfr,
+        "iterations_batched_dcfr": iters_dcfr,
         "iterations_batched": iters,
         "instances_reached": int((done_at >= 0).sum()),
         "iterations_per_instance_p50_p90_max": [float(np.percentile(done_at[done_at > 0], q))
