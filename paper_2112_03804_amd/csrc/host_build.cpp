@@ -936,6 +936,7 @@ int build_rm_plan(HostGame& hg, int p, int cap, std::string& msg) {
       t.rows_off = (int32_t)P.rows.size();
       t.n_rows = (int32_t)seqs.size();
       P.rows.insert(P.rows.end(), seqs.begin(), seqs.end());
+      t.row0 = (!seqs.empty() && seqs.back() - seqs.front() + 1 == (int)seqs.size()) ? seqs.front() : -1;
       std::vector<int32_t> ext;
       t.inf_off = (int32_t)P.infs.size();
       const int nm = (int)members.size();

@@ -915,9 +915,14 @@ __global__ void k_set1(double* tdev, double v) { tdev[0] = v; }
 // one entry per lane and read with readlane, so the walk touches LDS only
 // for the slab itself.
 // ---------------------------------------------------------------------------
+// One workgroup of a regret-update launch: its piece and first hand.
+struct RmBlock {
+  RmTask t;
+  int32_t h0, pad[3];
+};
+
 struct RmParams {
-  const RmTask* tasks;
-  const int2* blocks;           // (task, first hand)
+  const RmBlock* blocks;
   const int32_t* rows;
   const int32_t* infs;
   const int32_t* pulls;
@@ -1044,12 +1049,12 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
                                                   float* __restrict__ x, double* __restrict__ xs,
                                                   float* __restrict__ stage, const double* __restrict__ tdev) {
   extern __shared__ float rsm[];
-  const int2 bt = P.blocks[blockIdx.x];
-  const RmTask T = P.tasks[bt.x];
+  const RmTask T = P.blocks[blockIdx.x].t;
+  const int h0 = P.blocks[blockIdx.x].h0;
   if (P.active && !P.active[T.inst]) return;   // whole block: T is uniform
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int h = bt.y + lane;
+  const int h = h0 + lane;
   const bool act = h < T.n_hands;
   const int SL = T.n_rows;
   float* Al = rsm;                          // [max_rows][64]: g, then the new x
@@ -1059,7 +1064,8 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
   float* Xw = One + 64;                     // [RMW][kRmGroupSlots][64]: group-root values
   const int64_t base = T.vec_base + h, stride = T.stride;
   const RmStep K = rm_step(P.dcfr, P.gamma, P.alpha, P.beta, *tdev);
-  const int rowv = lane < SL ? P.rows[T.rows_off + lane] : 0;
+  // row ids, one per lane: computed for contiguous pieces, else from the table
+  const int rowv = T.row0 >= 0 ? T.row0 + lane : (lane < SL ? P.rows[T.rows_off + lane] : 0);
   const int infv = lane < T.n_inf ? P.infs[T.inf_off + lane] : 0;
   const bool grouped = T.grp_off >= 0;
   const int grpv = grouped ? P.grp[T.grp_off + lane] : 0;
@@ -1169,13 +1175,21 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
   }
   __syncthreads();
   if (act) {
+    // all LDS reads first, then the stores
+    float a[RMR], b[RMR];
+#pragma unroll
+    for (int k = 0; k < RMR; ++k) {
+      const int r = min(wv + RMW * k, SL - 1);
+      if (MODE != 2) b[k] = Rl[r * 64 + lane];
+      if (MODE != 1) a[k] = Al[r * 64 + lane];
+    }
 #pragma unroll
     for (int k = 0; k < RMR; ++k) {
       const int r = wv + RMW * k;
       if (r < SL) {
         const int64_t idx = base + (int64_t)rl(rowv, r) * stride;
-        if (MODE != 2) R[idx] = Rl[r * 64 + lane];
-        if (MODE != 1) x[idx] = Al[r * 64 + lane];
+        if (MODE != 2) R[idx] = b[k];
+        if (MODE != 1) x[idx] = a[k];
       }
     }
   }
@@ -1453,9 +1467,8 @@ struct DevTp {
 };
 
 struct DevRm {                  // regret-update pieces of one player
-  DBuf<RmTask> tasks;
   DBuf<int32_t> rows, infs, pulls, ext_seq, ext_slot, grp;
-  DBuf<int2> blocks;            // all depths, depth d at [blk_off[d], blk_off[d + 1])
+  DBuf<RmBlock> blocks;         // all depths, depth d at [blk_off[d], blk_off[d + 1])
   std::vector<int> blk_off;
   std::vector<int> max_rows, max_ext;   // per depth
   DBuf<float> stage;
@@ -1598,11 +1611,11 @@ static int upload_rm(Game* g, int p) {
   const RmPlan& T = g->hg.rm[p];
   DevRm& E = g->drm[p];
   int rc;
-  if ((rc = E.tasks.upload(T.tasks)) || (rc = E.rows.upload(T.rows)) || (rc = E.infs.upload(T.infs)) ||
+  if ((rc = E.rows.upload(T.rows)) || (rc = E.infs.upload(T.infs)) ||
       (rc = E.pulls.upload(T.pulls)) || (rc = E.ext_seq.upload(T.ext_seq)) || (rc = E.ext_slot.upload(T.ext_slot)) ||
       (rc = E.grp.upload(T.grp)))
     return rc;
-  std::vector<int2> blocks;
+  std::vector<RmBlock> blocks;
   const int D = (int)T.by_depth.size();
   E.blk_off.assign(D + 1, 0);
   E.max_rows.assign(D, 0);
@@ -1613,7 +1626,12 @@ static int upload_rm(Game* g, int p) {
       const RmTask& t = T.tasks[id];
       E.max_rows[d] = std::max(E.max_rows[d], (int)t.n_rows);
       E.max_ext[d] = std::max(E.max_ext[d], (int)t.n_ext);
-      for (int h0 = 0; h0 < t.n_hands; h0 += 64) blocks.push_back(make_int2(id, h0));
+      for (int h0 = 0; h0 < t.n_hands; h0 += 64) {
+        RmBlock bk{};
+        bk.t = t;
+        bk.h0 = h0;
+        blocks.push_back(bk);
+      }
     }
   }
   E.blk_off[D] = (int)blocks.size();
@@ -1920,7 +1938,6 @@ static TpParams tp_params(Game* g, int p, const int2* blocks) {
 static RmParams rm_params(Game* g, int p, int depth) {
   DevRm& E = g->drm[p];
   RmParams P;
-  P.tasks = E.tasks.p;
   P.blocks = E.blocks.p + E.blk_off[depth];
   P.rows = E.rows.p;
   P.infs = E.infs.p;

@@ -231,7 +231,8 @@ struct RmTask {
   int32_t pull_off, n_pull;             // stage rows added into local rows before the walk
   int32_t ext_off, n_ext;               // external parents: sequence and stage row
   int32_t inst, depth;
-  int32_t grp_off, pad;                 // 64-int group table, -1: one wavefront walks the piece
+  int32_t grp_off;                      // 64-int group table, -1: one wavefront walks the piece
+  int32_t row0;                         // rows are row0 .. row0 + n_rows - 1, or -1: use the table
 };
 // Packed local infoset: first local row (bits 0-7) | actions (bits 8-14) |
 // group-root accumulator slot + 1 (bits 15-19, 0: none) | parent (bits

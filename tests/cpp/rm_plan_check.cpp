@@ -79,7 +79,14 @@ extern "C" int check_rm_plan(const GameDesc* d, int n, int cap, char* msg, int m
           snprintf(msg, msglen, "piece with %d rows above the cap %d", t.n_rows, cap);
           return 1;
         }
-        for (int r = 0; r < t.n_rows; ++r) count[P.rows[t.rows_off + r]]++;
+        for (int r = 0; r < t.n_rows; ++r) {
+          count[P.rows[t.rows_off + r]]++;
+          if (t.row0 >= 0 && P.rows[t.rows_off + r] != t.row0 + r) {
+            snprintf(msg, msglen, "piece marked contiguous from %d has row %d at %d", t.row0,
+                     P.rows[t.rows_off + r], r);
+            return 1;
+          }
+        }
       }
       for (int s = 0; s < S; ++s)
         if (count[s] != 1) {
