@@ -167,6 +167,48 @@ def test_matvec_max_hands(kernel):
     g.close()
 
 
+@pytest.mark.parametrize("kernel,rows", [(2, 1), (3, 2), (0, 1)])
+def test_matvec_extreme_ragged_batch(kernel, rows):
+    """One batch holding a 2-vs-3-hand instance, a 1280-hand instance on a
+    57-card deck and a mid-size one (every hands-per-thread class at once);
+    then one solver step of the batch equals each instance's own step."""
+    pmx = _need_gpu()
+    descs = [I.river_config(seed=41, n_keep=(2, 3), bet_fracs=(1.0,), max_raises=1),
+             I.river_config(seed=42, deck_size=57, n_keep=(1280, 1277), bet_fracs=(0.5,), max_raises=1),
+             I.river_config(seed=43, n_keep=(640, 333), bet_fracs=(0.33, 1.5), max_raises=2)]
+    _say("extreme ragged batch", kernel, rows)
+    g = pmx.Game(descs)
+    g.game_tune(kernel, rows)
+    os_ = [payoff.Game(d) for d in descs]
+    rng = np.random.default_rng(77)
+    ys = [_rand_vectors(o, rng, 1) for o in os_]
+    xs = [_rand_vectors(o, rng, 0) for o in os_]
+    Ay = torch.full((g.elems[0],), 5.0, dtype=torch.float32, device="cuda")
+    ATx = torch.full((g.elems[1],), 5.0, dtype=torch.float32, device="cuda")
+    g.matvec_pair(_dev(g.pack(1, ys), np.float32), _dev(g.pack(0, xs), np.float32), Ay, ATx)
+    torch.cuda.synchronize()
+    gA, gAT = g.unpack(0, Ay.cpu().numpy()), g.unpack(1, ATx.cpu().numpy())
+    for i, o in enumerate(os_):
+        fl = F32_FLOOR * o.abs_row_sums().max() * np.abs(ys[i]).max()
+        _assert_close(gA[i], o.matvec_A(ys[i]), payoff.abs_matvec_A(o, ys[i]), 1e-6, fl, f"A y inst {i}")
+        fl = F32_FLOOR * o.abs_col_sums().max() * np.abs(xs[i]).max()
+        _assert_close(gAT[i], o.matvec_AT(xs[i]), payoff.abs_matvec_AT(o, xs[i]), 1e-6, fl, f"A^T x inst {i}")
+    # the batch's iterates equal each instance solved on its own
+    g.solver_step(7)
+    torch.cuda.synchronize()
+    for i, d in enumerate(descs):
+        gi = pmx.Game(d)
+        gi.game_tune(kernel, rows)
+        gi.solver_step(7)
+        torch.cuda.synchronize()
+        for p in range(2):
+            xb = g.unpack(p, g.solver_get_state(p)["plan"])[i]
+            xi = gi.unpack(p, gi.solver_get_state(p)["plan"])[0]
+            assert np.abs(xb - xi).max() <= 1e-6, (i, p)
+        gi.close()
+    g.close()
+
+
 def test_matvec_batched_uneven():
     pmx = _need_gpu()
     descs = [I.river_config(seed=100 + i, n_keep=(40 + 37 * i, 200 - 13 * i),
