@@ -32,8 +32,13 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 # known size (profiles/matvec_pair_traffic_counters.md).  They describe the
 # kernel sources whose SHA-1 is recorded here and are reported as null for any
 # other version of those sources.
-TRAFFIC = {"sources_sha1": "cb14f1f4546c01b6fba488f8781f3cad165eca7e", "river": 1626175, "batch": 449777304}
+TRAFFIC = {"sources_sha1": "792b8f3b45a845a0ba846c41278fe42795731b5f", "river": 1630206, "batch": 449781162}
 TRAFFIC_SOURCES = ("paper_2112_03804_amd/csrc/pmx_device.hip", "paper_2112_03804_amd/csrc/host_build.cpp")
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 
 
 def sources_sha1():
@@ -136,17 +141,21 @@ def batched_leg(args, stream):
     # batched time to gap: every instance at or below 1e-4 of its pot; solved
     # instances are retired from the iteration
     from paper_2112_03804_amd import warmstart as ws
+    log(f"batch: matvec pair {pair_us:.1f} us; solving to 1e-4 * pot")
     g.solver_reset()
     ttg_batched, iters, done_at = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters)
+    log(f"batch: time to gap {ttg_batched:.2f} s ({iters} iterations); without retirement")
     g.solver_reset()
     ttg_noretire, iters_nr, _ = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters,
                                                 retire=False)
     # the same with discounted CFR (the paper's solver family) instead of RM+
+    log(f"batch: without retirement {ttg_noretire:.2f} s; DCFR")
     g.solver_set_params("dcfr")
     g.solver_reset()
     ttg_dcfr, iters_dcfr, _ = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters)
     g.solver_set_params("rm+")
     g.close()
+    log(f"batch: DCFR {ttg_dcfr:.2f} s; plain single-instance sample")
     # plain single-instance solver on a sample of the same instances
     sample = list(range(0, len(descs), max(1, len(descs) // args.plain_sample)))[:args.plain_sample]
     plain_s, plain_it = [], []
@@ -234,6 +243,7 @@ def turn_river_leg(args, stream):
         gp = float(g.saddle_gap()[0][0]) / pot
         el = time.perf_counter() - t0
         traj.append([it, round(el, 3), gp])
+        log(f"turn+river precision run: {it} iterations, {el:.1f} s, gap/pot {gp:.3e}")
         if gp <= 1e-8:
             reached = True
             break
@@ -276,14 +286,17 @@ def warm_leg(args, stream, batched):
     t0 = time.perf_counter()
     train_descs = I.batched_configs(args.warm_train, seed=11)
     ds = ws.make_dataset(train_descs, batch=512, target=args.warm_label_gap, kind="rm+",
-                         max_iters=args.warm_label_iters)
+                         max_iters=args.warm_label_iters,
+                         progress=lambda a, n: log(f"warm start: labelled {a}/{n} instances"))
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = ws.WarmMLP(seed=0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log(f"warm start: {ds.rows} rows; training")
     hist = ws.train(net, ds, steps=args.warm_steps, batch_rows=8192, lr=1e-3,
-                    log_every=max(1, args.warm_steps // 10))
+                    log_every=max(1, args.warm_steps // 10),
+                    progress=lambda st, ls: log(f"warm start: step {st}, loss {ls:.4f}"))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     rows_trained = args.warm_steps * 8192
@@ -403,10 +416,12 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
+    log("importing torch")
     import torch
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    log("river leg")
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
 
@@ -505,14 +520,19 @@ def main():
         "game_create_s": t_create,
     }
     g.close()
+    log(f"river: {value:.0f} iterations/s, pair {pair_us:.2f} us, time to gap {ttg:.3f} s")
     if not args.no_batched:
         out["batched"] = batched_leg(args, stream)
+        log("batch leg done")
         if not args.no_warm:
             out["warm_start"] = warm_leg(args, stream, out["batched"])
+            log("warm-start leg done")
     if not args.no_turn:
         out["turn_river"] = turn_river_leg(args, stream)
+        log("turn+river leg done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(desc, args.cpu_budget)
+        log("CPU baseline done")
     print(json.dumps(out), flush=True)
 
 

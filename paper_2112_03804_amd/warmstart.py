@@ -171,7 +171,7 @@ class Dataset:
 
 
 def make_dataset(descs: Sequence, iters: int = 0, batch: int = 512, target: float = 0.0,
-                 kind: str = "rm+", max_iters: int = 100000) -> Dataset:
+                 kind: str = "rm+", max_iters: int = 100000, progress=None) -> Dataset:
     """Solve the instances in batches and collect training rows from the
     average strategies: for `iters` iterations of the chosen solver, or, with
     `target` > 0, until every instance's FP64 gap is at most target * its pot
@@ -187,11 +187,13 @@ def make_dataset(descs: Sequence, iters: int = 0, batch: int = 512, target: floa
         ds.add_game(g)
         _torch().cuda.synchronize()
         g.close()
+        if progress:
+            progress(min(a + batch, len(descs)), len(descs))
     return ds.finalize()
 
 
 def train(mlp: WarmMLP, ds: Dataset, steps: int, batch_rows: int = 8192, lr: float = 1e-3, seed: int = 0,
-          log_every: int = 0) -> List[float]:
+          log_every: int = 0, progress=None) -> List[float]:
     """Minibatch Adam on uniformly sampled rows; returns mean loss per logged
     interval (loss per unit weight)."""
     torch = _torch()
@@ -216,6 +218,8 @@ def train(mlp: WarmMLP, ds: Dataset, steps: int, batch_rows: int = 8192, lr: flo
             acc = float(loss.sum().item())
             wacc = float(Wb.sum().item())
             hist.append(acc / max(wacc, 1e-12))
+            if progress:
+                progress(it + 1, hist[-1])
     return hist
 
 
