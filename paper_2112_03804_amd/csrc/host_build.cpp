@@ -1020,12 +1020,18 @@ int build_rm_plan(HostGame& hg, int p, int cap, std::string& msg) {
       gb[kRmGroups] = (int)order.size();
       for (int m = 0; m < nm; ++m)
         if (group[m] < 0) order.push_back(m);
+      // parent code -> LDS row (root sink / root weight, external parent,
+      // local row)
+      auto lds_row = [](int par) {
+        return par == -1 ? kRmRowOne : (par <= -2 ? kRmRowExt + (-2 - par) : kRmRowLocal + par);
+      };
       for (int m : order) {
         const int i = members[m];
         const int f = local(inf[i].first);
-        const uint32_t jr = root_slot[m] >= 0 ? (uint32_t)(root_slot[m] + 1) : 0u;
-        P.infs.push_back((int32_t)((uint32_t)f | ((uint32_t)inf[i].nact << 8) | (jr << 15) |
-                                   ((uint32_t)par_of[m] << 20)));
+        const int down = lds_row(par_of[m]);
+        const int up = root_slot[m] >= 0 ? kRmRowSlot + kRmGroupSlots * group[m] + root_slot[m] : down;
+        P.infs.push_back((int32_t)((uint32_t)f | ((uint32_t)inf[i].nact << 8) | ((uint32_t)up << 16) |
+                                   ((uint32_t)down << 24)));
       }
       t.grp_off = -1;
       if (n_groups > 0) {
@@ -1036,7 +1042,7 @@ int build_rm_plan(HostGame& hg, int p, int cap, std::string& msg) {
           G[1 + w] = gb[w];
           G[5 + w] = gb[w + 1];
           G[11 + w] = (int)gtargets[w].size();
-          for (size_t j = 0; j < gtargets[w].size(); ++j) G[16 + kRmGroupSlots * w + j] = gtargets[w][j];
+          for (size_t j = 0; j < gtargets[w].size(); ++j) G[16 + kRmGroupSlots * w + j] = lds_row(gtargets[w][j]);
         }
         G[9] = gb[kRmGroups];
         G[10] = nm;

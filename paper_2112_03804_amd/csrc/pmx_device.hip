@@ -896,9 +896,19 @@ __device__ inline RmStep rm_step(int dcfr, int gamma, float alpha, float beta, d
 __device__ inline RmStep rm_step(const TpParams& P, double t) {
   return rm_step(P.dcfr, P.gamma, P.alpha, P.beta, t);
 }
+// New regret from the old one and the instantaneous regret: RM+ clips at 0;
+// discounted CFR scales positive and other regrets by their factors.
+template <bool DC>
 __device__ inline float rm_new(float r, float inst, const RmStep& k) {
-  const float v = r * (r > 0.f ? k.dp : k.dn) + inst;
-  return (k.floor && v < 0.f) ? 0.f : v;
+  if (!DC) return fmaxf(r + inst, 0.f);
+  return r * (r > 0.f ? k.dp : k.dn) + inst;
+}
+
+// num / den for den > 0 with one reciprocal; both are scaled by 2^64 when den
+// is so small that its reciprocal would overflow FP32.
+__device__ inline float rm_quot(float num, float den) {
+  const float sc = den < 0x1p-64f ? 0x1p64f : 1.f;
+  return (num * sc) * __builtin_amdgcn_rcpf(den * sc);
 }
 
 constexpr int TPB = 128;
@@ -940,54 +950,61 @@ constexpr int RMR = kTaskRowsMax / RMW;     // rows loaded per wavefront
 
 __device__ inline int rl(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
 
-// Bottom-up step of one infoset with N actions for one hand (LDS rows, 64
-// lanes apart): V(I) from the current behaviour, the regret update from
-// q = A (g plus the values below), and V added into the parent's slot `pp`
-// (a row of Al, an external-root accumulator, or a sink row for roots).  All LDS reads of
-// the step, the parent's included, issue together; the action count is a
-// template constant so the step has no branch per action.
-template <int N>
-__device__ inline void rmp_up_n(float* __restrict__ Al, float* __restrict__ Rl, float* pp, int f, int lane,
+// Bottom-up step of one infoset with n <= W actions for one hand (LDS rows,
+// 64 lanes apart): V(I) from the current behaviour, the regret update from
+// q = A (g plus the values below), and V added into the LDS row `pp` (the
+// parent's row, a group-root slot, or the sink).  The W row reads and the
+// parent's issue together; positions past the last action read and rewrite
+// the last action's row (the same value to the same address) and are left
+// out of the sums, so the step has no branch and one body serves every
+// action count up to W.
+template <int W, bool DC>
+__device__ inline void rmp_up_w(float* __restrict__ Al, float* __restrict__ Rl, float* pp, int f, int n, int lane,
                                 const RmStep& K) {
-  float rr[N], gg[N];
+  float rr[W], gg[W];
 #pragma unroll
-  for (int a = 0; a < N; ++a) {
-    rr[a] = Rl[(f + a) * 64 + lane];
-    gg[a] = Al[(f + a) * 64 + lane];
+  for (int a = 0; a < W; ++a) {
+    const int o = (f + min(a, n - 1)) * 64 + lane;
+    rr[a] = Rl[o];
+    gg[a] = Al[o];
   }
   const float pv = *pp;
   float rs = 0.f, dot = 0.f, gs = 0.f;
 #pragma unroll
-  for (int a = 0; a < N; ++a) {
-    const float r = fmaxf(rr[a], 0.f);
+  for (int a = 0; a < W; ++a) {
+    const float r = a < n ? fmaxf(rr[a], 0.f) : 0.f;
     rs += r;
     dot += r * gg[a];
-    gs += gg[a];
+    gs += a < n ? gg[a] : 0.f;
   }
-  const float V = rs > 0.f ? dot / rs : gs * (1.f / (float)N);
+  const bool pos = rs > 0.f;
+  const float V = rm_quot(pos ? dot : gs, pos ? rs : (float)n);
 #pragma unroll
-  for (int a = 0; a < N; ++a) Rl[(f + a) * 64 + lane] = rm_new(rr[a], gg[a] - V, K);
+  for (int a = 0; a < W; ++a) Rl[(f + min(a, n - 1)) * 64 + lane] = rm_new<DC>(rr[a], gg[a] - V, K);
   *pp = pv + V;
 }
 
 // Top-down step: the new behaviour from the regrets times the parent's
-// realization weight *xpp (a row holding 1 for roots), into the rows of Al.
-template <int N>
-__device__ inline void rmp_down_n(float* __restrict__ Al, const float* __restrict__ Rl, const float* xpp,
-                                  int f, int lane) {
-  float rr[N];
+// realization weight *xpp, into the rows of Al; positions past the last
+// action as in the bottom-up step.
+template <int W>
+__device__ inline void rmp_down_w(float* __restrict__ Al, const float* __restrict__ Rl, const float* xpp, int f,
+                                  int n, int lane) {
+  float rr[W];
 #pragma unroll
-  for (int a = 0; a < N; ++a) rr[a] = fmaxf(Rl[(f + a) * 64 + lane], 0.f);
+  for (int a = 0; a < W; ++a) rr[a] = fmaxf(Rl[(f + min(a, n - 1)) * 64 + lane], 0.f);
   const float xp = *xpp;
   float rs = 0.f;
 #pragma unroll
-  for (int a = 0; a < N; ++a) rs += rr[a];
-  const float inv = rs > 0.f ? xp / rs : 0.f, uni = xp * (1.f / (float)N);
+  for (int a = 0; a < W; ++a) rs += a < n ? rr[a] : 0.f;
+  const bool pos = rs > 0.f;
+  const float k = rm_quot(xp, pos ? rs : (float)n);
 #pragma unroll
-  for (int a = 0; a < N; ++a) Al[(f + a) * 64 + lane] = rs > 0.f ? rr[a] * inv : uni;
+  for (int a = 0; a < W; ++a) Al[(f + min(a, n - 1)) * 64 + lane] = (pos ? rr[a] : 1.f) * k;
 }
 
-// Any action count (beyond the specialized ones).
+// Any action count (beyond MAXA).
+template <bool DC>
 __device__ inline void rmp_up_any(float* __restrict__ Al, float* __restrict__ Rl, float* pp, int f, int n,
                                   int lane, const RmStep& K) {
   float rs = 0.f, dot = 0.f, gs = 0.f;
@@ -997,9 +1014,10 @@ __device__ inline void rmp_up_any(float* __restrict__ Al, float* __restrict__ Rl
     dot += r * gv;
     gs += gv;
   }
-  const float V = rs > 0.f ? dot / rs : gs / (float)n;
+  const bool pos = rs > 0.f;
+  const float V = rm_quot(pos ? dot : gs, pos ? rs : (float)n);
   for (int a = 0; a < n; ++a)
-    Rl[(f + a) * 64 + lane] = rm_new(Rl[(f + a) * 64 + lane], Al[(f + a) * 64 + lane] - V, K);
+    Rl[(f + a) * 64 + lane] = rm_new<DC>(Rl[(f + a) * 64 + lane], Al[(f + a) * 64 + lane] - V, K);
   *pp += V;
 }
 __device__ inline void rmp_down_any(float* __restrict__ Al, const float* __restrict__ Rl, const float* xpp,
@@ -1007,44 +1025,31 @@ __device__ inline void rmp_down_any(float* __restrict__ Al, const float* __restr
   const float xp = *xpp;
   float rs = 0.f;
   for (int a = 0; a < n; ++a) rs += fmaxf(Rl[(f + a) * 64 + lane], 0.f);
-  const float inv = rs > 0.f ? xp / rs : 0.f, uni = xp / (float)n;
-  for (int a = 0; a < n; ++a)
-    Al[(f + a) * 64 + lane] = rs > 0.f ? fmaxf(Rl[(f + a) * 64 + lane], 0.f) * inv : uni;
+  const bool pos = rs > 0.f;
+  const float k = rm_quot(xp, pos ? rs : (float)n);
+  for (int a = 0; a < n; ++a) Al[(f + a) * 64 + lane] = (pos ? fmaxf(Rl[(f + a) * 64 + lane], 0.f) : 1.f) * k;
 }
 
+// Two widths keep the common small infosets cheap; one call site per
+// direction in the kernel keeps its code small.
+template <bool DC>
 __device__ inline void rmp_up(float* Al, float* Rl, float* pp, int f, int n, int lane, const RmStep& K) {
-  switch (n) {
-    case 1: rmp_up_n<1>(Al, Rl, pp, f, lane, K); break;
-    case 2: rmp_up_n<2>(Al, Rl, pp, f, lane, K); break;
-    case 3: rmp_up_n<3>(Al, Rl, pp, f, lane, K); break;
-    case 4: rmp_up_n<4>(Al, Rl, pp, f, lane, K); break;
-    case 5: rmp_up_n<5>(Al, Rl, pp, f, lane, K); break;
-    case 6: rmp_up_n<6>(Al, Rl, pp, f, lane, K); break;
-    case 7: rmp_up_n<7>(Al, Rl, pp, f, lane, K); break;
-    case 8: rmp_up_n<8>(Al, Rl, pp, f, lane, K); break;
-    default: rmp_up_any(Al, Rl, pp, f, n, lane, K);
-  }
+  if (n <= 4) rmp_up_w<4, DC>(Al, Rl, pp, f, n, lane, K);
+  else if (n <= MAXA) rmp_up_w<MAXA, DC>(Al, Rl, pp, f, n, lane, K);
+  else rmp_up_any<DC>(Al, Rl, pp, f, n, lane, K);
 }
 __device__ inline void rmp_down(float* Al, const float* Rl, const float* xpp, int f, int n, int lane) {
-  switch (n) {
-    case 1: rmp_down_n<1>(Al, Rl, xpp, f, lane); break;
-    case 2: rmp_down_n<2>(Al, Rl, xpp, f, lane); break;
-    case 3: rmp_down_n<3>(Al, Rl, xpp, f, lane); break;
-    case 4: rmp_down_n<4>(Al, Rl, xpp, f, lane); break;
-    case 5: rmp_down_n<5>(Al, Rl, xpp, f, lane); break;
-    case 6: rmp_down_n<6>(Al, Rl, xpp, f, lane); break;
-    case 7: rmp_down_n<7>(Al, Rl, xpp, f, lane); break;
-    case 8: rmp_down_n<8>(Al, Rl, xpp, f, lane); break;
-    default: rmp_down_any(Al, Rl, xpp, f, n, lane);
-  }
+  if (n <= 4) rmp_down_w<4>(Al, Rl, xpp, f, n, lane);
+  else if (n <= MAXA) rmp_down_w<MAXA>(Al, Rl, xpp, f, n, lane);
+  else rmp_down_any(Al, Rl, xpp, f, n, lane);
 }
 
 // MODE 0: bottom-up and top-down of a piece with no external parent (pulls
 // from deeper pieces first); 1: bottom-up of a deep piece (root values to the
 // stage buffer); 2: top-down of a deep piece (parent weights from x).  The
 // running average takes the previous plan (weight K.w) in the pass that
-// overwrites x.
-template <int MODE>
+// overwrites x.  DC: discounted CFR regrets (else RM+).
+template <int MODE, bool DC>
 __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict__ g, float* __restrict__ R,
                                                   float* __restrict__ x, double* __restrict__ xs,
                                                   float* __restrict__ stage, const double* __restrict__ tdev) {
@@ -1057,13 +1062,12 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
   const int h = h0 + lane;
   const bool act = h < T.n_hands;
   const int SL = T.n_rows;
-  float* Al = rsm;                          // [max_rows][64]: g, then the new x
-  float* Rl = rsm + P.max_rows * 64;        // [max_rows][64]
-  float* Xl = Rl + P.max_rows * 64;         // [max_ext][64]: root values / parent weights
-  float* One = Xl + P.max_ext * 64;         // [64]: sink of root values, then 1 (root weight)
-  float* Xw = One + 64;                     // [RMW][kRmGroupSlots][64]: group-root values
+  float* Xw = rsm + kRmRowSlot * 64;        // group-root values
+  float* Xl = rsm + kRmRowExt * 64;         // root values / parent weights of external parents
+  float* Al = rsm + kRmRowLocal * 64;       // [max_rows][64]: g, then the new x
+  float* Rl = Al + P.max_rows * 64;         // [max_rows][64]
   const int64_t base = T.vec_base + h, stride = T.stride;
-  const RmStep K = rm_step(P.dcfr, P.gamma, P.alpha, P.beta, *tdev);
+  const RmStep K = rm_step(DC, P.gamma, P.alpha, P.beta, *tdev);
   // row ids, one per lane: computed for contiguous pieces, else from the table
   const int rowv = T.row0 >= 0 ? T.row0 + lane : (lane < SL ? P.rows[T.rows_off + lane] : 0);
   const int infv = lane < T.n_inf ? P.infs[T.inf_off + lane] : 0;
@@ -1071,11 +1075,13 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
   const int grpv = grouped ? P.grp[T.grp_off + lane] : 0;
   const int extv = (MODE != 0 && wv == 0 && lane < T.n_ext)
                        ? (MODE == 1 ? P.ext_slot[T.ext_off + lane] : P.ext_seq[T.ext_off + lane]) : 0;
+  // unconditional loads at clamped (in-bounds) rows and hands, so that all of
+  // them issue before the first is waited for; the old plan and the running
+  // average stay in registers until the stores at the end
+  float c[RMR];
+  double d[RMR];
   {
-    // unconditional loads at clamped (in-bounds) rows and hands, so that all
-    // of them issue before the first is waited for
-    float a[RMR], b[RMR], c[RMR];
-    double d[RMR];
+    float a[RMR], b[RMR];
     const int64_t cbase = T.vec_base + (act ? h : T.n_hands - 1);
 #pragma unroll
     for (int k = 0; k < RMR; ++k) {
@@ -1097,7 +1103,6 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
       if (r < SL) {
         if (MODE != 2) Al[r * 64 + lane] = a[k];
         Rl[r * 64 + lane] = b[k];
-        if (MODE != 1 && act) xs[base + (int64_t)rl(rowv, r) * stride] = d[k] + K.w * (double)c[k];
       }
     }
   }
@@ -1116,61 +1121,49 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
   }
   if (MODE != 2 && wv == 0)
     for (int k = 0; k < T.n_ext; ++k) Xl[k * 64 + lane] = 0.f;
-  __syncthreads();
   // infoset ranges: wavefront wv's group, and the top part (all infosets when
   // the piece is not split)
   const int gb = grouped ? rl(grpv, 1 + wv) : 0, ge = grouped ? rl(grpv, 5 + wv) : 0;
   const int tb = grouped ? rl(grpv, 9) : 0, te = grouped ? rl(grpv, 10) : T.n_inf;
+  if (MODE != 2 && grouped)
+    for (int j = 0; j < rl(grpv, 11 + wv); ++j) Xw[(wv * kRmGroupSlots + j) * 64 + lane] = 0.f;
+  __syncthreads();
   if (MODE != 2) {
-    if (grouped) {
-      // groups concurrently; a group root's value goes to its slot in Xw
-      float* Xa = Xw + wv * kRmGroupSlots * 64;
-      for (int j = 0; j < rl(grpv, 11 + wv); ++j) Xa[j * 64 + lane] = 0.f;
-      for (int i = ge - 1; i >= gb; --i) {
-        const int v = rl(infv, i);
-        const int jr = (v >> 15) & 31, par = v >> 20;
-        float* pp = jr ? &Xa[(jr - 1) * 64 + lane] : &Al[par * 64 + lane];
-        rmp_up(Al, Rl, pp, v & 255, (v >> 8) & 127, lane, K);
+    // pass 0: the wavefront's group (groups concurrently, a group root's
+    // value to its slot); pass 1: the top part on wavefront 0, after the
+    // slots are added into their targets in a fixed order
+#pragma unroll 1
+    for (int ps = grouped ? 0 : 1; ps < 2; ++ps) {
+      if (ps == 1 && grouped) {
+        __syncthreads();
+        if (wv == 0)
+          for (int w = 0; w < RMW; ++w)
+            for (int j = 0; j < rl(grpv, 11 + w); ++j)
+              rsm[rl(grpv, 16 + kRmGroupSlots * w + j) * 64 + lane] += Xw[(w * kRmGroupSlots + j) * 64 + lane];
       }
-      __syncthreads();
-      if (wv == 0) {   // group-root values into their targets, in a fixed order
-        for (int w = 0; w < RMW; ++w)
-          for (int j = 0; j < rl(grpv, 11 + w); ++j) {
-            const int tg = rl(grpv, 16 + kRmGroupSlots * w + j);
-            const float gv = Xw[(w * kRmGroupSlots + j) * 64 + lane];
-            if (tg >= 0) Al[tg * 64 + lane] += gv;
-            else if (tg <= -2) Xl[(-2 - tg) * 64 + lane] += gv;
-          }
+      if (ps == 1 && wv != 0) break;
+      const int i0 = ps ? tb : gb, i1 = ps ? te : ge;
+      for (int i = i1 - 1; i >= i0; --i) {
+        const int v = rl(infv, i);
+        rmp_up<DC>(Al, Rl, &rsm[((v >> 16) & 255) * 64 + lane], v & 255, (v >> 8) & 255, lane, K);
       }
     }
-    if (wv == 0) {
-      for (int i = te - 1; i >= tb; --i) {
-        const int v = rl(infv, i);
-        const int par = v >> 20;
-        float* pp = par >= 0 ? &Al[par * 64 + lane] : (par <= -2 ? &Xl[(-2 - par) * 64 + lane] : &One[lane]);
-        rmp_up(Al, Rl, pp, v & 255, (v >> 8) & 127, lane, K);
-      }
-      if (MODE == 1 && act)
-        for (int k = 0; k < T.n_ext; ++k)
-          stage[(int64_t)rl(extv, k) * P.stage_stride + h] = Xl[k * 64 + lane];
-    }
+    if (MODE == 1 && wv == 0 && act)
+      for (int k = 0; k < T.n_ext; ++k) stage[(int64_t)rl(extv, k) * P.stage_stride + h] = Xl[k * 64 + lane];
   }
   if (MODE != 1) {
-    auto down = [&](int i0, int i1) {
+    // pass 0: the top part on wavefront 0 (root weight 1); pass 1: the
+    // wavefront's group
+#pragma unroll 1
+    for (int ps = 0; ps < (grouped ? 2 : 1); ++ps) {
+      if (ps == 1) __syncthreads();
+      else if (wv != 0) continue;
+      else rsm[kRmRowOne * 64 + lane] = 1.f;
+      const int i0 = ps ? gb : tb, i1 = ps ? ge : te;
       for (int i = i0; i < i1; ++i) {
         const int v = rl(infv, i);
-        const int par = v >> 20;
-        const float* xpp = par >= 0 ? &Al[par * 64 + lane] : (par == -1 ? &One[lane] : &Xl[(-2 - par) * 64 + lane]);
-        rmp_down(Al, Rl, xpp, v & 255, (v >> 8) & 127, lane);
+        rmp_down(Al, Rl, &rsm[((uint32_t)v >> 24) * 64 + lane], v & 255, (v >> 8) & 255, lane);
       }
-    };
-    if (wv == 0) {
-      One[lane] = 1.f;
-      down(tb, te);
-    }
-    if (grouped) {
-      __syncthreads();
-      down(gb, ge);
     }
   }
   __syncthreads();
@@ -1189,7 +1182,10 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
       if (r < SL) {
         const int64_t idx = base + (int64_t)rl(rowv, r) * stride;
         if (MODE != 2) R[idx] = b[k];
-        if (MODE != 1) x[idx] = a[k];
+        if (MODE != 1) {
+          x[idx] = a[k];
+          xs[idx] = d[k] + K.w * (double)c[k];
+        }
       }
     }
   }
@@ -1968,16 +1964,20 @@ static int rm_update(Game* g, int p, hipStream_t s) {
     const int nb = E.blk_off[d + 1] - E.blk_off[d];
     if (nb == 0) return;
     const RmParams P = rm_params(g, p, d);
-    const size_t lds = sizeof(float) * 64 * (size_t)(2 * P.max_rows + P.max_ext + 1 + RMW * kRmGroupSlots);
-    if (mode == 0)
-      hipLaunchKernelGGL(k_rmp<0>, dim3(nb), dim3(64 * RMW), lds, s, P, gr, g->R[p].p, g->x[p].p, g->xs[p].p,
+    const size_t lds = sizeof(float) * 64 * (size_t)(kRmRowLocal + 2 * P.max_rows);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(64 * RMW), lds, s, P, gr, g->R[p].p, g->x[p].p, g->xs[p].p,
                          E.stage.p, td);
-    else if (mode == 1)
-      hipLaunchKernelGGL(k_rmp<1>, dim3(nb), dim3(64 * RMW), lds, s, P, gr, g->R[p].p, g->x[p].p, g->xs[p].p,
-                         E.stage.p, td);
-    else
-      hipLaunchKernelGGL(k_rmp<2>, dim3(nb), dim3(64 * RMW), lds, s, P, gr, g->R[p].p, g->x[p].p, g->xs[p].p,
-                         E.stage.p, td);
+    };
+    if (P.dcfr) {
+      if (mode == 0) go(k_rmp<0, true>);
+      else if (mode == 1) go(k_rmp<1, true>);
+      else go(k_rmp<2, true>);
+    } else {
+      if (mode == 0) go(k_rmp<0, false>);
+      else if (mode == 1) go(k_rmp<1, false>);
+      else go(k_rmp<2, false>);
+    }
   };
   for (int d = D - 1; d >= 1; --d) launch(1, d);
   if (D > 0) launch(0, 0);

@@ -220,9 +220,19 @@ struct TpPlan {                         // one player
 // "deep" piece) passes its root values up through a stage buffer and reads
 // the parent sequence's realization weight back in its top-down pass.
 constexpr int kTaskRowsMax = 64;        // rows per piece (one per lane of a wavefront)
-constexpr int kTaskExtMax = 16;         // distinct external parents per piece
+constexpr int kTaskExtMax = 15;         // distinct external parents per piece
 constexpr int kRmGroups = 4;            // subtree groups walked concurrently (wavefronts per block)
 constexpr int kRmGroupSlots = 4;        // distinct parent targets of one group's roots
+// LDS rows of a regret-update workgroup in one index space (a row holds one
+// value per hand of the workgroup): the root sink / root weight, the
+// group-root accumulator slots (kRmGroupSlots per wavefront), the external
+// parents, then the piece's rows.  With a 64-row piece the values (g, then
+// the new x) and the regrets take 2 * 64 rows after these 32, 40 KiB per
+// workgroup, so four workgroups share a CU's 160 KiB.
+constexpr int kRmRowOne = 0;
+constexpr int kRmRowSlot = 1;
+constexpr int kRmRowExt = kRmRowSlot + kRmGroups * kRmGroupSlots;
+constexpr int kRmRowLocal = kRmRowExt + kTaskExtMax;
 struct RmTask {
   int64_t vec_base;
   int32_t stride, n_hands;
@@ -234,15 +244,17 @@ struct RmTask {
   int32_t grp_off;                      // 64-int group table, -1: one wavefront walks the piece
   int32_t row0;                         // rows are row0 .. row0 + n_rows - 1, or -1: use the table
 };
-// Packed local infoset: first local row (bits 0-7) | actions (bits 8-14) |
-// group-root accumulator slot + 1 (bits 15-19, 0: none) | parent (bits
-// 20-31, signed): >= 0 local row, -1 empty sequence, -2-k the k-th external
-// parent.  Pull: local row (bits 0-7) | stage row << 8.  Group table:
-// [0] groups, [1 + w] / [5 + w] infoset range of group w, [9] / [10] range of
-// the top part, [11 + w] targets of group w, [16 + kRmGroupSlots w + j]
-// its target j
-// (parent code as above).  Infosets are listed group by group, then the top
-// part, each in depth-first order.
+// Packed local infoset: first local row (bits 0-7) | actions (bits 8-15) |
+// LDS row that receives the infoset's value in the bottom-up pass (bits
+// 16-23: the group-root slot for a group root, else the parent sequence's
+// row, the external parent's row, or the sink) | LDS row holding the parent
+// sequence's realization weight in the top-down pass (bits 24-31: the
+// parent's row, the external parent's row, or the root-weight row).  LDS
+// rows as numbered by kRmRow*.  Pull: local row (bits 0-7) | stage row << 8.
+// Group table: [0] groups, [1 + w] / [5 + w] infoset range of group w, [9] /
+// [10] range of the top part, [11 + w] targets of group w,
+// [16 + kRmGroupSlots w + j] the LDS row of its target j.  Infosets are
+// listed group by group, then the top part, each in depth-first order.
 struct RmPlan {                         // one player
   std::vector<RmTask> tasks;
   std::vector<int32_t> rows, infs, pulls, ext_seq, ext_slot, grp;

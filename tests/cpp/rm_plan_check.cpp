@@ -5,7 +5,8 @@
 // one hand per instance through the pieces exactly as the launch sequence
 // does: bottom-up passes of the deep pieces from the deepest depth up, the
 // pieces without external parents (pulls, grouped bottom-up walk, top-down
-// walk), then the top-down passes of the deep pieces.  The result is compared
+// walk), then the top-down passes of the deep pieces, with the workgroup's
+// LDS rows in the numbering the packed infosets and group tables use.  The result is compared
 // with a plain walk over the whole treeplex (children before parents for the
 // values, parents before children for the plan).  Also checks that every
 // sequence belongs to exactly one piece and that pieces respect the cap.
@@ -28,7 +29,7 @@ float rm_plus(float r, float inst) {
 }
 
 // regret update of one infoset (rows f .. f+n of q and R); returns V(I)
-float update_infoset(std::vector<float>& q, std::vector<float>& R, int f, int n) {
+float update_infoset(float* q, float* R, int f, int n) {
   float rs = 0.f;
   for (int a = 0; a < n; ++a) rs += std::max(R[f + a], 0.f);
   float V = 0.f;
@@ -38,7 +39,7 @@ float update_infoset(std::vector<float>& q, std::vector<float>& R, int f, int n)
 }
 
 // behaviour from regrets times the parent's weight, into rows f .. f+n of x
-void descend_infoset(std::vector<float>& x, const std::vector<float>& R, int f, int n, float xp) {
+void descend_infoset(float* x, const float* R, int f, int n, float xp) {
   float rs = 0.f;
   for (int a = 0; a < n; ++a) rs += std::max(R[f + a], 0.f);
   for (int a = 0; a < n; ++a) x[f + a] = xp * (rs > 0.f ? std::max(R[f + a], 0.f) / rs : 1.f / n);
@@ -102,29 +103,31 @@ extern "C" int check_rm_plan(const GameDesc* d, int n, int cap, char* msg, int m
       // reference: the whole treeplex
       std::vector<float> qr = g, Rr = R, xr(S, 0.f);
       for (int i = (int)inf.size() - 1; i >= 0; --i) {
-        const float V = update_infoset(qr, Rr, inf[i].first, inf[i].nact);
+        const float V = update_infoset(qr.data(), Rr.data(), inf[i].first, inf[i].nact);
         if (inf[i].parent >= 0) qr[inf[i].parent] += V;
       }
       for (const Infoset& I : inf)
-        descend_infoset(xr, Rr, I.first, I.nact, I.parent >= 0 ? xr[I.parent] : 1.f);
-      // the pieces, in launch order
+        descend_infoset(xr.data(), Rr.data(), I.first, I.nact, I.parent >= 0 ? xr[I.parent] : 1.f);
+      // the pieces, in launch order; U models a workgroup's LDS rows (sink /
+      // root weight, group-root slots, external parents, the piece's rows)
       std::vector<float> stage(std::max(P.n_slot, 1), 0.f);
       auto run = [&](int mode, int depth) {
         for (int id : P.by_depth[depth]) {
           const RmTask& t = P.tasks[id];
           if (t.inst != (int)ii) continue;
-          std::vector<float> A(t.n_rows), Rl(t.n_rows), Xl(std::max(t.n_ext, 1), 0.f);
+          std::vector<float> U(kRmRowLocal + t.n_rows, 0.f), Rl(t.n_rows);
+          float* A = &U[kRmRowLocal];
           for (int r = 0; r < t.n_rows; ++r) {
             const int s = P.rows[t.rows_off + r];
             A[r] = mode == 2 ? 0.f : g[s];
             Rl[r] = R[s];
           }
-          auto decode = [&](int i, int& f, int& na, int& jr, int& par) {
-            const int v = P.infs[t.inf_off + i];
+          auto decode = [&](int i, int& f, int& na, int& up, int& dn) {
+            const uint32_t v = (uint32_t)P.infs[t.inf_off + i];
             f = v & 255;
-            na = (v >> 8) & 127;
-            jr = (v >> 15) & 31;
-            par = v >> 20;
+            na = (v >> 8) & 255;
+            up = (v >> 16) & 255;
+            dn = v >> 24;
           };
           const int* G = t.grp_off >= 0 ? &P.grp[t.grp_off] : nullptr;
           const int tb = G ? G[9] : 0, te = G ? G[10] : t.n_inf;
@@ -133,43 +136,39 @@ extern "C" int check_rm_plan(const GameDesc* d, int n, int cap, char* msg, int m
               const int v = P.pulls[t.pull_off + j];
               A[v & 255] += stage[(uint32_t)v >> 8];
             }
-            float acc[kRmGroups][kRmGroupSlots] = {};
             if (G)
               for (int w = 0; w < kRmGroups; ++w)
                 for (int i = G[5 + w] - 1; i >= G[1 + w]; --i) {
-                  int f, na, jr, par;
-                  decode(i, f, na, jr, par);
-                  const float V = update_infoset(A, Rl, f, na);
-                  if (jr) acc[w][jr - 1] += V;
-                  else A[par] += V;
+                  int f, na, up, dn;
+                  decode(i, f, na, up, dn);
+                  const bool own_slot = up >= kRmRowSlot + kRmGroupSlots * w && up < kRmRowSlot + kRmGroupSlots * (w + 1);
+                  if (!own_slot && up < kRmRowLocal) {
+                    snprintf(msg, msglen, "group %d infoset %d sends its value to LDS row %d", w, i, up);
+                    throw 1;
+                  }
+                  U[up] += update_infoset(A, Rl.data(), f, na);
                 }
             if (G)
               for (int w = 0; w < kRmGroups; ++w)
-                for (int j = 0; j < G[11 + w]; ++j) {
-                  const int tg = G[16 + kRmGroupSlots * w + j];
-                  if (tg >= 0) A[tg] += acc[w][j];
-                  else if (tg <= -2) Xl[-2 - tg] += acc[w][j];
-                }
+                for (int j = 0; j < G[11 + w]; ++j) U[G[16 + kRmGroupSlots * w + j]] += U[kRmRowSlot + kRmGroupSlots * w + j];
             for (int i = te - 1; i >= tb; --i) {
-              int f, na, jr, par;
-              decode(i, f, na, jr, par);
-              const float V = update_infoset(A, Rl, f, na);
-              if (par >= 0) A[par] += V;
-              else if (par <= -2) Xl[-2 - par] += V;
+              int f, na, up, dn;
+              decode(i, f, na, up, dn);
+              U[up] += update_infoset(A, Rl.data(), f, na);
             }
             if (mode == 1)
-              for (int k = 0; k < t.n_ext; ++k) stage[P.ext_slot[t.ext_off + k]] = Xl[k];
+              for (int k = 0; k < t.n_ext; ++k) stage[P.ext_slot[t.ext_off + k]] = U[kRmRowExt + k];
             for (int r = 0; r < t.n_rows; ++r) R[P.rows[t.rows_off + r]] = Rl[r];
           }
           if (mode != 1) {
             if (mode == 2)
-              for (int k = 0; k < t.n_ext; ++k) Xl[k] = x[P.ext_seq[t.ext_off + k]];
+              for (int k = 0; k < t.n_ext; ++k) U[kRmRowExt + k] = x[P.ext_seq[t.ext_off + k]];
+            U[kRmRowOne] = 1.f;
             auto down = [&](int i0, int i1) {
               for (int i = i0; i < i1; ++i) {
-                int f, na, jr, par;
-                decode(i, f, na, jr, par);
-                const float xp = par >= 0 ? A[par] : (par == -1 ? 1.f : Xl[-2 - par]);
-                descend_infoset(A, Rl, f, na, xp);
+                int f, na, up, dn;
+                decode(i, f, na, up, dn);
+                descend_infoset(A, Rl.data(), f, na, U[dn]);
               }
             };
             down(tb, te);
@@ -179,9 +178,13 @@ extern "C" int check_rm_plan(const GameDesc* d, int n, int cap, char* msg, int m
         }
       };
       const int D = (int)P.by_depth.size();
-      for (int dd = D - 1; dd >= 1; --dd) run(1, dd);
-      run(0, 0);
-      for (int dd = 1; dd < D; ++dd) run(2, dd);
+      try {
+        for (int dd = D - 1; dd >= 1; --dd) run(1, dd);
+        run(0, 0);
+        for (int dd = 1; dd < D; ++dd) run(2, dd);
+      } catch (int) {
+        return 1;
+      }
       for (int s = 0; s < S; ++s) {
         if (std::fabs(R[s] - Rr[s]) > 1e-4f * (1.f + std::fabs(Rr[s])) || std::fabs(x[s] - xr[s]) > 1e-5f) {
           snprintf(msg, msglen, "instance %zu player %d sequence %d: R %g vs %g, x %g vs %g", ii, p, s, R[s],
