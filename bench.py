@@ -66,30 +66,81 @@ def algorithmic_bytes_pair(layouts):
     return tot
 
 
-def cpu_baseline(desc, budget_s=15.0):
-    """The oracle's FP64 matvec pair (A y and A^T x from the definition),
-    timed on this host for about budget_s seconds."""
-    from oracle import payoff
+def _cpu_model():
     try:
-        from threadpoolctl import threadpool_info
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(desc, budget_s=15.0, gpu_iters=None):
+    """The oracle's FP64 matvec pair (A y and A^T x from the definition),
+    timed on this host for about budget_s seconds with its thread pool, and
+    for a few seconds on one thread; the oracle's RM+ solve of the 13-card
+    game to 1e-6 * pot; and the oracle's river time to 1e-4 * pot
+    extrapolated from its pair rate and the GPU solver's iteration count."""
+    from oracle import payoff
+    from oracle import solver as osolver
+    from paper_2112_03804_amd import instances as I
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = 1
     o = payoff.Game(desc)
     rng = np.random.default_rng(0)
     y = rng.random((o.S[1], o.N[1]))
     x = rng.random((o.S[0], o.N[0]))
     o.matvec_A(y)
-    n = 0
+
+    def rate(budget):
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget:
+            o.matvec_A(y)
+            o.matvec_AT(x)
+            n += 1
+        dt = time.perf_counter() - t0
+        return n, dt
+
+    n, dt = rate(budget_s)
+    out = {"value": n / dt, "unit": "matvec pairs/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{n} FP64 matvec pairs of the river endgame (definition-level sum over "
+                     f"61 terminals x 1081 x 1081 hand pairs), {dt:.1f} s",
+           "host": {"nproc": os.cpu_count(), "model": _cpu_model()}}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            n1, dt1 = rate(max(2.0, budget_s / 4))
+        out["single_thread"] = {"value": n1 / dt1, "unit": "matvec pairs/s",
+                                "sample": f"{n1} pairs, {dt1:.1f} s"}
+    # the 13-card game solved by the oracle's plain FP64 RM+ (gap every 100
+    # iterations, stopped after 10 s)
+    tiny = I.config(0)
+    ot = payoff.Game(tiny)
+    pot = 2 * tiny.contrib
+    sol = osolver.RMPlus(ot)
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        o.matvec_A(y)
-        o.matvec_AT(x)
-        n += 1
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "matvec pairs/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n} FP64 matvec pairs of the river endgame (definition-level sum over "
-                      f"61 terminals x 1081 x 1081 hand pairs), {dt:.1f} s"}
+    it, gap = 0, float("inf")
+    while it < 200000 and time.perf_counter() - t0 < 10.0:
+        for _ in range(100):
+            sol.step()
+        it += 100
+        gap = float(sol.gap()[0])
+        if gap <= 1e-6 * pot:
+            break
+    out["tiny_time_to_gap"] = {"target": "1e-6*pot", "seconds": time.perf_counter() - t0, "iterations": it,
+                               "gap_over_pot": gap / pot, "reached": gap <= 1e-6 * pot}
+    if gpu_iters:
+        out["river_time_to_gap_extrapolated"] = {
+            "target": "1e-4*pot", "iterations": gpu_iters, "seconds": gpu_iters / (n / dt),
+            "note": "the GPU solver's RM+ iteration count times the oracle's time per matvec pair "
+                    "(regret updates and gap checks not counted)"}
+    return out
 
 
 def batched_leg(args, stream):
@@ -174,6 +225,33 @@ def batched_leg(args, stream):
         plain_it.append(it)
         gi.close()
     plain_total_est = float(np.mean(plain_s)) * len(descs)
+    big = None
+    if args.batch_big > 0:
+        # a batch four times larger than the Infinity Cache holds: the same
+        # tuned schedule, the matvec pair alone
+        log(f"batch: matvec pair on {args.batch_big} instances")
+        gb = pmx.Game(I.batched_configs(args.batch_big))
+        gb.game_tune(*sched)
+        yb = torch.from_numpy(rng.random(gb.elems[1]).astype(np.float32)).cuda()
+        xb = torch.from_numpy(rng.random(gb.elems[0]).astype(np.float32)).cuda()
+        Ayb = torch.empty(gb.elems[0], dtype=torch.float32, device="cuda")
+        ATxb = torch.empty(gb.elems[1], dtype=torch.float32, device="cuda")
+        for _ in range(5):
+            gb.matvec_pair(yb, xb, Ayb, ATxb)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(50):
+            gb.matvec_pair(yb, xb, Ayb, ATxb)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        big_us = e0.elapsed_time(e1) * 1e3 / 50
+        big_bytes = algorithmic_bytes_pair(gb.layouts)
+        big_gbs = big_bytes / (big_us * 1e-6) / 1e9
+        big = {"instances": args.batch_big, "schedule": list(sched), "us_per_launch": big_us,
+               "algorithmic_bytes_per_launch": big_bytes, "achieved_gbs": big_gbs,
+               "frac": big_gbs / HBM_PEAK_GBS}
+        gb.close()
+        del yb, xb, Ayb, ATxb
     return {
         "workload": f"{len(descs)} river endgames, hands U[200,1081] per player, 1-3 bet sizes, "
                     "raise caps 2-4, pots U[20,400], stack/pot U[1,10]",
@@ -198,6 +276,7 @@ def batched_leg(args, stream):
                                          "mean_iterations": float(np.mean(plain_it)),
                                          "sum_over_batch_extrapolated_s": plain_total_est},
         "speedup_batched_vs_plain": plain_total_est / ttg_batched,
+        "matvec_pair_beyond_infinity_cache": big,
     }
 
 
@@ -395,6 +474,8 @@ def main():
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=256)
     ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--batch-big", type=int, default=2048,
+                    help="instances of the batch whose matvec pair is timed beyond the Infinity Cache (0: skip)")
     ap.add_argument("--max-iters", type=int, default=100000)
     ap.add_argument("--no-turn", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -490,6 +571,23 @@ def main():
     ttg_d, iters_d, gap_d = time_to_gap("dcfr")
     g.solver_set_params("rm+")
 
+    # ---- the 13-card game to 1e-6 * pot (launch-latency bound) ------------
+    tiny = I.config(0)
+    gt = pmx.Game(tiny)
+    tpot = 2 * tiny.contrib
+    gt.solver_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_it, t_gap = 0, float("inf")
+    while t_it < 200000:
+        gt.solver_step(25)
+        t_it += 25
+        t_gap = float(gt.saddle_gap()[0][0])
+        if t_gap <= 1e-6 * tpot:
+            break
+    tiny_ttg = time.perf_counter() - t0
+    gt.close()
+
     out = {
         "metric": "matvec pairs/s (A·y+Aᵀx) & time to gap 1e-4·pot: plain vs batched/warm-start",
         "value": value,
@@ -518,6 +616,9 @@ def main():
                         "dcfr": {"seconds": ttg_d, "iterations": iters_d, "gap_over_pot": gap_d / pot,
                                  "params": "alpha 1.5, beta 0, gamma 2"}},
         "game_create_s": t_create,
+        "tiny_time_to_gap": {"workload": "13-card deck, one card per hand, bet 1x pot, one raise, pot 2",
+                             "target": "1e-6*pot", "seconds": tiny_ttg, "iterations": t_it,
+                             "gap_over_pot": t_gap / tpot, "solver": "plain RM+, FP64 gap every 25"},
     }
     g.close()
     log(f"river: {value:.0f} iterations/s, pair {pair_us:.2f} us, time to gap {ttg:.3f} s")
@@ -531,7 +632,7 @@ def main():
         out["turn_river"] = turn_river_leg(args, stream)
         log("turn+river leg done")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(desc, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(desc, args.cpu_budget, gpu_iters=iters)
         log("CPU baseline done")
     print(json.dumps(out), flush=True)
 

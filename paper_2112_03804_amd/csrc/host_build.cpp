@@ -706,6 +706,7 @@ void build_matvec_plan(HostGame& hg, int d, int rows_per_block) {
       MvItem& m = D.items[it];
       const bool joins = it + 1 < D.blk[b + 1] && m.ctx >= 0 && D.items[it + 1].ctx == m.ctx;
       m.run_end = joins ? D.items[it + 1].run_end : it + 1;
+      m.n_opp = m.ctx >= 0 ? D.ctx[m.ctx].n_opp : 0;
     }
   }
 }

@@ -196,12 +196,11 @@ __global__ __launch_bounds__(BLOCK, sizeof(IO) == 4 ? 4 : 3) void k_matvec(MvPar
   const int it0 = P.blk[b], it1 = P.blk[b + 1];
   auto fetch = [&](int it) {
     const MvItem nx = P.items[it];
-    const int nopp = nx.ctx >= 0 ? P.ctx[nx.ctx].n_opp : 0;
 #pragma unroll
     for (int k = 0; k < KH; ++k) {
       const int h = tid + k * BLOCK;
-      nxs[k] = (h < nopp && nx.in_s >= 0) ? in[nx.in_s + h] : (IO)0;
-      nxf[k] = (h < nopp && nx.in_f >= 0) ? in[nx.in_f + h] : (IO)0;
+      nxs[k] = (h < nx.n_opp && nx.in_s >= 0) ? in[nx.in_s + h] : (IO)0;
+      nxf[k] = (h < nx.n_opp && nx.in_f >= 0) ? in[nx.in_f + h] : (IO)0;
     }
   };
   if (it0 < it1) fetch(it0);
@@ -524,14 +523,33 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
   const int it0 = cr.x, it1 = cr.y;
   auto fetch = [&](int it) {
     const MvItem nx = P.items[it];
-    const int nopp = nx.ctx >= 0 ? P.ctx[nx.ctx].n_opp : 0;
 #pragma unroll
     for (int k = 0; k < KH; ++k) {
       const int h = tid + k * BLOCK;
-      nxs[k] = (h < nopp && nx.in_s >= 0) ? in[nx.in_s + h] : (IO)0;
-      nxf[k] = (h < nopp && nx.in_f >= 0) ? in[nx.in_f + h] : (IO)0;
+      nxs[k] = (h < nx.n_opp && nx.in_s >= 0) ? in[nx.in_s + h] : (IO)0;
+      nxf[k] = (h < nx.n_opp && nx.in_f >= 0) ? in[nx.in_f + h] : (IO)0;
     }
   };
+  // the records of the chunk's first context load beside its first item, so
+  // that both the inputs and the context's per-hand records are one
+  // dependent load away from the chunk record
+  auto load_ctx = [&](int c) {
+    const McCtx C = P.ctx[c];
+    n_own = C.n_own;
+    cph = C.cph;
+    n_chunk = C.n_chunk;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int h = tid + k * BLOCK;
+      qr[k] = h < C.n_own ? P.q[C.q_off + h] : make_uint4(0xffffffffu, 0u, 0u, 0u);
+      lo[k] = h < C.n_own ? lam[C.lam_own_off + h] : (IO)0;
+      ps[k] = h < C.n_opp ? P.pos[C.pos_off + h] : make_uint2(0xffffffffu, 0xffffffffu);
+      lp[k] = h < C.n_opp ? lam[C.lam_opp_off + h] : (IO)0;
+    }
+    cm = P.meta[C.meta_off + tid];
+    cur = c;
+  };
+  if (cr.w >= 0) load_ctx(cr.w);
   if (it0 < it1) fetch(it0);
   for (int it = it0; it < it1; ++it) {
     const MvItem item = P.items[it];
@@ -551,22 +569,7 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
       continue;
     }
     __syncthreads();   // the previous item's readers of S, F and segT are done
-    if (item.ctx != cur) {
-      const McCtx C = P.ctx[item.ctx];
-      n_own = C.n_own;
-      cph = C.cph;
-      n_chunk = C.n_chunk;
-#pragma unroll
-      for (int k = 0; k < KH; ++k) {
-        const int h = tid + k * BLOCK;
-        qr[k] = h < C.n_own ? P.q[C.q_off + h] : make_uint4(0xffffffffu, 0u, 0u, 0u);
-        lo[k] = h < C.n_own ? lam[C.lam_own_off + h] : (IO)0;
-        ps[k] = h < C.n_opp ? P.pos[C.pos_off + h] : make_uint2(0xffffffffu, 0xffffffffu);
-        lp[k] = h < C.n_opp ? lam[C.lam_opp_off + h] : (IO)0;
-      }
-      cm = P.meta[C.meta_off + tid];
-      cur = item.ctx;
-    }
+    if (item.ctx != cur) load_ctx(item.ctx);
     const bool hs = item.in_s >= 0, hf = item.in_f >= 0;
     // weighted opponent inputs into their slots
     const IO ks = (IO)item.ks, kf = (IO)item.kf;

@@ -138,7 +138,7 @@ struct MvItem {
   int32_t n_own, stride;                // output row length and padded stride
   double kf, ks;                        // coefficients (payoff x chance)
   int32_t run_end;                      // one past the last item of this chunk with the same ctx
-  int32_t pad;
+  int32_t n_opp;                        // opponent hands of the context (0 without one)
 };
 struct MvDir {                          // host copy of one direction's plan
   std::vector<MvCtx> ctx;
