@@ -959,8 +959,9 @@ int build_rm_plan(HostGame& hg, int p, int cap, std::string& msg) {
         }
         par_of[m] = par;
       }
-      // Split the piece for the four wavefronts of a block: up to four groups
-      // of whole subtrees (largest first onto the least loaded wavefront)
+      // Split the piece for the kRmGroups wavefronts of a block: up to that
+      // many groups of whole subtrees (largest first onto the least loaded
+      // wavefront)
       // walked concurrently, and the top part above them walked by wavefront
       // 0.  A group root's value goes to its wavefront's accumulator slot j
       // (one per distinct parent target); wavefront 0 adds the slots into
@@ -982,7 +983,7 @@ int build_rm_plan(HostGame& hg, int p, int cap, std::string& msg) {
         for (int m = 0; m < nm; ++m)
           if (rows_t[m] <= target && (pinf[m] < 0 || rows_t[pinf[m]] > target)) cand.push_back(m);
         std::stable_sort(cand.begin(), cand.end(), [&](int a, int c) { return rows_t[a] > rows_t[c]; });
-        int load[kRmGroups] = {0, 0, 0, 0};
+        int load[kRmGroups] = {};
         for (int m : cand) {
           int w = 0;
           for (int q2 = 1; q2 < kRmGroups; ++q2)
@@ -1039,14 +1040,21 @@ int build_rm_plan(HostGame& hg, int p, int cap, std::string& msg) {
         t.grp_off = (int32_t)P.grp.size();
         std::vector<int32_t> G(64, 0);
         G[0] = kRmGroups;
+        std::vector<std::pair<int, int>> merge;   // (target row, slot row)
         for (int w = 0; w < kRmGroups; ++w) {
-          G[1 + w] = gb[w];
-          G[5 + w] = gb[w + 1];
-          G[11 + w] = (int)gtargets[w].size();
-          for (size_t j = 0; j < gtargets[w].size(); ++j) G[16 + kRmGroupSlots * w + j] = lds_row(gtargets[w][j]);
+          G[kRmGBeg + w] = gb[w];
+          G[kRmGEnd + w] = gb[w + 1];
+          G[kRmGCnt + w] = (int)gtargets[w].size();
+          for (size_t j = 0; j < gtargets[w].size(); ++j)
+            merge.emplace_back(lds_row(gtargets[w][j]), kRmRowSlot + kRmGroupSlots * w + (int)j);
         }
-        G[9] = gb[kRmGroups];
-        G[10] = nm;
+        while ((int)merge.size() < kRmMergeMax) merge.emplace_back(kRmRowOne, kRmRowOne);
+        std::stable_sort(merge.begin(), merge.end(),
+                         [](const std::pair<int, int>& a, const std::pair<int, int>& c) { return a.first < c.first; });
+        for (int e = 0; e < kRmMergeMax; ++e)
+          G[kRmGMrg + e / 2] |= (merge[e].second | (merge[e].first << 8)) << (16 * (e & 1));
+        G[kRmGTop] = gb[kRmGroups];
+        G[kRmGTop + 1] = nm;
         P.grp.insert(P.grp.end(), G.begin(), G.end());
       }
       t.ext_off = (int32_t)P.ext_seq.size();

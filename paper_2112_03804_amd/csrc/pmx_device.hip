@@ -907,11 +907,13 @@ __device__ inline float rm_new(float r, float inst, const RmStep& k) {
   return r * (r > 0.f ? k.dp : k.dn) + inst;
 }
 
-// num / den for den > 0 with one reciprocal; both are scaled by 2^64 when den
-// is so small that its reciprocal would overflow FP32.
-__device__ inline float rm_quot(float num, float den) {
-  const float sc = den < 0x1p-64f ? 0x1p64f : 1.f;
-  return (num * sc) * __builtin_amdgcn_rcpf(den * sc);
+// 1 / (den * sc) for den > 0, with sc = 2^64 when den is so small that 1 / den
+// would overflow FP32.  A quotient v / den is formed as (v * sc) * rcp, so
+// it never passes through 1 / den: behaviour probabilities (v <= den) stay
+// at most 1 and expected values stay in the range of v / den.
+__device__ inline float rm_rcp(float den, float& sc) {
+  sc = den < 0x1p-64f ? 0x1p64f : 1.f;
+  return __builtin_amdgcn_rcpf(den * sc);
 }
 
 constexpr int TPB = 128;
@@ -922,11 +924,12 @@ __global__ void k_set1(double* tdev, double v) { tdev[0] = v; }
 
 // ---------------------------------------------------------------------------
 // regret update on treeplex pieces (RmTask): the piece's rows of g, R and x
-// for 64 hands live in LDS; every wavefront of the block loads and stores a
-// quarter of the rows (all loads in flight at once), wavefront 0 walks the
-// piece's infosets.  Row, infoset, pull and external-parent tables are held
-// one entry per lane and read with readlane, so the walk touches LDS only
-// for the slab itself.
+// for 64 hands live in LDS; every wavefront of the block loads and stores an
+// equal share of the rows (all loads in flight at once), each wavefront walks
+// one subtree group of the piece and wavefront 0 the top part.  Row,
+// infoset, pull, group and external-parent tables are held one entry per
+// lane and read with readlane, so the walk touches LDS only for the slab
+// itself.
 // ---------------------------------------------------------------------------
 // One workgroup of a regret-update launch: its piece and first hand.
 struct RmBlock {
@@ -948,7 +951,7 @@ struct RmParams {
   int32_t dcfr, gamma;
   float alpha, beta;
 };
-constexpr int RMW = 4;                      // wavefronts per block
+constexpr int RMW = kRmGroups;              // wavefronts per block, one per subtree group
 constexpr int RMR = kTaskRowsMax / RMW;     // rows loaded per wavefront
 
 __device__ inline int rl(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
@@ -981,7 +984,9 @@ __device__ inline void rmp_up_w(float* __restrict__ Al, float* __restrict__ Rl, 
     gs += a < n ? gg[a] : 0.f;
   }
   const bool pos = rs > 0.f;
-  const float V = rm_quot(pos ? dot : gs, pos ? rs : (float)n);
+  float sc;
+  const float rc = rm_rcp(pos ? rs : (float)n, sc);
+  const float V = ((pos ? dot : gs) * sc) * rc;
 #pragma unroll
   for (int a = 0; a < W; ++a) Rl[(f + min(a, n - 1)) * 64 + lane] = rm_new<DC>(rr[a], gg[a] - V, K);
   *pp = pv + V;
@@ -1001,9 +1006,10 @@ __device__ inline void rmp_down_w(float* __restrict__ Al, const float* __restric
 #pragma unroll
   for (int a = 0; a < W; ++a) rs += a < n ? rr[a] : 0.f;
   const bool pos = rs > 0.f;
-  const float k = rm_quot(xp, pos ? rs : (float)n);
+  float sc;
+  const float rc = rm_rcp(pos ? rs : (float)n, sc);
 #pragma unroll
-  for (int a = 0; a < W; ++a) Al[(f + min(a, n - 1)) * 64 + lane] = (pos ? rr[a] : 1.f) * k;
+  for (int a = 0; a < W; ++a) Al[(f + min(a, n - 1)) * 64 + lane] = xp * (((pos ? rr[a] : 1.f) * sc) * rc);
 }
 
 // Any action count (beyond MAXA).
@@ -1018,7 +1024,9 @@ __device__ inline void rmp_up_any(float* __restrict__ Al, float* __restrict__ Rl
     gs += gv;
   }
   const bool pos = rs > 0.f;
-  const float V = rm_quot(pos ? dot : gs, pos ? rs : (float)n);
+  float sc;
+  const float rc = rm_rcp(pos ? rs : (float)n, sc);
+  const float V = ((pos ? dot : gs) * sc) * rc;
   for (int a = 0; a < n; ++a)
     Rl[(f + a) * 64 + lane] = rm_new<DC>(Rl[(f + a) * 64 + lane], Al[(f + a) * 64 + lane] - V, K);
   *pp += V;
@@ -1029,8 +1037,10 @@ __device__ inline void rmp_down_any(float* __restrict__ Al, const float* __restr
   float rs = 0.f;
   for (int a = 0; a < n; ++a) rs += fmaxf(Rl[(f + a) * 64 + lane], 0.f);
   const bool pos = rs > 0.f;
-  const float k = rm_quot(xp, pos ? rs : (float)n);
-  for (int a = 0; a < n; ++a) Al[(f + a) * 64 + lane] = (pos ? fmaxf(Rl[(f + a) * 64 + lane], 0.f) : 1.f) * k;
+  float sc;
+  const float rc = rm_rcp(pos ? rs : (float)n, sc);
+  for (int a = 0; a < n; ++a)
+    Al[(f + a) * 64 + lane] = xp * (((pos ? fmaxf(Rl[(f + a) * 64 + lane], 0.f) : 1.f) * sc) * rc);
 }
 
 // Two widths keep the common small infosets cheap; one call site per
@@ -1126,10 +1136,10 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
     for (int k = 0; k < T.n_ext; ++k) Xl[k * 64 + lane] = 0.f;
   // infoset ranges: wavefront wv's group, and the top part (all infosets when
   // the piece is not split)
-  const int gb = grouped ? rl(grpv, 1 + wv) : 0, ge = grouped ? rl(grpv, 5 + wv) : 0;
-  const int tb = grouped ? rl(grpv, 9) : 0, te = grouped ? rl(grpv, 10) : T.n_inf;
+  const int gb = grouped ? rl(grpv, kRmGBeg + wv) : 0, ge = grouped ? rl(grpv, kRmGEnd + wv) : 0;
+  const int tb = grouped ? rl(grpv, kRmGTop) : 0, te = grouped ? rl(grpv, kRmGTop + 1) : T.n_inf;
   if (MODE != 2 && grouped)
-    for (int j = 0; j < rl(grpv, 11 + wv); ++j) Xw[(wv * kRmGroupSlots + j) * 64 + lane] = 0.f;
+    for (int j = 0; j < rl(grpv, kRmGCnt + wv); ++j) Xw[(wv * kRmGroupSlots + j) * 64 + lane] = 0.f;
   __syncthreads();
   if (MODE != 2) {
     // pass 0: the wavefront's group (groups concurrently, a group root's
@@ -1139,10 +1149,32 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
     for (int ps = grouped ? 0 : 1; ps < 2; ++ps) {
       if (ps == 1 && grouped) {
         __syncthreads();
-        if (wv == 0)
-          for (int w = 0; w < RMW; ++w)
-            for (int j = 0; j < rl(grpv, 11 + w); ++j)
-              rsm[rl(grpv, 16 + kRmGroupSlots * w + j) * 64 + lane] += Xw[(w * kRmGroupSlots + j) * 64 + lane];
+        if (wv == 0) {
+          // every slot value and target value is read before the first
+          // wait; a run of entries with one target (entries are sorted by
+          // target) sums its slots in registers, and every entry writes the
+          // target's value plus the run so far, so the run's last write,
+          // which lands last, leaves the whole sum: no branch per entry
+          int mge[kRmMergeMax / 2];   // two entries per int, into SGPRs
+#pragma unroll
+          for (int e = 0; e < kRmMergeMax / 2; ++e) mge[e] = rl(grpv, kRmGMrg + e);
+          float sv[kRmMergeMax], tv[kRmMergeMax];
+#pragma unroll
+          for (int e = 0; e < kRmMergeMax; ++e) {
+            const int c = (mge[e / 2] >> (16 * (e & 1))) & 0xffff;
+            sv[e] = rsm[(c & 255) * 64 + lane];
+            tv[e] = rsm[(c >> 8) * 64 + lane];
+          }
+          float run = 0.f;
+          int prev = -1;
+#pragma unroll
+          for (int e = 0; e < kRmMergeMax; ++e) {
+            const int tg = ((mge[e / 2] >> (16 * (e & 1))) >> 8) & 255;
+            run = (tg == prev ? run : 0.f) + sv[e];
+            rsm[tg * 64 + lane] = tv[e] + run;
+            prev = tg;
+          }
+        }
       }
       if (ps == 1 && wv != 0) break;
       const int i0 = ps ? tb : gb, i1 = ps ? te : ge;

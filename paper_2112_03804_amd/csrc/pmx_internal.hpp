@@ -223,6 +223,23 @@ constexpr int kTaskRowsMax = 64;        // rows per piece (one per lane of a wav
 constexpr int kTaskExtMax = 15;         // distinct external parents per piece
 constexpr int kRmGroups = 4;            // subtree groups walked concurrently (wavefronts per block)
 constexpr int kRmGroupSlots = 4;        // distinct parent targets of one group's roots
+// Group table of a split piece (64 ints): [kRmGBeg + w] / [kRmGEnd + w] the
+// infoset range of group w, [kRmGTop] / [kRmGTop + 1] the range of the top
+// part, [kRmGCnt + w] the number of accumulator slots of group w, and
+// kRmMergeMax merge entries, two per int from [kRmGMrg] (entry 2i in bits
+// 0-15, 2i+1 in bits 16-31): the LDS row of a group-root slot (bits 0-7) and
+// of its target (bits 8-15).  Entries are sorted by target, the slots of one
+// target in group order; the list is filled up at its front with entries
+// whose slot and target are the root sink row (nothing reads it before the
+// top-down pass sets it to 1).
+constexpr int kRmMergeMax = kRmGroups * kRmGroupSlots;
+constexpr int kRmGBeg = 1;
+constexpr int kRmGEnd = kRmGBeg + kRmGroups;
+constexpr int kRmGTop = kRmGEnd + kRmGroups;
+constexpr int kRmGCnt = kRmGTop + 2;
+constexpr int kRmGMrg = kRmGCnt + kRmGroups;
+static_assert(kRmMergeMax % 2 == 0 && kRmGMrg + kRmMergeMax / 2 <= 64,
+              "the group table is read one entry per lane");
 // LDS rows of a regret-update workgroup in one index space (a row holds one
 // value per hand of the workgroup): the root sink / root weight, the
 // group-root accumulator slots (kRmGroupSlots per wavefront), the external
@@ -251,10 +268,8 @@ struct RmTask {
 // sequence's realization weight in the top-down pass (bits 24-31: the
 // parent's row, the external parent's row, or the root-weight row).  LDS
 // rows as numbered by kRmRow*.  Pull: local row (bits 0-7) | stage row << 8.
-// Group table: [0] groups, [1 + w] / [5 + w] infoset range of group w, [9] /
-// [10] range of the top part, [11 + w] targets of group w,
-// [16 + kRmGroupSlots w + j] the LDS row of its target j.  Infosets are
-// listed group by group, then the top part, each in depth-first order.
+// Group table: as described at kRmGBeg.  Infosets are listed group by group,
+// then the top part, each in depth-first order.
 struct RmPlan {                         // one player
   std::vector<RmTask> tasks;
   std::vector<int32_t> rows, infs, pulls, ext_seq, ext_slot, grp;

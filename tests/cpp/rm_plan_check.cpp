@@ -130,7 +130,7 @@ extern "C" int check_rm_plan(const GameDesc* d, int n, int cap, char* msg, int m
             dn = v >> 24;
           };
           const int* G = t.grp_off >= 0 ? &P.grp[t.grp_off] : nullptr;
-          const int tb = G ? G[9] : 0, te = G ? G[10] : t.n_inf;
+          const int tb = G ? G[kRmGTop] : 0, te = G ? G[kRmGTop + 1] : t.n_inf;
           if (mode != 2) {
             for (int j = 0; j < t.n_pull; ++j) {
               const int v = P.pulls[t.pull_off + j];
@@ -138,7 +138,7 @@ extern "C" int check_rm_plan(const GameDesc* d, int n, int cap, char* msg, int m
             }
             if (G)
               for (int w = 0; w < kRmGroups; ++w)
-                for (int i = G[5 + w] - 1; i >= G[1 + w]; --i) {
+                for (int i = G[kRmGEnd + w] - 1; i >= G[kRmGBeg + w]; --i) {
                   int f, na, up, dn;
                   decode(i, f, na, up, dn);
                   const bool own_slot = up >= kRmRowSlot + kRmGroupSlots * w && up < kRmRowSlot + kRmGroupSlots * (w + 1);
@@ -148,9 +148,38 @@ extern "C" int check_rm_plan(const GameDesc* d, int n, int cap, char* msg, int m
                   }
                   U[up] += update_infoset(A, Rl.data(), f, na);
                 }
-            if (G)
-              for (int w = 0; w < kRmGroups; ++w)
-                for (int j = 0; j < G[11 + w]; ++j) U[G[16 + kRmGroupSlots * w + j]] += U[kRmRowSlot + kRmGroupSlots * w + j];
+            if (G) {
+              // merge entries: every group slot once plus sink fillers,
+              // sorted by target; each entry writes the target's value plus
+              // the sum of its run so far
+              std::vector<int> slots_seen;
+              int prev = -1;
+              float run = 0.f;
+              std::vector<float> before(U);
+              for (int e = 0; e < kRmMergeMax; ++e) {
+                const int c = (G[kRmGMrg + e / 2] >> (16 * (e & 1))) & 0xffff, sl = c & 255, tg = c >> 8;
+                if (tg < prev) {
+                  snprintf(msg, msglen, "merge entries not sorted by target");
+                  throw 1;
+                }
+                if (sl != kRmRowOne) slots_seen.push_back(sl);
+                else if (tg != kRmRowOne) {
+                  snprintf(msg, msglen, "a filler merge entry targets LDS row %d", tg);
+                  throw 1;
+                }
+                run = (tg == prev ? run : 0.f) + before[sl];
+                U[tg] = before[tg] + run;
+                prev = tg;
+              }
+              int n_slots = 0;
+              for (int w = 0; w < kRmGroups; ++w) n_slots += G[kRmGCnt + w];
+              std::sort(slots_seen.begin(), slots_seen.end());
+              if ((int)slots_seen.size() != n_slots ||
+                  std::unique(slots_seen.begin(), slots_seen.end()) != slots_seen.end()) {
+                snprintf(msg, msglen, "merge entries do not cover the %d group slots once each", n_slots);
+                throw 1;
+              }
+            }
             for (int i = te - 1; i >= tb; --i) {
               int f, na, up, dn;
               decode(i, f, na, up, dn);

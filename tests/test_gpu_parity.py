@@ -401,6 +401,49 @@ def test_single_step_any_piece_size(name, fn, rows, kind):
     g.close()
 
 
+@pytest.mark.parametrize("kind", ["rm+", "dcfr"])
+@pytest.mark.parametrize("tiny", [1e-30, 1e-42])
+def test_single_step_tiny_regret_sums(tiny, kind):
+    """Regret sums far below 1 (1e-30, and subnormal FP32 at 1e-42) give
+    finite results: the walk's reciprocal is taken of a rescaled sum and no
+    step passes through 1 / sum, which overflows FP32 for a subnormal sum (a
+    hand whose gradient is 0 keeps its tiny regrets into the top-down pass).
+    At 1e-30 the step matches the oracle to the usual tolerance; subnormal
+    regrets times the gradient keep only a few bits, so at 1e-42 the check is
+    finiteness and a plan that is the realization of the device's regrets."""
+    pmx = _need_gpu()
+    d = I.config(1)
+    _say("tiny regret sums", tiny, kind)
+    o = payoff.Game(d)
+    g = pmx.Game(d)
+    g.solver_set_params(kind)
+    rng = np.random.default_rng(5)
+    ref = solver.RMPlus(o, kind=kind)
+    t0, w0 = 3, 6.0
+    for p in range(2):
+        R = (rng.random((o.S[p], o.N[p])) * tiny + tiny * 0.01).astype(np.float32).astype(np.float64)
+        x = ref.tp[p].realization(ref.tp[p].behaviour_from_regret(R)).astype(np.float32).astype(np.float64)
+        s = rng.random((o.S[p], o.N[p]))
+        ref.R[p], ref.x[p], ref.sum[p] = R, x, s.copy()
+        g.solver_set_state(p, regret=g.pack(p, [R]), plan=g.pack(p, [x]),
+                           avg_sum=g.pack(p, [s], np.float64), t=t0, wsum=w0)
+    ref.t, ref.wsum = t0, w0
+    g.solver_step(1)
+    torch.cuda.synchronize()
+    ref.step()
+    for p in range(2):
+        st = g.solver_get_state(p)
+        R = g.unpack(p, st["regret"])[0]
+        x = g.unpack(p, st["plan"])[0]
+        assert np.isfinite(R).all() and np.isfinite(x).all(), p
+        scale = max(1.0, np.abs(ref.R[p]).max())
+        if tiny >= 1e-37:
+            assert np.abs(R - ref.R[p]).max() <= 1e-5 * scale, (p, np.abs(R - ref.R[p]).max())
+        tp = ref.tp[p]
+        assert np.abs(x - tp.realization(tp.behaviour_from_regret(R))).max() <= 1e-5, p
+    g.close()
+
+
 def test_piece_size_rejects_too_small():
     pmx = _need_gpu()
     g = pmx.Game(I.config(1))
