@@ -518,7 +518,7 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
 #pragma unroll
   for (int k = 0; k < KH; ++k) acc[k] = 0.0;
   uint32_t cm = 0;
-  int n_own = 0, cph = 1, n_chunk = 0, cur = -2;
+  int n_own = 0, cph = 1, n_chunk = 0, cur = -2, fz = -2;
 
   const int it0 = cr.x, it1 = cr.y;
   auto fetch = [&](int it) {
@@ -569,6 +569,20 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
       continue;
     }
     __syncthreads();   // the previous item's readers of S, F and segT are done
+    if (item.ctx != fz) {
+      // fold slots are written only by the scatter, so once zeroed for a
+      // context its slots past each segment's entries stay 0 and the fold
+      // chunk sums need no mask
+#pragma unroll
+      for (int j = 0; j < SK; j += VN) {
+        IO z[VN];
+#pragma unroll
+        for (int u = 0; u < VN; ++u) z[u] = (IO)0;
+        Vec4<IO>::st(&F[tid * SK + j], z);
+      }
+      fz = item.ctx;
+      __syncthreads();
+    }
     if (item.ctx != cur) load_ctx(item.ctx);
     const bool hs = item.in_s >= 0, hf = item.in_f >= 0;
     // weighted opponent inputs into their slots
@@ -616,7 +630,7 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
         IO v[VN];
         Vec4<IO>::ld(&F[tid * SK + j], v);
 #pragma unroll
-        for (int u = 0; u < VN; ++u) lf += j + u < nv ? v[u] : (IO)0;
+        for (int u = 0; u < VN; ++u) lf += v[u];
       }
     }
     const double ts = (double)ls, tf = (double)lf;
