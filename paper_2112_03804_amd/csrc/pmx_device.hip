@@ -569,19 +569,26 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
       continue;
     }
     __syncthreads();   // the previous item's readers of S, F and segT are done
-    if (item.ctx != fz) {
-      // fold slots are written only by the scatter, so once zeroed for a
-      // context its slots past each segment's entries stay 0 and the fold
-      // chunk sums need no mask
-#pragma unroll
-      for (int j = 0; j < SK; j += VN) {
+    {
+      // Slots past each segment's entries must read as 0 in the chunk sums.
+      // Fold slots are written only by the scatter, so they are zeroed once
+      // per context; showdown slots also receive the previous item's
+      // prefixes, so each thread zeroes its own chunk before every scatter.
+      // Both replace a mask per entry in the sums.
+      const bool zf = item.ctx != fz, zs = item.in_s >= 0;
+      if (zf || zs) {
         IO z[VN];
 #pragma unroll
         for (int u = 0; u < VN; ++u) z[u] = (IO)0;
-        Vec4<IO>::st(&F[tid * SK + j], z);
+        if (zs)
+#pragma unroll
+          for (int j = 0; j < KE; j += VN) Vec4<IO>::st(&S[tid * SK + j], z);
+        if (zf)
+#pragma unroll
+          for (int j = 0; j < SK; j += VN) Vec4<IO>::st(&F[tid * SK + j], z);
+        fz = item.ctx;
+        __syncthreads();
       }
-      fz = item.ctx;
-      __syncthreads();
     }
     if (item.ctx != cur) load_ctx(item.ctx);
     const bool hs = item.in_s >= 0, hf = item.in_f >= 0;
@@ -608,11 +615,10 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
       }
     }
     __syncthreads();
-    // chunk sums (slots past the chunk's valid entries read as 0)
-    // Chunk sums in the I/O type (at most KE terms), carried across chunks in
-    // FP64; the chunk is read again after the scan rather than held in
-    // registers.  Wavefronts past the last chunk skip both passes.
-    const int nv = (int)(cm & 255u);
+    // Chunk sums in the I/O type (at most KE terms; slots past a segment's
+    // entries hold 0), carried across chunks in FP64; the chunk is read
+    // again after the scan rather than held in registers.  Wavefronts past
+    // the last chunk skip both passes.
     const bool wlive = (tid & ~63) < n_chunk;
     IO ls = (IO)0, lf = (IO)0;
     if (hs && wlive) {
@@ -621,7 +627,7 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
         IO v[VN];
         Vec4<IO>::ld(&S[tid * SK + j], v);
 #pragma unroll
-        for (int u = 0; u < VN; ++u) ls += j + u < nv ? v[u] : (IO)0;
+        for (int u = 0; u < VN; ++u) ls += v[u];
       }
     }
     if (hf && wlive) {
@@ -638,10 +644,9 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
     block_seg_scan_x<NW>((int)((cm >> 8) & 1u), ts, tf, scr, es, ef);
     if (hs && wlive) {
       // FP32: the FP64 carry as a rounded head plus its remainder, so each
-      // prefix is head + (remainder + partial) in two FP32 adds.  Slots past
-      // a segment's end slot (which only sums valid entries) receive
-      // unspecified values; the first pass masks them and no query reads
-      // them.
+      // prefix is head + (remainder + partial) in two FP32 adds.  The slot
+      // after a segment's last entry receives the segment's total; the
+      // zeroed slots after it add nothing, and no query reads past it.
       const IO eh = (IO)es;
       IO run = sizeof(IO) == 4 ? (IO)(es - (double)eh) : (IO)0;
 #pragma unroll
