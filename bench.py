@@ -390,6 +390,15 @@ def warm_leg(args, stream, batched):
     ws.apply_prior(g, net, args.warm_scale, args.warm_avg)
     sec, iters, done = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters)
     t_warm = time.perf_counter() - t2
+    # the same prior under discounted CFR
+    log(f"warm start: RM+ {t_warm:.2f} s; DCFR from the same prior")
+    g.solver_set_params("dcfr")
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ws.apply_prior(g, net, args.warm_scale, args.warm_avg)
+    _, iters_d, done_d = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters)
+    t_warm_d = time.perf_counter() - t3
+    g.solver_set_params("rm+")
     g.close()
     plain_total = batched["plain_single_instance_sample"]["sum_over_batch_extrapolated_s"]
     return {"train_instances": len(train_descs),
@@ -405,7 +414,11 @@ def warm_leg(args, stream, batched):
                                                     for q in (50, 90, 100)] if (done >= 0).any() else None,
             "instances_reached": int((done >= 0).sum()),
             "speedup_vs_plain_single_instance": plain_total / t_warm,
-            "speedup_vs_batched_uniform": batched["time_to_gap_batched_s"] / t_warm}
+            "speedup_vs_batched_uniform": batched["time_to_gap_batched_s"] / t_warm,
+            "dcfr": {"time_to_gap_warm_batched_s": t_warm_d, "iterations": iters_d,
+                     "instances_reached": int((done_d >= 0).sum()),
+                     "speedup_vs_plain_single_instance_rm+": plain_total / t_warm_d,
+                     "speedup_vs_batched_uniform_dcfr": batched["time_to_gap_batched_dcfr_s"] / t_warm_d}}
 
 
 def pmc_probe(args):
