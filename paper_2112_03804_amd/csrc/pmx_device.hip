@@ -957,8 +957,6 @@ struct RmBlock {
 };
 
 struct RmParams {
-  RmTask one;                   // the launch's piece when it has only one (use_one)
-  int32_t use_one;
   const RmBlock* blocks;
   const int32_t* rows;
   const int32_t* infs;
@@ -1088,10 +1086,8 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
                                                   float* __restrict__ x, double* __restrict__ xs,
                                                   float* __restrict__ stage, const double* __restrict__ tdev) {
   extern __shared__ float rsm[];
-  // a launch of one piece takes it from the kernel arguments, one dependent
-  // load fewer than the per-block record
-  const RmTask T = P.use_one ? P.one : P.blocks[blockIdx.x].t;
-  const int h0 = P.use_one ? (int)blockIdx.x * 64 : P.blocks[blockIdx.x].h0;
+  const RmTask T = P.blocks[blockIdx.x].t;
+  const int h0 = P.blocks[blockIdx.x].h0;
   if (P.active && !P.active[T.inst]) return;   // whole block: T is uniform
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1525,7 +1521,6 @@ struct DevRm {                  // regret-update pieces of one player
   DBuf<RmBlock> blocks;         // all depths, depth d at [blk_off[d], blk_off[d + 1])
   std::vector<int> blk_off;
   std::vector<int> max_rows, max_ext;   // per depth
-  std::vector<RmTask> one;      // per depth: its only piece, if it has one (else n_rows = 0)
   DBuf<float> stage;
   int stage_stride = 1;
 };
@@ -1675,10 +1670,8 @@ static int upload_rm(Game* g, int p) {
   E.blk_off.assign(D + 1, 0);
   E.max_rows.assign(D, 0);
   E.max_ext.assign(D, 0);
-  E.one.assign(D, RmTask{});
   for (int d = 0; d < D; ++d) {
     E.blk_off[d] = (int)blocks.size();
-    if (T.by_depth[d].size() == 1) E.one[d] = T.tasks[T.by_depth[d][0]];
     for (int id : T.by_depth[d]) {
       const RmTask& t = T.tasks[id];
       E.max_rows[d] = std::max(E.max_rows[d], (int)t.n_rows);
@@ -1995,8 +1988,6 @@ static TpParams tp_params(Game* g, int p, const int2* blocks) {
 static RmParams rm_params(Game* g, int p, int depth) {
   DevRm& E = g->drm[p];
   RmParams P;
-  P.one = E.one[depth];
-  P.use_one = E.one[depth].n_rows > 0;
   P.blocks = E.blocks.p + E.blk_off[depth];
   P.rows = E.rows.p;
   P.infs = E.infs.p;
