@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 # known size (profiles/matvec_pair_traffic_counters.md).  They describe the
 # kernel sources whose SHA-1 is recorded here and are reported as null for any
 # other version of those sources.
-TRAFFIC = {"sources_sha1": "792b8f3b45a845a0ba846c41278fe42795731b5f", "river": 1630206, "batch": 449781162}
+TRAFFIC = {"sources_sha1": "06eac292cc4b54218c14dbdb78c5ba696190088d", "river": 2395273, "batch": 449607746}
 TRAFFIC_SOURCES = ("paper_2112_03804_amd/csrc/pmx_device.hip", "paper_2112_03804_amd/csrc/host_build.cpp")
 
 
@@ -491,6 +491,7 @@ def main():
                     help="instances of the batch whose matvec pair is timed beyond the Infinity Cache (0: skip)")
     ap.add_argument("--max-iters", type=int, default=100000)
     ap.add_argument("--no-turn", action="store_true")
+    ap.add_argument("--no-tiny", action="store_true", help="skip the 13-card game's time to gap")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run the launches profiled for HBM traffic counters")
     ap.add_argument("--trace-probe", action="store_true",
@@ -586,20 +587,22 @@ def main():
 
     # ---- the 13-card game to 1e-6 * pot (launch-latency bound) ------------
     tiny = I.config(0)
-    gt = pmx.Game(tiny)
     tpot = 2 * tiny.contrib
-    gt.solver_reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    t_it, t_gap = 0, float("inf")
-    while t_it < 200000:
-        gt.solver_step(25)
-        t_it += 25
-        t_gap = float(gt.saddle_gap()[0][0])
-        if t_gap <= 1e-6 * tpot:
-            break
-    tiny_ttg = time.perf_counter() - t0
-    gt.close()
+    tiny_ttg, t_it, t_gap = None, 0, float("nan")
+    if not args.no_tiny:
+        gt = pmx.Game(tiny)
+        gt.solver_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_gap = float("inf")
+        while t_it < 200000:
+            gt.solver_step(25)
+            t_it += 25
+            t_gap = float(gt.saddle_gap()[0][0])
+            if t_gap <= 1e-6 * tpot:
+                break
+        tiny_ttg = time.perf_counter() - t0
+        gt.close()
 
     out = {
         "metric": "matvec pairs/s (A·y+Aᵀx) & time to gap 1e-4·pot: plain vs batched/warm-start",

@@ -521,20 +521,13 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
   int n_own = 0, cph = 1, n_chunk = 0, cur = -2, fz = -2;
 
   const int it0 = cr.x, it1 = cr.y;
-  auto fetch = [&](int it) {
-    const MvItem nx = P.items[it];
-#pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      const int h = tid + k * BLOCK;
-      nxs[k] = (h < nx.n_opp && nx.in_s >= 0) ? in[nx.in_s + h] : (IO)0;
-      nxf[k] = (h < nx.n_opp && nx.in_f >= 0) ? in[nx.in_f + h] : (IO)0;
-    }
-  };
   // the records of the chunk's first context load beside its first item, so
   // that both the inputs and the context's per-hand records are one
-  // dependent load away from the chunk record
-  auto load_ctx = [&](int c) {
-    const McCtx C = P.ctx[c];
+  // dependent load away from the chunk record.  These loads and the input
+  // fetches are written out at each use: lambdas capturing the per-hand
+  // arrays by reference kept those arrays in scratch memory.
+  if (cr.w >= 0) {
+    const McCtx C = P.ctx[cr.w];
     n_own = C.n_own;
     cph = C.cph;
     n_chunk = C.n_chunk;
@@ -547,10 +540,18 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
       lp[k] = h < C.n_opp ? lam[C.lam_opp_off + h] : (IO)0;
     }
     cm = P.meta[C.meta_off + tid];
-    cur = c;
-  };
-  if (cr.w >= 0) load_ctx(cr.w);
-  if (it0 < it1) fetch(it0);
+    cur = cr.w;
+  }
+  if (it0 < it1)
+  {
+    const MvItem nx = P.items[it0];
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int h = tid + k * BLOCK;
+      nxs[k] = (h < nx.n_opp && nx.in_s >= 0) ? in[nx.in_s + h] : (IO)0;
+      nxf[k] = (h < nx.n_opp && nx.in_f >= 0) ? in[nx.in_f + h] : (IO)0;
+    }
+  }
   for (int it = it0; it < it1; ++it) {
     const MvItem item = P.items[it];
     IO cs_in[KH], cf_in[KH];
@@ -559,7 +560,16 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
       cs_in[k] = nxs[k];
       cf_in[k] = nxf[k];
     }
-    if (it + 1 < it1) fetch(it + 1);
+    if (it + 1 < it1)
+    {
+      const MvItem nx = P.items[it + 1];
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int h = tid + k * BLOCK;
+        nxs[k] = (h < nx.n_opp && nx.in_s >= 0) ? in[nx.in_s + h] : (IO)0;
+        nxf[k] = (h < nx.n_opp && nx.in_f >= 0) ? in[nx.in_f + h] : (IO)0;
+      }
+    }
     if (item.ctx < 0) {
 #pragma unroll
       for (int k = 0; k < KH; ++k) {
@@ -590,7 +600,22 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
         __syncthreads();
       }
     }
-    if (item.ctx != cur) load_ctx(item.ctx);
+    if (item.ctx != cur) {
+      const McCtx C = P.ctx[item.ctx];
+      n_own = C.n_own;
+      cph = C.cph;
+      n_chunk = C.n_chunk;
+  #pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int h = tid + k * BLOCK;
+        qr[k] = h < C.n_own ? P.q[C.q_off + h] : make_uint4(0xffffffffu, 0u, 0u, 0u);
+        lo[k] = h < C.n_own ? lam[C.lam_own_off + h] : (IO)0;
+        ps[k] = h < C.n_opp ? P.pos[C.pos_off + h] : make_uint2(0xffffffffu, 0xffffffffu);
+        lp[k] = h < C.n_opp ? lam[C.lam_opp_off + h] : (IO)0;
+      }
+      cm = P.meta[C.meta_off + tid];
+      cur = item.ctx;
+    }
     const bool hs = item.in_s >= 0, hf = item.in_f >= 0;
     // weighted opponent inputs into their slots
     const IO ks = (IO)item.ks, kf = (IO)item.kf;
