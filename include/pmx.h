@@ -217,11 +217,12 @@ int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk);
 int game_get_tuning(const Game* g, int32_t* kernel, int32_t* rows_per_chunk);
 
 /* Regret-update schedule: each player's treeplex is cut into pieces of at
- * most `rows` sequences (default and maximum 64) whose rows stay in LDS for
- * 64 hands at a time; pieces hanging below other pieces exchange root values
- * and parent weights through a stage buffer.  Results do not depend on the
- * cut (same arithmetic per infoset).  PMX_EINVAL if rows is outside [1, 64]
- * or below the largest action count of an infoset (the previous cut stays).
+ * most `rows` sequences (default and maximum 64) and 64 infosets whose rows
+ * stay in LDS for 64 hands at a time; pieces hanging below other pieces
+ * exchange root values and parent weights through a stage buffer.  Results
+ * do not depend on the cut (same arithmetic per infoset).  PMX_EINVAL if rows
+ * is outside [1, 64] or below the largest action count of an infoset (the
+ * previous cut stays).
  * Synchronizes the device; drops the captured solver graph. */
 int solver_set_task_rows(Game* g, int32_t rows);
 

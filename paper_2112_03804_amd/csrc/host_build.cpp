@@ -901,22 +901,32 @@ int build_rm_plan(HostGame& hg, int p, int cap, std::string& msg) {
     for (int i = 0; i < ni; ++i)
       if (inf[i].parent >= 0) kids[inf[i].parent].push_back(i);
     std::vector<char> alive(ni, 1);
-    std::vector<int> rows(ni, 0);
+    std::vector<int> rows(ni, 0), nis(ni, 0);   // alive subtree rows and infosets
     std::vector<std::vector<int32_t>> pending(S);   // stage rows waiting for the piece holding seq
     const int first_task = (int)P.tasks.size();
+    int64_t total_inf = 0;
     auto count_rows = [&]() {
       int64_t total = 0;
+      total_inf = 0;
       for (int i = ni - 1; i >= 0; --i) {
         if (!alive[i]) continue;
-        int r = inf[i].nact;
+        int r = inf[i].nact, c = 1;
         for (int a = 0; a < inf[i].nact; ++a)
           for (int j : kids[inf[i].first + a])
-            if (alive[j]) r += rows[j];
+            if (alive[j]) {
+              r += rows[j];
+              c += nis[j];
+            }
         rows[i] = r;
-        if (inf[i].parent < 0) total += r;
+        nis[i] = c;
+        if (inf[i].parent < 0) {
+          total += r;
+          total_inf += c;
+        }
       }
       return total;
     };
+    auto fits = [&](int i) { return rows[i] <= cap && nis[i] <= kTaskInfMax; };
     // emit one piece from a list of infosets (depth-first order)
     auto emit = [&](std::vector<int>& members) {
       std::sort(members.begin(), members.end());
@@ -1075,20 +1085,20 @@ int build_rm_plan(HostGame& hg, int p, int cap, std::string& msg) {
       P.tasks.push_back(t);
     };
     int64_t total = count_rows();
-    while (total > cap) {
+    while (total > cap || total_inf > kTaskInfMax) {
       // maximal subtrees that fit, in depth-first order
       std::vector<int> roots;
       for (int i = 0; i < ni; ++i) {
-        if (!alive[i] || rows[i] > cap) continue;
+        if (!alive[i] || !fits(i)) continue;
         const int par = inf[i].parent;
-        if (par < 0 || rows[owner[par]] > cap) roots.push_back(i);
+        if (par < 0 || !fits(owner[par])) roots.push_back(i);
       }
       if (roots.empty()) {
         msg = "treeplex cannot be cut into pieces of task_rows";
         return PMX_EINVAL;
       }
       std::vector<int> members, exts;
-      int r_sum = 0;
+      int r_sum = 0, n_sum = 0;
       auto collect = [&](int root, std::vector<int>& out) {
         std::vector<int> st{root};
         while (!st.empty()) {
@@ -1103,14 +1113,16 @@ int build_rm_plan(HostGame& hg, int p, int cap, std::string& msg) {
       for (int i : roots) {
         const int par = inf[i].parent;
         const bool new_ext = par >= 0 && std::find(exts.begin(), exts.end(), par) == exts.end();
-        if (!members.empty() && (r_sum + rows[i] > cap || (new_ext && (int)exts.size() >= kTaskExtMax))) {
+        if (!members.empty() && (r_sum + rows[i] > cap || n_sum + nis[i] > kTaskInfMax ||
+                                 (new_ext && (int)exts.size() >= kTaskExtMax))) {
           emit(members);
           members.clear();
           exts.clear();
-          r_sum = 0;
+          r_sum = n_sum = 0;
         }
         collect(i, members);
         r_sum += rows[i];
+        n_sum += nis[i];
         if (par >= 0 && std::find(exts.begin(), exts.end(), par) == exts.end()) exts.push_back(par);
       }
       if (!members.empty()) emit(members);

@@ -1125,8 +1125,13 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
   float* Rl = Al + P.max_rows * 64;         // [max_rows][64]
   const int64_t base = T.vec_base + h, stride = T.stride;
   const RmStep K = rm_step(DC, P.gamma, P.alpha, P.beta, *tdev);
-  // row ids, one per lane: computed for contiguous pieces, else from the table
+  // row ids, one per lane (a second for rows 64 + lane when pieces may
+  // exceed 64 rows): computed for contiguous pieces, else from the table
+  static_assert(kTaskRowsMax <= 128, "row ids are held in at most two registers");
   const int rowv = T.row0 >= 0 ? T.row0 + lane : (lane < SL ? P.rows[T.rows_off + lane] : 0);
+  int rowv2 = 0;
+  if (kTaskRowsMax > 64) rowv2 = T.row0 >= 0 ? T.row0 + 64 + lane : (64 + lane < SL ? P.rows[T.rows_off + 64 + lane] : 0);
+  auto row_id = [rowv, rowv2](int r) { return kTaskRowsMax <= 64 || r < 64 ? rl(rowv, r) : rl(rowv2, r - 64); };
   const int infv = lane < T.n_inf ? P.infs[T.inf_off + lane] : 0;
   const bool grouped = T.grp_off >= 0;
   const int grpv = grouped ? P.grp[T.grp_off + lane] : 0;
@@ -1143,7 +1148,7 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
 #pragma unroll
     for (int k = 0; k < RMR; ++k) {
       const int r = min(wv + RMW * k, SL - 1);
-      const int64_t idx = cbase + (int64_t)rl(rowv, r) * stride;
+      const int64_t idx = cbase + (int64_t)row_id(r) * stride;
       if (MODE != 2) a[k] = g[idx];
       b[k] = R[idx];
       if (MODE != 1) {
@@ -1259,7 +1264,7 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
     for (int k = 0; k < RMR; ++k) {
       const int r = wv + RMW * k;
       if (r < SL) {
-        const int64_t idx = base + (int64_t)rl(rowv, r) * stride;
+        const int64_t idx = base + (int64_t)row_id(r) * stride;
         if (MODE != 2) R[idx] = b[k];
         if (MODE != 1) {
           x[idx] = a[k];
@@ -2272,7 +2277,8 @@ int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk) {
 int solver_set_task_rows(Game* g, int32_t rows) {
   int rc = ensure_device(g);
   if (rc) return rc;
-  if (rows < 1 || rows > kTaskRowsMax) return fail(PMX_EINVAL, "rows must be in [1, 64]");
+  if (rows < 1 || rows > kTaskRowsMax)
+    return fail(PMX_EINVAL, "rows must be in [1, " + std::to_string(kTaskRowsMax) + "]");
   HIP_TRY(hipDeviceSynchronize());
   if (g->graph_exec) {
     (void)hipGraphExecDestroy(g->graph_exec);

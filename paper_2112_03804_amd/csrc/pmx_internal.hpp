@@ -213,13 +213,15 @@ struct TpPlan {                         // one player
 };
 
 // Regret-update tasks.  Each player's treeplex is cut into pieces of at most
-// `task_rows` sequences, so that a piece's rows for 64 hands stay resident in
-// LDS during the bottom-up and top-down passes.  A piece is a forest of whole
+// `task_rows` sequences and kTaskInfMax infosets, so that a piece's rows for
+// 64 hands stay resident in LDS during the bottom-up and top-down passes.
+// A piece is a forest of whole
 // infoset subtrees of what remains of the treeplex once the deeper pieces are
 // cut away.  A piece whose roots hang from a sequence of another piece (a
 // "deep" piece) passes its root values up through a stage buffer and reads
 // the parent sequence's realization weight back in its top-down pass.
 constexpr int kTaskRowsMax = 64;        // rows per piece (one per lane of a wavefront)
+constexpr int kTaskInfMax = 64;         // infosets per piece (one per lane)
 constexpr int kTaskExtMax = 15;         // distinct external parents per piece
 constexpr int kRmGroups = 4;            // subtree groups walked concurrently (wavefronts per block)
 constexpr int kRmGroupSlots = 4;        // distinct parent targets of one group's roots
