@@ -55,5 +55,29 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def kernel_resources(source: str) -> dict:
+    """Per-kernel register, scratch and occupancy figures of one HIP source
+    for gfx950, from the compiler's resource-usage remarks (device code
+    only, nothing is written).  Returns {mangled kernel name: {field: value}}."""
+    cmd = [hipcc()] + [f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC")] + [
+        "-I", INCLUDE, "-I", CSRC, "--cuda-device-only", "-c", os.path.join(CSRC, source),
+        "-o", os.devnull, "-Rpass-analysis=kernel-resource-usage"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stderr)
+        raise RuntimeError(f"hipcc failed on {source}")
+    out, cur = {}, None
+    for line in res.stderr.splitlines():
+        if "remark:" not in line:
+            continue
+        text = line.split("remark:", 1)[1].split("[-Rpass", 1)[0].strip()
+        if text.startswith("Function Name:"):
+            cur = out.setdefault(text.split(":", 1)[1].strip(), {})
+        elif cur is not None and ":" in text:
+            k, v = text.rsplit(":", 1)
+            cur[k.strip()] = v.strip()
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
