@@ -1075,10 +1075,21 @@ int build_rm_plan(HostGame& hg, int p, int cap, std::string& msg) {
         pending[e].push_back(P.n_slot);
         ++P.n_slot;
       }
+      // pulls: a header of per-wavefront counts, then each wavefront's pulls
+      // (rows r with r % kRmGroups == w, the rows that wavefront loads), in
+      // row order, so a row's pulls are consecutive
       t.pull_off = (int32_t)P.pulls.size();
+      std::vector<std::vector<int32_t>> by_wave(kRmGroups);
       for (int r = 0; r < (int)seqs.size(); ++r) {
-        for (int32_t slot : pending[seqs[r]]) P.pulls.push_back((int32_t)((uint32_t)r | ((uint32_t)slot << 8)));
+        for (int32_t slot : pending[seqs[r]])
+          by_wave[r % kRmGroups].push_back((int32_t)((uint32_t)r | ((uint32_t)slot << 8)));
         pending[seqs[r]].clear();
+      }
+      size_t n_pulls = 0;
+      for (const auto& v : by_wave) n_pulls += v.size();
+      if (n_pulls > 0) {
+        for (const auto& v : by_wave) P.pulls.push_back((int32_t)v.size());
+        for (const auto& v : by_wave) P.pulls.insert(P.pulls.end(), v.begin(), v.end());
       }
       t.n_pull = (int32_t)P.pulls.size() - t.pull_off;
       for (int i : members) alive[i] = 0;

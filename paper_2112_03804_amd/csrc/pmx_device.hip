@@ -1168,18 +1168,42 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
       }
     }
   }
-  if (MODE != 2) {
-    // values of deeper pieces into the rows they hang from (each wavefront
-    // adds into the rows it loaded)
-    for (int c0 = 0; c0 < T.n_pull; c0 += 64) {
-      const int pv = c0 + lane < T.n_pull ? P.pulls[T.pull_off + c0 + lane] : 0;
-      const int nn = min(64, T.n_pull - c0);
-      for (int j = 0; j < nn; ++j) {
-        const int v = rl(pv, j);
-        const int lr = v & 255;
-        if (lr % RMW == wv && act) Al[lr * 64 + lane] += stage[(int64_t)((uint32_t)v >> 8) * P.stage_stride + h];
+  if (MODE != 2 && T.n_pull > 0) {
+    // values of deeper pieces into the rows they hang from: each wavefront
+    // takes its own pulls (into the rows it loaded), eight stage loads in
+    // flight at a time; a row's pulls are consecutive, so they are summed in
+    // a register and the sum is added into the row once
+    const int32_t* pl = P.pulls + T.pull_off;
+    const int hdr = lane < RMW ? pl[lane] : 0;
+    int beg = RMW;
+    for (int w = 0; w < wv; ++w) beg += rl(hdr, w);
+    const int cnt = rl(hdr, wv);
+    const int64_t hs = act ? h : T.n_hands - 1;   // in-bounds hand for the loads
+    float acc = 0.f;
+    int row = -1;
+    for (int c0 = 0; c0 < cnt; c0 += 64) {
+      const int pv = c0 + lane < cnt ? pl[beg + c0 + lane] : 0;
+      const int nn = min(64, cnt - c0);
+      for (int j0 = 0; j0 < nn; j0 += 8) {
+        float sv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          sv[u] = stage[(int64_t)((uint32_t)rl(pv, min(j0 + u, nn - 1)) >> 8) * P.stage_stride + hs];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (j0 + u < nn) {
+            const int lr = rl(pv, j0 + u) & 255;
+            if (lr != row) {
+              if (row >= 0) Al[row * 64 + lane] += acc;
+              acc = 0.f;
+              row = lr;
+            }
+            acc += sv[u];
+          }
+        }
       }
     }
+    if (row >= 0) Al[row * 64 + lane] += acc;
   }
   if (MODE != 2 && wv == 0)
     for (int k = 0; k < T.n_ext; ++k) Xl[k * 64 + lane] = 0.f;

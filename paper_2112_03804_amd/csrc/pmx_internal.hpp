@@ -269,7 +269,9 @@ struct RmTask {
 // row, the external parent's row, or the sink) | LDS row holding the parent
 // sequence's realization weight in the top-down pass (bits 24-31: the
 // parent's row, the external parent's row, or the root-weight row).  LDS
-// rows as numbered by kRmRow*.  Pull: local row (bits 0-7) | stage row << 8.
+// rows as numbered by kRmRow*.  Pulls of a piece (when it has any): kRmGroups
+// counts, then wavefront w's pulls (local rows r with r % kRmGroups == w),
+// each local row (bits 0-7) | stage row << 8, in row order.
 // Group table: as described at kRmGBeg.  Infosets are listed group by group,
 // then the top part, each in depth-first order.
 struct RmPlan {                         // one player

@@ -132,9 +132,35 @@ extern "C" int check_rm_plan(const GameDesc* d, int n, int cap, char* msg, int m
           const int* G = t.grp_off >= 0 ? &P.grp[t.grp_off] : nullptr;
           const int tb = G ? G[kRmGTop] : 0, te = G ? G[kRmGTop + 1] : t.n_inf;
           if (mode != 2) {
-            for (int j = 0; j < t.n_pull; ++j) {
-              const int v = P.pulls[t.pull_off + j];
-              A[v & 255] += stage[(uint32_t)v >> 8];
+            if (t.n_pull > 0) {
+              // header of per-wavefront counts, then each wavefront's pulls
+              // (rows r % kRmGroups == w) in row order, summed per row
+              int beg = kRmGroups, total = kRmGroups;
+              for (int w = 0; w < kRmGroups; ++w) total += P.pulls[t.pull_off + w];
+              if (total != t.n_pull) {
+                snprintf(msg, msglen, "pull header counts %d entries for %d", total, t.n_pull);
+                throw 1;
+              }
+              for (int w = 0; w < kRmGroups; ++w) {
+                const int cnt = P.pulls[t.pull_off + w];
+                float acc = 0.f;
+                int row = -1;
+                for (int j = 0; j < cnt; ++j) {
+                  const int v = P.pulls[t.pull_off + beg + j], lr = v & 255;
+                  if (lr % kRmGroups != w || lr < row) {
+                    snprintf(msg, msglen, "pull into row %d listed for wavefront %d out of row order", lr, w);
+                    throw 1;
+                  }
+                  if (lr != row) {
+                    if (row >= 0) A[row] += acc;
+                    acc = 0.f;
+                    row = lr;
+                  }
+                  acc += stage[(uint32_t)v >> 8];
+                }
+                if (row >= 0) A[row] += acc;
+                beg += cnt;
+              }
             }
             if (G)
               for (int w = 0; w < kRmGroups; ++w)
