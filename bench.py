@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 # known size (profiles/matvec_pair_traffic_counters.md).  They describe the
 # kernel sources whose SHA-1 is recorded here and are reported as null for any
 # other version of those sources.
-TRAFFIC = {"sources_sha1": "9633787bf740977b972cd757b188089e3463dc9c", "river": 1640469, "batch": 449578205}
+TRAFFIC = {"sources_sha1": "820f3c1a298c4a9c833702bda8a0dffbcbaf69ba", "river": 1637385, "batch": 449569292}
 TRAFFIC_SOURCES = ("paper_2112_03804_amd/csrc/pmx_device.hip", "paper_2112_03804_amd/csrc/host_build.cpp")
 
 

@@ -1156,9 +1156,16 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
         d[k] = xs[idx];
       }
     }
-    if (MODE == 2 && wv == 0)
-      for (int k = 0; k < T.n_ext; ++k)
-        Xl[k * 64 + lane] = act ? x[base + (int64_t)rl(extv, k) * stride] : 0.f;
+    if (MODE == 2 && wv == 0 && T.n_ext > 0) {
+      // parent weights of the external parents, all loads in flight at once
+      float xe[kTaskExtMax];
+#pragma unroll
+      for (int k = 0; k < kTaskExtMax; ++k)
+        xe[k] = x[cbase + (int64_t)rl(extv, min(k, T.n_ext - 1)) * stride];
+#pragma unroll
+      for (int k = 0; k < kTaskExtMax; ++k)
+        if (k < T.n_ext) Xl[k * 64 + lane] = xe[k];
+    }
 #pragma unroll
     for (int k = 0; k < RMR; ++k) {
       const int r = wv + RMW * k;
