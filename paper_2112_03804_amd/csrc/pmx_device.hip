@@ -1,9 +1,12 @@
 // libpmx device code for gfx950 (CDNA4) and the C ABI.
 //
 // Kernels
-//   k_matvec      rows of A y (or A^T x): one workgroup per chunk of output
-//                 rows that share a board context.  Per item it applies the
-//                 hand factor of Prop. 1 without forming it:
+//   k_mvc         rows of A y (or A^T x), the default schedules (2, 3): one
+//                 workgroup of 256 or 512 threads per chunk of output rows,
+//                 one launch per hands-per-thread class, on the
+//                 chunk-aligned layout (every segment starts at a thread's
+//                 chunk of slots).  Per item it applies the hand factor of
+//                 Prop. 1 without forming it:
 //                   - fold / compatibility (eq. cf): total of the opponent's
 //                     weighted vector minus its per-card sums plus the
 //                     identical hand (inclusion-exclusion over shared cards);
@@ -12,14 +15,18 @@
 //                     by strength): exclusive prefix sums over the sorted
 //                     opponent hands and inside each card's sorted sub-list,
 //                     read at the tie-aware positions of each own hand.
-//                 All prefix sums come from one segmented scan over LDS with
-//                 FP64 accumulation (FP64 adds issue at the unpacked FP32
-//                 rate on CDNA4, so this costs less than compensated FP32).
+//                 All prefix sums come from one segmented scan over LDS:
+//                 FP32 sums inside a thread's chunk, FP64 carries across
+//                 chunks (FP64 adds issue at the unpacked FP32 rate on
+//                 CDNA4, so this costs less than compensated FP32).
+//   k_matvec,     the earlier sentinel-list schedules (0, 1), kept as
+//   k_matvec_w    autotuner candidates.
 //   k_rmp         regret matching+ (or discounted CFR) on pieces of a
 //                 treeplex of at most 64 sequences, one lane per hand (the
 //                 paper's GPU solver updates all hands in parallel), the
-//                 piece's rows resident in LDS during the walk.
-//   k_br_*        FP64 best responses (bottom-up max / min) and the gap.
+//                 piece's rows resident in LDS during the walk; four
+//                 wavefronts walk subtree groups of the piece concurrently.
+//   k_br          FP64 best responses (bottom-up max / min) for the gap.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
