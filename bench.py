@@ -30,9 +30,9 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 # HBM bytes per matvec-pair launch from two rocprofv3 --pmc runs (FETCH_SIZE,
 # then WRITE_SIZE), each scaled by what the counter reads for a plain copy of
 # known size (profiles/matvec_pair_traffic_counters.md).  They describe the
-# kernel sources whose SHA-1 is recorded here and are reported as null for any
-# other version of those sources.
-TRAFFIC = {"sources_sha1": "820f3c1a298c4a9c833702bda8a0dffbcbaf69ba", "river": 1637385, "batch": 449569292}
+# kernel sources whose code (comments and whitespace removed) has the SHA-1
+# recorded here and are reported as null for any other version of that code.
+TRAFFIC = {"sources_sha1": "8694d87c951741365a744d19f8521e01f67d4a96", "river": 1637385, "batch": 449569292}
 TRAFFIC_SOURCES = ("paper_2112_03804_amd/csrc/pmx_device.hip", "paper_2112_03804_amd/csrc/host_build.cpp")
 
 
@@ -41,12 +41,18 @@ def log(msg):
     print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 
 
-def sources_sha1():
+def sources_sha1(root=None):
+    """SHA-1 of the kernel sources' code: comments and whitespace removed, so
+    that an edit of the comments keeps the measured traffic."""
     import hashlib
+    import re
     h = hashlib.sha1()
     for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(root or ROOT, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 
