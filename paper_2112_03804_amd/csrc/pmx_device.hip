@@ -1094,16 +1094,18 @@ __device__ inline void rmp_down_any(float* __restrict__ Al, const float* __restr
     Al[(f + a) * 64 + lane] = xp * (((pos ? fmaxf(Rl[(f + a) * 64 + lane], 0.f) : 1.f) * sc) * rc);
 }
 
-// Two widths keep the common small infosets cheap; one call site per
-// direction in the kernel keeps its code small.
+// Three widths (2: fold / call, 4, 8) keep the common small infosets cheap;
+// one call site per direction in the kernel keeps its code small.
 template <bool DC>
 __device__ inline void rmp_up(float* Al, float* Rl, float* pp, int f, int n, int lane, const RmStep& K) {
-  if (n <= 4) rmp_up_w<4, DC>(Al, Rl, pp, f, n, lane, K);
+  if (n <= 2) rmp_up_w<2, DC>(Al, Rl, pp, f, n, lane, K);
+  else if (n <= 4) rmp_up_w<4, DC>(Al, Rl, pp, f, n, lane, K);
   else if (n <= MAXA) rmp_up_w<MAXA, DC>(Al, Rl, pp, f, n, lane, K);
   else rmp_up_any<DC>(Al, Rl, pp, f, n, lane, K);
 }
 __device__ inline void rmp_down(float* Al, const float* Rl, const float* xpp, int f, int n, int lane) {
-  if (n <= 4) rmp_down_w<4>(Al, Rl, xpp, f, n, lane);
+  if (n <= 2) rmp_down_w<2>(Al, Rl, xpp, f, n, lane);
+  else if (n <= 4) rmp_down_w<4>(Al, Rl, xpp, f, n, lane);
   else if (n <= MAXA) rmp_down_w<MAXA>(Al, Rl, xpp, f, n, lane);
   else rmp_down_any(Al, Rl, xpp, f, n, lane);
 }
