@@ -226,6 +226,16 @@ int game_get_tuning(const Game* g, int32_t* kernel, int32_t* rows_per_chunk);
  * Synchronizes the device; drops the captured solver graph. */
 int solver_set_task_rows(Game* g, int32_t rows);
 
+/* Regret-update kernel choice: a launch of at most `max_records` block
+ * records (64 hands of one piece each) runs with four lanes per hand and 16
+ * hands per workgroup (its walk is latency-bound: few workgroups), a larger
+ * one with one lane per hand (it is bound by HBM bytes).  Default 256; 0
+ * selects the one-lane form everywhere, INT32_MAX the four-lane form.  Both
+ * compute the same update (sums over an infoset's actions in another
+ * order).  PMX_EINVAL if max_records < 0.  Synchronizes the device; drops the
+ * captured solver graph. */
+int solver_set_rm_quad(Game* g, int32_t max_records);
+
 /* ---- gradients (Section 2 app. 3; Prop. 1; eq. cf; Technique B) ----------- */
 
 /* out = A y (Player 1's gradient).  y: player 1's vectors (all instances),

@@ -1315,6 +1315,274 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// Regret update with four lanes per hand (k_rmq), for launches of few
+// workgroups, where the walk's latency is the cost: a workgroup holds 16
+// hands, lane 4 h + q of a wavefront takes action q (and q + 4, ...) of each
+// infoset for hand h, and the sums over an infoset's actions are two DPP
+// steps across the quad.  A walk step so runs about a quarter of the
+// per-lane instructions of k_rmp.  Same pieces, tables and LDS row numbering
+// as k_rmp, with rows of 16 hands; a block record of 64 hands is taken by
+// four workgroups.
+// ---------------------------------------------------------------------------
+constexpr int RQH = 16;   // hands per workgroup
+
+__device__ inline float quad_sum(float v) {
+  v += __int_as_float(dpp_i<0xB1, 0xf>(__float_as_int(v)));   // quad_perm [1,0,3,2]
+  v += __int_as_float(dpp_i<0x4E, 0xf>(__float_as_int(v)));   // quad_perm [2,3,0,1]
+  return v;
+}
+
+// Bottom-up step for one hand's quad: actions q, q + 4, ... of the infoset.
+template <bool DC>
+__device__ inline void rmq_up(float* __restrict__ Al, float* __restrict__ Rl, float* __restrict__ rsm, int f,
+                              int n, int up, int q, int hl, const RmStep& K) {
+  const int na = (n + 3) >> 2;   // actions per lane
+  float rs = 0.f, dot = 0.f, gs = 0.f;
+  float rr[2], gg[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int a = q + 4 * c;
+    const int o = (f + min(a, n - 1)) * RQH + hl;
+    rr[c] = Rl[o];
+    gg[c] = Al[o];
+    const bool on = c < na && a < n;
+    const float r = on ? fmaxf(rr[c], 0.f) : 0.f;
+    rs += r;
+    dot += r * gg[c];
+    gs += on ? gg[c] : 0.f;
+  }
+  for (int c = 2; c < na; ++c) {   // infosets of more than 8 actions
+    const int a = q + 4 * c;
+    const int o = (f + min(a, n - 1)) * RQH + hl;
+    const bool on = a < n;
+    const float r = on ? fmaxf(Rl[o], 0.f) : 0.f, gv = Al[o];
+    rs += r;
+    dot += r * gv;
+    gs += on ? gv : 0.f;
+  }
+  rs = quad_sum(rs);
+  dot = quad_sum(dot);
+  gs = quad_sum(gs);
+  const bool pos = rs > 0.f;
+  float sc;
+  const float rc = rm_rcp(pos ? rs : (float)n, sc);
+  const float V = ((pos ? dot : gs) * sc) * rc;
+  // positions past the last action rewrite the last action's row with the
+  // value its own lane writes
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+    if (c < na) Rl[(f + min(q + 4 * c, n - 1)) * RQH + hl] = rm_new<DC>(rr[c], gg[c] - V, K);
+  for (int c = 2; c < na; ++c) {
+    const int o = (f + min(q + 4 * c, n - 1)) * RQH + hl;
+    Rl[o] = rm_new<DC>(Rl[o], Al[o] - V, K);
+  }
+  if (q == 0) rsm[up * RQH + hl] += V;
+}
+
+// Top-down step for one hand's quad.
+__device__ inline void rmq_down(float* __restrict__ Al, const float* __restrict__ Rl, const float* __restrict__ rsm,
+                                int f, int n, int dn, int q, int hl) {
+  const int na = (n + 3) >> 2;
+  float rs = 0.f;
+  for (int c = 0; c < na; ++c) {
+    const int a = q + 4 * c;
+    rs += a < n ? fmaxf(Rl[(f + min(a, n - 1)) * RQH + hl], 0.f) : 0.f;
+  }
+  rs = quad_sum(rs);
+  const float xp = rsm[dn * RQH + hl];
+  const bool pos = rs > 0.f;
+  float sc;
+  const float rc = rm_rcp(pos ? rs : (float)n, sc);
+  for (int c = 0; c < na; ++c) {
+    const int o = (f + min(q + 4 * c, n - 1)) * RQH + hl;
+    Al[o] = xp * (((pos ? fmaxf(Rl[o], 0.f) : 1.f) * sc) * rc);
+  }
+}
+
+template <int MODE, bool DC>
+__global__ __launch_bounds__(64 * RMW) void k_rmq(RmParams P, float* __restrict__ g, float* __restrict__ R,
+                                                  float* __restrict__ x, double* __restrict__ xs,
+                                                  float* __restrict__ stage, const double* __restrict__ tdev) {
+  extern __shared__ float rsm[];
+  const RmTask T = P.blocks[blockIdx.x >> 2].t;
+  const int h0 = P.blocks[blockIdx.x >> 2].h0 + RQH * (int)(blockIdx.x & 3);
+  if (h0 >= T.n_hands) return;                 // whole block
+  if (P.active && !P.active[T.inst]) return;   // whole block: T is uniform
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int q = lane & 3, hl = lane >> 2;
+  const int h = h0 + hl;
+  const bool act = h < T.n_hands;
+  const int SL = T.n_rows;
+  float* Xw = rsm + kRmRowSlot * RQH;
+  float* Xl = rsm + kRmRowExt * RQH;
+  float* Al = rsm + kRmRowLocal * RQH;
+  float* Rl = Al + P.max_rows * RQH;
+  const int64_t hc = act ? h : T.n_hands - 1;   // in-bounds hand for loads
+  const int64_t stride = T.stride;
+  const RmStep K = rm_step(DC, P.gamma, P.alpha, P.beta, *tdev);
+  const int rowv = T.row0 >= 0 ? T.row0 + lane : (lane < SL ? P.rows[T.rows_off + lane] : 0);
+  const int infv = lane < T.n_inf ? P.infs[T.inf_off + lane] : 0;
+  const bool grouped = T.grp_off >= 0;
+  const int grpv = grouped ? P.grp[T.grp_off + lane] : 0;
+  const int extv = (MODE != 0 && lane < T.n_ext)
+                       ? (MODE == 1 ? P.ext_slot[T.ext_off + lane] : P.ext_seq[T.ext_off + lane]) : 0;
+  // rows 4 (wv + RMW k) + q for k < 4, 16 hands each: lane (hl, q) takes
+  // row 4 (wv + RMW k) + q of hand hl
+  constexpr int RQK = kTaskRowsMax / (4 * RMW);
+  float c[RQK];
+  double d[RQK];
+  int rid[RQK];
+  {
+    float a[RQK], b[RQK];
+#pragma unroll
+    for (int k = 0; k < RQK; ++k) {
+      const int r = min(4 * (wv + RMW * k) + q, SL - 1);
+      rid[k] = T.row0 >= 0 ? T.row0 + r : __shfl(rowv, r, 64);
+      const int64_t idx = T.vec_base + hc + (int64_t)rid[k] * stride;
+      if (MODE != 2) a[k] = g[idx];
+      b[k] = R[idx];
+      if (MODE != 1) {
+        c[k] = x[idx];
+        d[k] = xs[idx];
+      }
+    }
+    if (MODE == 2 && wv == 0 && T.n_ext > 0) {
+      float xe[kTaskExtMax];
+#pragma unroll
+      for (int k = 0; k < kTaskExtMax; ++k)
+        xe[k] = x[T.vec_base + hc + (int64_t)rl(extv, min(k, T.n_ext - 1)) * stride];
+#pragma unroll
+      for (int k = 0; k < kTaskExtMax; ++k)
+        if (k < T.n_ext && q == 0) Xl[k * RQH + hl] = xe[k];
+    }
+#pragma unroll
+    for (int k = 0; k < RQK; ++k) {
+      const int r = 4 * (wv + RMW * k) + q;
+      if (r < SL) {
+        if (MODE != 2) Al[r * RQH + hl] = a[k];
+        Rl[r * RQH + hl] = b[k];
+      }
+    }
+  }
+  if (MODE != 2 && wv == 0 && q == 0)
+    for (int k = 0; k < T.n_ext; ++k) Xl[k * RQH + hl] = 0.f;
+  const int gb = grouped ? rl(grpv, kRmGBeg + wv) : 0, ge = grouped ? rl(grpv, kRmGEnd + wv) : 0;
+  const int tb = grouped ? rl(grpv, kRmGTop) : 0, te = grouped ? rl(grpv, kRmGTop + 1) : T.n_inf;
+  if (MODE != 2 && grouped && q == 0)
+    for (int j = 0; j < rl(grpv, kRmGCnt + wv); ++j) Xw[(wv * kRmGroupSlots + j) * RQH + hl] = 0.f;
+  __syncthreads();
+  if (MODE != 2 && T.n_pull > 0) {
+    // values of deeper pieces (after the barrier: a wavefront's pulls target
+    // rows other wavefronts loaded); lanes q == 0 sum each row's
+    // consecutive pulls in a register, eight loads in flight
+    const int32_t* pl = P.pulls + T.pull_off;
+    const int hdr = lane < RMW ? pl[lane] : 0;
+    int beg = RMW;
+    for (int w = 0; w < wv; ++w) beg += rl(hdr, w);
+    const int cnt = rl(hdr, wv);
+    float acc = 0.f;
+    int row = -1;
+    for (int c0 = 0; c0 < cnt; c0 += 64) {
+      const int pv = c0 + lane < cnt ? pl[beg + c0 + lane] : 0;
+      const int nn = min(64, cnt - c0);
+      for (int j0 = 0; j0 < nn; j0 += 8) {
+        float sv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          sv[u] = stage[(int64_t)((uint32_t)rl(pv, min(j0 + u, nn - 1)) >> 8) * P.stage_stride + hc];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (j0 + u < nn) {
+            const int lr = rl(pv, j0 + u) & 255;
+            if (lr != row) {
+              if (row >= 0 && q == 0) Al[row * RQH + hl] += acc;
+              acc = 0.f;
+              row = lr;
+            }
+            acc += sv[u];
+          }
+        }
+      }
+    }
+    if (row >= 0 && q == 0) Al[row * RQH + hl] += acc;
+    __syncthreads();
+  }
+  if (MODE != 2) {
+#pragma unroll 1
+    for (int ps = grouped ? 0 : 1; ps < 2; ++ps) {
+      if (ps == 1 && grouped) {
+        __syncthreads();
+        if (wv == 0) {
+          int mge[kRmMergeMax / 2];
+#pragma unroll
+          for (int e = 0; e < kRmMergeMax / 2; ++e) mge[e] = rl(grpv, kRmGMrg + e);
+          float sv[kRmMergeMax], tv[kRmMergeMax];
+#pragma unroll
+          for (int e = 0; e < kRmMergeMax; ++e) {
+            const int cc = (mge[e / 2] >> (16 * (e & 1))) & 0xffff;
+            sv[e] = rsm[(cc & 255) * RQH + hl];
+            tv[e] = rsm[(cc >> 8) * RQH + hl];
+          }
+          float run = 0.f;
+          int prev = -1;
+#pragma unroll
+          for (int e = 0; e < kRmMergeMax; ++e) {
+            const int tg = ((mge[e / 2] >> (16 * (e & 1))) >> 8) & 255;
+            run = (tg == prev ? run : 0.f) + sv[e];
+            if (q == 0) rsm[tg * RQH + hl] = tv[e] + run;
+            prev = tg;
+          }
+        }
+      }
+      if (ps == 1 && wv != 0) break;
+      const int i0 = ps ? tb : gb, i1 = ps ? te : ge;
+      for (int i = i1 - 1; i >= i0; --i) {
+        const int v = rl(infv, i);
+        rmq_up<DC>(Al, Rl, rsm, v & 255, (v >> 8) & 255, (v >> 16) & 255, q, hl, K);
+      }
+    }
+    if (MODE == 1 && wv == 0 && act && q == 0)
+      for (int k = 0; k < T.n_ext; ++k) stage[(int64_t)rl(extv, k) * P.stage_stride + h] = Xl[k * RQH + hl];
+  }
+  if (MODE != 1) {
+#pragma unroll 1
+    for (int ps = 0; ps < (grouped ? 2 : 1); ++ps) {
+      if (ps == 1) __syncthreads();
+      else if (wv != 0) continue;
+      else if (q == 0) rsm[kRmRowOne * RQH + hl] = 1.f;
+      const int i0 = ps ? gb : tb, i1 = ps ? ge : te;
+      for (int i = i0; i < i1; ++i) {
+        const int v = rl(infv, i);
+        rmq_down(Al, Rl, rsm, v & 255, (v >> 8) & 255, (uint32_t)v >> 24, q, hl);
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+    float a[RQK], b[RQK];
+#pragma unroll
+    for (int k = 0; k < RQK; ++k) {
+      const int r = min(4 * (wv + RMW * k) + q, SL - 1);
+      if (MODE != 2) b[k] = Rl[r * RQH + hl];
+      if (MODE != 1) a[k] = Al[r * RQH + hl];
+    }
+#pragma unroll
+    for (int k = 0; k < RQK; ++k) {
+      const int r = 4 * (wv + RMW * k) + q;
+      if (r < SL) {
+        const int64_t idx = T.vec_base + h + (int64_t)rid[k] * stride;
+        if (MODE != 2) R[idx] = b[k];
+        if (MODE != 1) {
+          x[idx] = a[k];
+          xs[idx] = d[k] + K.w * (double)c[k];
+        }
+      }
+    }
+  }
+}
+
 // Best response: per hand, bottom-up max (Player 1) or min (Player 2) of g
 // plus the values below; sums of root values go to hv[hand_base + h].
 template <int MODE, bool MAXIMIZE>
@@ -2088,12 +2356,25 @@ static int rm_update(Game* g, int p, hipStream_t s) {
     const int nb = E.blk_off[d + 1] - E.blk_off[d];
     if (nb == 0) return;
     const RmParams P = rm_params(g, p, d);
-    const size_t lds = sizeof(float) * 64 * (size_t)(kRmRowLocal + 2 * P.max_rows);
+    // few workgroups: the walk's latency is the cost, four lanes per hand
+    // (k_rmq); many: the bytes are, one lane per hand (k_rmp)
+    const bool quad = nb <= g->hg.rm_quad_max;
+    const size_t lds = sizeof(float) * (quad ? RQH : 64) * (size_t)(kRmRowLocal + 2 * P.max_rows);
     auto go = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(nb), dim3(64 * RMW), lds, s, P, gr, g->R[p].p, g->x[p].p, g->xs[p].p,
-                         E.stage.p, td);
+      hipLaunchKernelGGL(kern, dim3(quad ? 4 * nb : nb), dim3(64 * RMW), lds, s, P, gr, g->R[p].p, g->x[p].p,
+                         g->xs[p].p, E.stage.p, td);
     };
-    if (P.dcfr) {
+    if (quad) {
+      if (P.dcfr) {
+        if (mode == 0) go(k_rmq<0, true>);
+        else if (mode == 1) go(k_rmq<1, true>);
+        else go(k_rmq<2, true>);
+      } else {
+        if (mode == 0) go(k_rmq<0, false>);
+        else if (mode == 1) go(k_rmq<1, false>);
+        else go(k_rmq<2, false>);
+      }
+    } else if (P.dcfr) {
       if (mode == 0) go(k_rmp<0, true>);
       else if (mode == 1) go(k_rmp<1, true>);
       else go(k_rmp<2, true>);
@@ -2311,6 +2592,23 @@ int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk) {
     classify_chunks(g->hg.dir[d]);
     if ((rc = upload_dir(g, d))) return rc;
   }
+  return PMX_OK;
+}
+
+int solver_set_rm_quad(Game* g, int32_t max_records) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (max_records < 0) return fail(PMX_EINVAL, "max_records must be >= 0");
+  HIP_TRY(hipDeviceSynchronize());
+  if (g->graph_exec) {
+    (void)hipGraphExecDestroy(g->graph_exec);
+    g->graph_exec = nullptr;
+  }
+  if (g->graph) {
+    (void)hipGraphDestroy(g->graph);
+    g->graph = nullptr;
+  }
+  g->hg.rm_quad_max = max_records;
   return PMX_OK;
 }
 

@@ -293,6 +293,7 @@ struct HostGame {
   TpPlan tp[2];
   RmPlan rm[2];
   int task_rows = kTaskRowsMax;
+  int rm_quad_max = 256;                // regret launches of at most this many block records use k_rmq
   int max_stride = 0;
 };
 

@@ -78,7 +78,7 @@ EXPORTS = [
     "set_initial_strategy", "pmx_last_error", "game_tune", "game_get_tuning",
     "warm_num_rows", "warm_features", "warm_targets", "warm_apply",
     "mlp_gemm_bf16", "mlp_softmax_xent", "mlp_colsum", "mlp_adam", "mlp_gather_bf16",
-    "mlp_gather_f32", "mlp_cast_bf16", "solver_set_active", "solver_set_params", "solver_set_task_rows",
+    "mlp_gather_f32", "mlp_cast_bf16", "solver_set_active", "solver_set_params", "solver_set_task_rows", "solver_set_rm_quad",
 ]
 
 
@@ -118,6 +118,7 @@ def lib():
     L.game_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     L.game_get_tuning.argtypes = [vp, _c_i32p, _c_i32p]
     L.solver_set_task_rows.argtypes = [vp, ctypes.c_int32]
+    L.solver_set_rm_quad.argtypes = [vp, ctypes.c_int32]
     i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     L.warm_num_rows.argtypes = [vp, i32, ctypes.POINTER(i64)]
     L.warm_features.argtypes = [vp, i32, vp, vp]
@@ -282,6 +283,11 @@ class Game:
 
     def game_tune(self, kernel: int, rows_per_chunk: int):
         _check(lib().game_tune(self._h, int(kernel), int(rows_per_chunk)))
+
+    def solver_set_rm_quad(self, max_records: int):
+        """Regret launches of at most max_records block records use the
+        four-lanes-per-hand kernel (0: never)."""
+        _check(lib().solver_set_rm_quad(self._h, int(max_records)))
 
     def solver_set_task_rows(self, rows: int):
         """Cut each treeplex into regret-update pieces of at most `rows` sequences."""

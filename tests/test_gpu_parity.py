@@ -341,23 +341,29 @@ def test_single_solver_step_from_given_state(name, fn):
     g.close()
 
 
+RM_KERNELS = {"lane": 0, "quad": 2 ** 31 - 1}   # solver_set_rm_quad: one lane / four lanes per hand
+
+
 BIG_TREE = ("river_big_tree", lambda: I.river_config(seed=21, n_keep=(150, 170), bet_fracs=(0.33, 0.75, 1.5),
                                                       max_raises=4, stack=400.0))
 
 
+@pytest.mark.parametrize("rmk", sorted(RM_KERNELS))
 @pytest.mark.parametrize("kind", ["rm+", "dcfr"])
 @pytest.mark.parametrize("rows", [8, 13, 64])
 @pytest.mark.parametrize("name,fn", [SMALL[6], ("river", lambda: I.config(1)), BIG_TREE])
-def test_single_step_any_piece_size(name, fn, rows, kind):
+def test_single_step_any_piece_size(name, fn, rows, kind, rmk):
     """One solver step from a given state is the same whatever the cut of the
     treeplex into regret-update pieces (small cuts give several levels of
-    pieces exchanging values through the stage buffer)."""
+    pieces exchanging values through the stage buffer), with one lane or four
+    lanes per hand."""
     pmx = _need_gpu()
     d = fn()
-    _say("piece-size step parity", name, rows, kind)
+    _say("piece-size step parity", name, rows, kind, rmk)
     o = payoff.Game(d)
     g = pmx.Game(d)
     g.solver_set_task_rows(rows)
+    g.solver_set_rm_quad(RM_KERNELS[rmk])
     g.solver_set_params(kind)
     rng = np.random.default_rng(21)
     ref = solver.RMPlus(o, kind=kind)
@@ -401,9 +407,10 @@ def test_single_step_any_piece_size(name, fn, rows, kind):
     g.close()
 
 
+@pytest.mark.parametrize("rmk", sorted(RM_KERNELS))
 @pytest.mark.parametrize("kind", ["rm+", "dcfr"])
 @pytest.mark.parametrize("tiny", [1e-30, 1e-42])
-def test_single_step_tiny_regret_sums(tiny, kind):
+def test_single_step_tiny_regret_sums(tiny, kind, rmk):
     """Regret sums far below 1 (1e-30, and subnormal FP32 at 1e-42) give
     finite results: the walk's reciprocal is taken of a rescaled sum and no
     step passes through 1 / sum, which overflows FP32 for a subnormal sum (a
@@ -413,10 +420,11 @@ def test_single_step_tiny_regret_sums(tiny, kind):
     finiteness and a plan that is the realization of the device's regrets."""
     pmx = _need_gpu()
     d = I.config(1)
-    _say("tiny regret sums", tiny, kind)
+    _say("tiny regret sums", tiny, kind, rmk)
     o = payoff.Game(d)
     g = pmx.Game(d)
     g.solver_set_params(kind)
+    g.solver_set_rm_quad(RM_KERNELS[rmk])
     rng = np.random.default_rng(5)
     ref = solver.RMPlus(o, kind=kind)
     t0, w0 = 3, 6.0
@@ -589,12 +597,14 @@ def test_matvec_schedules_agree(kernel, rows):
     g.close()
 
 
-def test_retired_instances_stay_frozen():
+@pytest.mark.parametrize("rmk", sorted(RM_KERNELS))
+def test_retired_instances_stay_frozen(rmk):
     pmx = _need_gpu()
     descs = [I.river_config(seed=900 + i, n_keep=(120, 140), bet_fracs=(0.5, 1.0), max_raises=2,
                             pot=40.0, stack=120.0) for i in range(3)]
-    _say("retirement")
+    _say("retirement", rmk)
     g = pmx.Game(descs)
+    g.solver_set_rm_quad(RM_KERNELS[rmk])
     g.solver_step(40)
     before = [g.unpack(p, g.solver_get_state(p)["avg_sum"]) for p in range(2)]
     gap0 = g.saddle_gap()[0]
