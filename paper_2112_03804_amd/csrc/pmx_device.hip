@@ -1110,6 +1110,75 @@ __device__ inline void rmp_down(float* Al, const float* Rl, const float* xpp, in
   else rmp_down_any(Al, Rl, xpp, f, n, lane);
 }
 
+// Values of deeper pieces into the rows they hang from (pulls; the host lists
+// them per wavefront, a row's pulls consecutive, behind a header of counts):
+// each wavefront takes its own, eight stage loads in flight, and adds each
+// row's sum once.  Rows of RW hands; `col` is the lane's hand column, `hs` an
+// in-bounds hand for the loads, `wr` whether the lane writes.
+template <int RW>
+__device__ inline void rm_pulls(const RmParams& P, const RmTask& T, float* __restrict__ Al,
+                                const float* __restrict__ stage, int lane, int wv, int col, int64_t hs, bool wr) {
+  const int32_t* pl = P.pulls + T.pull_off;
+  const int hdr = lane < RMW ? pl[lane] : 0;
+  int beg = RMW;
+  for (int w = 0; w < wv; ++w) beg += rl(hdr, w);
+  const int cnt = rl(hdr, wv);
+  float acc = 0.f;
+  int row = -1;
+  for (int c0 = 0; c0 < cnt; c0 += 64) {
+    const int pv = c0 + lane < cnt ? pl[beg + c0 + lane] : 0;
+    const int nn = min(64, cnt - c0);
+    for (int j0 = 0; j0 < nn; j0 += 8) {
+      float sv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        sv[u] = stage[(int64_t)((uint32_t)rl(pv, min(j0 + u, nn - 1)) >> 8) * P.stage_stride + hs];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (j0 + u < nn) {
+          const int lr = rl(pv, j0 + u) & 255;
+          if (lr != row) {
+            if (row >= 0 && wr) Al[row * RW + col] += acc;
+            acc = 0.f;
+            row = lr;
+          }
+          acc += sv[u];
+        }
+      }
+    }
+  }
+  if (row >= 0 && wr) Al[row * RW + col] += acc;
+}
+
+// Group-root values into their targets (wavefront 0, after the groups): every
+// slot value and target value is read before the first wait; a run of
+// entries with one target (entries are sorted by target) sums its slots in
+// registers, and every entry writes the target's value plus the run so far,
+// so the run's last write, which lands last, leaves the whole sum: no branch
+// per entry.  Rows of RW hands, as in rm_pulls.
+template <int RW>
+__device__ inline void rm_merge(float* __restrict__ rsm, int grpv, int col, bool wr) {
+  int mge[kRmMergeMax / 2];   // two entries per int, into SGPRs
+#pragma unroll
+  for (int e = 0; e < kRmMergeMax / 2; ++e) mge[e] = rl(grpv, kRmGMrg + e);
+  float sv[kRmMergeMax], tv[kRmMergeMax];
+#pragma unroll
+  for (int e = 0; e < kRmMergeMax; ++e) {
+    const int c = (mge[e / 2] >> (16 * (e & 1))) & 0xffff;
+    sv[e] = rsm[(c & 255) * RW + col];
+    tv[e] = rsm[(c >> 8) * RW + col];
+  }
+  float run = 0.f;
+  int prev = -1;
+#pragma unroll
+  for (int e = 0; e < kRmMergeMax; ++e) {
+    const int tg = ((mge[e / 2] >> (16 * (e & 1))) >> 8) & 255;
+    run = (tg == prev ? run : 0.f) + sv[e];
+    if (wr) rsm[tg * RW + col] = tv[e] + run;
+    prev = tg;
+  }
+}
+
 // MODE 0: bottom-up and top-down of a piece with no external parent (pulls
 // from deeper pieces first); 1: bottom-up of a deep piece (root values to the
 // stage buffer); 2: top-down of a deep piece (parent weights from x).  The
@@ -1184,43 +1253,8 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
       }
     }
   }
-  if (MODE != 2 && T.n_pull > 0) {
-    // values of deeper pieces into the rows they hang from: each wavefront
-    // takes its own pulls (into the rows it loaded), eight stage loads in
-    // flight at a time; a row's pulls are consecutive, so they are summed in
-    // a register and the sum is added into the row once
-    const int32_t* pl = P.pulls + T.pull_off;
-    const int hdr = lane < RMW ? pl[lane] : 0;
-    int beg = RMW;
-    for (int w = 0; w < wv; ++w) beg += rl(hdr, w);
-    const int cnt = rl(hdr, wv);
-    const int64_t hs = act ? h : T.n_hands - 1;   // in-bounds hand for the loads
-    float acc = 0.f;
-    int row = -1;
-    for (int c0 = 0; c0 < cnt; c0 += 64) {
-      const int pv = c0 + lane < cnt ? pl[beg + c0 + lane] : 0;
-      const int nn = min(64, cnt - c0);
-      for (int j0 = 0; j0 < nn; j0 += 8) {
-        float sv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          sv[u] = stage[(int64_t)((uint32_t)rl(pv, min(j0 + u, nn - 1)) >> 8) * P.stage_stride + hs];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (j0 + u < nn) {
-            const int lr = rl(pv, j0 + u) & 255;
-            if (lr != row) {
-              if (row >= 0) Al[row * 64 + lane] += acc;
-              acc = 0.f;
-              row = lr;
-            }
-            acc += sv[u];
-          }
-        }
-      }
-    }
-    if (row >= 0) Al[row * 64 + lane] += acc;
-  }
+  if (MODE != 2 && T.n_pull > 0)   // a wavefront's pulls go into rows it loaded: no barrier first
+    rm_pulls<64>(P, T, Al, stage, lane, wv, lane, act ? h : T.n_hands - 1, true);
   if (MODE != 2 && wv == 0)
     for (int k = 0; k < T.n_ext; ++k) Xl[k * 64 + lane] = 0.f;
   // infoset ranges: wavefront wv's group, and the top part (all infosets when
@@ -1238,32 +1272,7 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
     for (int ps = grouped ? 0 : 1; ps < 2; ++ps) {
       if (ps == 1 && grouped) {
         __syncthreads();
-        if (wv == 0) {
-          // every slot value and target value is read before the first
-          // wait; a run of entries with one target (entries are sorted by
-          // target) sums its slots in registers, and every entry writes the
-          // target's value plus the run so far, so the run's last write,
-          // which lands last, leaves the whole sum: no branch per entry
-          int mge[kRmMergeMax / 2];   // two entries per int, into SGPRs
-#pragma unroll
-          for (int e = 0; e < kRmMergeMax / 2; ++e) mge[e] = rl(grpv, kRmGMrg + e);
-          float sv[kRmMergeMax], tv[kRmMergeMax];
-#pragma unroll
-          for (int e = 0; e < kRmMergeMax; ++e) {
-            const int c = (mge[e / 2] >> (16 * (e & 1))) & 0xffff;
-            sv[e] = rsm[(c & 255) * 64 + lane];
-            tv[e] = rsm[(c >> 8) * 64 + lane];
-          }
-          float run = 0.f;
-          int prev = -1;
-#pragma unroll
-          for (int e = 0; e < kRmMergeMax; ++e) {
-            const int tg = ((mge[e / 2] >> (16 * (e & 1))) >> 8) & 255;
-            run = (tg == prev ? run : 0.f) + sv[e];
-            rsm[tg * 64 + lane] = tv[e] + run;
-            prev = tg;
-          }
-        }
+        if (wv == 0) rm_merge<64>(rsm, grpv, lane, true);
       }
       if (ps == 1 && wv != 0) break;
       const int i0 = ps ? tb : gb, i1 = ps ? te : ge;
@@ -1474,39 +1483,9 @@ __global__ __launch_bounds__(64 * RMW) void k_rmq(RmParams P, float* __restrict_
     for (int j = 0; j < rl(grpv, kRmGCnt + wv); ++j) Xw[(wv * kRmGroupSlots + j) * RQH + hl] = 0.f;
   __syncthreads();
   if (MODE != 2 && T.n_pull > 0) {
-    // values of deeper pieces (after the barrier: a wavefront's pulls target
-    // rows other wavefronts loaded); lanes q == 0 sum each row's
-    // consecutive pulls in a register, eight loads in flight
-    const int32_t* pl = P.pulls + T.pull_off;
-    const int hdr = lane < RMW ? pl[lane] : 0;
-    int beg = RMW;
-    for (int w = 0; w < wv; ++w) beg += rl(hdr, w);
-    const int cnt = rl(hdr, wv);
-    float acc = 0.f;
-    int row = -1;
-    for (int c0 = 0; c0 < cnt; c0 += 64) {
-      const int pv = c0 + lane < cnt ? pl[beg + c0 + lane] : 0;
-      const int nn = min(64, cnt - c0);
-      for (int j0 = 0; j0 < nn; j0 += 8) {
-        float sv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          sv[u] = stage[(int64_t)((uint32_t)rl(pv, min(j0 + u, nn - 1)) >> 8) * P.stage_stride + hc];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (j0 + u < nn) {
-            const int lr = rl(pv, j0 + u) & 255;
-            if (lr != row) {
-              if (row >= 0 && q == 0) Al[row * RQH + hl] += acc;
-              acc = 0.f;
-              row = lr;
-            }
-            acc += sv[u];
-          }
-        }
-      }
-    }
-    if (row >= 0 && q == 0) Al[row * RQH + hl] += acc;
+    // after the barrier: a wavefront's pulls target rows other wavefronts
+    // loaded; one lane per hand writes
+    rm_pulls<RQH>(P, T, Al, stage, lane, wv, hl, hc, q == 0);
     __syncthreads();
   }
   if (MODE != 2) {
@@ -1514,27 +1493,7 @@ __global__ __launch_bounds__(64 * RMW) void k_rmq(RmParams P, float* __restrict_
     for (int ps = grouped ? 0 : 1; ps < 2; ++ps) {
       if (ps == 1 && grouped) {
         __syncthreads();
-        if (wv == 0) {
-          int mge[kRmMergeMax / 2];
-#pragma unroll
-          for (int e = 0; e < kRmMergeMax / 2; ++e) mge[e] = rl(grpv, kRmGMrg + e);
-          float sv[kRmMergeMax], tv[kRmMergeMax];
-#pragma unroll
-          for (int e = 0; e < kRmMergeMax; ++e) {
-            const int cc = (mge[e / 2] >> (16 * (e & 1))) & 0xffff;
-            sv[e] = rsm[(cc & 255) * RQH + hl];
-            tv[e] = rsm[(cc >> 8) * RQH + hl];
-          }
-          float run = 0.f;
-          int prev = -1;
-#pragma unroll
-          for (int e = 0; e < kRmMergeMax; ++e) {
-            const int tg = ((mge[e / 2] >> (16 * (e & 1))) >> 8) & 255;
-            run = (tg == prev ? run : 0.f) + sv[e];
-            if (q == 0) rsm[tg * RQH + hl] = tv[e] + run;
-            prev = tg;
-          }
-        }
+        if (wv == 0) rm_merge<RQH>(rsm, grpv, hl, q == 0);
       }
       if (ps == 1 && wv != 0) break;
       const int i0 = ps ? tb : gb, i1 = ps ? te : ge;
