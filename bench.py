@@ -291,7 +291,7 @@ def turn_river_leg(args, stream):
     per player (352 MB per matvec pair): tuned matvec-pair roofline, solver
     iteration time, and the precision run: discounted CFR from a uniform
     start toward an FP64 saddle gap of 1e-8 * pot, the gap checked at doubling
-    iteration counts, within a time budget."""
+    iteration counts up to 16384 and every 2048 after, within a time budget."""
     import torch
     from paper_2112_03804_amd import autotune
     from paper_2112_03804_amd import instances as I
@@ -332,12 +332,13 @@ def turn_river_leg(args, stream):
         if gp <= 1e-8:
             reached = True
             break
-        # next check: double, or what the measured rate still allows in budget
+        # next check: double up to 16384 iterations, then every 2048 (a check
+        # costs a few ms), within what the measured rate allows in budget
         per_it = el / it
         left = args.turn_budget - el
         if left < 256 * per_it:
             break
-        nxt = it + min(it, int(left / per_it) // 256 * 256)
+        nxt = it + min(it if it < 16384 else 2048, int(left / per_it) // 256 * 256)
     out = {"workload": "turn + river endgame: 4-card board, 48 river cards, 1128 hands/player, "
                        "bets {0.33,0.75,1.5}xpot + all-in, max 3 raises per street, pot 100, stacks 400",
            "game_create_s": t_create,
