@@ -279,8 +279,12 @@ int solver_step(Game* g, int32_t n_iters, void* stream);
 /* Retire or revive instances of a batch: active_host[i] = 0 makes
  * solver_step skip instance i (its regrets, plans and averages stay frozen
  * and its iteration count no longer advances with the others); saddle_gap
- * still reports every instance.  solver_reset revives all.  Synchronizes
- * `stream`. */
+ * still reports every instance.  When the active set has halved since the
+ * solver's launch lists were built, or a revived instance is missing from
+ * them, the lists are rebuilt without the retired instances (their
+ * workgroups are then not dispatched); this synchronizes the device and
+ * drops the captured solver graph.  solver_reset revives all (and restores
+ * the lists the same way).  Synchronizes `stream`. */
 int solver_set_active(Game* g, const int32_t* active_host, void* stream);
 
 /* FP64 saddle gap of the average strategies (exploitability = gap / 2, over

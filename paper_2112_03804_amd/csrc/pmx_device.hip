@@ -972,6 +972,7 @@ constexpr int TPB = 128;
 constexpr int MAXA = 8;       // actions handled in registers by the walks
 
 __global__ void k_set1(double* tdev, double v) { tdev[0] = v; }
+__global__ void k_add1(double* tdev) { tdev[0] += 1.0; }
 
 // ---------------------------------------------------------------------------
 // regret update on treeplex pieces (RmTask): the piece's rows of g, R and x
@@ -1798,6 +1799,8 @@ struct DevMc {                  // chunk-aligned matvec layout of one direction
   DBuf<uint32_t> q, pos, meta;
   DBuf<int32_t> chunks[kMcClasses];
   int count[kMcClasses] = {0, 0, 0, 0, 0};
+  DBuf<int32_t> chunks_act[kMcClasses];   // the solver's lists: chunks of active instances only
+  int count_act[kMcClasses] = {0, 0, 0, 0, 0};
   int block = 0;                // 0: not built
 };
 
@@ -1815,7 +1818,7 @@ struct DevTp {
 
 struct DevRm {                  // regret-update pieces of one player
   DBuf<int32_t> rows, infs, pulls, ext_seq, ext_slot, grp;
-  DBuf<RmBlock> blocks;         // all depths, depth d at [blk_off[d], blk_off[d + 1])
+  DBuf<RmBlock> blocks;         // blocks of the active instances, depth d at [blk_off[d], blk_off[d + 1])
   std::vector<int> blk_off;
   std::vector<int> max_rows, max_ext;   // per depth
   DBuf<float> stage;
@@ -1844,6 +1847,8 @@ struct Game {
   int max_lds = 64 * 1024;          // dynamic LDS bytes a workgroup may use on this device
   DBuf<double> tdev;                // iteration index of the next step (device)
   DBuf<int32_t> active;             // per-instance: 1 = iterated by solver_step
+  std::vector<char> listed;         // instances the solver's launch lists include
+  int n_listed = 0;
   int dcfr = 0, gamma = 1;          // solver rule (see solver_set_params)
   double alpha = 1.5, beta = 0.0;
   // warm start: per player infoset segments, their blocks, features
@@ -1883,6 +1888,24 @@ static std::vector<int2> tp_blocks(const TpPlan& T, const std::vector<int32_t>& 
   return b;
 }
 
+// The solver's row-chunk lists of one direction: the chunks of the instances
+// its launch lists include (g->listed; every instance when unset).
+static int upload_mc_active(Game* g, int d) {
+  DevMc& E = g->dm[d];
+  const McDir& M = g->hg.mc[d];
+  const bool all = g->listed.size() != g->hg.inst.size();
+  for (int c = 0; c < kMcClasses; ++c) {
+    std::vector<int32_t> L;
+    const std::vector<int32_t>& F = M.chunks[c];
+    for (size_t i = 0; i + 3 < F.size(); i += 4)
+      if (all || g->listed[F[i + 2]]) L.insert(L.end(), F.begin() + i, F.begin() + i + 4);
+    int rc = E.chunks_act[c].upload(L);
+    if (rc) return rc;
+    E.count_act[c] = (int)L.size() / 4;
+  }
+  return PMX_OK;
+}
+
 static int upload_mc(Game* g, int d) {
   HostGame& hg = g->hg;
   DevMc& E = g->dm[d];
@@ -1914,7 +1937,7 @@ static int upload_mc(Game* g, int d) {
     E.count[c] = (int)M.chunks[c].size() / 4;
   }
   E.block = block;
-  return PMX_OK;
+  return upload_mc_active(g, d);
 }
 
 static int upload_dir(Game* g, int d) {
@@ -1954,25 +1977,20 @@ static int upload_dir(Game* g, int d) {
   return PMX_OK;
 }
 
-static int upload_rm(Game* g, int p) {
+// Block records of one player's regret launches for the instances marked in
+// `act` (every instance when empty); the LDS sizing per depth covers every
+// piece either way.
+static int upload_rm_blocks(Game* g, int p, const std::vector<char>& act) {
   const RmPlan& T = g->hg.rm[p];
   DevRm& E = g->drm[p];
-  int rc;
-  if ((rc = E.rows.upload(T.rows)) || (rc = E.infs.upload(T.infs)) ||
-      (rc = E.pulls.upload(T.pulls)) || (rc = E.ext_seq.upload(T.ext_seq)) || (rc = E.ext_slot.upload(T.ext_slot)) ||
-      (rc = E.grp.upload(T.grp)))
-    return rc;
   std::vector<RmBlock> blocks;
   const int D = (int)T.by_depth.size();
   E.blk_off.assign(D + 1, 0);
-  E.max_rows.assign(D, 0);
-  E.max_ext.assign(D, 0);
   for (int d = 0; d < D; ++d) {
     E.blk_off[d] = (int)blocks.size();
     for (int id : T.by_depth[d]) {
       const RmTask& t = T.tasks[id];
-      E.max_rows[d] = std::max(E.max_rows[d], (int)t.n_rows);
-      E.max_ext[d] = std::max(E.max_ext[d], (int)t.n_ext);
+      if (!act.empty() && !act[t.inst]) continue;
       for (int h0 = 0; h0 < t.n_hands; h0 += 64) {
         RmBlock bk{};
         bk.t = t;
@@ -1982,7 +2000,27 @@ static int upload_rm(Game* g, int p) {
     }
   }
   E.blk_off[D] = (int)blocks.size();
-  if ((rc = E.blocks.upload(blocks))) return rc;
+  return E.blocks.upload(blocks);
+}
+
+static int upload_rm(Game* g, int p) {
+  const RmPlan& T = g->hg.rm[p];
+  DevRm& E = g->drm[p];
+  int rc;
+  if ((rc = E.rows.upload(T.rows)) || (rc = E.infs.upload(T.infs)) ||
+      (rc = E.pulls.upload(T.pulls)) || (rc = E.ext_seq.upload(T.ext_seq)) || (rc = E.ext_slot.upload(T.ext_slot)) ||
+      (rc = E.grp.upload(T.grp)))
+    return rc;
+  const int D = (int)T.by_depth.size();
+  E.max_rows.assign(D, 0);
+  E.max_ext.assign(D, 0);
+  for (int d = 0; d < D; ++d)
+    for (int id : T.by_depth[d]) {
+      E.max_rows[d] = std::max(E.max_rows[d], (int)T.tasks[id].n_rows);
+      E.max_ext[d] = std::max(E.max_ext[d], (int)T.tasks[id].n_ext);
+    }
+  if ((rc = upload_rm_blocks(g, p, g->listed.size() == g->hg.inst.size() ? g->listed : std::vector<char>())))
+    return rc;
   E.stage_stride = std::max(T.stage_stride, 1);
   return E.stage.alloc((size_t)std::max(T.n_slot, 1) * E.stage_stride);
 }
@@ -2043,6 +2081,8 @@ static int upload_game(Game* g) {
   if ((rc = g->br_inst.alloc(2 * hg.inst.size()))) return rc;
   if ((rc = g->tdev.alloc(1))) return rc;
   if ((rc = g->active.upload(std::vector<int32_t>(hg.inst.size(), 1)))) return rc;
+  g->listed.assign(hg.inst.size(), 1);
+  g->n_listed = (int)hg.inst.size();
   for (int p = 0; p < 2; ++p) {
     std::vector<WarmSeg> segs;
     std::vector<int2> blks;
@@ -2151,7 +2191,10 @@ static McParams mc_params(Game* g, int d, const MvParams& like, int c) {
   DevMc& E = g->dm[d];
   McParams P;
   P.items = g->dd[d].items.p;
-  P.chunks = (const int4*)E.chunks[c].p;
+  // the solver's launches (active flags set) take the lists without retired
+  // instances; the FP64 gap takes the full lists
+  const bool solver = like.active != nullptr;
+  P.chunks = (const int4*)(solver ? E.chunks_act[c].p : E.chunks[c].p);
   P.ctx = E.ctx.p;
   P.q = (const uint4*)E.q.p;
   P.pos = (const uint2*)E.pos.p;
@@ -2160,7 +2203,7 @@ static McParams mc_params(Game* g, int d, const MvParams& like, int c) {
   P.lamf = g->lamf.p;
   P.active = like.active;
   P.scale = like.scale;
-  P.nchunk = like.nblk > 0 ? E.count[c] : 0;
+  P.nchunk = like.nblk > 0 ? (solver ? E.count_act[c] : E.count[c]) : 0;
   return P;
 }
 
@@ -2223,6 +2266,8 @@ static int launch_mc(Game* g, const MvParams& P0, const IO* in0, IO* out0, const
     }
     tick = nullptr;   // the iteration tick belongs to the first launch
   }
+  // every instance retired from the lists: the iteration still counts
+  if (tick) hipLaunchKernelGGL(k_add1, dim3(1), dim3(1), 0, s, tick);
   HIP_TRY(hipGetLastError());
   return PMX_OK;
 }
@@ -2648,6 +2693,32 @@ int matvec_pair(Game* g, const float* y, const float* x, float* Ay, float* ATx, 
                           (hipStream_t)stream);
 }
 
+// The solver's launch lists restricted to the instances marked in `act`: the
+// matvec row chunks and regret blocks of the others are left out, so their
+// workgroups are not dispatched at all (they would return at once on the
+// active flags); the FP64 gap keeps the full lists.  Drops the captured
+// solver graph, whose grid sizes change.
+static int set_solver_lists(Game* g, const std::vector<char>& act) {
+  HIP_TRY(hipDeviceSynchronize());
+  if (g->graph_exec) {
+    (void)hipGraphExecDestroy(g->graph_exec);
+    g->graph_exec = nullptr;
+  }
+  if (g->graph) {
+    (void)hipGraphDestroy(g->graph);
+    g->graph = nullptr;
+  }
+  g->listed = act;
+  g->n_listed = 0;
+  for (char v : act) g->n_listed += v ? 1 : 0;
+  int rc;
+  for (int d = 0; d < 2; ++d)
+    if (g->dm[d].block && (rc = upload_mc_active(g, d))) return rc;
+  for (int p = 0; p < 2; ++p)
+    if ((rc = upload_rm_blocks(g, p, g->listed))) return rc;
+  return PMX_OK;
+}
+
 int solver_reset(Game* g, void* stream) {
   int rc = ensure_device(g);
   if (rc) return rc;
@@ -2664,6 +2735,10 @@ int solver_reset(Game* g, void* stream) {
   HIP_TRY(hipGetLastError());
   g->t = 0;
   g->wsum = 0.0;
+  // every instance is active again: the launch lists must include them all
+  if (g->n_listed < (int)g->hg.inst.size()) {
+    if ((rc = set_solver_lists(g, std::vector<char>(g->hg.inst.size(), 1)))) return rc;
+  }
   return PMX_OK;
 }
 
@@ -2677,6 +2752,19 @@ int solver_set_active(Game* g, const int32_t* active_host, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(hipMemcpyAsync(g->active.p, a.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
+  // rebuild the launch lists when an active instance is missing from them
+  // (required) or the active set has halved since they were built
+  int n_act = 0;
+  bool missing = false;
+  for (size_t i = 0; i < n; ++i) {
+    n_act += a[i];
+    if (a[i] && !g->listed[i]) missing = true;
+  }
+  if (missing || 2 * n_act <= g->n_listed) {
+    std::vector<char> act(n);
+    for (size_t i = 0; i < n; ++i) act[i] = (char)a[i];
+    if ((rc = set_solver_lists(g, act))) return rc;
+  }
   return PMX_OK;
 }
 

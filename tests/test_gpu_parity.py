@@ -615,6 +615,28 @@ def test_retired_instances_stay_frozen(rmk):
         assert np.array_equal(before[p][1], after[p][1])
         assert not np.array_equal(before[p][0], after[p][0])
         assert not np.array_equal(before[p][2], after[p][2])
+    # halving the active set rebuilds the launch lists without the retired
+    # instances; their state stays as it was
+    g.solver_set_active([0, 0, 1])
+    g.solver_step(8)
+    mid = [g.unpack(p, g.solver_get_state(p)["avg_sum"]) for p in range(2)]
+    for p in range(2):
+        assert np.array_equal(after[p][0], mid[p][0]) and np.array_equal(after[p][1], mid[p][1])
+        assert not np.array_equal(after[p][2], mid[p][2])
+    # reactivated instances must be in the lists again
+    g.solver_set_active([1, 1, 1])
+    g.solver_step(8)
+    end = [g.unpack(p, g.solver_get_state(p)["avg_sum"]) for p in range(2)]
+    for p in range(2):
+        for i in range(3):
+            assert not np.array_equal(mid[p][i], end[p][i]), (p, i)
+    # every instance retired: iterations still count, nothing changes
+    g.solver_set_active([0, 0, 0])
+    t0 = g.solver_get_state(0)["t"]
+    g.solver_step(4)
+    st = g.solver_get_state(0)
+    assert st["t"] == t0 + 4
+    assert all(np.array_equal(a, b) for a, b in zip(end[0], g.unpack(0, st["avg_sum"])))
     g.solver_reset()
     g.solver_step(8)
     assert all(np.abs(a).sum() > 0 for a in g.unpack(0, g.solver_get_state(0)["avg_sum"]))
