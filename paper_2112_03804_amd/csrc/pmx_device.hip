@@ -405,15 +405,27 @@ __device__ inline void block_seg_scan_x(int flag, double a, double b, double* sc
     scr[3 * wid + 2] = bi;
   }
   __syncthreads();
+  // carry into this wavefront: lane w holds wavefront w's (flag, totals),
+  // a segmented scan across those lanes (three DPP steps, NW <= 8) combines
+  // them, and the carry is the scan at lane wid - 1
+  static_assert(NW <= 8, "wavefront totals are scanned within one DPP row");
+  int fw = 0;
+  double aw = 0.0, bw = 0.0;
+  if (lane < NW) {
+    fw = scr[3 * lane] != 0.0;
+    aw = scr[3 * lane + 1];
+    bw = scr[3 * lane + 2];
+  }
+  seg_step<0x111, 0xf>(fw, aw, bw);
+  seg_step<0x112, 0xf>(fw, aw, bw);
+  seg_step<0x114, 0xf>(fw, aw, bw);
   double ca = 0.0, cb = 0.0;
-  for (int w = 0; w < wid && w < NW; ++w) {
-    if (scr[3 * w] != 0.0) {
-      ca = scr[3 * w + 1];
-      cb = scr[3 * w + 2];
-    } else {
-      ca += scr[3 * w + 1];
-      cb += scr[3 * w + 2];
-    }
+  if (wid > 0) {
+    const int src = wid - 1;
+    ca = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(aw), src),
+                          __builtin_amdgcn_readlane(__double2loint(aw), src));
+    cb = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(bw), src),
+                          __builtin_amdgcn_readlane(__double2loint(bw), src));
   }
   if (!f) {
     ai += ca;
