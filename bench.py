@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 # known size (profiles/matvec_pair_traffic_counters.md).  They describe the
 # kernel sources whose code (comments and whitespace removed) has the SHA-1
 # recorded here and are reported as null for any other version of that code.
-TRAFFIC = {"sources_sha1": "1c947c2aa815e793898c9608394921197e8d9309", "river": 1628196, "batch": 449650184}
+TRAFFIC = {"sources_sha1": "e254641001dc036e30a96a864ebff7f7286220b2", "river": 1637386, "batch": 449601982}
 TRAFFIC_SOURCES = ("paper_2112_03804_amd/csrc/pmx_device.hip", "paper_2112_03804_amd/csrc/host_build.cpp")
 
 
