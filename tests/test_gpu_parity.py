@@ -464,6 +464,16 @@ def test_piece_size_rejects_too_small():
     g.close()
 
 
+def test_rm_kernel_choice_rejects_negative():
+    pmx = _need_gpu()
+    g = pmx.Game(I.config(1))
+    with pytest.raises(pmx.PmxError):
+        g.solver_set_rm_quad(-1)
+    g.solver_step(3)                   # the previous choice is still in place
+    torch.cuda.synchronize()
+    g.close()
+
+
 @pytest.mark.parametrize("name,fn,target", [("tiny", I.tiny_config, 1e-6),
                                             ("kuhn", I.kuhn, 1e-5),
                                             ("river", lambda: I.config(1), 1e-4),
