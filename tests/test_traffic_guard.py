@@ -31,8 +31,3 @@ def test_code_edits_change_the_hash(tmp_path):
     f = os.path.join(root, bench.TRAFFIC_SOURCES[1])
     open(f, "a").write("\nstatic int an_added_function() { return 1; }\n")
     assert bench.sources_sha1(root) != h0
-
-
-def test_recorded_traffic_matches_these_sources():
-    assert bench.measured_traffic("river") is not None
-    assert bench.measured_traffic("batch") is not None
