@@ -277,9 +277,10 @@ int solver_set_params(Game* g, int32_t kind, double alpha, double beta, int32_t 
 int solver_step(Game* g, int32_t n_iters, void* stream);
 
 /* Retire or revive instances of a batch: active_host[i] = 0 makes
- * solver_step skip instance i (its regrets, plans and averages stay frozen
- * and its iteration count no longer advances with the others); saddle_gap
- * still reports every instance.  When the active set has halved since the
+ * solver_step skip instance i (its regrets, plans and averages stay frozen,
+ * and so does its averaging weight total, see solver_get_weights);
+ * saddle_gap and get_average_strategy still report every instance, each
+ * normalized by its own weight total.  When the active set has halved since the
  * solver's launch lists were built, or a revived instance is missing from
  * them, the lists are rebuilt without the retired instances (their
  * workgroups are then not dispatched); this synchronizes the device and
@@ -288,7 +289,9 @@ int solver_step(Game* g, int32_t n_iters, void* stream);
 int solver_set_active(Game* g, const int32_t* active_host, void* stream);
 
 /* FP64 saddle gap of the average strategies (exploitability = gap / 2, over
- * the initial pot 2 * contrib).  gap, br1, br2 are host arrays with one
+ * the initial pot 2 * contrib).  An instance's average is its weighted sum
+ * divided by its own weight total; one with no weight yet (retired before
+ * its first iteration) stands at its current plan.  gap, br1, br2 are host arrays with one
  * entry per instance: br1 = max_x x^T A ybar, br2 = min_y xbar^T A y,
  * gap = br1 - br2 >= 0 (chips).  Synchronizes `stream`. */
 int saddle_gap(Game* g, double* gap, double* br1, double* br2, void* stream);
@@ -299,14 +302,26 @@ int saddle_gap_of(Game* g, const double* x_dev, const double* y_dev, double* gap
                   double* br1, double* br2, void* stream);
 
 /* Copy solver state to / from host arrays (NULL skips a field).  Regrets and
- * current plans are FP32, averages FP64 (weighted sums, divide by wsum).
- * t = iterations done; wsum = sum of the averaging weights. */
+ * current plans are FP32, averages FP64 (weighted sums).  t = iterations
+ * done; wsum = sum of the averaging weights of all iterations, which is each
+ * instance's own total unless it was retired for some (solver_get_weights).
+ * solver_set_state gives every instance the weight total wsum. */
 int solver_get_state(Game* g, int32_t player, float* regret, float* plan,
                      double* avg_sum, int32_t* t, double* wsum);
 int solver_set_state(Game* g, int32_t player, const float* regret, const float* plan,
                      const double* avg_sum, int32_t t, double wsum);
 
-/* Average strategy in sequence form (FP64 host array, vec_elems). */
+/* Averaging weight totals, one per instance (host FP64 arrays): the sum of
+ * the weights of the iterations the instance took part in (DCFR: t^gamma;
+ * RM+: t), by which its averages are divided.  solver_set_weights restores
+ * them after solver_set_state; PMX_EINVAL on a negative or non-finite
+ * total.  Host-side only. */
+int solver_get_weights(Game* g, double* wsum_host);
+int solver_set_weights(Game* g, const double* wsum_host);
+
+/* Average strategy in sequence form (FP64 host array, vec_elems): each
+ * instance's weighted sums over its own weight total, or its current plan if
+ * it has none. */
 int get_average_strategy(Game* g, int32_t player, double* x_host);
 
 /* Warm start: behavioural strategy b(a|I) per sequence (device FP32,
@@ -329,7 +344,8 @@ int warm_features(Game* g, int32_t player, uint16_t* x_dev, void* stream);
 /* Training targets from the solver's average strategy: target_dev [rows][8]
  * holds xbar[Ia] / xbar[parent(I)] for valid slots (uniform if unreached) and
  * -1 for invalid slots; weight_dev [rows] = relative belief weight x average
- * reach of I.  Needs at least one solver iteration.  Asynchronous. */
+ * reach of I (0 for an instance with no weight total).  Needs at least one
+ * solver iteration.  Synchronizes `stream`. */
 int warm_targets(Game* g, int32_t player, float* target_dev, float* weight_dev, void* stream);
 /* Reset the solver to the prior given by network logits (device FP32
  * [rows][ldz] per player): masked softmax per row -> behavioural prior b0;

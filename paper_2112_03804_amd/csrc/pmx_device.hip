@@ -1659,6 +1659,11 @@ __global__ void k_fill_f64(double* p, int64_t n, double v) {
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
 }
+__global__ void k_f32_to_f64(const float* __restrict__ a, double* __restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (double)a[i];
+}
 __global__ void k_fill_i32(int* p, int n, int v) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
@@ -1674,7 +1679,7 @@ struct WarmSeg {
   int64_t row_base;        // first row of this infoset
   int64_t vec_base;        // instance's vector block
   int32_t stride, n_hands, hand_base, first;
-  int32_t nact, parent, pad0, pad1;
+  int32_t nact, parent, inst, pad1;
 };
 
 __device__ inline uint16_t dev_f2bf(float f) {
@@ -1702,10 +1707,12 @@ __global__ __launch_bounds__(256) void k_warm_features(const WarmSeg* __restrict
 
 // Targets from the solver's average: b*(a|I,h) = xbar[Ia] / xbar[parent]
 // (uniform where the parent is unreached); invalid action slots get -1.
-// Weight = belief weight relative to the mean x average reach of the infoset.
+// Weight = belief weight relative to the mean x average reach of the infoset
+// (the sums over the instance's own averaging weight total).
 __global__ __launch_bounds__(256) void k_warm_targets(const WarmSeg* __restrict__ segs,
                                                       const int2* __restrict__ blocks,
-                                                      const double* __restrict__ xs, double wsum,
+                                                      const double* __restrict__ xs,
+                                                      const double* __restrict__ wsum_inst,
                                                       const float* __restrict__ hand_feat,
                                                       float* __restrict__ T, float* __restrict__ W) {
   const int2 bt = blocks[blockIdx.x];
@@ -1722,6 +1729,7 @@ __global__ __launch_bounds__(256) void k_warm_targets(const WarmSeg* __restrict_
       v = tot > 0.0 ? (float)(xs[base + (int64_t)(S.first + a) * S.stride] / tot) : 1.f / (float)S.nact;
     tr[a] = v;
   }
+  const double wsum = wsum_inst[S.inst];
   const double reach = wsum > 0.0 ? tot / wsum : 0.0;
   W[row] = (float)(8.0 * hand_feat[(int64_t)(S.hand_base + h) * kHandFeat] * reach);
 }
@@ -1854,7 +1862,10 @@ struct Game {
   DBuf<float> R[2], x[2], grad[2];
   DBuf<double> xs[2], gd[2], sd[2], br_inst;
   int t = 0;
-  double wsum = 0.0;
+  double wsum = 0.0;                // averaging weight total of the iterations so far
+  std::vector<double> wsum_i;       // per instance: the weights of the iterations it took part in
+  std::vector<char> act_h;          // per instance: host copy of the active flags
+  DBuf<double> wsum_dev;            // wsum_i on the device (warm-start targets)
   int mv_block = 256;
   int max_lds = 64 * 1024;          // dynamic LDS bytes a workgroup may use on this device
   DBuf<double> tdev;                // iteration index of the next step (device)
@@ -2095,6 +2106,9 @@ static int upload_game(Game* g) {
   if ((rc = g->active.upload(std::vector<int32_t>(hg.inst.size(), 1)))) return rc;
   g->listed.assign(hg.inst.size(), 1);
   g->n_listed = (int)hg.inst.size();
+  g->act_h.assign(hg.inst.size(), 1);
+  g->wsum_i.assign(hg.inst.size(), 0.0);
+  if ((rc = g->wsum_dev.alloc(hg.inst.size()))) return rc;
   for (int p = 0; p < 2; ++p) {
     std::vector<WarmSeg> segs;
     std::vector<int2> blks;
@@ -2115,6 +2129,7 @@ static int upload_game(Game* g) {
         S.first = I.first;
         S.nact = I.nact;
         S.parent = I.parent;
+        S.inst = (int32_t)(&b - hg.inst.data());
         for (int h0 = 0; h0 < S.n_hands; h0 += 256) blks.push_back(make_int2((int)segs.size(), h0));
         segs.push_back(S);
         rb.push_back(row);
@@ -2747,6 +2762,8 @@ int solver_reset(Game* g, void* stream) {
   HIP_TRY(hipGetLastError());
   g->t = 0;
   g->wsum = 0.0;
+  g->wsum_i.assign(g->wsum_i.size(), 0.0);
+  g->act_h.assign(g->act_h.size(), 1);
   // every instance is active again: the launch lists must include them all
   if (g->n_listed < (int)g->hg.inst.size()) {
     if ((rc = set_solver_lists(g, std::vector<char>(g->hg.inst.size(), 1)))) return rc;
@@ -2764,6 +2781,7 @@ int solver_set_active(Game* g, const int32_t* active_host, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(hipMemcpyAsync(g->active.p, a.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
+  for (size_t i = 0; i < n; ++i) g->act_h[i] = (char)a[i];
   // rebuild the launch lists when an active instance is missing from them
   // (required) or the active set has halved since they were built
   int n_act = 0;
@@ -2839,11 +2857,16 @@ int solver_step(Game* g, int32_t n_iters, void* stream) {
   }
   for (int i = 0; i < left; ++i)
     if ((rc = enqueue_iteration(g, s))) return rc;
+  double w = 0.0;
   for (int i = 0; i < n_iters; ++i) {
     g->t += 1;
     const double t = (double)g->t;
-    g->wsum += g->gamma == 1 ? t : (g->gamma == 2 ? t * t : t * t * t);
+    w += g->gamma == 1 ? t : (g->gamma == 2 ? t * t : t * t * t);
   }
+  g->wsum += w;
+  // a retired instance's averages take no weight: its total stays with them
+  for (size_t i = 0; i < g->wsum_i.size(); ++i)
+    if (g->act_h[i]) g->wsum_i[i] += w;
   return PMX_OK;
 }
 
@@ -2869,7 +2892,18 @@ int solver_set_params(Game* g, int32_t kind, double alpha, double beta, int32_t 
   return PMX_OK;
 }
 
-static int gap_from_sums(Game* g, const double* xsum, const double* ysum, double scale,
+// Elements [b, e) of instance i in player p's vectors (instances are stored
+// one after another).
+static void inst_range(const Game* g, int p, size_t i, int64_t* b, int64_t* e) {
+  *b = g->hg.inst[i].vec_off[p];
+  *e = i + 1 < g->hg.inst.size() ? g->hg.inst[i + 1].vec_off[p] : g->hg.elems[p];
+}
+
+// Best responses to the given sequence-form sums; the values of instance i
+// are multiplied by scale[i] (NULL: 1), which normalizes unnormalized sums
+// since a best-response value is positively homogeneous in the opponent's
+// strategy and the instances do not interact.
+static int gap_from_sums(Game* g, const double* xsum, const double* ysum, const double* scale,
                          double* gap, double* br1, double* br2, hipStream_t s) {
   int rc;
   MvParams PA = mv_params(g, 0, 1.0), PT = mv_params(g, 1, 1.0);
@@ -2882,7 +2916,8 @@ static int gap_from_sums(Game* g, const double* xsum, const double* ysum, double
   HIP_TRY(hipMemcpyAsync(h.data(), g->br_inst.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   for (int i = 0; i < ni; ++i) {
-    double a = h[i] * scale, b = h[ni + i] * scale;
+    const double c = scale ? scale[i] : 1.0;
+    double a = h[i] * c, b = h[ni + i] * c;
     if (!std::isfinite(a) || !std::isfinite(b)) return fail(PMX_ENUMERIC, "non-finite best response");
     if (br1) br1[i] = a;
     if (br2) br2[i] = b;
@@ -2891,23 +2926,54 @@ static int gap_from_sums(Game* g, const double* xsum, const double* ysum, double
   return PMX_OK;
 }
 
+// Each instance's average is its weighted sum over its own weight total (the
+// weights of the iterations it took part in); an instance with none yet
+// stands at its current plan.
 int saddle_gap(Game* g, double* gap, double* br1, double* br2, void* stream) {
   int rc = ensure_device(g);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
-  if (g->wsum > 0)
-    return gap_from_sums(g, g->xs[0].p, g->xs[1].p, 1.0 / g->wsum, gap, br1, br2, s);
-  // no iteration yet: the average is the current (uniform) plan
+  const size_t ni = g->hg.inst.size();
+  std::vector<double> scale(ni);
+  bool any_sum = false, any_plan = false;
+  for (size_t i = 0; i < ni; ++i) {
+    const bool has = g->wsum_i[i] > 0;
+    scale[i] = has ? 1.0 / g->wsum_i[i] : 1.0;
+    any_sum |= has;
+    any_plan |= !has;
+  }
+  if (!any_plan) return gap_from_sums(g, g->xs[0].p, g->xs[1].p, scale.data(), gap, br1, br2, s);
   for (int p = 0; p < 2; ++p) {
     const int64_t n = g->hg.elems[p];
-    std::vector<float> xf((size_t)n);
-    std::vector<double> xd((size_t)n);
-    HIP_TRY(hipMemcpyAsync(xf.data(), g->x[p].p, n * sizeof(float), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    for (int64_t i = 0; i < n; ++i) xd[i] = xf[i];
-    HIP_TRY(hipMemcpy(g->sd[p].p, xd.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    if (!any_sum) {
+      if (n > 0) {
+        const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_f32_to_f64, dim3(blocks), dim3(256), 0, s, g->x[p].p, g->sd[p].p, n);
+      }
+      continue;
+    }
+    HIP_TRY(hipMemcpyAsync(g->sd[p].p, g->xs[p].p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // runs of instances without a weight total take their current plan
+    for (size_t i = 0; i < ni;) {
+      if (g->wsum_i[i] > 0) {
+        ++i;
+        continue;
+      }
+      size_t j = i;
+      while (j < ni && !(g->wsum_i[j] > 0)) ++j;
+      int64_t b, e, b2, e2;
+      inst_range(g, p, i, &b, &e);
+      inst_range(g, p, j - 1, &b2, &e2);
+      if (e2 > b) {
+        const int blocks = (int)std::min<int64_t>((e2 - b + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_f32_to_f64, dim3(blocks), dim3(256), 0, s, g->x[p].p + b, g->sd[p].p + b,
+                           e2 - b);
+      }
+      i = j;
+    }
   }
-  return gap_from_sums(g, g->sd[0].p, g->sd[1].p, 1.0, gap, br1, br2, s);
+  HIP_TRY(hipGetLastError());
+  return gap_from_sums(g, g->sd[0].p, g->sd[1].p, scale.data(), gap, br1, br2, s);
 }
 
 int saddle_gap_of(Game* g, const double* x, const double* y, double* gap, double* br1, double* br2,
@@ -2915,7 +2981,7 @@ int saddle_gap_of(Game* g, const double* x, const double* y, double* gap, double
   int rc = ensure_device(g);
   if (rc) return rc;
   if (!x || !y) return fail(PMX_EINVAL, "null vector");
-  return gap_from_sums(g, x, y, 1.0, gap, br1, br2, (hipStream_t)stream);
+  return gap_from_sums(g, x, y, nullptr, gap, br1, br2, (hipStream_t)stream);
 }
 
 int solver_get_state(Game* g, int32_t player, float* regret, float* plan, double* avg_sum, int32_t* t,
@@ -2946,8 +3012,28 @@ int solver_set_state(Game* g, int32_t player, const float* regret, const float* 
   if (avg_sum) HIP_TRY(hipMemcpy(g->xs[player].p, avg_sum, n * sizeof(double), hipMemcpyHostToDevice));
   g->t = t;
   g->wsum = wsum;
+  g->wsum_i.assign(g->wsum_i.size(), wsum);
   const double cur = (double)t;   // the next iteration's first launch makes it t + 1
   HIP_TRY(hipMemcpy(g->tdev.p, &cur, sizeof(double), hipMemcpyHostToDevice));
+  return PMX_OK;
+}
+
+int solver_get_weights(Game* g, double* wsum_host) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!wsum_host) return fail(PMX_EINVAL, "null argument");
+  std::copy(g->wsum_i.begin(), g->wsum_i.end(), wsum_host);
+  return PMX_OK;
+}
+
+int solver_set_weights(Game* g, const double* wsum_host) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!wsum_host) return fail(PMX_EINVAL, "null argument");
+  const size_t n = g->wsum_i.size();
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(wsum_host[i]) || wsum_host[i] < 0) return fail(PMX_EINVAL, "bad weight total");
+  std::copy(wsum_host, wsum_host + n, g->wsum_i.begin());
   return PMX_OK;
 }
 
@@ -2957,13 +3043,22 @@ int get_average_strategy(Game* g, int32_t player, double* x_host) {
   if (player < 0 || player > 1 || !x_host) return fail(PMX_EINVAL, "bad argument");
   const size_t n = (size_t)g->hg.elems[player];
   HIP_TRY(hipDeviceSynchronize());
-  if (g->wsum > 0) {
-    HIP_TRY(hipMemcpy(x_host, g->xs[player].p, n * sizeof(double), hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < n; ++i) x_host[i] /= g->wsum;
-  } else {
-    std::vector<float> xf(n);
-    HIP_TRY(hipMemcpy(xf.data(), g->x[player].p, n * sizeof(float), hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < n; ++i) x_host[i] = xf[i];
+  HIP_TRY(hipMemcpy(x_host, g->xs[player].p, n * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<float> xf;
+  for (size_t i = 0; i < g->hg.inst.size(); ++i) {
+    int64_t b, e;
+    inst_range(g, player, i, &b, &e);
+    const double w = g->wsum_i[i];
+    if (w > 0) {
+      for (int64_t k = b; k < e; ++k) x_host[k] /= w;
+      continue;
+    }
+    // no iteration of this instance yet: its average is the current plan
+    if (xf.empty()) {
+      xf.resize(n);
+      HIP_TRY(hipMemcpy(xf.data(), g->x[player].p, n * sizeof(float), hipMemcpyDeviceToHost));
+    }
+    for (int64_t k = b; k < e; ++k) x_host[k] = xf[k];
   }
   return PMX_OK;
 }
@@ -3012,10 +3107,15 @@ int warm_targets(Game* g, int32_t player, float* target_dev, float* weight_dev, 
   if (player < 0 || player > 1 || !target_dev || !weight_dev) return fail(PMX_EINVAL, "bad argument");
   if (!g->warm_ok) return fail(PMX_EINVAL, "an infoset has more actions than the network's slots");
   if (!(g->wsum > 0)) return fail(PMX_ESTATE, "no solver iterations to take targets from");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(g->wsum_dev.p, g->wsum_i.data(), g->wsum_i.size() * sizeof(double),
+                         hipMemcpyHostToDevice, s));
   if (g->wn_blk[player])
-    hipLaunchKernelGGL(k_warm_targets, dim3(g->wn_blk[player]), dim3(256), 0, (hipStream_t)stream,
-                       g->wseg[player].p, g->wblk[player].p, g->xs[player].p, g->wsum, g->whand[player].p,
-                       target_dev, weight_dev);
+    hipLaunchKernelGGL(k_warm_targets, dim3(g->wn_blk[player]), dim3(256), 0, s, g->wseg[player].p,
+                       g->wblk[player].p, g->xs[player].p, g->wsum_dev.p, g->whand[player].p, target_dev,
+                       weight_dev);
+  // the weight totals are host memory that later solver steps change
+  HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipGetLastError());
   return PMX_OK;
 }
@@ -3050,6 +3150,7 @@ int warm_apply(Game* g, const float* logits0_dev, const float* logits1_dev, int3
   HIP_TRY(hipGetLastError());
   g->t = 0;
   g->wsum = avg_weight;
+  g->wsum_i.assign(g->wsum_i.size(), avg_weight);
   return PMX_OK;
 }
 

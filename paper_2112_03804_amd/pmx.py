@@ -74,7 +74,8 @@ EXPORTS = [
     "game_num_instances", "game_layout", "game_terminals", "game_hand_meta",
     "matvec_A", "matvec_AT", "matvec_A_f64", "matvec_AT_f64", "matvec_pair",
     "solver_reset", "solver_step", "saddle_gap", "saddle_gap_of",
-    "solver_get_state", "solver_set_state", "get_average_strategy",
+    "solver_get_state", "solver_set_state", "solver_get_weights", "solver_set_weights",
+    "get_average_strategy",
     "set_initial_strategy", "pmx_last_error", "game_tune", "game_get_tuning",
     "warm_num_rows", "warm_features", "warm_targets", "warm_apply",
     "mlp_gemm_bf16", "mlp_softmax_xent", "mlp_colsum", "mlp_adam", "mlp_gather_bf16",
@@ -113,6 +114,8 @@ def lib():
     L.solver_get_state.argtypes = [vp, ctypes.c_int32, _c_f32p, _c_f32p, _c_f64p, _c_i32p, _c_f64p]
     L.solver_set_state.argtypes = [vp, ctypes.c_int32, _c_f32p, _c_f32p, _c_f64p, ctypes.c_int32,
                                    ctypes.c_double]
+    L.solver_get_weights.argtypes = [vp, _c_f64p]
+    L.solver_set_weights.argtypes = [vp, _c_f64p]
     L.get_average_strategy.argtypes = [vp, ctypes.c_int32, _c_f64p]
     L.set_initial_strategy.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_float, vp]
     L.game_tune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
@@ -381,6 +384,17 @@ class Game:
         s = None if avg_sum is None else np.ascontiguousarray(avg_sum, np.float64)
         _check(lib().solver_set_state(self._h, player, _ptr(r, ctypes.c_float), _ptr(x, ctypes.c_float),
                                       _ptr(s, ctypes.c_double), int(t), float(wsum)))
+
+    def solver_get_weights(self) -> np.ndarray:
+        w = np.zeros(self.n_instances, np.float64)
+        _check(lib().solver_get_weights(self._h, _ptr(w, ctypes.c_double)))
+        return w
+
+    def solver_set_weights(self, wsum):
+        w = np.ascontiguousarray(wsum, np.float64)
+        if w.shape != (self.n_instances,):
+            raise ValueError(f"need {self.n_instances} weight totals, got shape {w.shape}")
+        _check(lib().solver_set_weights(self._h, _ptr(w, ctypes.c_double)))
 
     def get_average_strategy(self, player: int) -> np.ndarray:
         out = np.zeros(self.elems[player], np.float64)

@@ -654,6 +654,73 @@ def test_retired_instances_stay_frozen(rmk):
     g.close()
 
 
+def _retire_descs(n):
+    return [I.river_config(seed=930 + i, n_keep=(100, 120), bet_fracs=(0.5, 1.0), max_raises=2,
+                           pot=40.0, stack=120.0) for i in range(n)]
+
+
+def test_retired_average_keeps_its_own_weight():
+    """A retired instance's averages are divided by the weights of the
+    iterations it took part in, not by the batch's running total: its average
+    strategy and gap stay as they were at retirement, and the gap of every
+    instance matches the oracle's on the normalized averages."""
+    pmx = _need_gpu()
+    descs = _retire_descs(3)
+    _say("retired averages")
+    g = pmx.Game(descs)
+    g.solver_step(24)
+    avg0 = [g.unpack(p, g.get_average_strategy(p)) for p in range(2)]
+    gap0 = g.saddle_gap()[0]
+    g.solver_set_active([1, 0, 1])
+    g.solver_step(40)
+    w = g.solver_get_weights()
+    assert w[1] == sum(range(1, 25)) and w[0] == w[2] == sum(range(1, 65))
+    assert g.solver_get_state(0)["wsum"] == w[0]
+    avg1 = [g.unpack(p, g.get_average_strategy(p)) for p in range(2)]
+    gap1 = g.saddle_gap()[0]
+    for p in range(2):
+        assert np.array_equal(avg0[p][1], avg1[p][1])
+    assert abs(gap1[1] - gap0[1]) <= 1e-12 * 2 * descs[1].contrib
+    for i, d in enumerate(descs):
+        o = payoff.Game(d)
+        rgap, _, _ = solver.saddle_gap(o, avg1[0][i], avg1[1][i])
+        assert abs(gap1[i] - rgap) <= 1e-9 * 2 * d.contrib, (i, gap1[i], rgap)
+    # the totals travel with the state
+    st = [g.solver_get_state(p) for p in range(2)]
+    g.solver_reset()
+    for p in range(2):
+        g.solver_set_state(p, st[p]["regret"], st[p]["plan"], st[p]["avg_sum"], st[p]["t"], st[p]["wsum"])
+    assert np.all(g.solver_get_weights() == st[0]["wsum"])
+    g.solver_set_weights(w)
+    assert np.array_equal(g.solver_get_weights(), w)
+    assert np.allclose(g.saddle_gap()[0], gap1, rtol=0, atol=1e-12 * 2 * descs[0].contrib)
+    with pytest.raises(pmx.PmxError):
+        g.solver_set_weights(np.array([1.0, -1.0, 1.0]))
+    g.close()
+
+
+def test_instance_retired_before_any_iteration_keeps_its_plan():
+    pmx = _need_gpu()
+    descs = _retire_descs(3)
+    _say("retired at start")
+    g = pmx.Game(descs)
+    plan0 = [g.unpack(p, g.solver_get_state(p)["plan"]) for p in range(2)]
+    gap0 = g.saddle_gap()[0]
+    g.solver_set_active([1, 0, 1])
+    g.solver_step(16)
+    assert g.solver_get_weights()[1] == 0.0
+    gap1 = g.saddle_gap()[0]
+    assert abs(gap1[1] - gap0[1]) <= 1e-12 * 2 * descs[1].contrib
+    for p in range(2):
+        avg = g.unpack(p, g.get_average_strategy(p))
+        assert np.array_equal(avg[1], plan0[p][1].astype(np.float64))
+    o = payoff.Game(descs[0])
+    avg = [g.unpack(p, g.get_average_strategy(p))[0] for p in range(2)]
+    rgap, _, _ = solver.saddle_gap(o, avg[0], avg[1])
+    assert abs(gap1[0] - rgap) <= 1e-9 * 2 * descs[0].contrib
+    g.close()
+
+
 @pytest.mark.parametrize("name,fn", [SMALL[2], SMALL[6], ("river", lambda: I.config(1))])
 def test_dcfr_single_step_from_given_state(name, fn):
     pmx = _need_gpu()

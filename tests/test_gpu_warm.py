@@ -205,3 +205,35 @@ def test_short_training_lowers_loss():
     hist = ws.train(net, ds, steps=300, batch_rows=2048, lr=1e-3, log_every=50)
     assert np.all(np.isfinite(hist))
     assert hist[-1] < 0.85 * hist[0], hist
+
+
+def test_targets_of_retired_instance_use_its_own_weight():
+    """Training weights (belief weight x average reach) of an instance retired
+    early are those it had at retirement: its reach is its weighted sum over
+    its own weight total, however long the others keep iterating."""
+    pmx, ws = _need()
+    descs = [I.river_config(seed=950 + i, n_keep=(90, 110), bet_fracs=(0.5, 1.0), max_raises=2,
+                            pot=40.0, stack=120.0) for i in range(2)]
+    g = pmx.Game(descs)
+    g.solver_step(24)
+
+    def weights(p):
+        n = g.warm_num_rows(p)
+        T = torch.empty((n, ws.K), dtype=torch.float32, device="cuda")
+        W = torch.empty((n,), dtype=torch.float32, device="cuda")
+        g.warm_targets(p, T, W)
+        torch.cuda.synchronize()
+        return T.cpu().numpy(), W.cpu().numpy()
+
+    before = [weights(p) for p in range(2)]
+    g.solver_set_active([0, 1])
+    g.solver_step(40)
+    after = [weights(p) for p in range(2)]
+    for p in range(2):
+        L = g.layouts[0][p]
+        r0 = L["n_infosets"] * L["n_hands"]
+        assert np.array_equal(before[p][0][:r0], after[p][0][:r0])
+        assert np.array_equal(before[p][1][:r0], after[p][1][:r0])
+        assert before[p][1][:r0].max() > 0
+        assert not np.array_equal(before[p][1][r0:], after[p][1][r0:])
+    g.close()
