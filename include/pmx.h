@@ -291,7 +291,10 @@ int solver_set_active(Game* g, const int32_t* active_host, void* stream);
 /* FP64 saddle gap of the average strategies (exploitability = gap / 2, over
  * the initial pot 2 * contrib).  An instance's average is its weighted sum
  * divided by its own weight total; one with no weight yet (retired before
- * its first iteration) stands at its current plan.  gap, br1, br2 are host arrays with one
+ * its first iteration) stands at its current plan.  Values are kept per
+ * instance: one not iterated since the last call (a retired instance)
+ * reuses them, until solver_reset, solver_set_state, solver_set_weights,
+ * set_initial_strategy or warm_apply changes the state.  gap, br1, br2 are host arrays with one
  * entry per instance: br1 = max_x x^T A ybar, br2 = min_y xbar^T A y,
  * gap = br1 - br2 >= 0 (chips).  Synchronizes `stream`. */
 int saddle_gap(Game* g, double* gap, double* br1, double* br2, void* stream);

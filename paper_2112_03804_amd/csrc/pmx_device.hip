@@ -1562,6 +1562,7 @@ __global__ __launch_bounds__(TPB) void k_br(TpParams P, double* __restrict__ g,
                                             double* __restrict__ stage, double* __restrict__ hv) {
   const int2 bt = P.blocks[blockIdx.x];
   const TpTask T = P.tasks[bt.x];
+  if (P.active && !P.active[T.inst]) return;   // instance not asked for
   const int h = bt.y + threadIdx.x;
   if (h >= T.n_hands) return;
   const int64_t base = T.vec_base + h, stride = T.stride;
@@ -1866,6 +1867,10 @@ struct Game {
   std::vector<double> wsum_i;       // per instance: the weights of the iterations it took part in
   std::vector<char> act_h;          // per instance: host copy of the active flags
   DBuf<double> wsum_dev;            // wsum_i on the device (warm-start targets)
+  // last FP64 gap per instance; valid while the instance's state is unchanged
+  std::vector<double> gap_c, br1_c, br2_c;
+  std::vector<char> gap_ok;
+  DBuf<int32_t> gap_need;           // per instance: 1 = the gap call computes it
   int mv_block = 256;
   int max_lds = 64 * 1024;          // dynamic LDS bytes a workgroup may use on this device
   DBuf<double> tdev;                // iteration index of the next step (device)
@@ -2109,6 +2114,11 @@ static int upload_game(Game* g) {
   g->act_h.assign(hg.inst.size(), 1);
   g->wsum_i.assign(hg.inst.size(), 0.0);
   if ((rc = g->wsum_dev.alloc(hg.inst.size()))) return rc;
+  g->gap_c.assign(hg.inst.size(), 0.0);
+  g->br1_c.assign(hg.inst.size(), 0.0);
+  g->br2_c.assign(hg.inst.size(), 0.0);
+  g->gap_ok.assign(hg.inst.size(), 0);
+  if ((rc = g->gap_need.alloc(hg.inst.size()))) return rc;
   for (int p = 0; p < 2; ++p) {
     std::vector<WarmSeg> segs;
     std::vector<int2> blks;
@@ -2422,28 +2432,36 @@ static int rm_update(Game* g, int p, hipStream_t s) {
   return PMX_OK;
 }
 
-static int br_values(Game* g, int p, double* gvec, hipStream_t s) {
+static TpParams tp_params_for(Game* g, int p, const int2* blocks, const int32_t* need) {
+  TpParams P = tp_params(g, p, blocks);
+  P.active = need;
+  return P;
+}
+
+// Best-response values per hand and their per-instance sums; need (device,
+// NULL: all) limits the work to the instances flagged.
+static int br_values(Game* g, int p, double* gvec, hipStream_t s, const int32_t* need) {
   DevTp& E = g->dt[p];
   if (p == 0) {
     if (E.n_single)
       hipLaunchKernelGGL((k_br<0, true>), dim3(E.n_single), dim3(TPB), 0, s,
-                         tp_params(g, p, E.b_single.p), gvec, E.stage_d.p, E.hv.p);
+                         tp_params_for(g, p, E.b_single.p, need), gvec, E.stage_d.p, E.hv.p);
     if (E.n_deep)
       hipLaunchKernelGGL((k_br<1, true>), dim3(E.n_deep), dim3(TPB), 0, s,
-                         tp_params(g, p, E.b_deep.p), gvec, E.stage_d.p, E.hv.p);
+                         tp_params_for(g, p, E.b_deep.p, need), gvec, E.stage_d.p, E.hv.p);
     if (E.n_top)
       hipLaunchKernelGGL((k_br<2, true>), dim3(E.n_top), dim3(TPB), 0, s,
-                         tp_params(g, p, E.b_top.p), gvec, E.stage_d.p, E.hv.p);
+                         tp_params_for(g, p, E.b_top.p, need), gvec, E.stage_d.p, E.hv.p);
   } else {
     if (E.n_single)
       hipLaunchKernelGGL((k_br<0, false>), dim3(E.n_single), dim3(TPB), 0, s,
-                         tp_params(g, p, E.b_single.p), gvec, E.stage_d.p, E.hv.p);
+                         tp_params_for(g, p, E.b_single.p, need), gvec, E.stage_d.p, E.hv.p);
     if (E.n_deep)
       hipLaunchKernelGGL((k_br<1, false>), dim3(E.n_deep), dim3(TPB), 0, s,
-                         tp_params(g, p, E.b_deep.p), gvec, E.stage_d.p, E.hv.p);
+                         tp_params_for(g, p, E.b_deep.p, need), gvec, E.stage_d.p, E.hv.p);
     if (E.n_top)
       hipLaunchKernelGGL((k_br<2, false>), dim3(E.n_top), dim3(TPB), 0, s,
-                         tp_params(g, p, E.b_top.p), gvec, E.stage_d.p, E.hv.p);
+                         tp_params_for(g, p, E.b_top.p, need), gvec, E.stage_d.p, E.hv.p);
   }
   const int ni = (int)g->hg.inst.size();
   hipLaunchKernelGGL(k_sum_instances, dim3(ni), dim3(256), 0, s, E.hv.p, g->inst_hand_off[p].p,
@@ -2764,6 +2782,7 @@ int solver_reset(Game* g, void* stream) {
   g->wsum = 0.0;
   g->wsum_i.assign(g->wsum_i.size(), 0.0);
   g->act_h.assign(g->act_h.size(), 1);
+  g->gap_ok.assign(g->gap_ok.size(), 0);
   // every instance is active again: the launch lists must include them all
   if (g->n_listed < (int)g->hg.inst.size()) {
     if ((rc = set_solver_lists(g, std::vector<char>(g->hg.inst.size(), 1)))) return rc;
@@ -2864,9 +2883,13 @@ int solver_step(Game* g, int32_t n_iters, void* stream) {
     w += g->gamma == 1 ? t : (g->gamma == 2 ? t * t : t * t * t);
   }
   g->wsum += w;
-  // a retired instance's averages take no weight: its total stays with them
+  // a retired instance's averages take no weight: its total stays with them,
+  // and so does its last gap
   for (size_t i = 0; i < g->wsum_i.size(); ++i)
-    if (g->act_h[i]) g->wsum_i[i] += w;
+    if (g->act_h[i] && n_iters > 0) {
+      g->wsum_i[i] += w;
+      g->gap_ok[i] = 0;
+    }
   return PMX_OK;
 }
 
@@ -2903,19 +2926,27 @@ static void inst_range(const Game* g, int p, size_t i, int64_t* b, int64_t* e) {
 // are multiplied by scale[i] (NULL: 1), which normalizes unnormalized sums
 // since a best-response value is positively homogeneous in the opponent's
 // strategy and the instances do not interact.
+//
+// need_dev (device flags, NULL: every instance) limits the work to the
+// instances flagged, whose row chunks must all be in the solver's launch
+// lists (the matvec then takes those lists); need_host is the same set on
+// the host, and only its instances are written.
 static int gap_from_sums(Game* g, const double* xsum, const double* ysum, const double* scale,
-                         double* gap, double* br1, double* br2, hipStream_t s) {
+                         const int32_t* need_dev, const int32_t* need_host, double* gap, double* br1,
+                         double* br2, hipStream_t s) {
   int rc;
   MvParams PA = mv_params(g, 0, 1.0), PT = mv_params(g, 1, 1.0);
+  PA.active = PT.active = need_dev;
   if ((rc = launch_mv<double>(g, PA, ysum, g->gd[0].p, empty_params(PA), nullptr, nullptr, s))) return rc;
   if ((rc = launch_mv<double>(g, PT, xsum, g->gd[1].p, empty_params(PT), nullptr, nullptr, s))) return rc;
-  if ((rc = br_values(g, 0, g->gd[0].p, s))) return rc;
-  if ((rc = br_values(g, 1, g->gd[1].p, s))) return rc;
+  if ((rc = br_values(g, 0, g->gd[0].p, s, need_dev))) return rc;
+  if ((rc = br_values(g, 1, g->gd[1].p, s, need_dev))) return rc;
   const int ni = (int)g->hg.inst.size();
   std::vector<double> h(2 * (size_t)ni);
   HIP_TRY(hipMemcpyAsync(h.data(), g->br_inst.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   for (int i = 0; i < ni; ++i) {
+    if (need_host && !need_host[i]) continue;
     const double c = scale ? scale[i] : 1.0;
     double a = h[i] * c, b = h[ni + i] * c;
     if (!std::isfinite(a) || !std::isfinite(b)) return fail(PMX_ENUMERIC, "non-finite best response");
@@ -2928,52 +2959,81 @@ static int gap_from_sums(Game* g, const double* xsum, const double* ysum, const 
 
 // Each instance's average is its weighted sum over its own weight total (the
 // weights of the iterations it took part in); an instance with none yet
-// stands at its current plan.
+// stands at its current plan.  An instance whose state has not changed since
+// the last call (a retired one) reuses that call's values; the others are
+// computed, on the solver's launch lists when those hold them all.
 int saddle_gap(Game* g, double* gap, double* br1, double* br2, void* stream) {
   int rc = ensure_device(g);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   const size_t ni = g->hg.inst.size();
-  std::vector<double> scale(ni);
-  bool any_sum = false, any_plan = false;
+  std::vector<int32_t> need(ni);
+  size_t n_need = 0;
+  bool unlisted = false;
   for (size_t i = 0; i < ni; ++i) {
-    const bool has = g->wsum_i[i] > 0;
-    scale[i] = has ? 1.0 / g->wsum_i[i] : 1.0;
-    any_sum |= has;
-    any_plan |= !has;
+    need[i] = g->gap_ok[i] ? 0 : 1;
+    n_need += need[i];
+    if (need[i] && !g->listed[i]) unlisted = true;
   }
-  if (!any_plan) return gap_from_sums(g, g->xs[0].p, g->xs[1].p, scale.data(), gap, br1, br2, s);
-  for (int p = 0; p < 2; ++p) {
-    const int64_t n = g->hg.elems[p];
-    if (!any_sum) {
-      if (n > 0) {
-        const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_f32_to_f64, dim3(blocks), dim3(256), 0, s, g->x[p].p, g->sd[p].p, n);
-      }
-      continue;
+  if (n_need) {
+    const bool part = n_need < ni && !unlisted;
+    if (part)
+      HIP_TRY(hipMemcpyAsync(g->gap_need.p, need.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    const int32_t* need_dev = part ? g->gap_need.p : nullptr;
+    std::vector<double> scale(ni);
+    bool any_sum = false, any_plan = false;
+    for (size_t i = 0; i < ni; ++i) {
+      const bool has = g->wsum_i[i] > 0;
+      scale[i] = has ? 1.0 / g->wsum_i[i] : 1.0;
+      any_sum |= has;
+      any_plan |= !has;
     }
-    HIP_TRY(hipMemcpyAsync(g->sd[p].p, g->xs[p].p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    // runs of instances without a weight total take their current plan
-    for (size_t i = 0; i < ni;) {
-      if (g->wsum_i[i] > 0) {
-        ++i;
-        continue;
+    const double *xa = g->xs[0].p, *ya = g->xs[1].p;
+    if (any_plan) {
+      for (int p = 0; p < 2; ++p) {
+        const int64_t n = g->hg.elems[p];
+        if (!any_sum) {
+          if (n > 0) {
+            const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+            hipLaunchKernelGGL(k_f32_to_f64, dim3(blocks), dim3(256), 0, s, g->x[p].p, g->sd[p].p, n);
+          }
+          continue;
+        }
+        HIP_TRY(hipMemcpyAsync(g->sd[p].p, g->xs[p].p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        // runs of instances without a weight total take their current plan
+        for (size_t i = 0; i < ni;) {
+          if (g->wsum_i[i] > 0) {
+            ++i;
+            continue;
+          }
+          size_t j = i;
+          while (j < ni && !(g->wsum_i[j] > 0)) ++j;
+          int64_t b, e, b2, e2;
+          inst_range(g, p, i, &b, &e);
+          inst_range(g, p, j - 1, &b2, &e2);
+          if (e2 > b) {
+            const int blocks = (int)std::min<int64_t>((e2 - b + 255) / 256, 4096);
+            hipLaunchKernelGGL(k_f32_to_f64, dim3(blocks), dim3(256), 0, s, g->x[p].p + b,
+                               g->sd[p].p + b, e2 - b);
+          }
+          i = j;
+        }
       }
-      size_t j = i;
-      while (j < ni && !(g->wsum_i[j] > 0)) ++j;
-      int64_t b, e, b2, e2;
-      inst_range(g, p, i, &b, &e);
-      inst_range(g, p, j - 1, &b2, &e2);
-      if (e2 > b) {
-        const int blocks = (int)std::min<int64_t>((e2 - b + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_f32_to_f64, dim3(blocks), dim3(256), 0, s, g->x[p].p + b, g->sd[p].p + b,
-                           e2 - b);
-      }
-      i = j;
+      HIP_TRY(hipGetLastError());
+      xa = g->sd[0].p;
+      ya = g->sd[1].p;
     }
+    if ((rc = gap_from_sums(g, xa, ya, scale.data(), need_dev, need.data(), g->gap_c.data(),
+                            g->br1_c.data(), g->br2_c.data(), s)))
+      return rc;
+    for (size_t i = 0; i < ni; ++i) g->gap_ok[i] = 1;
   }
-  HIP_TRY(hipGetLastError());
-  return gap_from_sums(g, g->sd[0].p, g->sd[1].p, scale.data(), gap, br1, br2, s);
+  for (size_t i = 0; i < ni; ++i) {
+    if (gap) gap[i] = g->gap_c[i];
+    if (br1) br1[i] = g->br1_c[i];
+    if (br2) br2[i] = g->br2_c[i];
+  }
+  return PMX_OK;
 }
 
 int saddle_gap_of(Game* g, const double* x, const double* y, double* gap, double* br1, double* br2,
@@ -2981,7 +3041,7 @@ int saddle_gap_of(Game* g, const double* x, const double* y, double* gap, double
   int rc = ensure_device(g);
   if (rc) return rc;
   if (!x || !y) return fail(PMX_EINVAL, "null vector");
-  return gap_from_sums(g, x, y, nullptr, gap, br1, br2, (hipStream_t)stream);
+  return gap_from_sums(g, x, y, nullptr, nullptr, nullptr, gap, br1, br2, (hipStream_t)stream);
 }
 
 int solver_get_state(Game* g, int32_t player, float* regret, float* plan, double* avg_sum, int32_t* t,
@@ -3013,6 +3073,7 @@ int solver_set_state(Game* g, int32_t player, const float* regret, const float* 
   g->t = t;
   g->wsum = wsum;
   g->wsum_i.assign(g->wsum_i.size(), wsum);
+  g->gap_ok.assign(g->gap_ok.size(), 0);
   const double cur = (double)t;   // the next iteration's first launch makes it t + 1
   HIP_TRY(hipMemcpy(g->tdev.p, &cur, sizeof(double), hipMemcpyHostToDevice));
   return PMX_OK;
@@ -3034,6 +3095,7 @@ int solver_set_weights(Game* g, const double* wsum_host) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(wsum_host[i]) || wsum_host[i] < 0) return fail(PMX_EINVAL, "bad weight total");
   std::copy(wsum_host, wsum_host + n, g->wsum_i.begin());
+  g->gap_ok.assign(g->gap_ok.size(), 0);
   return PMX_OK;
 }
 
@@ -3069,6 +3131,7 @@ int set_initial_strategy(Game* g, int32_t player, const float* behav, float scal
   if (player < 0 || player > 1 || !behav) return fail(PMX_EINVAL, "bad argument");
   if (!(scale >= 0) || !std::isfinite(scale)) return fail(PMX_EINVAL, "scale must be finite and >= 0");
   hipStream_t s = (hipStream_t)stream;
+  g->gap_ok.assign(g->gap_ok.size(), 0);
   DevTp& E = g->dt[player];
   if (E.n_single)
     hipLaunchKernelGGL(k_warm, dim3(E.n_single), dim3(TPB), 0, s, tp_params(g, player, E.b_single.p),
@@ -3151,6 +3214,7 @@ int warm_apply(Game* g, const float* logits0_dev, const float* logits1_dev, int3
   g->t = 0;
   g->wsum = avg_weight;
   g->wsum_i.assign(g->wsum_i.size(), avg_weight);
+  g->gap_ok.assign(g->gap_ok.size(), 0);
   return PMX_OK;
 }
 

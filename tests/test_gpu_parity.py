@@ -699,6 +699,54 @@ def test_retired_average_keeps_its_own_weight():
     g.close()
 
 
+def test_gap_recomputes_only_changed_instances():
+    """Gaps of retired instances are reused; the instances computed alone, on
+    the solver's lists with and without retired instances, agree with a full
+    recomputation."""
+    pmx = _need_gpu()
+    descs = _retire_descs(4)
+    _say("partial gap")
+    g = pmx.Game(descs)
+    tol = 1e-12 * 2 * max(d.contrib for d in descs)
+
+    def full():
+        g.solver_set_weights(g.solver_get_weights())   # drops every kept value
+        return g.saddle_gap()
+
+    g.solver_step(16)
+    g.saddle_gap()
+    g.solver_set_active([1, 0, 1, 1])                  # lists keep the retired instance
+    g.solver_step(16)
+    part = g.saddle_gap()
+    ref = full()
+    for a, b in zip(part, ref):
+        assert np.allclose(a, b, rtol=0, atol=tol)
+    g.solver_set_active([0, 0, 1, 0])                  # lists rebuilt without three
+    g.solver_step(16)
+    part = g.saddle_gap()
+    ref = full()
+    for a, b in zip(part, ref):
+        assert np.allclose(a, b, rtol=0, atol=tol)
+    for i, d in enumerate(descs):
+        o = payoff.Game(d)
+        avg = [g.unpack(p, g.get_average_strategy(p))[i] for p in range(2)]
+        rgap, _, _ = solver.saddle_gap(o, avg[0], avg[1])
+        assert abs(part[0][i] - rgap) <= 1e-9 * 2 * d.contrib, (i, part[0][i], rgap)
+    # a state import drops the kept values of retired instances too
+    st = [g.solver_get_state(p) for p in range(2)]
+    w = g.solver_get_weights()
+    g.solver_reset()
+    g.solver_step(4)
+    g.solver_set_active([0, 0, 1, 0])
+    other = g.saddle_gap()[0]
+    assert not np.allclose(other, ref[0], rtol=0, atol=tol)
+    for p in range(2):
+        g.solver_set_state(p, st[p]["regret"], st[p]["plan"], st[p]["avg_sum"], st[p]["t"], st[p]["wsum"])
+    g.solver_set_weights(w)
+    assert np.allclose(g.saddle_gap()[0], ref[0], rtol=0, atol=tol)
+    g.close()
+
+
 def test_instance_retired_before_any_iteration_keeps_its_plan():
     pmx = _need_gpu()
     descs = _retire_descs(3)
