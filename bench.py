@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 # known size (profiles/matvec_pair_traffic_counters.md).  They describe the
 # kernel sources whose code (comments and whitespace removed) has the SHA-1
 # recorded here and are reported as null for any other version of that code.
-TRAFFIC = {"sources_sha1": "4cc05a4259807f5d0ab90872cfa9736321ba2b6c", "river": 1630244, "batch": 449609579}
+TRAFFIC = {"sources_sha1": "a5a7042461077e7be5be6559e39d2750cc55c2be", "river": 1637386, "batch": 449587515}
 TRAFFIC_SOURCES = ("paper_2112_03804_amd/csrc/pmx_device.hip", "paper_2112_03804_amd/csrc/host_build.cpp")
 
 
