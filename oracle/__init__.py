@@ -20,6 +20,10 @@ Techniques for Structured Extensive-Form Games", AAAI 2022):
                   saddle-point gap in FP64, and the sequence-form LP (eq. lp).
 * ``play``      - expected payoff by playing out every deal on the game tree
                   (independent of A), used to pin A.
+* ``mlp``       - the warm-start network in FP64 with its backward pass.
+* ``sparsify``  - Technique B's explicit factors A = Ahat + U M^-1 V^T of a
+                  river endgame (Section 4), its postprocessing, and the
+                  size metric of Table 1.
 
 It shares no code with the GPU library; both consume the same seeded
 instances from ``paper_2112_03804_amd.instances`` (inputs only).
