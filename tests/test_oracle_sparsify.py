@@ -104,3 +104,26 @@ def test_sparsification_is_smaller_on_a_mid_size_river():
     after = sparsify.size(Ahat, U2, M2, V2)
     print(f"nnz(A) {nA}, Technique B {before}, postprocessed {after} ({nA / after:.1f}x smaller)")
     assert after <= before < nA
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_postprocessing_on_random_triangular_systems(seed):
+    """Substitution with general coefficients and runs of consecutive zero
+    columns of V: U M^-1 V^T is unchanged (dense solve on both sides)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    n, r, c = 12, 7, 5
+    M = np.eye(n)
+    for j in range(1, n):
+        for i in rng.choice(j, size=min(j, 2), replace=False):
+            M[j, i] = rng.normal()
+    U = rng.normal(size=(r, n)) * (rng.random((r, n)) < 0.6)
+    V = rng.normal(size=(c, n))
+    zero = rng.random(n) < 0.45
+    zero[[3, 4, 5]] = True                     # a run of three
+    V[:, zero] = 0.0
+    ref = U @ np.linalg.solve(M, V.T)
+    U2, M2, V2 = sparsify.postprocess(sp.csc_matrix(U), sp.csr_matrix(M), sp.csc_matrix(V))
+    assert M2.shape[0] == n - zero.sum()
+    got = U2.toarray() @ np.linalg.solve(M2.toarray(), V2.toarray().T)
+    assert np.abs(got - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
