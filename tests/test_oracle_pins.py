@@ -341,3 +341,130 @@ def test_dcfr_single_update_closed_form():
     R[f, 0], R[f + 1, 0] = 2.0, -2.0
     Rn = tp.dcfr_update(R, gvec, 1.0, 1.5, 0.0)
     assert Rn[f, 0] == 1.0 and Rn[f + 1, 0] == 1.0
+
+
+# ---------------------------------------------------------------------------
+# Tolerance scales: |A| |y|, row and column sums of |A|
+# ---------------------------------------------------------------------------
+
+ABS_GAMES = [
+    ("tiny", I.tiny_config),
+    ("river_pruned", lambda: I.small_river(5, deck_size=11, n_keep=(20, 13))),
+    ("turn2card", lambda: I.small_turn_river(1, deck_size=9, n_board=3, cards_per_hand=2,
+                                             bet_fracs=(0.5,), max_raises=0, stack=8.0)),
+]
+
+
+@pytest.mark.parametrize("name,desc_fn", ABS_GAMES)
+def test_abs_scales_equal_dense_abs_products(name, desc_fn):
+    """Every parity tolerance is scaled by |A| |v| or a row / column sum of
+    |A|.  The matrix-free forms must equal the same products taken on the
+    dense A (which deal enumeration pins); an inflated scale would loosen
+    every bound silently."""
+    g = payoff.Game(desc_fn())
+    A = np.abs(g.dense_A())
+    S1, S2 = g.S
+    N1, N2 = g.N
+    rng = np.random.default_rng(7)
+    y = rng.standard_normal((S2, N2))
+    x = rng.standard_normal((S1, N1))
+    ref_y = (A @ np.abs(y).ravel()).reshape(S1, N1)
+    ref_x = (A.T @ np.abs(x).ravel()).reshape(S2, N2)
+    tol = 1e-13 * max(1.0, float(A.max()))
+    assert np.allclose(payoff.abs_matvec_A(g, y), ref_y, atol=tol, rtol=1e-13)
+    assert np.allclose(payoff.abs_matvec_AT(g, x), ref_x, atol=tol, rtol=1e-13)
+    assert np.allclose(g.abs_row_sums().ravel(), A.sum(axis=1), atol=tol, rtol=1e-13)
+    assert np.allclose(g.abs_col_sums().ravel(), A.sum(axis=0), atol=tol, rtol=1e-13)
+    for _ in range(12):
+        s, h = int(rng.integers(S1)), int(rng.integers(N1))
+        assert abs(payoff.abs_entry_A(g, y, s, h) - ref_y[s, h]) <= tol + 1e-13 * ref_y[s, h]
+        s, h = int(rng.integers(S2)), int(rng.integers(N2))
+        assert abs(payoff.abs_entry_AT(g, x, s, h) - ref_x[s, h]) <= tol + 1e-13 * ref_x[s, h]
+
+
+def test_kuhn_abs_row_and_column_sums_by_hand():
+    """Kuhn poker (antes 1, a bet of 1, no raise): each card has two
+    compatible opponent cards of deal probability 1/6.  Row sums of |A| per
+    Player 1 sequence: check -> showdown for 1 (2/6); bet -> fold for 1 plus
+    showdown for 2 (2/6 + 4/6 = 1); check-bet-fold -> 1 (1/3); check-bet-call
+    -> 2 (2/3).  Column sums per Player 2 sequence: after a check, check (1/3)
+    and bet (1/3 + 2/3); after a bet, fold (1/3) and call (2/3)."""
+    g = payoff.Game(I.kuhn())
+    rows = g.abs_row_sums()
+    cols = g.abs_col_sums()
+    tp1 = solver.Treeplex(g, 0)
+    root = tp1.inf[tp1.roots[0]]
+    lab1 = {}
+    for i, I1 in enumerate(g.sf.infosets[0]):
+        for a, lab in enumerate(I1.labels):
+            lab1[I1.first_seq + a] = ("root" if I1.parent_seq < 0 else "after", lab)
+    want1 = {("root", "check"): 1 / 3, ("root", "bet"): 1.0, ("after", "fold"): 1 / 3,
+             ("after", "call"): 2 / 3}
+    assert root[2] == 2
+    for s, key in lab1.items():
+        assert np.allclose(rows[s], want1[key], atol=1e-15), key
+    want2 = {"check": 1 / 3, "bet": 1.0, "fold": 1 / 3, "call": 2 / 3}
+    for I2 in g.sf.infosets[1]:
+        for a, lab in enumerate(I2.labels):
+            assert np.allclose(cols[I2.first_seq + a], want2[lab], atol=1e-15), lab
+    assert abs(rows.max() - 1.0) < 1e-15 and abs(cols.max() - 1.0) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# A two-round skeleton (turn, chance node, river) derived by hand
+# ---------------------------------------------------------------------------
+
+def _walk_leaves(node, path, out):
+    """(path, kind, c1, c2, runout) of every leaf, depth first; a chance node
+    adds "/" to the path and continues into its river round."""
+    if node.kind == "leaf":
+        out.append((",".join(path), node.term_kind, node.runout, node.c[0], node.c[1]))
+        return
+    if node.kind == "chance":
+        assert len(node.children) == 1
+        _walk_leaves(node.children[0], path + ["/"], out)
+        return
+    for lab, ch in zip(node.labels, node.children):
+        _walk_leaves(ch, path + [lab], out)
+
+
+def test_two_round_skeleton_matches_hand_derivation(golden_dir):
+    kinds = {"fold1": (sk.FOLD1, False), "fold2": (sk.FOLD2, False), "sd": (sk.SHOWDOWN, False),
+             "ro": (sk.SHOWDOWN, True)}
+    want = []
+    with open(os.path.join(golden_dir, "two_round_leaves.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            path, kind, c1, c2 = line.split()
+            k, ro = kinds[kind]
+            want.append((path, k, ro, float(c1), float(c2)))
+    root = sk.build_tree(1.0, (4.0, 4.0), [0.5], 0, True, two_rounds=True)
+    got = []
+    _walk_leaves(root, [], got)
+    assert len(got) == len(want) == 49
+    for g_, w_ in zip(got, want):
+        assert g_ == w_, (g_, w_)
+    # the sequence form expands each chance node once per river card: the 10
+    # turn leaves stay, the 3 river rounds of 13 leaves repeat per card
+    sf = sk.sequence_form(root, n_rivers=2)
+    assert len(sf.terminals) == 10 + 3 * 13 * 2
+    first = [t for t in sf.terminals if t.board < 0]
+    assert len(first) == 10
+    assert sum(t.runout for t in first) == 4 and not any(t.runout for t in sf.terminals if t.board >= 0)
+    for r in range(2):
+        assert sum(t.board == r for t in sf.terminals) == 39
+    # the river rounds under different cards share sizes but not sequences
+    r0 = sorted((t.seq1, t.seq2) for t in sf.terminals if t.board == 0)
+    r1 = sorted((t.seq1, t.seq2) for t in sf.terminals if t.board == 1)
+    assert not set(r0) & set(r1)
+
+
+def test_tiny_game_value_is_minus_one_thirteenth():
+    """The 13-card game (antes 1, one pot-sized bet, at most one raise, no
+    all-in): both players' LPs give Player 1 the value -1/13."""
+    g = payoff.Game(I.tiny_config())
+    v1, _ = solver.lp_value(g, player=0)
+    v2, _ = solver.lp_value(g, player=1)
+    assert abs(v1 - (-1.0 / 13.0)) < 1e-9
+    assert abs(v2 - (1.0 / 13.0)) < 1e-9
