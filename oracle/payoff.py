@@ -183,36 +183,46 @@ class Game:
                                       self.sf.terminals[i].kind == sk.SHOWDOWN))
         return [self.sf.terminals[i] for i in order]
 
+    def _groups(self):
+        """Terminals grouped by their hand matrix up to the payoff factor:
+        (board, run-out, showdown or fold) -> (base Q with u1 = 1, terminals).
+        Bases are built one group at a time (a turn + river game has 100 of
+        them, 10 MB each)."""
+        groups = {}
+        for t in self._by_board():
+            groups.setdefault((t.board, t.runout, t.kind == sk.SHOWDOWN), []).append(t)
+        for key, ts in groups.items():
+            t0 = ts[0]
+            base = self.hm.q_matrix(sk.Terminal(0, 0, t0.kind if t0.kind == sk.SHOWDOWN else sk.FOLD2,
+                                                1.0, 1.0, t0.board, t0.runout))
+            yield base, ts
+
+    @staticmethod
+    def _coef(t):
+        return t.c1 if t.kind == sk.SHOWDOWN else t.u1
+
     def matvec_A(self, y):
-        """A y for y of shape (S2, N2): sum over terminals of Q_z y[sigma2(z)]."""
+        """A y for y of shape (S2, N2): sum over terminals of Q_z y[sigma2(z)].
+        Terminals sharing a base matrix are taken together: one product of
+        the base with their stacked input rows, each scaled by its payoff."""
         y = np.asarray(y, dtype=np.float64)
         out = np.zeros((self.S[0], self.N[0]))
-        cache = {}
-        for t in self._by_board():
-            key = (t.board, t.runout, t.kind == sk.SHOWDOWN)
-            if key not in cache:
-                cache.clear()
-                base = self.hm.q_matrix(sk.Terminal(0, 0, t.kind if t.kind == sk.SHOWDOWN else sk.FOLD2,
-                                                    1.0, 1.0, t.board, t.runout))
-                cache[key] = base
-            coef = t.c1 if t.kind == sk.SHOWDOWN else t.u1
-            out[t.seq1] += coef * (cache[key] @ y[t.seq2])
+        for base, ts in self._groups():
+            s1 = np.array([t.seq1 for t in ts])
+            s2 = np.array([t.seq2 for t in ts])
+            coef = np.array([self._coef(t) for t in ts])
+            np.add.at(out, s1, coef[:, None] * (y[s2] @ base.T))
         return out
 
     def matvec_AT(self, x):
         """A^T x for x of shape (S1, N1)."""
         x = np.asarray(x, dtype=np.float64)
         out = np.zeros((self.S[1], self.N[1]))
-        cache = {}
-        for t in self._by_board():
-            key = (t.board, t.runout, t.kind == sk.SHOWDOWN)
-            if key not in cache:
-                cache.clear()
-                base = self.hm.q_matrix(sk.Terminal(0, 0, t.kind if t.kind == sk.SHOWDOWN else sk.FOLD2,
-                                                    1.0, 1.0, t.board, t.runout))
-                cache[key] = base
-            coef = t.c1 if t.kind == sk.SHOWDOWN else t.u1
-            out[t.seq2] += coef * (cache[key].T @ x[t.seq1])
+        for base, ts in self._groups():
+            s1 = np.array([t.seq1 for t in ts])
+            s2 = np.array([t.seq2 for t in ts])
+            coef = np.array([self._coef(t) for t in ts])
+            np.add.at(out, s2, coef[:, None] * (x[s1] @ base))
         return out
 
     def entry_A(self, y, s1, h1):
@@ -232,18 +242,21 @@ class Game:
         return acc
 
     def abs_row_sums(self):
-        """max_row sum |A| (the infinity norm), matrix-free."""
-        S1, N1 = self.S[0], self.N[0]
-        acc = np.zeros((S1, N1))
-        for t in self.sf.terminals:
-            acc[t.seq1] += np.abs(self.hm.q_matrix(t)).sum(axis=1)
+        """Row sums of |A| (their max is the infinity norm), matrix-free:
+        |Q_z| = |u1(z)| |base| within a group of terminals."""
+        acc = np.zeros((self.S[0], self.N[0]))
+        for base, ts in self._groups():
+            rs = np.abs(base).sum(axis=1)
+            for t in ts:
+                acc[t.seq1] += abs(self._coef(t)) * rs
         return acc
 
     def abs_col_sums(self):
-        S2, N2 = self.S[1], self.N[1]
-        acc = np.zeros((S2, N2))
-        for t in self.sf.terminals:
-            acc[t.seq2] += np.abs(self.hm.q_matrix(t)).sum(axis=0)
+        acc = np.zeros((self.S[1], self.N[1]))
+        for base, ts in self._groups():
+            cs = np.abs(base).sum(axis=0)
+            for t in ts:
+                acc[t.seq2] += abs(self._coef(t)) * cs
         return acc
 
 
@@ -266,14 +279,22 @@ def abs_entry_AT(game: Game, x, s2, h2):
 
 def abs_matvec_A(game: Game, y):
     """|A| |y| for every entry (matrix-free)."""
+    ay = np.abs(np.asarray(y, dtype=np.float64))
     out = np.zeros((game.S[0], game.N[0]))
-    for t in game.sf.terminals:
-        out[t.seq1] += np.abs(game.hm.q_matrix(t)) @ np.abs(y[t.seq2])
+    for base, ts in game._groups():
+        s1 = np.array([t.seq1 for t in ts])
+        s2 = np.array([t.seq2 for t in ts])
+        coef = np.abs(np.array([game._coef(t) for t in ts]))
+        np.add.at(out, s1, coef[:, None] * (ay[s2] @ np.abs(base).T))
     return out
 
 
 def abs_matvec_AT(game: Game, x):
+    ax = np.abs(np.asarray(x, dtype=np.float64))
     out = np.zeros((game.S[1], game.N[1]))
-    for t in game.sf.terminals:
-        out[t.seq2] += np.abs(game.hm.q_matrix(t)).T @ np.abs(x[t.seq1])
+    for base, ts in game._groups():
+        s1 = np.array([t.seq1 for t in ts])
+        s2 = np.array([t.seq2 for t in ts])
+        coef = np.abs(np.array([game._coef(t) for t in ts]))
+        np.add.at(out, s2, coef[:, None] * (ax[s1] @ np.abs(base)))
     return out
