@@ -1,13 +1,16 @@
 """Benchmark: matvec pairs/s and time to gap 1e-4 * pot on one MI355X.
 
-A step is one alternating RM+ iteration of the whole hot path on the river
-endgame (52-card deck, 5-card board, 1081 hands per player, bets
-{0.5, 1, 2} x pot + all-in, 3 raises): the structured product A y, Player 1's
-treeplex update, A^T x, Player 2's update.  Each step performs exactly one
-matvec pair, so `value` (pairs/s) is whole-job iterations per second with all
+A step is one alternating RM+ iteration of the whole hot path over the batch
+of 512 uneven river endgames (hands U[200, 1081] per player, 1-3 bet sizes,
+raise caps 2-4, pots U[20, 400], stack/pot U[1, 10]), all in one game: the
+structured products A y of every instance, Player 1's treeplex updates,
+A^T x, Player 2's updates.  Each step performs one matvec pair per instance,
+so `value` (instance matvec pairs/s) is 512 x steps per second with all
 inputs resident in HBM.  Extra fields report the isolated matvec-pair kernel
-(its roofline), the time to a saddle gap of 1e-4 * pot from a uniform start,
-and the CPU oracle timed on this host.
+on the batch (its roofline), the batch's time to a saddle gap of
+1e-4 * pot against the plain single-instance solver run on every one of the
+512 instances, the learned warm start, the single river endgame, the
+turn + river precision run, and the CPU oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -83,12 +86,19 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(desc, budget_s=15.0, gpu_iters=None):
-    """The oracle's FP64 matvec pair (A y and A^T x from the definition),
-    timed on this host for about budget_s seconds with its thread pool, and
-    for a few seconds on one thread; the oracle's RM+ solve of the 13-card
-    game to 1e-6 * pot; and the oracle's river time to 1e-4 * pot
-    extrapolated from its pair rate and the GPU solver's iteration count."""
+def cpu_baseline(args, river_desc, batch_descs, gpu_iters=None, precision=None):
+    """The oracle on this host's cores (a reported baseline, not the target):
+
+    * its FP64 matvec pairs (A y and A^T x from the definition, summed over
+      terminals and hand pairs) on an even sample of the batch's instances,
+      each timed in turn for about --cpu-budget seconds in all: instance
+      pairs per second on that sample, the headline's unit;
+    * the same on the single river endgame, with its thread pool and on one
+      thread, and the oracle's river time to 1e-4 * pot extrapolated from
+      that rate and the GPU solver's iteration count;
+    * the 13-card game solved by the oracle's FP64 RM+ to 1e-6 * pot;
+    * the oracle's FP64 saddle gap of the turn + river precision run's
+      averages, beside the GPU's (the error the precision run reports)."""
     from oracle import payoff
     from oracle import solver as osolver
     from paper_2112_03804_amd import instances as I
@@ -98,8 +108,33 @@ def cpu_baseline(desc, budget_s=15.0, gpu_iters=None):
     except Exception:
         threadpool_limits = None
         threads = 1
-    o = payoff.Game(desc)
+    budget_s = args.cpu_budget
     rng = np.random.default_rng(0)
+
+    # batch sample: one pair per sampled instance, round robin, until the budget
+    step = max(1, len(batch_descs) // args.cpu_batch_sample)
+    idx = list(range(0, len(batch_descs), step))[:args.cpu_batch_sample]
+    games = []
+    for i in idx:
+        o = payoff.Game(batch_descs[i])
+        games.append((o, rng.random((o.S[1], o.N[1])), rng.random((o.S[0], o.N[0]))))
+    n_pairs, t_used = 0, 0.0
+    t0 = time.perf_counter()
+    while n_pairs == 0 or time.perf_counter() - t0 < budget_s:
+        for o, y, x in games:
+            o.matvec_A(y)
+            o.matvec_AT(x)
+            n_pairs += 1
+    t_used = time.perf_counter() - t0
+    out = {"value": n_pairs / t_used, "unit": "instance matvec pairs/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{len(idx)} of the batch's {len(batch_descs)} instances (one in {step}), "
+                     f"{n_pairs // len(idx)} FP64 matvec pairs each (definition-level sums over terminals x "
+                     f"hand pairs), {t_used:.1f} s",
+           "host": {"nproc": os.cpu_count(), "model": _cpu_model()}}
+    del games
+
+    # the single river endgame
+    o = payoff.Game(river_desc)
     y = rng.random((o.S[1], o.N[1]))
     x = rng.random((o.S[0], o.N[0]))
     o.matvec_A(y)
@@ -111,54 +146,63 @@ def cpu_baseline(desc, budget_s=15.0, gpu_iters=None):
             o.matvec_A(y)
             o.matvec_AT(x)
             n += 1
-        dt = time.perf_counter() - t0
-        return n, dt
+        return n, time.perf_counter() - t0
 
-    n, dt = rate(budget_s)
-    out = {"value": n / dt, "unit": "matvec pairs/s", "cores": int(threads), "kind": "oracle",
-           "sample": f"{n} FP64 matvec pairs of the river endgame (definition-level sum over "
-                     f"61 terminals x 1081 x 1081 hand pairs), {dt:.1f} s",
-           "host": {"nproc": os.cpu_count(), "model": _cpu_model()}}
+    n, dt = rate(max(2.0, budget_s / 3))
+    river = {"value": n / dt, "unit": "matvec pairs/s", "cores": int(threads),
+             "sample": f"{n} FP64 matvec pairs of the river endgame, {dt:.1f} s"}
     if threadpool_limits is not None:
         with threadpool_limits(limits=1):
-            n1, dt1 = rate(max(2.0, budget_s / 4))
-        out["single_thread"] = {"value": n1 / dt1, "unit": "matvec pairs/s",
-                                "sample": f"{n1} pairs, {dt1:.1f} s"}
-    # the 13-card game solved by the oracle's plain FP64 RM+ (gap every 100
-    # iterations, stopped after 10 s)
-    tiny = I.config(0)
-    ot = payoff.Game(tiny)
-    pot = 2 * tiny.contrib
-    sol = osolver.RMPlus(ot)
-    t0 = time.perf_counter()
-    it, gap = 0, float("inf")
-    while it < 200000 and time.perf_counter() - t0 < 10.0:
-        for _ in range(100):
-            sol.step()
-        it += 100
-        gap = float(sol.gap()[0])
-        if gap <= 1e-6 * pot:
-            break
-    out["tiny_time_to_gap"] = {"target": "1e-6*pot", "seconds": time.perf_counter() - t0, "iterations": it,
-                               "gap_over_pot": gap / pot, "reached": gap <= 1e-6 * pot}
+            n1, dt1 = rate(max(2.0, budget_s / 6))
+        river["single_thread"] = {"value": n1 / dt1, "unit": "matvec pairs/s", "sample": f"{n1} pairs, {dt1:.1f} s"}
     if gpu_iters:
-        out["river_time_to_gap_extrapolated"] = {
+        river["time_to_gap_extrapolated"] = {
             "target": "1e-4*pot", "iterations": gpu_iters, "seconds": gpu_iters / (n / dt),
             "note": "the GPU solver's RM+ iteration count times the oracle's time per matvec pair "
                     "(regret updates and gap checks not counted)"}
+    out["river"] = river
+    # the 13-card game solved by the oracle's plain FP64 RM+ (gap every 100
+    # iterations, stopped after 10 s)
+    if not args.no_tiny:
+        tiny = I.config(0)
+        ot = payoff.Game(tiny)
+        pot = 2 * tiny.contrib
+        sol = osolver.RMPlus(ot)
+        t0 = time.perf_counter()
+        it, gap = 0, float("inf")
+        while it < 200000 and time.perf_counter() - t0 < 10.0:
+            for _ in range(100):
+                sol.step()
+            it += 100
+            gap = float(sol.gap()[0])
+            if gap <= 1e-6 * pot:
+                break
+        out["tiny_time_to_gap"] = {"target": "1e-6*pot", "seconds": time.perf_counter() - t0, "iterations": it,
+                                   "gap_over_pot": gap / pot, "reached": gap <= 1e-6 * pot}
+    # the oracle's gap of the precision run's averages
+    if precision is not None:
+        xa, ya = precision["averages"]
+        od = payoff.Game(I.config(2))
+        t0 = time.perf_counter()
+        rgap, rb1, rb2 = osolver.saddle_gap(od, xa, ya)
+        pot = 2 * od.desc.contrib
+        out["precision_run_oracle_gap"] = {"gap_over_pot": rgap / pot, "br1": rb1, "br2": rb2,
+                                           "seconds": time.perf_counter() - t0}
     return out
 
 
 def batched_leg(args, stream):
-    """Configuration of 512 uneven river endgames in one game: matvec-pair
-    throughput and roofline over the batch, batched time to 1e-4 * pot for
-    every instance, and the plain single-instance solver on a sample of the
-    same instances for comparison."""
+    """The headline workload: 512 uneven river endgames in one game.  The
+    timed steps (whole solver iterations over the batch), the matvec-pair
+    kernel's roofline over the batch, the batched time to 1e-4 * pot for
+    every instance, and the plain single-instance solver on every instance
+    of the same batch (or on an even sample of --plain-sample of them)."""
     import torch
+    from paper_2112_03804_amd import autotune
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
+    from paper_2112_03804_amd import warmstart as ws
 
-    from paper_2112_03804_amd import autotune
     descs = I.batched_configs(args.batch)
     t_create = time.perf_counter()
     g = pmx.Game(descs)
@@ -166,18 +210,19 @@ def batched_leg(args, stream):
     L = g.layouts
     default_sched = g.game_get_tuning()
     sched, sched_us = autotune.tune(g, use_cache=False)
+    log(f"batch: {len(descs)} instances, schedule {sched}; {args.warmup} warm-up and {args.steps} timed steps")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    # solver iterations over the whole batch
+    # ---- the timed steps: whole solver iterations over the batch ----------
     g.solver_reset()
-    g.solver_step(64)
+    g.solver_step(args.warmup)
     torch.cuda.synchronize()
-    K = args.batch_steps
     e0.record(stream)
-    g.solver_step(K)
+    g.solver_step(args.steps)
     e1.record(stream)
     torch.cuda.synchronize()
-    it_ms = e0.elapsed_time(e1) / K
-    # the matvec pair alone
+    ms = e0.elapsed_time(e1)
+    it_ms = ms / args.steps
+    # ---- the matvec pair alone (roofline) --------------------------------
     rng = np.random.default_rng(2)
     y = torch.from_numpy(rng.random(g.elems[1]).astype(np.float32)).cuda()
     x = torch.from_numpy(rng.random(g.elems[0]).astype(np.float32)).cuda()
@@ -195,10 +240,10 @@ def batched_leg(args, stream):
     pair_us = e0.elapsed_time(e1) * 1e3 / reps
     bytes_pair = algorithmic_bytes_pair(L)
     achieved = bytes_pair / (pair_us * 1e-6) / 1e9
-    # batched time to gap: every instance at or below 1e-4 of its pot; solved
-    # instances are retired from the iteration
-    from paper_2112_03804_amd import warmstart as ws
-    log(f"batch: matvec pair {pair_us:.1f} us; solving to 1e-4 * pot")
+    del y, x, Ay, ATx
+    # ---- batched time to gap: every instance at or below 1e-4 of its pot;
+    # solved instances are retired from the iteration
+    log(f"batch: {it_ms:.3f} ms per step, matvec pair {pair_us:.1f} us; solving to 1e-4 * pot")
     g.solver_reset()
     ttg_batched, iters, done_at = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters)
     log(f"batch: time to gap {ttg_batched:.2f} s ({iters} iterations); without retirement")
@@ -212,11 +257,12 @@ def batched_leg(args, stream):
     ttg_dcfr, iters_dcfr, _ = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters)
     g.solver_set_params("rm+")
     g.close()
-    log(f"batch: DCFR {ttg_dcfr:.2f} s; plain single-instance sample")
-    # plain single-instance solver on a sample of the same instances
-    sample = list(range(0, len(descs), max(1, len(descs) // args.plain_sample)))[:args.plain_sample]
+    # ---- the plain single-instance solver on the same instances -----------
+    n_plain = len(descs) if args.plain_sample <= 0 else min(args.plain_sample, len(descs))
+    sample = list(range(0, len(descs), max(1, len(descs) // n_plain)))[:n_plain]
+    log(f"batch: DCFR {ttg_dcfr:.2f} s; plain single-instance solver on {len(sample)} instances")
     plain_s, plain_it = [], []
-    for i in sample:
+    for k, i in enumerate(sample):
         gi = pmx.Game(descs[i])
         pot = 2 * descs[i].contrib
         torch.cuda.synchronize()
@@ -230,7 +276,9 @@ def batched_leg(args, stream):
         plain_s.append(time.perf_counter() - t0)
         plain_it.append(it)
         gi.close()
-    plain_total_est = float(np.mean(plain_s)) * len(descs)
+        if (k + 1) % 64 == 0:
+            log(f"batch: plain solver, {k + 1}/{len(sample)} instances, {sum(plain_s):.1f} s")
+    plain_total = float(np.sum(plain_s)) * (len(descs) / len(sample))
     big = None
     if args.batch_big > 0:
         # a batch four times larger than the Infinity Cache holds: the same
@@ -258,12 +306,21 @@ def batched_leg(args, stream):
                "frac": big_gbs / HBM_PEAK_GBS}
         gb.close()
         del yb, xb, Ayb, ATxb
+    n_seq = [[l[p]["n_seq"] for l in L] for p in range(2)]
+    n_hands = [[l[p]["n_hands"] for l in L] for p in range(2)]
     return {
-        "workload": f"{len(descs)} river endgames, hands U[200,1081] per player, 1-3 bet sizes, "
-                    "raise caps 2-4, pots U[20,400], stack/pot U[1,10]",
+        "workload": f"{len(descs)} river endgames in one game: hands U[200,1081] per player, 1-3 bet "
+                    "sizes from {0.33,0.5,0.75,1,1.5,2}xpot + all-in, raise caps 2-4, pots U[20,400], "
+                    "stack/pot U[1,10]",
+        "instances": len(descs),
+        "sizes": {"sequences_per_player_mean": [float(np.mean(s)) for s in n_seq],
+                  "hands_per_player_mean": [float(np.mean(h)) for h in n_hands],
+                  "entries_per_vector_total": [int(sum(a * b for a, b in zip(n_seq[p], n_hands[p])))
+                                               for p in range(2)]},
         "game_create_s": t_create,
         "schedule": {"default": list(default_sched), "tuned": list(sched),
                      "us_per_pair_by_schedule": sched_us},
+        "steps": args.steps, "warmup": args.warmup, "ms": ms,
         "iteration_ms": it_ms,
         "matvec_pairs_per_s": len(descs) / (it_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -278,10 +335,15 @@ def batched_leg(args, stream):
         "instances_reached": int((done_at >= 0).sum()),
         "iterations_per_instance_p50_p90_max": [float(np.percentile(done_at[done_at > 0], q))
                                                 for q in (50, 90, 100)] if (done_at > 0).any() else None,
-        "plain_single_instance_sample": {"instances": len(sample), "mean_s": float(np.mean(plain_s)),
-                                         "mean_iterations": float(np.mean(plain_it)),
-                                         "sum_over_batch_extrapolated_s": plain_total_est},
-        "speedup_batched_vs_plain": plain_total_est / ttg_batched,
+        "plain_single_instance": {"instances": len(sample), "of": len(descs),
+                                  "sum_s": float(np.sum(plain_s)), "mean_s": float(np.mean(plain_s)),
+                                  "mean_iterations": float(np.mean(plain_it)),
+                                  "sum_over_batch_s": plain_total,
+                                  "extrapolated": len(sample) < len(descs),
+                                  "solver": "plain RM+ on one instance, uniform start, FP64 gap every 32 "
+                                            "iterations"},
+        "speedup_batched_vs_plain": plain_total / ttg_batched,
+        "speedup_batched_dcfr_vs_plain": plain_total / ttg_dcfr,
         "matvec_pair_beyond_infinity_cache": big,
     }
 
@@ -356,6 +418,8 @@ def turn_river_leg(args, stream):
                              "target_gap_over_pot": 1e-8, "reached": reached,
                              "iterations": it, "seconds": traj[-1][1], "gap_over_pot": traj[-1][2],
                              "trajectory_iters_s_gap": traj, "budget_s": args.turn_budget}}
+    # the run's FP64 averages, for the oracle's gap on the host
+    out["_averages"] = (g.unpack(0, g.get_average_strategy(0))[0], g.unpack(1, g.get_average_strategy(1))[0])
     g.close()
     return out
 
@@ -407,7 +471,7 @@ def warm_leg(args, stream, batched):
     t_warm_d = time.perf_counter() - t3
     g.solver_set_params("rm+")
     g.close()
-    plain_total = batched["plain_single_instance_sample"]["sum_over_batch_extrapolated_s"]
+    plain_total = batched["plain_single_instance"]["sum_over_batch_s"]
     return {"train_instances": len(train_descs),
             "labels": f"average strategies of the plain batched RM+ solver run to {args.warm_label_gap:g} * pot "
                       f"(at most {args.warm_label_iters} iterations)",
@@ -483,20 +547,111 @@ def trace_probe(args):
         g.close()
 
 
+def river_leg(args, stream):
+    """The single river endgame (52-card deck, 5-card board, 1081 hands per
+    player, bets {0.5, 1, 2} x pot + all-in, 3 raises): solver iterations per
+    second, the matvec-pair launch (0.86 MB, cache-resident and latency
+    bound), time to 1e-4 * pot (RM+ and DCFR) and the 13-card game to
+    1e-6 * pot."""
+    import torch
+    from paper_2112_03804_amd import instances as I
+    from paper_2112_03804_amd import pmx
+
+    desc = I.config(1)
+    pot = 2 * desc.contrib
+    t_create = time.perf_counter()
+    g = pmx.Game(desc)
+    t_create = time.perf_counter() - t_create
+    steps, warmup = 2000, 100
+    g.solver_reset()
+    g.solver_step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.solver_step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    rng = np.random.default_rng(1)
+    L = [g.layouts[0]]
+    y = torch.from_numpy(rng.random(g.elems[1]).astype(np.float32)).cuda()
+    x = torch.from_numpy(rng.random(g.elems[0]).astype(np.float32)).cuda()
+    Ay = torch.empty(g.elems[0], dtype=torch.float32, device="cuda")
+    ATx = torch.empty(g.elems[1], dtype=torch.float32, device="cuda")
+    for _ in range(50):
+        g.matvec_pair(y, x, Ay, ATx)
+    reps = 2000
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        g.matvec_pair(y, x, Ay, ATx)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    pair_us = e0.elapsed_time(e1) * 1e3 / reps
+    bytes_pair = algorithmic_bytes_pair(L)
+
+    def time_to_gap(gm, kind, target, tpot):
+        gm.solver_set_params(kind)
+        gm.solver_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters, gap = 0, float("inf")
+        while iters < 200000:
+            gm.solver_step(25)
+            iters += 25
+            gap = float(gm.saddle_gap()[0][0])
+            if gap <= target * tpot:
+                break
+        gm.solver_set_params("rm+")
+        return time.perf_counter() - t0, iters, gap
+
+    ttg, iters, gap = time_to_gap(g, "rm+", 1e-4, pot)
+    ttg_d, iters_d, gap_d = time_to_gap(g, "dcfr", 1e-4, pot)
+    out = {"workload": "river endgame: 52-card deck, 5-card board, 1081 hands/player, bets {0.5,1,2}xpot + "
+                       "all-in, max 3 raises, pot 100, stacks 400",
+           "n_seq": [L[0][0]["n_seq"], L[0][1]["n_seq"]], "n_hands": [L[0][0]["n_hands"], L[0][1]["n_hands"]],
+           "game_create_s": t_create,
+           "iterations_per_s": steps / (ms / 1e3), "iteration_us": ms * 1e3 / steps,
+           "matvec_pair": {"kernel": "k_mvc (matvec_pair launch, schedule %d:%d)" % g.game_get_tuning(),
+                           "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair,
+                           "achieved_gbs": bytes_pair / (pair_us * 1e-6) / 1e9,
+                           "traffic": measured_traffic("river"),
+                           "note": "0.86 MB per pair stays in the caches; the launch is latency bound"},
+           "time_to_gap": {"target": "1e-4*pot", "seconds": ttg, "iterations": iters,
+                           "gap_over_pot": gap / pot, "solver": "plain RM+, uniform start, "
+                           "FP64 gap checked every 25 iterations",
+                           "dcfr": {"seconds": ttg_d, "iterations": iters_d, "gap_over_pot": gap_d / pot,
+                                    "params": "alpha 1.5, beta 0, gamma 2"}}}
+    g.close()
+    if not args.no_tiny:
+        tiny = I.config(0)
+        gt = pmx.Game(tiny)
+        t_ttg, t_it, t_gap = time_to_gap(gt, "rm+", 1e-6, 2 * tiny.contrib)
+        gt.close()
+        out["tiny_time_to_gap"] = {"workload": "13-card deck, one card per hand, bet 1x pot, one raise, pot 2",
+                                   "target": "1e-6*pot", "seconds": t_ttg, "iterations": t_it,
+                                   "gap_over_pot": t_gap / (2 * tiny.contrib),
+                                   "solver": "plain RM+, FP64 gap every 25"}
+    log(f"river: {out['iterations_per_s']:.0f} iterations/s, pair {pair_us:.2f} us, time to gap {ttg:.3f} s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=1024, help="timed solver iterations over the batch")
+    ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--cpu-batch-sample", type=int, default=16,
+                    help="instances of the batch in the oracle's timed sample")
     ap.add_argument("--batch", type=int, default=512)
-    ap.add_argument("--batch-steps", type=int, default=256)
-    ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--plain-sample", type=int, default=0,
+                    help="instances solved by the plain single-instance solver (0: all of the batch)")
     ap.add_argument("--batch-big", type=int, default=2048,
                     help="instances of the batch whose matvec pair is timed beyond the Infinity Cache (0: skip)")
     ap.add_argument("--max-iters", type=int, default=100000)
+    ap.add_argument("--no-river", action="store_true")
     ap.add_argument("--no-turn", action="store_true")
     ap.add_argument("--no-tiny", action="store_true", help="skip the 13-card game's time to gap")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -523,9 +678,7 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
-    log("river leg")
     from paper_2112_03804_amd import instances as I
-    from paper_2112_03804_amd import pmx
 
     if args.pmc_probe:
         pmc_probe(args)
@@ -533,129 +686,54 @@ def main():
     if args.trace_probe:
         trace_probe(args)
         return
-    desc = I.config(1)
-    pot = 2 * desc.contrib
     stream = torch.cuda.current_stream()
-    t_create = time.perf_counter()
-    g = pmx.Game(desc)
-    t_create = time.perf_counter() - t_create
-
-    # ---- whole hot path: K solver iterations (one matvec pair each) --------
-    g.solver_reset()
-    g.solver_step(args.warmup)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    g.solver_step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    ms_per_step = ms / args.steps
-    value = args.steps / (ms / 1e3)
-
-    # ---- the matvec-pair kernel alone (roofline) ---------------------------
-    rng = np.random.default_rng(1)
-    L = [g.layouts[0]]
-    y = torch.from_numpy(rng.random(g.elems[1]).astype(np.float32)).cuda()
-    x = torch.from_numpy(rng.random(g.elems[0]).astype(np.float32)).cuda()
-    Ay = torch.empty(g.elems[0], dtype=torch.float32, device="cuda")
-    ATx = torch.empty(g.elems[1], dtype=torch.float32, device="cuda")
-    for _ in range(50):
-        g.matvec_pair(y, x, Ay, ATx)
-    reps = 2000
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(reps):
-        g.matvec_pair(y, x, Ay, ATx)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    pair_us = e0.elapsed_time(e1) * 1e3 / reps
-    bytes_pair = algorithmic_bytes_pair(L)
-    achieved = bytes_pair / (pair_us * 1e-6) / 1e9
-
-    # ---- time to gap 1e-4 * pot from a uniform start -----------------------
-    def time_to_gap(kind):
-        g.solver_set_params(kind)
-        g.solver_reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        iters, gap = 0, float("inf")
-        while iters < 200000:
-            g.solver_step(25)
-            iters += 25
-            gap = float(g.saddle_gap()[0][0])
-            if gap <= 1e-4 * pot:
-                break
-        return time.perf_counter() - t0, iters, gap
-
-    ttg, iters, gap = time_to_gap("rm+")
-    ttg_d, iters_d, gap_d = time_to_gap("dcfr")
-    g.solver_set_params("rm+")
-
-    # ---- the 13-card game to 1e-6 * pot (launch-latency bound) ------------
-    tiny = I.config(0)
-    tpot = 2 * tiny.contrib
-    tiny_ttg, t_it, t_gap = None, 0, float("nan")
-    if not args.no_tiny:
-        gt = pmx.Game(tiny)
-        gt.solver_reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        t_gap = float("inf")
-        while t_it < 200000:
-            gt.solver_step(25)
-            t_it += 25
-            t_gap = float(gt.saddle_gap()[0][0])
-            if t_gap <= 1e-6 * tpot:
-                break
-        tiny_ttg = time.perf_counter() - t0
-        gt.close()
-
+    log("batch leg (headline)")
+    batched = batched_leg(args, stream)
+    log("batch leg done")
     out = {
         "metric": "matvec pairs/s (A·y+Aᵀx) & time to gap 1e-4·pot: plain vs batched/warm-start",
-        "value": value,
-        "unit": "matvec pairs/s",
+        "value": batched["matvec_pairs_per_s"],
+        "unit": "instance matvec pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": batched["iteration_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 (FP64 scan accumulation)",
         "data": "synthetic",
-        "config": {"workload": "river endgame: 52-card deck, 5-card board, 1081 hands/player, "
-                               "bets {0.5,1,2}xpot + all-in, max 3 raises, pot 100, stacks 400; "
-                               "step = one RM+ iteration (A y, P1 update, A^T x, P2 update)",
-                   "n_seq": [L[0][0]["n_seq"], L[0][1]["n_seq"]],
-                   "n_hands": [L[0][0]["n_hands"], L[0][1]["n_hands"]]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("river"),
-                     "kernel": "k_mvc (matvec_pair launch, schedule %d:%d)" % g.game_get_tuning(),
-                     "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair},
-        "time_to_gap": {"target": "1e-4*pot", "seconds": ttg, "iterations": iters,
-                        "gap_over_pot": gap / pot, "solver": "plain RM+, uniform start, "
-                        "FP64 gap checked every 25 iterations",
-                        "dcfr": {"seconds": ttg_d, "iterations": iters_d, "gap_over_pot": gap_d / pot,
-                                 "params": "alpha 1.5, beta 0, gamma 2"}},
-        "game_create_s": t_create,
-        "tiny_time_to_gap": {"workload": "13-card deck, one card per hand, bet 1x pot, one raise, pot 2",
-                             "target": "1e-6*pot", "seconds": tiny_ttg, "iterations": t_it,
-                             "gap_over_pot": t_gap / tpot, "solver": "plain RM+, FP64 gap every 25"},
+        "config": {"workload": batched["workload"] + "; step = one RM+ iteration of every instance "
+                               "(A y, P1 update, A^T x, P2 update)",
+                   "instances": batched["instances"]},
+        "roofline": batched["roofline"],
     }
-    g.close()
-    log(f"river: {value:.0f} iterations/s, pair {pair_us:.2f} us, time to gap {ttg:.3f} s")
-    if not args.no_batched:
-        out["batched"] = batched_leg(args, stream)
-        log("batch leg done")
-        if not args.no_warm:
-            out["warm_start"] = warm_leg(args, stream, out["batched"])
-            log("warm-start leg done")
+    out["batched"] = batched
+    if not args.no_warm:
+        out["warm_start"] = warm_leg(args, stream, batched)
+        log("warm-start leg done")
+    river_iters = None
+    if not args.no_river:
+        out["river"] = river_leg(args, stream)
+        river_iters = out["river"]["time_to_gap"]["iterations"]
+        log("river leg done")
+    precision = None
     if not args.no_turn:
-        out["turn_river"] = turn_river_leg(args, stream)
+        tr = turn_river_leg(args, stream)
+        precision = {"averages": tr.pop("_averages")}
+        out["turn_river"] = tr
         log("turn+river leg done")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(desc, args.cpu_budget, gpu_iters=iters)
+        cb = cpu_baseline(args, I.config(1), I.batched_configs(args.batch), gpu_iters=river_iters,
+                          precision=precision)
+        og = cb.pop("precision_run_oracle_gap", None)
+        if og is not None:
+            pr = out["turn_river"]["precision_run"]
+            pr["oracle_gap_over_pot"] = og["gap_over_pot"]
+            pr["gap_diff_over_pot"] = abs(og["gap_over_pot"] - pr["gap_over_pot"])
+            pr["gap_diff_within_1e-9_pot"] = pr["gap_diff_over_pot"] <= 1e-9
+            pr["oracle_gap_seconds"] = og["seconds"]
+        out["cpu_baseline"] = cb
         log("CPU baseline done")
     print(json.dumps(out), flush=True)
 

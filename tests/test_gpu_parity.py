@@ -235,45 +235,51 @@ def test_matvec_batched_uneven():
     g.close()
 
 
-def test_matvec_turn_river_full_size_sampled():
+TR_SCHEDULES = [(0, 8), (2, 4), (2, 8), (3, 4), (3, 8)]   # the candidates the bench tunes over
+
+
+def test_matvec_turn_river_full_size():
+    """Every entry of A y and A^T x (FP32 under each schedule the bench
+    tunes over, and FP64) on the full turn + river game, 19,480 sequences x
+    1128 hands per player, against the oracle's definition-level sums."""
     pmx = _need_gpu()
     d = I.config(2)
-    _say("matvec parity turn+river (sampled entries)")
-    g = pmx.Game(d)
+    _say("matvec parity turn+river, every entry")
     o = payoff.Game(d)
+    g = pmx.Game(d)
     rng = np.random.default_rng(21)
     y = _rand_vectors(o, rng, 1)
     x = _rand_vectors(o, rng, 0)
-    Ay = torch.zeros(g.elems[0], dtype=torch.float32, device="cuda")
-    ATx = torch.zeros(g.elems[1], dtype=torch.float32, device="cuda")
-    g.matvec_pair(_dev(g.pack(1, [y]), np.float32), _dev(g.pack(0, [x]), np.float32), Ay, ATx)
-    Ayd = torch.zeros(g.elems[0], dtype=torch.float64, device="cuda")
+    yd, xd = _dev(g.pack(1, [y]), np.float32), _dev(g.pack(0, [x]), np.float32)
+    ref_A, ref_AT = o.matvec_A(y), o.matvec_AT(x)
+    mag_A, mag_AT = payoff.abs_matvec_A(o, y), payoff.abs_matvec_AT(o, x)
+    normA, normAT = o.abs_row_sums().max(), o.abs_col_sums().max()
+    fl_A, fl_AT = F32_FLOOR * normA * np.abs(y).max(), F32_FLOOR * normAT * np.abs(x).max()
+    Ay = torch.empty(g.elems[0], dtype=torch.float32, device="cuda")
+    ATx = torch.empty(g.elems[1], dtype=torch.float32, device="cuda")
+    for sched in TR_SCHEDULES:
+        _say("  schedule", sched)
+        g.game_tune(*sched)
+        Ay.fill_(7.0)
+        ATx.fill_(7.0)
+        g.matvec_pair(yd, xd, Ay, ATx)
+        torch.cuda.synchronize()
+        got_A = g.unpack(0, Ay.cpu().numpy())[0].astype(np.float64)
+        got_AT = g.unpack(1, ATx.cpu().numpy())[0].astype(np.float64)
+        assert np.abs(got_A - ref_A).max() <= 1e-5 * normA * np.abs(y).max()
+        assert np.abs(got_AT - ref_AT).max() <= 1e-5 * normAT * np.abs(x).max()
+        _assert_close(got_A, ref_A, mag_A, 1e-6, fl_A, f"A y (fp32, schedule {sched})")
+        _assert_close(got_AT, ref_AT, mag_AT, 1e-6, fl_AT, f"A^T x (fp32, schedule {sched})")
+    del Ay, ATx
+    Ayd = torch.empty(g.elems[0], dtype=torch.float64, device="cuda")
+    ATxd = torch.empty(g.elems[1], dtype=torch.float64, device="cuda")
     g.matvec_A_f64(_dev(g.pack(1, [y], np.float64), np.float64), Ayd)
+    g.matvec_AT_f64(_dev(g.pack(0, [x], np.float64), np.float64), ATxd)
     torch.cuda.synchronize()
-    gA, gAT = g.unpack(0, Ay.cpu().numpy())[0], g.unpack(1, ATx.cpu().numpy())[0]
-    gAd = g.unpack(0, Ayd.cpu().numpy())[0]
-    T = g.terminals(0)
-    # absolute floors relative to the scale of a whole row of A
-    floor = F32_FLOOR * 2 * d.stack[0] * np.abs(y).max()
-    floor64 = F64_FLOOR * 2 * d.stack[0] * np.abs(y).max()
-    # sample rows of every kind: runout rows, first-round fold rows, river rows
-    runout_rows = sorted(set(T["seq1"][T["runout"] == 1].tolist()))[:3]
-    first_rows = sorted(set(T["seq1"][(T["board"] < 0) & (T["runout"] == 0)].tolist()))[:3]
-    river_rows = rng.choice(sorted(set(T["seq1"][T["board"] >= 0].tolist())), size=6, replace=False)
-    rows = list(runout_rows) + list(first_rows) + [int(r) for r in river_rows]
-    for s in rows:
-        for h in rng.choice(o.N[0], size=4, replace=False):
-            ref = o.entry_A(y, s, h)
-            mag = payoff.abs_entry_A(o, y, s, h)
-            assert abs(gA[s, h] - ref) <= 1e-6 * mag + floor, (s, h, gA[s, h], ref, mag)
-            assert abs(gAd[s, h] - ref) <= 1e-12 * mag + floor64, (s, h, gAd[s, h], ref, mag)
-    cols = sorted(set(T["seq2"][T["runout"] == 1].tolist()))[:2] + \
-        [int(c) for c in rng.choice(sorted(set(T["seq2"].tolist())), size=6, replace=False)]
-    for s in cols:
-        for h in rng.choice(o.N[1], size=4, replace=False):
-            ref = o.entry_AT(x, s, h)
-            mag = payoff.abs_entry_AT(o, x, s, h)
-            assert abs(gAT[s, h] - ref) <= 1e-6 * mag + floor, (s, h, gAT[s, h], ref, mag)
+    _assert_close(g.unpack(0, Ayd.cpu().numpy())[0], ref_A, mag_A, 1e-12, F64_FLOOR * normA * np.abs(y).max(),
+                  "A y (fp64)")
+    _assert_close(g.unpack(1, ATxd.cpu().numpy())[0], ref_AT, mag_AT, 1e-12,
+                  F64_FLOOR * normAT * np.abs(x).max(), "A^T x (fp64)")
     g.close()
 
 
@@ -878,4 +884,36 @@ def test_matvec_matches_technique_b_factors(name, fn):
     _assert_close(g.unpack(1, ATx.cpu().numpy())[0], ref_AT, magAT, 1e-6, F32_FLOOR * normAT, "A^T x (fp32)")
     _assert_close(g.unpack(0, Ayd.cpu().numpy())[0], ref_A, magA, 1e-12, F64_FLOOR * normA, "A y (fp64)")
     _assert_close(g.unpack(1, ATxd.cpu().numpy())[0], ref_AT, magAT, 1e-12, F64_FLOOR * normAT, "A^T x (fp64)")
+    g.close()
+
+
+def test_turn_river_gap_full_size_certified():
+    """The FP64 saddle gap and best responses of the full turn + river game
+    (19,480 sequences x 1128 hands per player) agree with the oracle to
+    1e-9 * pot, on random strategies and on the averages of 1024 DCFR
+    iterations (the solver and gap of the precision run)."""
+    pmx = _need_gpu()
+    d = I.config(2)
+    _say("turn+river gap, full size")
+    o = payoff.Game(d)
+    g = pmx.Game(d)
+    pot = 2 * d.contrib
+    rng = np.random.default_rng(12)
+    x, y = _random_plans(o, rng)
+    gap, b1, b2 = g.saddle_gap_of(_dev(g.pack(0, [x], np.float64), np.float64),
+                                  _dev(g.pack(1, [y], np.float64), np.float64))
+    rgap, rb1, rb2 = solver.saddle_gap(o, x, y)
+    _say(f"  random strategies: gap/pot {gap[0] / pot:.6e}, oracle {rgap / pot:.6e}")
+    assert abs(b1[0] - rb1) <= 1e-9 * pot and abs(b2[0] - rb2) <= 1e-9 * pot
+    assert abs(gap[0] - rgap) <= 1e-9 * pot
+    g.solver_set_params("dcfr")
+    g.solver_step(1024)
+    gap, b1, b2 = g.saddle_gap()
+    xa = g.unpack(0, g.get_average_strategy(0))[0]
+    ya = g.unpack(1, g.get_average_strategy(1))[0]
+    rgap, rb1, rb2 = solver.saddle_gap(o, xa, ya)
+    _say(f"  DCFR averages after 1024 iterations: gap/pot {gap[0] / pot:.6e}, oracle {rgap / pot:.6e}")
+    assert abs(b1[0] - rb1) <= 1e-9 * pot and abs(b2[0] - rb2) <= 1e-9 * pot
+    assert abs(gap[0] - rgap) <= 1e-9 * pot
+    assert 0 <= gap[0] < 1e-3 * pot
     g.close()
