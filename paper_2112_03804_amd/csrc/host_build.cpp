@@ -13,6 +13,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <numeric>
 #include <utility>
 
@@ -838,6 +839,423 @@ int build_mc_layout(HostGame& hg, int d, int block, std::string& msg) {
     L.push_back(it1);
     L.push_back(ii);
     L.push_back(ctx);
+  }
+  return PMX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// grouped matvec layout (kernel 4)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct GTerm {
+  int out;        // own sequence (output row)
+  int ctx;        // board context
+  bool fold;
+  int in;         // opponent sequence (input row)
+  double coef;    // payoff x chance probability (sign of the direction included)
+};
+
+struct GroupH {   // a group before offsets: rows as sequence ids
+  int ctx = -1;
+  int in[kGrpComps] = {-1, -1, -1, -1};
+  int fc[kGrpComps] = {0, 0, 0, 0};        // component of output o's fold term
+  double ks[kGrpComps] = {0, 0, 0, 0}, kf[kGrpComps] = {0, 0, 0, 0};
+  bool sd[kGrpComps] = {false, false, false, false}, f[kGrpComps] = {false, false, false, false};
+};
+using Slots = std::array<int, kGrpComps>;   // output row of each slot, -1: empty
+
+// Places the terms of one context, for outputs in fixed slots, into as many
+// groups as they need: a showdown term of the output in slot o takes
+// component o, a fold term a component holding its input row or a free one.
+// Terms that do not fit wait for the next group.
+void place_terms(const Slots& slots, int ctx, std::vector<GTerm> pending, std::vector<GroupH>& res) {
+  auto slot_of = [&](int row) {
+    for (int o = 0; o < kGrpComps; ++o)
+      if (slots[o] == row) return o;
+    return -1;
+  };
+  while (!pending.empty()) {
+    GroupH G;
+    G.ctx = ctx;
+    std::vector<GTerm> next;
+    for (const GTerm& t : pending) {
+      if (t.fold) continue;
+      const int o = slot_of(t.out);
+      if (!G.sd[o] && (G.in[o] < 0 || G.in[o] == t.in)) {
+        G.in[o] = t.in;
+        G.ks[o] = t.coef;
+        G.sd[o] = true;
+      } else if (G.sd[o] && G.in[o] == t.in) {
+        G.ks[o] += t.coef;
+      } else {
+        next.push_back(t);
+      }
+    }
+    for (const GTerm& t : pending) {
+      if (!t.fold) continue;
+      const int o = slot_of(t.out);
+      if (G.f[o]) {
+        if (G.in[G.fc[o] ? o ^ 1 : o] == t.in) G.kf[o] += t.coef;
+        else next.push_back(t);
+        continue;
+      }
+      int pick = -1;
+      for (int c = 0; c < kGrpComps && pick < 0; ++c)
+        if (G.in[c] == t.in) pick = c;
+      for (int c = 0; c < kGrpComps && pick < 0; ++c)
+        if (G.in[c] < 0) pick = c;
+      if (pick < 0) {
+        next.push_back(t);
+        continue;
+      }
+      G.in[pick] = t.in;
+      G.fc[o] = pick;
+      G.kf[o] = t.coef;
+      G.f[o] = true;
+    }
+    res.push_back(G);
+    pending.swap(next);
+  }
+}
+
+}  // namespace
+
+// Grouped layout of one direction (kernel 4): per instance, the terms of each
+// board context are joined into connected sets of output and input rows
+// (each output row reads at most one fold and one showdown input per context
+// in these games, so the sets are small) and packed into groups of at most
+// kGrpComps outputs and components; rows with terms in several contexts (the
+// turn's all-in runouts) form sequences of groups over their contexts that
+// carry each row's sum; rows without terms are written as zeros.  Groups are
+// cut into workgroup chunks of about `gpc` groups at sequence boundaries.
+int build_grp_layout(HostGame& hg, int d, int gpc, std::string& msg) {
+  const int p = d, q = 1 - d;
+  GrpDir& M = hg.grp[d];
+  M = GrpDir();
+  if (hg.elems[0] >= ((int64_t)1 << 31) || hg.elems[1] >= ((int64_t)1 << 31)) {
+    msg = "vectors of 2^31 elements or more: matvec kernel 4 takes 32-bit offsets";
+    return PMX_EINVAL;
+  }
+  const int BLK = kGrpBlock;
+  auto lohi = [](uint32_t lo, uint32_t hi) { return (lo & 0xffffu) | ((hi & 0xffffu) << 16); };
+  for (size_t ii = 0; ii < hg.inst.size(); ++ii) {
+    const Built& b = hg.inst[ii];
+    const Instance& in = b.inst;
+    // hands-per-thread class: the smallest whose entry chunks fit every context
+    const int nmax = std::max(in.n[p], in.n[q]);
+    int cls = std::max(1, (nmax + BLK - 1) / BLK) - 1;
+    std::vector<int> len_all;
+    auto chunks_needed = [&](int ke) {
+      int worst = 0;
+      for (int c = 0; c < b.n_ctx; ++c) {
+        const CtxMeta& opp = b.ctx[q][c];
+        std::vector<int> len(1 + in.deck, 0);
+        len[0] = opp.n_live;
+        for (int h = 0; h < in.n[q]; ++h)
+          if (opp.rank[h] >= 0)
+            for (int k = 0; k < in.cph; ++k) ++len[1 + in.cards[q][(size_t)h * in.cph + k]];
+        int n = 0;
+        for (int l : len) n += (l + 1 + ke - 1) / ke;
+        worst = std::max(worst, n);
+      }
+      return worst;
+    };
+    while (cls < kGrpClasses && chunks_needed(kGrpKE[cls]) > BLK) ++cls;
+    if (cls >= kGrpClasses) {
+      msg = "instance " + std::to_string(ii) + " has too many hands for matvec kernel 4";
+      return PMX_EINVAL;
+    }
+    const int KE = kGrpKE[cls];
+    const int ctx_base = (int)M.ctx.size();
+    for (int c = 0; c < b.n_ctx; ++c) {
+      const CtxMeta& own = b.ctx[p][c];
+      const CtxMeta& opp = b.ctx[q][c];
+      const int n_seg = 1 + in.deck;
+      std::vector<int> order(opp.n_live);
+      for (int h = 0; h < in.n[q]; ++h)
+        if (opp.rank[h] >= 0) order[opp.rank[h]] = h;
+      std::vector<std::vector<int>> card_list(in.deck);   // sorted positions of each card's holders
+      for (int i = 0; i < opp.n_live; ++i)
+        for (int k = 0; k < in.cph; ++k) card_list[in.cards[q][(size_t)order[i] * in.cph + k]].push_back(i);
+      std::vector<int> len(n_seg), cstart(n_seg + 1, 0);
+      len[0] = opp.n_live;
+      for (int cd = 0; cd < in.deck; ++cd) len[1 + cd] = (int)card_list[cd].size();
+      for (int sg = 0; sg < n_seg; ++sg) cstart[sg + 1] = cstart[sg] + (len[sg] + 1 + KE - 1) / KE;
+      const int n_chunk = cstart[n_seg];
+      auto slot = [&](int sg, int i) { return (uint32_t)((i % KE) * BLK + cstart[sg] + i / KE); };
+      auto urow = [&](int pos) { return (uint32_t)(16 * grp_urow(pos)); };
+      GCtx m{};
+      m.n_own = in.n[p];
+      m.n_opp = in.n[q];
+      m.cph = in.cph;
+      m.n_chunk = n_chunk;
+      m.zrow = (int32_t)urow(opp.n_live);
+      m.trash = m.zrow + 16;
+      m.lam_own_off = m.lam_opp_off = -1;   // filled by the ABI layer
+      // staging rows of the opponent's hands
+      m.rk_off = (int64_t)M.rk.size();
+      for (int h = 0; h < in.n[q]; ++h)
+        M.rk.push_back((uint16_t)(opp.rank[h] >= 0 ? urow(opp.rank[h]) : (uint32_t)m.trash));
+      while (M.rk.size() % 8) M.rk.push_back(0);
+      // entry sources and chunk descriptors
+      std::vector<uint32_t> ent((size_t)BLK * KE, (uint32_t)m.zrow);
+      std::vector<uint32_t> meta(BLK, 0u);
+      for (int sg = 0; sg < n_seg; ++sg) {
+        const int nch = cstart[sg + 1] - cstart[sg];
+        for (int j = 0; j < nch; ++j) {
+          const int t = cstart[sg] + j;
+          for (int i = 0; i < KE; ++i) {
+            const int idx = j * KE + i;
+            if (idx < len[sg]) ent[(size_t)t * KE + i] = urow(sg == 0 ? idx : card_list[sg - 1][idx]);
+          }
+          uint32_t v = 0;
+          if (j == 0) v |= 1u << 8;
+          if (j == nch - 1) v |= (uint32_t)(sg + 1) << 16;
+          meta[t] = v;
+        }
+      }
+      m.src_off = (int64_t)M.src.size();
+      for (int j = 0; j < KE / 2; ++j)
+        for (int t = 0; t < BLK; ++t)
+          M.src.push_back(lohi(ent[(size_t)t * KE + 2 * j], ent[(size_t)t * KE + 2 * j + 1]));
+      m.meta_off = (int64_t)M.meta.size();
+      M.meta.insert(M.meta.end(), meta.begin(), meta.end());
+      // query records of the own hands
+      m.q_off = (int64_t)M.q.size() / 4;
+      for (int h = 0; h < in.n[p]; ++h) {
+        const QueryRec& r = own.q[h];
+        if (r.lt < 0) {
+          M.q.insert(M.q.end(), {0xffffffffu, 0u, 0u, 0u});
+          continue;
+        }
+        uint32_t cw[2] = {0, 0};
+        int cards[2] = {255, 255};
+        for (int k = 0; k < in.cph; ++k) {
+          const int card = in.cards[p][(size_t)h * in.cph + k];
+          const int base_old = opp.seg_end[card] + 1;   // the card's list in the sentinel entry list
+          const int lt = (k == 0 ? r.lt0 : r.lt1) - base_old, le = (k == 0 ? r.le0 : r.le1) - base_old;
+          cards[k] = card;
+          cw[k] = lohi(slot(1 + card, lt), slot(1 + card, le));
+        }
+        uint32_t w = (uint32_t)cards[0] | ((uint32_t)(in.cph == 2 ? cards[1] : 0) << 6);
+        if (r.self >= 0)
+          w |= (1u << 12) | ((uint32_t)(r.self % KE == KE - 1) << 13) | (slot(0, r.self) << 14);
+        M.q.push_back(lohi(slot(0, r.lt), slot(0, r.le)));
+        M.q.push_back(cw[0]);
+        M.q.push_back(cw[1]);
+        M.q.push_back(w);
+      }
+      M.ctx.push_back(m);
+    }
+
+    // terms of this direction: output = own sequence, input = opponent sequence
+    const int S = b.sf.n_seq[p];
+    std::vector<GTerm> terms;
+    const double rem = in.two_rounds() ? (double)in.remaining() : 1.0;
+    for (const Terminal& t : b.sf.terms) {
+      const int sg = t.seq[p], other = t.seq[q];
+      if (t.kind != PMX_SHOWDOWN) {
+        const double u1 = t.kind == PMX_FOLD_P1 ? -t.c1 : t.c2;
+        if (t.board < 0) terms.push_back({sg, 0, true, other, u1});
+        else terms.push_back({sg, 1 + t.board, true, other, u1 / rem});
+      } else {
+        const double st = (d == 0 ? 1.0 : -1.0) * t.c1;
+        if (t.runout) {
+          for (int r = 0; r < (int)in.rivers.size(); ++r) terms.push_back({sg, 1 + r, false, other, st / rem});
+        } else if (t.board < 0) {
+          terms.push_back({sg, 0, false, other, st});
+        } else {
+          terms.push_back({sg, 1 + t.board, false, other, st / rem});
+        }
+      }
+    }
+    std::vector<std::vector<int>> row_terms(S);
+    for (size_t i = 0; i < terms.size(); ++i) row_terms[terms[i].out].push_back((int)i);
+    std::vector<int> empty, multi;
+    std::vector<std::vector<int>> single(b.n_ctx);
+    for (int sg = 0; sg < S; ++sg) {
+      std::vector<int> cs;
+      for (int i : row_terms[sg]) cs.push_back(terms[i].ctx);
+      std::sort(cs.begin(), cs.end());
+      cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
+      if (cs.empty()) empty.push_back(sg);
+      else if (cs.size() == 1) single[cs[0]].push_back(sg);
+      else multi.push_back(sg);
+    }
+    const int64_t out_base = b.vec_off[p], in_base = b.vec_off[q];
+    const int64_t sp = b.stride[p], sq = b.stride[q];
+    // a sequence of groups over fixed output slots: offsets and carry flags
+    std::vector<std::pair<int, int>> seqs;   // group ranges
+    auto emit = [&](const Slots& slots, const std::vector<GroupH>& gs) {
+      const int g0 = (int)M.groups.size();
+      for (size_t k = 0; k < gs.size(); ++k) {
+        const GroupH& H = gs[k];
+        GGroup G{};
+        G.ctx = H.ctx < 0 ? -1 : ctx_base + H.ctx;
+        G.n_own = in.n[p];
+        G.stride = b.stride[p];
+        G.n_in = in.n[q];
+        G.fc = 0;
+        G.acc = 0;
+        for (int o = 0; o < kGrpComps; ++o) {
+          G.in[o] = H.in[o] >= 0 ? (int32_t)(in_base + H.in[o] * sq) : -1;
+          G.out[o] = slots[o] >= 0 ? (int32_t)(out_base + slots[o] * sp) : -1;
+          G.ks[o] = H.ks[o];
+          G.kf[o] = H.kf[o];
+          G.fc |= (H.fc[o] & 3) << (2 * o);
+          if (slots[o] >= 0) {
+            if (k == 0) G.acc |= 1 << o;
+            if (k + 1 == gs.size()) G.acc |= 1 << (4 + o);
+          }
+        }
+        M.groups.push_back(G);
+      }
+      seqs.push_back({g0, (int)M.groups.size()});
+    };
+    // the groups of a set of rows over their contexts, for a slot assignment
+    auto place_slots = [&](const Slots& slots, const std::vector<int>& tids) {
+      std::vector<int> cs;
+      for (int i : tids) cs.push_back(terms[i].ctx);
+      std::sort(cs.begin(), cs.end());
+      cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
+      std::vector<GroupH> gs;
+      for (int c : cs) {
+        std::vector<GTerm> tl;
+        for (int i : tids)
+          if (terms[i].ctx == c) tl.push_back(terms[i]);
+        place_terms(slots, c, tl, gs);
+      }
+      return gs;
+    };
+    // rows in slot order
+    auto place_all = [&](const std::vector<int>& outs, const std::vector<int>& tids, Slots* used) {
+      Slots sl = {-1, -1, -1, -1};
+      for (size_t k = 0; k < outs.size(); ++k) sl[k] = outs[k];
+      if (used) *used = sl;
+      return place_slots(sl, tids);
+    };
+    // single-context rows: connected sets of rows (through shared input
+    // rows) packed into groups while they fit in one
+    for (int c = 0; c < b.n_ctx; ++c) {
+      const std::vector<int>& rows = single[c];
+      if (rows.empty()) continue;
+      std::vector<int> parent(rows.size());
+      std::iota(parent.begin(), parent.end(), 0);
+      std::function<int(int)> find = [&](int a) { return parent[a] == a ? a : parent[a] = find(parent[a]); };
+      std::vector<int> first_user(b.sf.n_seq[q], -1);
+      for (size_t k = 0; k < rows.size(); ++k)
+        for (int i : row_terms[rows[k]]) {
+          int& fu = first_user[terms[i].in];
+          if (fu < 0) fu = (int)k;
+          else parent[find((int)k)] = find(fu);
+        }
+      std::vector<std::vector<int>> comps;
+      std::vector<int> comp_of(rows.size(), -1);
+      for (size_t k = 0; k < rows.size(); ++k) {
+        const int r = find((int)k);
+        if (comp_of[r] < 0) {
+          comp_of[r] = (int)comps.size();
+          comps.push_back({});
+        }
+        comps[comp_of[r]].push_back((int)k);
+      }
+      // first fit, larger sets first, into groups that stay one group
+      std::stable_sort(comps.begin(), comps.end(),
+                       [](const std::vector<int>& x, const std::vector<int>& y) { return x.size() > y.size(); });
+      std::vector<std::pair<std::vector<int>, std::vector<int>>> open;   // (outputs, terms)
+      for (const auto& cm : comps) {
+        std::vector<int> co, ct;
+        for (int k : cm) {
+          co.push_back(rows[k]);
+          for (int i : row_terms[rows[k]]) ct.push_back(i);
+        }
+        // best fit: the open group left with the fewest free output and component slots
+        int best = -1, best_free = 1 << 30;
+        for (size_t oi = 0; oi < open.size(); ++oi) {
+          auto& os = open[oi];
+          if (os.first.size() + co.size() > (size_t)kGrpComps) continue;
+          std::vector<int> o2 = os.first, t2 = os.second;
+          o2.insert(o2.end(), co.begin(), co.end());
+          t2.insert(t2.end(), ct.begin(), ct.end());
+          const std::vector<GroupH> gs = place_all(o2, t2, nullptr);
+          if (gs.size() != 1) continue;
+          int used = 0;
+          for (int j = 0; j < kGrpComps; ++j) used += gs[0].in[j] >= 0;
+          const int free_slots = (kGrpComps - (int)o2.size()) + (kGrpComps - used);
+          if (free_slots < best_free) {
+            best_free = free_slots;
+            best = (int)oi;
+          }
+        }
+        if (best >= 0) {
+          open[best].first.insert(open[best].first.end(), co.begin(), co.end());
+          open[best].second.insert(open[best].second.end(), ct.begin(), ct.end());
+          continue;
+        }
+        if (co.size() <= (size_t)kGrpComps && place_all(co, ct, nullptr).size() == 1) {
+          open.push_back({co, ct});
+          continue;
+        }
+        // a set that needs several groups: slices of kGrpComps rows, each its own sequence
+        for (size_t a2 = 0; a2 < cm.size(); a2 += kGrpComps) {
+          std::vector<int> o2, t2;
+          for (size_t k = a2; k < std::min(cm.size(), a2 + kGrpComps); ++k) {
+            o2.push_back(rows[cm[k]]);
+            for (int i : row_terms[rows[cm[k]]]) t2.push_back(i);
+          }
+          Slots sl;
+          std::vector<GroupH> gs = place_all(o2, t2, &sl);
+          emit(sl, gs);
+        }
+      }
+      for (auto& os : open) {
+        Slots sl;
+        std::vector<GroupH> gs = place_all(os.first, os.second, &sl);
+        emit(sl, gs);
+      }
+    }
+    // rows over several contexts: kGrpComps at a time, context by context
+    for (size_t a = 0; a < multi.size(); a += kGrpComps) {
+      std::vector<int> outs, tids;
+      for (size_t k = a; k < std::min(multi.size(), a + kGrpComps); ++k) {
+        outs.push_back(multi[k]);
+        for (int i : row_terms[multi[k]]) tids.push_back(i);
+      }
+      Slots sl;
+      std::vector<GroupH> gs = place_all(outs, tids, &sl);
+      emit(sl, gs);
+    }
+    // rows without terms
+    for (size_t a = 0; a < empty.size(); a += kGrpComps) {
+      Slots sl = {-1, -1, -1, -1};
+      for (size_t k = a; k < std::min(empty.size(), a + kGrpComps); ++k) sl[k - a] = empty[k];
+      emit(sl, {GroupH()});
+    }
+    // workgroup chunks: about gpc groups, cut at sequence boundaries
+    size_t k = 0;
+    while (k < seqs.size()) {
+      const int g0 = seqs[k].first;
+      int g1 = seqs[k].second;
+      const bool carry = g1 - g0 > 1;
+      ++k;
+      // rows without terms take chunks of their own (a separate path of the
+      // kernel), and sequences of several groups chunks of the carrying kind
+      while (k < seqs.size() && seqs[k].second - g0 <= gpc &&
+             (M.groups[seqs[k].first].ctx < 0) == (M.groups[g0].ctx < 0) &&
+             (seqs[k].second - seqs[k].first > 1) == carry) {
+        g1 = seqs[k].second;
+        ++k;
+      }
+      std::vector<int32_t>& L = M.chunks[carry ? 1 : 0][cls];
+      L.push_back(g0);
+      L.push_back(g1);
+      L.push_back((int32_t)ii);
+      L.push_back(M.groups[g0].ctx);
+    }
+    int mc = 0;
+    for (int c = 0; c < b.n_ctx; ++c) mc = std::max(mc, M.ctx[ctx_base + c].n_chunk);
+    M.max_chunk[cls] = std::max(M.max_chunk[cls], mc);
   }
   return PMX_OK;
 }

@@ -749,6 +749,404 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
   }
 }
 
+// ---------------------------------------------------------------------------
+// grouped matvec (kernel 4, FP32; layout in GCtx / GGroup)
+// ---------------------------------------------------------------------------
+struct GParams {
+  const GGroup* groups;
+  const int4* chunks;            // (first group, end group, instance, context of the first group)
+  const GCtx* ctx;
+  const uint4* q;
+  const uint16_t* rk;
+  const uint32_t* src;
+  const uint32_t* meta;
+  const float* lamf;
+  const int32_t* active;         // per-instance flag (NULL: all)
+  double scale;
+  int32_t nchunk;
+};
+
+// One step of an inclusive segmented scan of (flag, a[0..3]): the values of
+// the earlier lane are added unless this lane's run already holds a flag.
+// With every row enabled, a lane without a source reads 0 through the DPP
+// bound control, and no old value has to be set first.
+template <int CTRL>
+__device__ inline int dpp_iz(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL>
+__device__ inline double dpp_dz(double v) {
+  return __hiloint2double(dpp_iz<CTRL>(__double2hiint(v)), dpp_iz<CTRL>(__double2loint(v)));
+}
+template <int CTRL, int RM>
+__device__ inline void seg_step4(int& f, double (&a)[kGrpComps]) {
+  const int f2 = RM == 0xf ? dpp_iz<CTRL>(f) : dpp_i<CTRL, RM>(f);
+  const double m = f ? 0.0 : 1.0;
+#pragma unroll
+  for (int j = 0; j < kGrpComps; ++j) a[j] = fma(RM == 0xf ? dpp_dz<CTRL>(a[j]) : dpp_d<CTRL, RM>(a[j]), m, a[j]);
+  f |= f2;
+}
+
+// Exclusive segmented scan of four values over the threads of a block (as
+// block_seg_scan_x): the exclusive sum is the inclusive one minus the own
+// value.  One barrier; `scr` holds 5 doubles per wavefront.
+template <int NW>
+__device__ inline void block_seg_scan4(int flag, const double (&a)[kGrpComps], double* scr,
+                                       double (&e)[kGrpComps]) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int f = flag;
+  double ai[kGrpComps];
+#pragma unroll
+  for (int j = 0; j < kGrpComps; ++j) ai[j] = a[j];
+  seg_step4<0x111, 0xf>(f, ai);
+  seg_step4<0x112, 0xf>(f, ai);
+  seg_step4<0x114, 0xf>(f, ai);
+  seg_step4<0x118, 0xf>(f, ai);
+  seg_step4<0x142, 0xa>(f, ai);
+  seg_step4<0x143, 0xc>(f, ai);
+  if (lane == 63) {
+    scr[5 * wid] = (double)f;
+#pragma unroll
+    for (int j = 0; j < kGrpComps; ++j) scr[5 * wid + 1 + j] = ai[j];
+  }
+  __syncthreads();
+  static_assert(NW <= 8, "wavefront totals are scanned within one DPP row");
+  int fw = 0;
+  double aw[kGrpComps];
+#pragma unroll
+  for (int j = 0; j < kGrpComps; ++j) aw[j] = 0.0;
+  if (lane < NW) {
+    fw = scr[5 * lane] != 0.0;
+#pragma unroll
+    for (int j = 0; j < kGrpComps; ++j) aw[j] = scr[5 * lane + 1 + j];
+  }
+  seg_step4<0x111, 0xf>(fw, aw);
+  seg_step4<0x112, 0xf>(fw, aw);
+  seg_step4<0x114, 0xf>(fw, aw);
+  const double m = (wid > 0 && !f) ? 1.0 : 0.0;
+  const int src = wid > 0 ? wid - 1 : 0;
+#pragma unroll
+  for (int j = 0; j < kGrpComps; ++j) {
+    const double c = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(aw[j]), src),
+                                      __builtin_amdgcn_readlane(__double2loint(aw[j]), src));
+    e[j] = fma(c, m, ai[j]) - a[j];
+  }
+}
+
+// Records every lane reads at the same address (chunks, groups, contexts) are
+// read through the constant address space: the plans do not change during a
+// launch, so the loads go through the scalar cache into scalar registers.
+template <typename T>
+__device__ inline const __attribute__((address_space(4))) T* cst(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
+
+// Loads issued whatever the condition (at index 0 when it fails) and
+// selected afterwards, so that no branch waits on them.
+template <typename T>
+__device__ inline T ld_sel(const T* p, int64_t i, bool ok, T zero) {
+  const T v = p[ok ? i : 0];
+  return ok ? v : zero;
+}
+
+// A group record in scalar registers.
+struct GGroupS {
+  int32_t in[kGrpComps], out[kGrpComps];
+  double ks[kGrpComps], kf[kGrpComps];
+  int32_t ctx, fc, acc, n_own, stride, n_in;
+};
+__device__ inline GGroupS load_group(const GGroup* p) {
+  const auto gp = cst(p);
+  GGroupS G;
+#pragma unroll
+  for (int j = 0; j < kGrpComps; ++j) {
+    G.in[j] = gp->in[j];
+    G.out[j] = gp->out[j];
+    G.ks[j] = gp->ks[j];
+    G.kf[j] = gp->kf[j];
+  }
+  G.ctx = gp->ctx;
+  G.fc = gp->fc;
+  G.acc = gp->acc;
+  G.n_own = gp->n_own;
+  G.stride = gp->stride;
+  G.n_in = gp->n_in;
+  return G;
+}
+
+// Position of a workgroup in the chunk list: the hardware deals workgroups
+// to the eight XCDs in turn, so consecutive chunks (one instance, its
+// context records and input rows) are given to the workgroups of one XCD
+// and share its L2.
+__device__ inline int xcd_chunk(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+__device__ inline float4 grp_slot(const char* R, uint32_t slot) { return *(const float4*)(R + 16 * slot); }
+
+// Showdown and fold values of the four components for one own hand from the
+// prefix slots, the segment totals and the identical hand.
+template <int KE>
+__device__ inline void grp_query(const char* R, const double* segT, uint4 r, int cph, double (&sd)[kGrpComps],
+                                 double (&fo)[kGrpComps]) {
+  constexpr int BLK = kGrpBlock;
+  const float4 g0 = grp_slot(R, r.x & 0xffffu), g1 = grp_slot(R, r.x >> 16);
+  const float4 a0 = grp_slot(R, r.y & 0xffffu), a1 = grp_slot(R, r.y >> 16);
+  const int c0 = r.w & 63, c1 = (r.w >> 6) & 63;
+  const double2* T = (const double2*)segT;   // 4 doubles per segment
+  const double2 t0a = T[0], t0b = T[1];
+  const double2 taa = T[2 * (1 + c0)], tab = T[2 * (1 + c0) + 1];
+  const double t0[4] = {t0a.x, t0a.y, t0b.x, t0b.y}, ta[4] = {taa.x, taa.y, tab.x, tab.y};
+  const float gs[4] = {g0.x + g1.x, g0.y + g1.y, g0.z + g1.z, g0.w + g1.w};
+  const float as[4] = {a0.x + a1.x, a0.y + a1.y, a0.z + a1.z, a0.w + a1.w};
+#pragma unroll
+  for (int j = 0; j < kGrpComps; ++j) {
+    sd[j] = ((double)gs[j] - t0[j]) - ((double)as[j] - ta[j]);
+    fo[j] = t0[j] - ta[j];
+  }
+  if (cph == 2) {
+    const float4 b0 = grp_slot(R, r.z & 0xffffu), b1 = grp_slot(R, r.z >> 16);
+    const double2 tba = T[2 * (1 + c1)], tbb = T[2 * (1 + c1) + 1];
+    const double tb[4] = {tba.x, tba.y, tbb.x, tbb.y};
+    const float bs[4] = {b0.x + b1.x, b0.y + b1.y, b0.z + b1.z, b0.w + b1.w};
+    float4 us = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r.w & (1u << 12)) {
+      // the identical opponent hand: the difference of the prefix sums at
+      // its global entry and the next one (the next chunk's first entry when
+      // it ends its chunk)
+      const uint32_t s0 = r.w >> 14;
+      const uint32_t s1 = (r.w & (1u << 13)) ? s0 - (uint32_t)((KE - 1) * BLK) + 1u : s0 + (uint32_t)BLK;
+      const float4 p0 = grp_slot(R, s0);
+      const float4 p1 = grp_slot(R, s1);
+      us = make_float4(p1.x - p0.x, p1.y - p0.y, p1.z - p0.z, p1.w - p0.w);
+    }
+    const float u[4] = {us.x, us.y, us.z, us.w};
+#pragma unroll
+    for (int j = 0; j < kGrpComps; ++j) {
+      sd[j] -= (double)bs[j] - tb[j];
+      fo[j] += (double)u[j] - tb[j];
+    }
+  }
+}
+
+// One workgroup per chunk of groups.  Per group: every opponent hand stages
+// its weighted values of the group's components (one 16-byte row at its
+// strength position), each thread gathers its chunk of the segmented entry
+// list from those rows and sums it, a segmented block scan carries the sums
+// across the chunks of a segment in FP64, every entry's exclusive prefix sum
+// (rounded once to FP32) is stored at its slot over the staging rows, and
+// every own hand reads six prefix sums, the segment totals and the identical
+// hand (Technique B's solve and the inclusion-exclusion of eq. cf) for all
+// four components at once, then weights them by each output's coefficients.
+// Wavefronts per SIMD each class is built for: at most the workgroups per CU
+// its LDS region allows (four for one hand per thread, three for two or three,
+// two beyond), lowered where the registers of a class would otherwise spill
+// (the carrying form serves only the few sequences of rows summed over boards).
+template <int KH, bool CARRY>
+constexpr int mvg_waves_per_simd() {
+  return KH == 1 ? 4 : (KH == 2 || (KH == 3 && !CARRY)) ? 3 : (KH == 5 && CARRY) ? 1 : 2;
+}
+
+template <int KH, int KE, bool CARRY>
+__global__ __launch_bounds__(kGrpBlock) __attribute__((amdgpu_waves_per_eu(mvg_waves_per_simd<KH, CARRY>())))
+void k_mvg(GParams P0, const float* __restrict__ in0,
+                                                  float* __restrict__ out0, GParams P1,
+                                                  const float* __restrict__ in1, float* __restrict__ out1,
+                                                  double* __restrict__ tick) {
+  constexpr int BLK = kGrpBlock, NW = BLK / 64, NC = kGrpComps;
+  static_assert(KE % 2 == 0, "entry sources are stored in pairs");
+  if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1.0;
+  const int b = xcd_chunk((int)blockIdx.x, P0.nchunk + P1.nchunk);
+  const bool second = b >= P0.nchunk;
+  const GParams& P = second ? P1 : P0;
+  const float* __restrict__ in = second ? in1 : in0;
+  float* __restrict__ out = second ? out1 : out0;
+  const auto crp = cst((const int32_t*)(P.chunks + (second ? b - P0.nchunk : b)));
+  const int4 cr = make_int4(crp[0], crp[1], crp[2], crp[3]);
+  if (P.active && !*cst(P.active + cr.z)) return;   // retired instance
+  const int tid = threadIdx.x;
+  extern __shared__ double smem[];
+  double* segT = smem;                         // [kMcSegMax][4] segment totals
+  double* scr = segT + NC * kMcSegMax;         // [5 * NW] scan scratch
+  char* R = (char*)(scr + 5 * NW);             // staging rows, then prefix slots (16 bytes each)
+
+  const int g0 = cr.x, g1 = cr.y;
+  if (cr.w < 0) {
+    // a chunk of rows without terms: zeros
+    for (int gi = g0; gi < g1; ++gi) {
+      const GGroupS G = load_group(P.groups + gi);
+#pragma unroll
+      for (int o = 0; o < NC; ++o) {
+        if (G.out[o] < 0) continue;
+#pragma unroll
+        for (int k = 0; k < KH; ++k) {
+          const int h = tid + k * BLK;
+          if (h < G.stride) out[G.out[o] + h] = 0.f;
+        }
+      }
+    }
+    return;
+  }
+
+  double acc[CARRY ? NC : 1][CARRY ? KH : 1];   // sums of rows over several groups
+  float v[NC][KH];                             // the inputs of the group in flight
+#pragma unroll
+  for (int o = 0; o < (CARRY ? NC : 1); ++o)
+#pragma unroll
+    for (int k = 0; k < (CARRY ? KH : 1); ++k) acc[o][k] = 0.0;
+  {
+    const GGroupS G = load_group(P.groups + g0);
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int h = tid + k * BLK;
+        v[j][k] = ld_sel(in, G.in[j] + h, G.in[j] >= 0 && h < G.n_in, 0.f);
+      }
+  }
+  int gi = g0;
+  while (gi < g1) {
+    // a run of groups on one board context: its records stay in registers
+    const int ctx = cst(P.groups + gi)->ctx;
+    const auto cp = cst(P.ctx + ctx);
+    const int n_own = cp->n_own, n_opp = cp->n_opp, cph = cp->cph, n_chunk = cp->n_chunk;
+    const int zrow = cp->zrow;
+    const uint32_t trash = (uint32_t)cp->trash;
+    uint32_t rko[KH], srcp[KE / 2];
+    float lop[KH], low[KH];
+    uint4 qr[KH];
+    {
+      const uint16_t* rk = P.rk + cp->rk_off;
+      const float* lopp = P.lamf + cp->lam_opp_off;
+      const float* lown = P.lamf + cp->lam_own_off;
+      const uint4* qp = P.q + cp->q_off;
+      const uint32_t* sp = P.src + cp->src_off;
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int h = tid + k * BLK;
+        rko[k] = h < n_opp ? (uint32_t)ld_sel(rk, h, h < n_opp, (uint16_t)0) : trash;
+        lop[k] = ld_sel(lopp, h, h < n_opp, 0.f);
+        qr[k] = ld_sel(qp, h, h < n_own, make_uint4(0xffffffffu, 0u, 0u, 0u));
+        low[k] = ld_sel(lown, h, h < n_own, 0.f);
+      }
+#pragma unroll
+      for (int j = 0; j < KE / 2; ++j) srcp[j] = sp[j * BLK + tid];
+    }
+    const uint32_t cm = P.meta[cp->meta_off + tid];
+    const bool wlive = (tid & ~63) < n_chunk;
+    for (; gi < g1; ++gi) {
+      const GGroupS G = load_group(P.groups + gi);
+      if (G.ctx != ctx) break;
+      // the per-hand records are decoded again in every group: hoisting the
+      // decoded LDS addresses out of the loop costs more registers than the
+      // few integer operations it saves
+#pragma unroll
+      for (int k = 0; k < KH; ++k) asm volatile("" : "+v"(qr[k].x), "+v"(qr[k].y), "+v"(qr[k].z), "+v"(qr[k].w));
+#pragma unroll
+      for (int j = 0; j < KE / 2; ++j) asm volatile("" : "+v"(srcp[j]));
+      // stage the weighted components at the hands' strength positions, then
+      // fetch the next group's inputs into the same registers
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int h = tid + k * BLK;
+        if (h < n_opp)
+          *(float4*)(R + rko[k]) =
+              make_float4(lop[k] * v[0][k], lop[k] * v[1][k], lop[k] * v[2][k], lop[k] * v[3][k]);
+      }
+      if (tid == 0) *(float4*)(R + zrow) = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gi + 1 < g1) {
+        const GGroupS N = load_group(P.groups + gi + 1);
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+#pragma unroll
+          for (int k = 0; k < KH; ++k) {
+            const int h = tid + k * BLK;
+            v[j][k] = ld_sel(in, N.in[j] + h, N.in[j] >= 0 && h < N.n_in, 0.f);
+          }
+      }
+      __syncthreads();
+      // gather the chunk and sum it; carry the sums across the segment's chunks
+      float4 ev[KE];
+      float s4[NC] = {0.f, 0.f, 0.f, 0.f};
+      if (wlive) {
+#pragma unroll
+        for (int i = 0; i < KE; ++i) {
+          const uint32_t off = (i & 1) ? srcp[i / 2] >> 16 : srcp[i / 2] & 0xffffu;
+          ev[i] = *(const float4*)(R + off);
+          s4[0] += ev[i].x;
+          s4[1] += ev[i].y;
+          s4[2] += ev[i].z;
+          s4[3] += ev[i].w;
+        }
+      }
+      double a[NC], e[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) a[j] = (double)s4[j];
+      block_seg_scan4<NW>((int)((cm >> 8) & 1u), a, scr, e);
+      // every gather is done (the scan's barrier): the exclusive prefix sums
+      // overwrite the staging rows, each the FP64 carry's FP32 head plus
+      // (remainder + partial)
+      if (wlive) {
+        float eh[NC], run[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          eh[j] = (float)e[j];
+          run[j] = (float)(e[j] - (double)eh[j]);
+        }
+#pragma unroll
+        for (int i = 0; i < KE; ++i) {
+          *(float4*)(R + 16 * (i * BLK + tid)) = make_float4(eh[0] + run[0], eh[1] + run[1], eh[2] + run[2],
+                                                             eh[3] + run[3]);
+          run[0] += ev[i].x;
+          run[1] += ev[i].y;
+          run[2] += ev[i].z;
+          run[3] += ev[i].w;
+        }
+      }
+      const int endseg = (int)((cm >> 16) & 255u);
+      if (endseg) {
+        double2* T = (double2*)(segT + NC * (endseg - 1));
+        T[0] = make_double2(e[0] + a[0], e[1] + a[1]);
+        T[1] = make_double2(e[2] + a[2], e[3] + a[3]);
+      }
+      __syncthreads();
+      // own hands: the outputs' values, stored (or carried to the next group
+      // of the sequence)
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int h = tid + k * BLK;
+        double val[NC] = {0.0, 0.0, 0.0, 0.0};
+        if (h < n_own && qr[k].x != 0xffffffffu) {
+          double sd[NC], fo[NC];
+          grp_query<KE>(R, segT, qr[k], cph, sd, fo);
+#pragma unroll
+          for (int o = 0; o < NC; ++o) {
+            const int fj = (G.fc >> (2 * o)) & 3;
+            const double f = fj == 0 ? fo[0] : fj == 1 ? fo[1] : fj == 2 ? fo[2] : fo[3];
+            val[o] = G.ks[o] * sd[o] + G.kf[o] * f;
+          }
+        }
+        const double sl = P.scale * (double)low[k];
+#pragma unroll
+        for (int o = 0; o < NC; ++o) {
+          if (CARRY) {
+            acc[o][k] = ((G.acc & (1 << o)) ? 0.0 : acc[o][k]) + val[o];
+            if (G.out[o] >= 0 && (G.acc & (1 << (4 + o))) && h < G.stride)
+              out[G.out[o] + h] = h < n_own ? (float)(sl * acc[o][k]) : 0.f;
+          } else if (G.out[o] >= 0 && h < G.stride) {
+            out[G.out[o] + h] = h < n_own ? (float)(sl * val[o]) : 0.f;
+          }
+        }
+        // one hand's LDS reads in flight at a time: the next hand's are not
+        // hoisted above this one's arithmetic (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      __syncthreads();   // the next group's staging overwrites the prefix slots
+    }
+  }
+}
+
 // Exclusive segmented scan over the 64 lanes of a wavefront (see
 // block_seg_scan).
 __device__ inline void wave_seg_scan(bool flag, double a, double b, double& ea, double& eb) {
@@ -1825,6 +2223,18 @@ struct DevMc {                  // chunk-aligned matvec layout of one direction
   int block = 0;                // 0: not built
 };
 
+struct DevGrp {                 // grouped matvec layout of one direction (kernel 4)
+  DBuf<GCtx> ctx;
+  DBuf<GGroup> groups;
+  DBuf<uint32_t> q, src, meta;
+  DBuf<uint16_t> rk;
+  DBuf<int32_t> chunks[2][kGrpClasses];       // [plain, carrying sums over groups][class]
+  int count[2][kGrpClasses] = {};
+  DBuf<int32_t> chunks_act[2][kGrpClasses];   // the solver's lists: chunks of active instances only
+  int count_act[2][kGrpClasses] = {};
+  bool built = false;
+};
+
 struct DevTp {
   DBuf<int32_t> inf_parent, inf_first, inf_nact, order;
   DBuf<TpTask> tasks;
@@ -1852,6 +2262,7 @@ struct Game {
   int device_id = 0;
   DevDir dd[2];
   DevMc dm[2];
+  DevGrp dg[2];
   DevTp dt[2];
   DevRm drm[2];
   DBuf<double> lam;
@@ -1937,7 +2348,7 @@ static int upload_mc_active(Game* g, int d) {
 static int upload_mc(Game* g, int d) {
   HostGame& hg = g->hg;
   DevMc& E = g->dm[d];
-  const int block = hg.mv_kernel == 3 ? 512 : 256;
+  const int block = hg.mv_kernel == 3 ? 512 : 256;   // kernel 4: its FP64 form runs kernel 2
   std::string m;
   int rc = build_mc_layout(hg, d, block, m);
   if (rc) return fail(rc, m);
@@ -1966,6 +2377,51 @@ static int upload_mc(Game* g, int d) {
   }
   E.block = block;
   return upload_mc_active(g, d);
+}
+
+// The solver's chunk lists of the grouped layout (as upload_mc_active).
+static int upload_grp_active(Game* g, int d) {
+  DevGrp& E = g->dg[d];
+  const GrpDir& M = g->hg.grp[d];
+  const bool all = g->listed.size() != g->hg.inst.size();
+  for (int kind = 0; kind < 2; ++kind)
+    for (int c = 0; c < kGrpClasses; ++c) {
+      std::vector<int32_t> L;
+      const std::vector<int32_t>& F = M.chunks[kind][c];
+      for (size_t i = 0; i + 3 < F.size(); i += 4)
+        if (all || g->listed[F[i + 2]]) L.insert(L.end(), F.begin() + i, F.begin() + i + 4);
+      int rc = E.chunks_act[kind][c].upload(L);
+      if (rc) return rc;
+      E.count_act[kind][c] = (int)L.size() / 4;
+    }
+  return PMX_OK;
+}
+
+static int upload_grp(Game* g, int d) {
+  HostGame& hg = g->hg;
+  DevGrp& E = g->dg[d];
+  E.built = false;
+  std::string m;
+  int rc = build_grp_layout(hg, d, hg.groups_per_chunk, m);
+  if (rc) return fail(rc, m);
+  GrpDir& M = hg.grp[d];
+  const int p = d, q = 1 - d;
+  size_t ci = 0;
+  for (size_t ii = 0; ii < hg.inst.size(); ++ii)
+    for (int c = 0; c < hg.inst[ii].n_ctx; ++c, ++ci) {
+      M.ctx[ci].lam_own_off = g->lam_off[p][ii];
+      M.ctx[ci].lam_opp_off = g->lam_off[q][ii];
+    }
+  if ((rc = E.ctx.upload(M.ctx)) || (rc = E.groups.upload(M.groups)) || (rc = E.q.upload(M.q)) ||
+      (rc = E.src.upload(M.src)) || (rc = E.meta.upload(M.meta)) || (rc = E.rk.upload(M.rk)))
+    return rc;
+  for (int kind = 0; kind < 2; ++kind)
+    for (int c = 0; c < kGrpClasses; ++c) {
+      if ((rc = E.chunks[kind][c].upload(M.chunks[kind][c]))) return rc;
+      E.count[kind][c] = (int)M.chunks[kind][c].size() / 4;
+    }
+  E.built = true;
+  return upload_grp_active(g, d);
 }
 
 static int upload_dir(Game* g, int d) {
@@ -2000,6 +2456,8 @@ static int upload_dir(Game* g, int d) {
       E.cls_n[c] = D.cls_n[c];
     }
   }
+  g->dg[d].built = false;
+  if (hg.mv_kernel == 4 && (rc = upload_grp(g, d))) return rc;
   if (hg.mv_kernel >= 2) return upload_mc(g, d);
   g->dm[d].block = 0;
   return PMX_OK;
@@ -2309,11 +2767,73 @@ static int launch_mc(Game* g, const MvParams& P0, const IO* in0, IO* out0, const
   return PMX_OK;
 }
 
+static GParams grp_params(Game* g, int d, const MvParams& like, int kind, int c) {
+  DevGrp& E = g->dg[d];
+  GParams P;
+  const bool solver = like.active != nullptr;
+  P.groups = E.groups.p;
+  P.chunks = (const int4*)(solver ? E.chunks_act[kind][c].p : E.chunks[kind][c].p);
+  P.ctx = E.ctx.p;
+  P.q = (const uint4*)E.q.p;
+  P.rk = E.rk.p;
+  P.src = E.src.p;
+  P.meta = E.meta.p;
+  P.lamf = g->lamf.p;
+  P.active = like.active;
+  P.scale = like.scale;
+  P.nchunk = like.nblk > 0 ? (solver ? E.count_act[kind][c] : E.count[kind][c]) : 0;
+  return P;
+}
+
+template <int KH, bool CARRY>
+static void launch_grp_class(const GParams& A, const float* in0, float* out0, const GParams& B, const float* in1,
+                             float* out1, hipStream_t s, double* tick) {
+  constexpr int KE = kGrpKE[KH - 1];
+  const size_t lds = sizeof(double) * (kGrpComps * kMcSegMax + 5 * (kGrpBlock / 64)) + 16 * (size_t)kGrpBlock * KE;
+  hipLaunchKernelGGL((k_mvg<KH, KE, CARRY>), dim3(A.nchunk + B.nchunk), dim3(kGrpBlock), lds, s, A, in0, out0, B,
+                     in1, out1, tick);
+}
+
+// Kernel 4 (FP32 only): one launch per hands-per-thread class present.
+static int launch_grp(Game* g, const MvParams& P0, const float* in0, float* out0, const MvParams& P1,
+                      const float* in1, float* out1, hipStream_t s, double* tick) {
+  if (!g->dg[0].built || !g->dg[1].built) return fail(PMX_ESTATE, "grouped matvec layout not built");
+  for (int kind = 0; kind < 2; ++kind)
+    for (int c = 0; c < kGrpClasses; ++c) {
+      const GParams A = grp_params(g, P0.dir, P0, kind, c), B = grp_params(g, P1.dir, P1, kind, c);
+      if (A.nchunk + B.nchunk == 0) continue;
+      if (kind == 0) {
+        switch (c) {
+          case 0: launch_grp_class<1, false>(A, in0, out0, B, in1, out1, s, tick); break;
+          case 1: launch_grp_class<2, false>(A, in0, out0, B, in1, out1, s, tick); break;
+          case 2: launch_grp_class<3, false>(A, in0, out0, B, in1, out1, s, tick); break;
+          case 3: launch_grp_class<4, false>(A, in0, out0, B, in1, out1, s, tick); break;
+          default: launch_grp_class<5, false>(A, in0, out0, B, in1, out1, s, tick); break;
+        }
+      } else {
+        switch (c) {
+          case 0: launch_grp_class<1, true>(A, in0, out0, B, in1, out1, s, tick); break;
+          case 1: launch_grp_class<2, true>(A, in0, out0, B, in1, out1, s, tick); break;
+          case 2: launch_grp_class<3, true>(A, in0, out0, B, in1, out1, s, tick); break;
+          case 3: launch_grp_class<4, true>(A, in0, out0, B, in1, out1, s, tick); break;
+          default: launch_grp_class<5, true>(A, in0, out0, B, in1, out1, s, tick); break;
+        }
+      }
+      tick = nullptr;   // the iteration tick belongs to the first launch
+    }
+  if (tick) hipLaunchKernelGGL(k_add1, dim3(1), dim3(1), 0, s, tick);
+  HIP_TRY(hipGetLastError());
+  return PMX_OK;
+}
+
 template <typename IO>
 static int launch_mv(Game* g, MvParams P0, const IO* in0, IO* out0, MvParams P1, const IO* in1,
                      IO* out1, hipStream_t s, double* tick = nullptr) {
   const int nb = P0.nblk + P1.nblk;
   if (nb == 0) return PMX_OK;
+  if constexpr (sizeof(IO) == 4) {
+    if (g->hg.mv_kernel == 4) return launch_grp(g, P0, in0, out0, P1, in1, out1, s, tick);
+  }
   // the chunk-aligned layout, unless its FP64 form needs more LDS than a
   // workgroup may take here (then the workgroup kernel on the sentinel entry
   // list serves the call)
@@ -2623,7 +3143,7 @@ int game_hand_meta(const Game* g, int32_t instance, int32_t ctx, int32_t player,
 int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk) {
   int rc = ensure_device(g);
   if (rc) return rc;
-  if (kernel < 0 || kernel > 3) return fail(PMX_EINVAL, "kernel must be in [0, 3]");
+  if (kernel < 0 || kernel > 4) return fail(PMX_EINVAL, "kernel must be in [0, 4]");
   if (rows_per_chunk < 1 || rows_per_chunk > 64) return fail(PMX_EINVAL, "rows_per_chunk must be in [1, 64]");
   HIP_TRY(hipDeviceSynchronize());
   if (g->graph_exec) {
@@ -2636,6 +3156,7 @@ int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk) {
   }
   g->hg.mv_kernel = kernel;
   g->hg.rows_per_block = rows_per_chunk;
+  if (kernel == 4) g->hg.groups_per_chunk = rows_per_chunk;
   for (int d = 0; d < 2; ++d) {
     build_matvec_plan(g->hg, d, rows_per_chunk);
     classify_chunks(g->hg.dir[d]);
@@ -2757,8 +3278,10 @@ static int set_solver_lists(Game* g, const std::vector<char>& act) {
   g->n_listed = 0;
   for (char v : act) g->n_listed += v ? 1 : 0;
   int rc;
-  for (int d = 0; d < 2; ++d)
+  for (int d = 0; d < 2; ++d) {
     if (g->dm[d].block && (rc = upload_mc_active(g, d))) return rc;
+    if (g->dg[d].built && (rc = upload_grp_active(g, d))) return rc;
+  }
   for (int p = 0; p < 2; ++p)
     if ((rc = upload_rm_blocks(g, p, g->listed))) return rc;
   return PMX_OK;

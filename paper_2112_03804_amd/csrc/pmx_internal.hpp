@@ -187,6 +187,66 @@ struct McDir {
   std::vector<int32_t> chunks[kMcClasses];   // per class: 4 ints per row chunk (it0, it1, inst, ctx)
 };
 
+// Grouped matvec layout (kernel 4, FP32).  A group applies the hand
+// operators to up to kGrpComps input rows of one board context at once: each
+// component is one opponent row u = lambda_opp * v; the fold operator of eq.
+// (cf) and the showdown operator (Technique B) are linear, so one segmented
+// scan of u serves every terminal that reads that row, and the payoff
+// coefficients enter when the own hands combine the prefix sums.  Output o
+// of a group takes the showdown operator of component o and the fold
+// operator of component fc(o).  Per context, the workgroup stages the
+// components' weighted opponent values as one 16-byte row per live hand in
+// strength order (row pu(i) = i + i / 16 for sorted position i; the zero row
+// follows the last hand and a trash row takes the hands dead in the
+// context), gathers each thread's chunk of the segmented entry list from
+// those rows, scans, and stores the exclusive prefix sums of entry i of chunk
+// t at slot i * BLOCK + t of the same LDS region.
+constexpr int kGrpComps = 4;
+constexpr int kGrpBlock = 256;                  // threads per workgroup
+constexpr int kGrpClasses = 5;                  // hands per thread 1..5
+constexpr int kGrpKE[kGrpClasses] = {4, 8, 12, 16, 18};   // scan entries per thread per class
+inline int grp_urow(int i) { return i + (i >> 4); }
+struct GCtx {                           // (instance, context) as seen by one direction
+  int32_t n_own, n_opp, cph, n_chunk;
+  int32_t zrow, trash;                  // LDS byte offsets of the zero row and the trash row
+  int32_t pad0, pad1;
+  int64_t q_off;                        // own hands' query records (uint4)
+  int64_t rk_off;                       // opponent hands' staging rows (uint16 LDS byte offsets)
+  int64_t src_off;                      // entry sources: pairs of uint16 LDS byte offsets, entry-pair major
+                                        // (pair j of thread t at src_off + j * kGrpBlock + t)
+  int64_t meta_off;                     // per-thread chunk descriptors (kGrpBlock entries)
+  int64_t lam_own_off, lam_opp_off;
+};
+struct GGroup {
+  int32_t in[kGrpComps];                // component input rows (element offsets; -1: none)
+  int32_t out[kGrpComps];               // output rows (element offsets; -1: none)
+  double ks[kGrpComps];                 // output o: coefficient of the showdown operator on component o
+  double kf[kGrpComps];                 // output o: coefficient of the fold operator on component fc(o)
+  int32_t ctx;                          // -1: the group only writes rows without terminals (zeros)
+  int32_t fc;                           // fold component of output o in bits 2o, 2o + 1
+  int32_t acc;                          // bit o: output o starts its sum here; bit 4 + o: it ends here (stored)
+  int32_t n_own, stride;                // row length and stride of the outputs
+  int32_t n_in;                         // row length of the inputs (opponent hands)
+  int32_t pad[2];
+};   // element offsets are 32-bit: the layout builder rejects vectors of 2^31 elements or more
+// Group query record (uint4): x = prefix slot of lt | slot of le << 16 (global
+// segment), y = the same in card c0's segment, z = in card c1's segment,
+// w = c0 | c1 << 6 | (identical opponent hand present) << 12 | (its global
+// entry is the last of its chunk) << 13 | (prefix slot of that entry) << 14;
+// a hand dead in the context has x = 0xffffffff.
+// Chunk descriptor bits: 8 first chunk of a segment, 16-23 (segment + 1)
+// when the chunk is the last of its segment.
+struct GrpDir {
+  std::vector<GCtx> ctx;
+  std::vector<GGroup> groups;
+  std::vector<uint32_t> q, src, meta;
+  std::vector<uint16_t> rk;
+  // per kind (0: every sequence one group, 1: sequences carrying sums over
+  // several groups) and class: 4 ints per chunk (g0, g1, inst, ctx of g0)
+  std::vector<int32_t> chunks[2][kGrpClasses];
+  int max_chunk[kGrpClasses] = {0, 0, 0, 0, 0};
+};
+
 struct TpTask {                         // treeplex task: one subtree of one instance
   int64_t vec_base;
   int32_t stride, n_hands;
@@ -290,6 +350,8 @@ struct HostGame {
                                         // chunk; 2 / 3: chunk-aligned layout, 256 / 512 threads
   MvDir dir[2];
   McDir mc[2];
+  GrpDir grp[2];
+  int groups_per_chunk = 8;             // kernel 4: groups per workgroup
   TpPlan tp[2];
   RmPlan rm[2];
   int task_rows = kTaskRowsMax;
@@ -308,5 +370,6 @@ void classify_chunks(MvDir& D);
 void build_matvec_plan(HostGame& hg, int d, int rows_per_block);
 int build_rm_plan(HostGame& hg, int p, int task_rows, std::string& msg);
 int build_mc_layout(HostGame& hg, int d, int block, std::string& msg);
+int build_grp_layout(HostGame& hg, int d, int groups_per_chunk, std::string& msg);
 
 }  // namespace pmx

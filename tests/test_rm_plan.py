@@ -145,3 +145,64 @@ def test_chunk_aligned_layout_reproduces_oracle_matvec(mc_helper, name, fn, bloc
             ref = o.matvec_A(vin[i]) if d == 0 else o.matvec_AT(vin[i])
             scale = (o.abs_row_sums() if d == 0 else o.abs_col_sums()).max() * np.abs(vin[i]).max()
             assert np.abs(got[i] - ref).max() <= 1e-12 * scale, (name, d, i)
+
+
+# ---------------------------------------------------------------------------
+# grouped matvec layout (kernel 4)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def grp_helper(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    out = str(tmp_path_factory.mktemp("grplayout") / "libgrplayout.so")
+    cmd = [gxx, "-O2", "-std=c++17", "-shared", "-fPIC",
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2112_03804_amd", "csrc"),
+           os.path.join(ROOT, "tests", "cpp", "grp_layout_check.cpp"),
+           os.path.join(ROOT, "paper_2112_03804_amd", "csrc", "host_build.cpp"), "-o", out]
+    subprocess.run(cmd, check=True)
+    L = ctypes.CDLL(out)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.grp_matvec.argtypes = [ctypes.POINTER(pmx.GameDescC), ctypes.c_int, ctypes.c_int, ctypes.c_int, dp,
+                             ctypes.c_int64, dp, ctypes.c_int64, ctypes.c_char_p, ctypes.c_int]
+    return L
+
+
+GRP_CASES = MC_CASES + [
+    ("turn_1card", lambda: [I.small_turn_river(0)]),
+    ("river", lambda: [I.config(1)]),
+    ("max_hands", lambda: [I.river_config(seed=5, deck_size=57, n_keep=(1280, 1280), bet_fracs=(0.5,),
+                                          max_raises=1)]),
+]
+
+
+@pytest.mark.parametrize("gpc", [1, 8])
+@pytest.mark.parametrize("name,fn", GRP_CASES)
+def test_grouped_layout_reproduces_oracle_matvec(grp_helper, name, fn, gpc):
+    """The grouped layout (components staged in strength order, entry
+    gathers, prefix slots, query records, group coefficients and the carry
+    flags of rows summed over several boards), evaluated in FP64 the way the
+    grouped workgroup kernel walks it, gives the oracle's A y and A^T x."""
+    import numpy as np
+    from oracle import payoff
+    descs = fn()
+    g = pmx.Game(descs, device=False)
+    os_ = [payoff.Game(d) for d in descs]
+    rng = np.random.default_rng(gpc)
+    packs = [pmx._DescPack(d) for d in descs]
+    arr = (pmx.GameDescC * len(descs))(*[p.c for p in packs])
+    dp = ctypes.POINTER(ctypes.c_double)
+    for d in (0, 1):
+        vin = [rng.standard_normal((o.S[1 - d], o.N[1 - d])) for o in os_]
+        flat_in = np.ascontiguousarray(g.pack(1 - d, vin, np.float64))
+        flat_out = np.zeros(g.elems[d])
+        msg = ctypes.create_string_buffer(256)
+        rc = grp_helper.grp_matvec(arr, len(descs), gpc, d, flat_in.ctypes.data_as(dp), flat_in.size,
+                                   flat_out.ctypes.data_as(dp), flat_out.size, msg, 256)
+        assert rc == 0, msg.value
+        got = g.unpack(d, flat_out)
+        for i, o in enumerate(os_):
+            ref = o.matvec_A(vin[i]) if d == 0 else o.matvec_AT(vin[i])
+            scale = (o.abs_row_sums() if d == 0 else o.abs_col_sums()).max() * np.abs(vin[i]).max()
+            assert np.abs(got[i] - ref).max() <= 1e-12 * scale, (name, d, i)
