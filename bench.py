@@ -363,7 +363,7 @@ def turn_river_leg(args, stream):
     t_create = time.perf_counter()
     g = pmx.Game(desc)
     t_create = time.perf_counter() - t_create
-    sched, sched_us = autotune.tune(g, candidates=[(0, 8), (2, 4), (2, 8), (3, 4), (3, 8)], reps=10,
+    sched, sched_us = autotune.tune(g, candidates=[(2, 4), (2, 8), (3, 4), (3, 8), (4, 1), (4, 2)], reps=10,
                                     use_cache=False)
     bytes_pair = algorithmic_bytes_pair(g.layouts)
     pair_us = min(sched_us.values())
@@ -496,7 +496,7 @@ def pmc_probe(args):
     """Launches for hardware-counter runs (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE):
     a plain 256 MiB device-to-device copy (known bytes: calibrates the counters),
     then matvec-pair launches on the river endgame (default schedule) and on
-    the batch (schedule 2:4)."""
+    the batch (default schedule)."""
     import torch
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
@@ -509,7 +509,6 @@ def pmc_probe(args):
     games = [("river", pmx.Game(I.config(1)))]
     if not args.no_batched:
         gb = pmx.Game(I.batched_configs(args.batch))
-        gb.game_tune(2, 4)
         games.append(("batch", gb))
     for name, g in games:
         rng = np.random.default_rng(0)
@@ -532,7 +531,7 @@ def trace_probe(args):
     import torch
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
-    for name, make, sched, iters in (("batch", lambda: pmx.Game(I.batched_configs(args.batch)), (2, 4), 64),
+    for name, make, sched, iters in (("batch", lambda: pmx.Game(I.batched_configs(args.batch)), (4, 1), 64),
                                      ("turn_river", lambda: pmx.Game(I.config(2)), (3, 8), 32)):
         g = make()
         g.game_tune(*sched)

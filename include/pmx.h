@@ -205,14 +205,18 @@ int game_layout(const Game* g, int32_t instance, int32_t player, Layout* out);
 int game_terminals(const Game* g, int32_t instance, Terminals* out);
 int game_hand_meta(const Game* g, int32_t instance, int32_t ctx, int32_t player, HandMeta* out);
 
-/* Matvec schedule (results agree to the FP32 rounding of the data):
- * kernel 0 = one workgroup per chunk of output rows, kernel 1 = one
- * wavefront per chunk (launched per hand-count class), both on the sentinel
- * entry list; kernels 2 and 3 = one workgroup of 256 / 512 threads per chunk
- * on the chunk-aligned scan layout, launched per hands-per-thread class
- * (prefix sums accumulated in FP64 and stored once rounded to the I/O type);
- * rows_per_chunk in [1, 64].  Synchronizes the device; drops the captured solver graph.  The
- * defaults depend on the number of rows; an autotuner may override them. */
+/* Matvec schedule of the FP32 products (results agree to the FP32 rounding
+ * of the data): kernels 2 and 3 = one workgroup of 256 / 512 threads per
+ * chunk of output rows on the chunk-aligned scan layout, launched per
+ * hands-per-thread class (prefix sums accumulated in FP64 and stored once
+ * rounded to FP32); kernel 4 (the default) = one workgroup per chunk of
+ * groups, a group scanning up to four input rows of one board context at
+ * once (Technique B's solve and the inclusion-exclusion of eq. cf applied to
+ * all of them).  rows_per_chunk in [1, 64]: output rows per chunk (2, 3) or
+ * groups per chunk (4).  The FP64 products always run the chunk-aligned
+ * layout.  Synchronizes the device; drops the captured solver graph.  The
+ * defaults depend on the game's size; an autotuner may override them.
+ * PMX_EINVAL for a kernel outside [2, 4]. */
 int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk);
 int game_get_tuning(const Game* g, int32_t* kernel, int32_t* rows_per_chunk);
 

@@ -1,10 +1,10 @@
 """Schedule autotuner for the structured matvec.
 
 For a game it times every candidate schedule (``game_tune(kernel, rows)``:
-kernel 0 = workgroup per row chunk, 1 = wavefront per row chunk launched per
-hand-count class, 2 / 3 = chunk-aligned scan layout with 256- / 512-thread
-workgroups launched per hands-per-thread class; rows = output rows per
-chunk) on the matvec-pair launch with
+kernel 2 / 3 = chunk-aligned scan layout with 256- / 512-thread workgroups,
+rows = output rows per chunk; kernel 4 = grouped layout, rows = groups of
+up to four input rows per chunk; each launched per hands-per-thread class)
+on the matvec-pair launch with
 HIP events, keeps the fastest, and remembers the choice in a JSON cache keyed
 by GPU architecture and a size class of the game (instances, rows, largest
 hand count), so later games of the same class are tuned without timing.
@@ -17,8 +17,7 @@ from typing import Dict, Iterable, Optional, Tuple
 
 import numpy as np
 
-DEFAULT_CANDIDATES = [(0, 1), (0, 4), (0, 8), (1, 2), (2, 1), (2, 2), (2, 4), (2, 8), (3, 1), (3, 2), (3, 4),
-                      (3, 8)]
+DEFAULT_CANDIDATES = [(2, 1), (2, 4), (2, 8), (3, 1), (3, 4), (3, 8), (4, 1), (4, 2), (4, 4)]
 CACHE_ENV = "PMX_TUNE_CACHE"
 
 

@@ -528,9 +528,11 @@ int default_rows_per_block(int64_t rows, int kernel) {
   return kernel == 3 ? 8 : 2;
 }
 
-// The chunk-aligned layout: 512-thread workgroups (fewer entries per thread,
-// shorter serial passes) when instances hold many hands on average, 256-thread
-// workgroups for batches of smaller instances.
+// The FP64 products (the gap) run the chunk-aligned layout: 512-thread
+// workgroups (fewer entries per thread, shorter serial passes) when instances
+// hold many hands on average, 256-thread workgroups for batches of smaller
+// instances.  The FP32 products default to the grouped kernel (4), one group
+// per workgroup.
 int default_mv_kernel(int64_t mean_hands) { return mean_hands > 800 ? 3 : 2; }
 
 namespace {
@@ -1260,32 +1262,6 @@ int build_grp_layout(HostGame& hg, int d, int gpc, std::string& msg) {
   return PMX_OK;
 }
 
-// Group the row chunks of one direction by hand-count class.
-void classify_chunks(MvDir& D) {
-  for (int c = 0; c < MvDir::kClasses; ++c) {
-    D.cls_chunks[c].clear();
-    D.cls_ent[c] = D.cls_n[c] = 0;
-  }
-  const int nch = (int)D.blk.size() - 1;
-  for (int b = 0; b < nch; ++b) {
-    int nmax = 0, emax = 0;
-    for (int it = D.blk[b]; it < D.blk[b + 1]; ++it) {
-      const MvItem& m = D.items[it];
-      if (m.ctx < 0) {
-        nmax = std::max(nmax, m.n_own);
-        continue;
-      }
-      const MvCtx& c = D.ctx[m.ctx];
-      nmax = std::max(nmax, std::max(c.n_own, c.n_opp));
-      emax = std::max(emax, c.n_ent);
-    }
-    int c = 0;
-    while (c < MvDir::kClasses - 1 && nmax > kClassN[c]) ++c;
-    D.cls_chunks[c].push_back(b);
-    D.cls_ent[c] = std::max(D.cls_ent[c], emax);
-    D.cls_n[c] = std::max(D.cls_n[c], nmax);
-  }
-}
 
 // Cut one player's treeplex of every instance into regret-update pieces of
 // at most `cap` rows.  Repeatedly: take the maximal infoset subtrees of the
@@ -1735,12 +1711,14 @@ int build_game(const GameDesc* descs, int n, HostGame& hg, std::string& msg) {
       rows += std::max(b.sf.n_seq[0], b.sf.n_seq[1]);
       hands += std::max(b.inst.n[0], b.inst.n[1]);
     }
-    hg.mv_kernel = default_mv_kernel(hands / (int64_t)hg.inst.size());
-    hg.rows_per_block = default_rows_per_block(rows, hg.mv_kernel);
+    const int mc_kernel = default_mv_kernel(hands / (int64_t)hg.inst.size());
+    hg.mv_kernel = 4;
+    hg.groups_per_chunk = 1;
+    hg.mc_block = mc_kernel == 3 ? 512 : 256;
+    hg.rows_per_block = default_rows_per_block(rows, mc_kernel);
   }
   for (int d = 0; d < 2; ++d) {
     build_matvec_plan(hg, d, hg.rows_per_block);
-    classify_chunks(hg.dir[d]);
   }
   for (int p = 0; p < 2; ++p) build_treeplex_plan(hg, p);
   for (int p = 0; p < 2; ++p) {

@@ -1,7 +1,7 @@
 // libpmx device code for gfx950 (CDNA4) and the C ABI.
 //
 // Kernels
-//   k_mvc         rows of A y (or A^T x), the default schedules (2, 3): one
+//   k_mvc         rows of A y (or A^T x), schedules 2 and 3 and every FP64 product: one
 //                 workgroup of 256 or 512 threads per chunk of output rows,
 //                 one launch per hands-per-thread class, on the
 //                 chunk-aligned layout (every segment starts at a thread's
@@ -19,8 +19,11 @@
 //                 FP32 sums inside a thread's chunk, FP64 carries across
 //                 chunks (FP64 adds issue at the unpacked FP32 rate on
 //                 CDNA4, so this costs less than compensated FP32).
-//   k_matvec,     the earlier sentinel-list schedules (0, 1), kept as
-//   k_matvec_w    autotuner candidates.
+//   k_mvg         rows of A y (or A^T x), the default FP32 schedule (4):
+//                 groups of up to four input rows of one board context
+//                 share one staged gather, one segmented scan and one set of
+//                 prefix slots; every output row takes its showdown and fold
+//                 terms by coefficient.
 //   k_rmp         regret matching+ (or discounted CFR) on pieces of a
 //                 treeplex of at most 64 sequences, one lane per hand (the
 //                 paper's GPU solver updates all hands in parallel), the
@@ -63,296 +66,17 @@ void pmx_set_error(const char* m) { g_err = m; }
 // ---------------------------------------------------------------------------
 // structured matvec
 // ---------------------------------------------------------------------------
+// One direction of a launch as the host sees it: the layouts of the
+// schedule in use supply the rest.
 struct MvParams {
-  const MvItem* items;
-  const int32_t* blk;
-  const MvCtx* ctx;
-  const uint4* q;
-  const int16_t* rank;
-  const int16_t* seg;
-  const int32_t* segend;
-  const double* lam;
-  const float* lamf;
   double scale;
-  int32_t nblk;
-  int32_t max_ent, max_n, max_seg;
+  int32_t nblk;              // row chunks of the direction (0: the direction is not launched)
   int32_t dir;
-  const int32_t* blk_inst;   // instance of each row chunk
   const int32_t* active;     // per-instance flag (NULL: all); inactive chunks are skipped
 };
 
-// LDS index with one spare double every 16: a thread's contiguous chunk of 16
-// entries then starts on a different bank than its neighbour's.
-__host__ __device__ inline int pd(int i) { return i + (i >> 4); }
-
-template <typename T>
-__device__ inline T shfl_up64(T v, int d) {
-  return __shfl_up(v, d, 64);
-}
-
-// Exclusive segmented scan over the threads of a block of (flag, a, b): a
-// thread's result sums the contributions of earlier threads back to (and
-// including the post-flag part of) the nearest earlier thread with flag set.
-// One barrier; the caller alternates `scratch` between consecutive scans.
-template <int BLOCK>
-__device__ inline void block_seg_scan(bool flag, double a, double b, double* scratch, double& ea,
-                                      double& eb) {
-  constexpr int NW = BLOCK / 64;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int f = flag ? 1 : 0;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    int f2 = shfl_up64(f, off);
-    double a2 = shfl_up64(a, off);
-    double b2 = shfl_up64(b, off);
-    if (lane >= off) {
-      if (!f) {
-        a += a2;
-        b += b2;
-      }
-      f |= f2;
-    }
-  }
-  // wave aggregates
-  if (lane == 63) {
-    scratch[3 * wid + 0] = (double)f;
-    scratch[3 * wid + 1] = a;
-    scratch[3 * wid + 2] = b;
-  }
-  int xf = shfl_up64(f, 1);
-  double xa = shfl_up64(a, 1);
-  double xb = shfl_up64(b, 1);
-  if (lane == 0) {
-    xf = 0;
-    xa = 0.0;
-    xb = 0.0;
-  }
-  __syncthreads();
-  double wa = 0.0, wb = 0.0;
-  for (int w = 0; w < wid && w < NW; ++w) {
-    if (scratch[3 * w] != 0.0) {
-      wa = scratch[3 * w + 1];
-      wb = scratch[3 * w + 2];
-    } else {
-      wa += scratch[3 * w + 1];
-      wb += scratch[3 * w + 2];
-    }
-  }
-  if (!xf) {
-    xa += wa;
-    xb += wb;
-  }
-  ea = xa;
-  eb = xb;
-}
-
 __device__ inline int lo16(uint32_t v) { return (int)(int16_t)(v & 0xffffu); }
 __device__ inline int hi16(uint32_t v) { return (int)(int16_t)(v >> 16); }
-
-template <typename IO>
-__device__ inline const IO* lam_of(const MvParams& P);
-template <>
-__device__ inline const float* lam_of<float>(const MvParams& P) { return P.lamf; }
-template <>
-__device__ inline const double* lam_of<double>(const MvParams& P) { return P.lam; }
-
-// One workgroup processes a chunk of items (output rows x board contexts).
-// KH own/opponent hands and KE scan entries per thread; metadata of the
-// current context stays in registers across the chunk's rows.
-template <int BLOCK, int KH, int KE, typename IO>
-__global__ __launch_bounds__(BLOCK, sizeof(IO) == 4 ? 4 : 3) void k_matvec(MvParams P0, const IO* __restrict__ in0,
-                                                     IO* __restrict__ out0, MvParams P1,
-                                                     const IO* __restrict__ in1, IO* __restrict__ out1,
-                                                     double* __restrict__ tick) {
-  static_assert(KE % 2 == 0, "entries are packed in pairs");
-  constexpr int NW = BLOCK / 64;
-  // FP32 rows double-buffer their inputs in LDS (no barrier between rows);
-  // FP64 rows would not fit twice, so they take one barrier instead.
-  constexpr bool DB = sizeof(IO) == 4;
-  if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1.0;
-  const bool second = (int)blockIdx.x >= P0.nblk;
-  const MvParams& P = second ? P1 : P0;
-  const IO* __restrict__ in = second ? in1 : in0;
-  IO* __restrict__ out = second ? out1 : out0;
-  const IO* __restrict__ lam = lam_of<IO>(P);
-  const int b = second ? (int)blockIdx.x - P0.nblk : (int)blockIdx.x;
-  const int tid = threadIdx.x;
-  if (P.active && !P.active[P.blk_inst[b]]) return;   // retired instance
-
-  // LDS: prefix sums, fold totals, two scan scratch buffers, two input buffers
-  extern __shared__ double smem[];
-  const int me = pd(P0.max_ent > P1.max_ent ? P0.max_ent : P1.max_ent) + 1;
-  const int mn = pd(P0.max_n > P1.max_n ? P0.max_n : P1.max_n) + 1;
-  const int ms = P0.max_seg > P1.max_seg ? P0.max_seg : P1.max_seg;
-  double* Pc = smem;                            // [me] exclusive segmented prefix (showdown channel)
-  double* segF = Pc + me;                       // [ms] per-segment fold totals
-  double* scratch = segF + ms;                  // [2][3 * NW]
-  IO* usb = (IO*)(scratch + 6 * NW);            // [1 or 2][mn] showdown input, sorted order
-  IO* ufb = usb + (DB ? 2 : 1) * mn;            // [1 or 2][mn] fold input, sorted order
-  int* segEnd = (int*)(ufb + (DB ? 2 : 1) * mn);  // [ms]
-
-  uint4 qr[KH];
-  IO lo[KH], lp[KH];
-  double acc[KH];
-  uint32_t rkp[(KH + 1) / 2];
-  uint32_t srcp[KE / 2];
-  IO nxs[KH], nxf[KH];                          // raw inputs of the next row (prefetched)
-#pragma unroll
-  for (int k = 0; k < KH; ++k) acc[k] = 0.0;
-
-  const int it0 = P.blk[b], it1 = P.blk[b + 1];
-  auto fetch = [&](int it) {
-    const MvItem nx = P.items[it];
-#pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      const int h = tid + k * BLOCK;
-      nxs[k] = (h < nx.n_opp && nx.in_s >= 0) ? in[nx.in_s + h] : (IO)0;
-      nxf[k] = (h < nx.n_opp && nx.in_f >= 0) ? in[nx.in_f + h] : (IO)0;
-    }
-  };
-  if (it0 < it1) fetch(it0);
-  int cur = -2, par = 0;
-  int n_own = 0, n_opp = 0, n_live = 0, n_ent = 0, cph = 1;
-  for (int it = it0; it < it1; ++it) {
-    const MvItem item = P.items[it];
-    IO cs_in[KH], cf_in[KH];
-#pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      cs_in[k] = nxs[k];
-      cf_in[k] = nxf[k];
-    }
-    if (it + 1 < it1) fetch(it + 1);
-    if (item.ctx < 0) {
-#pragma unroll
-      for (int k = 0; k < KH; ++k) {
-        int h = tid + k * BLOCK;
-        if (h < item.stride) out[item.out + h] = (IO)0;
-      }
-      continue;
-    }
-    if (item.ctx != cur || !DB) __syncthreads();   // previous rows no longer read segEnd / inputs
-    if (item.ctx != cur) {
-      const MvCtx C = P.ctx[item.ctx];
-      n_own = C.n_own;
-      n_opp = C.n_opp;
-      n_live = C.n_live;
-      n_ent = C.n_ent;
-      cph = C.cph;
-#pragma unroll
-      for (int k = 0; k < KH; ++k) {
-        const int h = tid + k * BLOCK;
-        if (h < n_own) {
-          qr[k] = P.q[C.q_off + h];
-          lo[k] = lam[C.lam_own_off + h];
-        } else {
-          qr[k] = make_uint4(0xffffu, 0, 0, 0);   // lt = -1: no output
-          lo[k] = (IO)0;
-        }
-        const int rv = h < n_opp ? (int)P.rank[C.rank_off + h] : -1;
-        lp[k] = h < n_opp ? lam[C.lam_opp_off + h] : (IO)0;
-        if (k & 1) rkp[k >> 1] |= (uint32_t)(uint16_t)(int16_t)rv << 16;
-        else rkp[k >> 1] = (uint32_t)(uint16_t)(int16_t)rv;
-      }
-#pragma unroll
-      for (int j = 0; j < KE; j += 2) {
-        const int e = tid * KE + j;
-        const int v0 = e < n_ent ? (int)P.seg[C.seg_off + e] : 0;
-        const int v1 = e + 1 < n_ent ? (int)P.seg[C.seg_off + e + 1] : 0;
-        srcp[j >> 1] = (uint32_t)(uint16_t)(int16_t)v0 | ((uint32_t)(uint16_t)(int16_t)v1 << 16);
-      }
-      for (int i = tid; i < C.n_seg; i += BLOCK) segEnd[i] = P.segend[C.segend_off + i];
-      cur = item.ctx;
-    }
-    IO* us = usb + par * mn;
-    IO* uf = ufb + par * mn;
-    double* scr = scratch + par * 3 * NW;
-    // phase 1: weighted opponent inputs scattered to strength order
-    const IO ks = (IO)item.ks, kf = (IO)item.kf;
-#pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      const int h = tid + k * BLOCK;
-      const int rk = (k & 1) ? hi16(rkp[k >> 1]) : lo16(rkp[k >> 1]);
-      if (h < n_opp && rk >= 0) {
-        const IO w = lp[k];
-        us[pd(rk)] = ks * w * cs_in[k];
-        uf[pd(rk)] = kf * w * cf_in[k];
-      }
-    }
-    __syncthreads();
-    // phase 2: segmented exclusive scan over the entry list (FP64 sums)
-    double rs = 0.0, rf = 0.0;
-    bool flag = false;
-#pragma unroll
-    for (int j = 0; j < KE; ++j) {
-      const int e = tid * KE + j;
-      if (e < n_ent) {
-        const int sidx = (j & 1) ? hi16(srcp[j >> 1]) : lo16(srcp[j >> 1]);
-        if (sidx >= 0) {
-          rs += (double)us[pd(sidx)];
-          rf += (double)uf[pd(sidx)];
-        } else {
-          flag = true;
-          rs = 0.0;
-          rf = 0.0;
-        }
-      }
-    }
-    double cs, cf;
-    block_seg_scan<BLOCK>(flag, rs, rf, scr, cs, cf);
-    rs = cs;
-    rf = cf;
-#pragma unroll
-    for (int j = 0; j < KE; ++j) {
-      const int e = tid * KE + j;
-      if (e < n_ent) {
-        const int sidx = (j & 1) ? hi16(srcp[j >> 1]) : lo16(srcp[j >> 1]);
-        Pc[pd(e)] = rs;
-        if (sidx >= 0) {
-          rs += (double)us[pd(sidx)];
-          rf += (double)uf[pd(sidx)];
-        } else {
-          segF[-1 - sidx] = rf;
-          rs = 0.0;
-          rf = 0.0;
-        }
-      }
-    }
-    __syncthreads();
-    // phase 3: read the prefix sums at each own hand's positions
-    const double tot_s = Pc[pd(n_live)];
-    const double tot_f = segF[0];
-#pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      const uint4 r = qr[k];
-      const int lt = lo16(r.x);
-      if (lt >= 0) {
-        double sd = Pc[pd(lt)] + Pc[pd(hi16(r.x))] - tot_s;
-        double fo = tot_f;
-        const int c0 = r.w & 255;
-        sd -= Pc[pd(lo16(r.y))] + Pc[pd(hi16(r.y))] - Pc[pd(segEnd[1 + c0])];
-        fo -= segF[1 + c0];
-        if (cph == 2) {
-          const int c1 = (r.w >> 8) & 255;
-          sd -= Pc[pd(lo16(r.z))] + Pc[pd(hi16(r.z))] - Pc[pd(segEnd[1 + c1])];
-          fo -= segF[1 + c1];
-          const int self = hi16(r.w);
-          if (self >= 0) fo += (double)uf[pd(self)];
-        }
-        acc[k] += sd + fo;
-      }
-    }
-    if (item.last) {
-#pragma unroll
-      for (int k = 0; k < KH; ++k) {
-        const int h = tid + k * BLOCK;
-        if (h < item.stride)
-          out[item.out + h] = (IO)(h < n_own ? P.scale * (double)lo[k] * acc[k] : 0.0);
-        acc[k] = 0.0;
-      }
-    }
-    if (DB) par ^= 1;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // chunk-aligned matvec (kernels 2 and 3; layout in McCtx)
@@ -1143,178 +867,6 @@ void k_mvg(GParams P0, const float* __restrict__ in0,
         __builtin_amdgcn_sched_barrier(0);
       }
       __syncthreads();   // the next group's staging overwrites the prefix slots
-    }
-  }
-}
-
-// Exclusive segmented scan over the 64 lanes of a wavefront (see
-// block_seg_scan).
-__device__ inline void wave_seg_scan(bool flag, double a, double b, double& ea, double& eb) {
-  const int lane = threadIdx.x & 63;
-  int f = flag ? 1 : 0;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    int f2 = shfl_up64(f, off);
-    double a2 = shfl_up64(a, off);
-    double b2 = shfl_up64(b, off);
-    if (lane >= off) {
-      if (!f) {
-        a += a2;
-        b += b2;
-      }
-      f |= f2;
-    }
-  }
-  double xa = shfl_up64(a, 1);
-  double xb = shfl_up64(b, 1);
-  ea = lane == 0 ? 0.0 : xa;
-  eb = lane == 0 ? 0.0 : xb;
-}
-
-// Wavefront-per-chunk form of k_matvec: a workgroup is one wavefront that owns
-// a chunk of output rows, so no row waits on another wavefront's barrier and
-// a CU keeps as many rows in flight as its LDS holds.  KH own/opponent hands
-// and KE scan entries per lane (the chunk's hand-count class bounds them).
-// Context metadata is read from global memory (L2-resident) per row.
-template <int KH, int KE, typename IO>
-__global__ __launch_bounds__(64) void k_matvec_w(MvParams P, const int32_t* __restrict__ chunks,
-                                                 const IO* __restrict__ in, IO* __restrict__ out,
-                                                 double* __restrict__ tick, int me, int mn, int ms) {
-  static_assert(KE % 2 == 0, "entries are packed in pairs");
-  if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1.0;
-  const int lane = threadIdx.x;
-  const int ch = chunks[blockIdx.x];
-  if (P.active && !P.active[P.blk_inst[ch]]) return;   // retired instance
-  const IO* __restrict__ lam = lam_of<IO>(P);
-  extern __shared__ double smem[];
-  double* Pc = smem;                      // [me]
-  double* segF = Pc + me;                 // [ms]
-  IO* us = (IO*)(segF + ms);              // [mn]
-  IO* uf = us + mn;                       // [mn]
-  int* segEnd = (int*)(uf + mn);          // [ms]
-
-  double acc[KH];
-#pragma unroll
-  for (int k = 0; k < KH; ++k) acc[k] = 0.0;
-  uint32_t srcp[KE / 2];
-  MvCtx C;
-  int cur = -2;
-  const int it0 = P.blk[ch], it1 = P.blk[ch + 1];
-  for (int it = it0; it < it1; ++it) {
-    const MvItem item = P.items[it];
-    if (item.ctx < 0) {
-#pragma unroll
-      for (int k = 0; k < KH; ++k) {
-        const int h = lane + 64 * k;
-        if (h < item.stride) out[item.out + h] = (IO)0;
-      }
-      continue;
-    }
-    __syncthreads();
-    if (item.ctx != cur) {
-      C = P.ctx[item.ctx];
-#pragma unroll
-      for (int j = 0; j < KE; j += 2) {
-        const int e = lane * KE + j;
-        const int v0 = e < C.n_ent ? (int)P.seg[C.seg_off + e] : 0;
-        const int v1 = e + 1 < C.n_ent ? (int)P.seg[C.seg_off + e + 1] : 0;
-        srcp[j >> 1] = (uint32_t)(uint16_t)(int16_t)v0 | ((uint32_t)(uint16_t)(int16_t)v1 << 16);
-      }
-      for (int i = lane; i < C.n_seg; i += 64) segEnd[i] = P.segend[C.segend_off + i];
-      cur = item.ctx;
-    }
-    // phase 1: weighted opponent inputs scattered to strength order
-    const bool has_s = item.in_s >= 0, has_f = item.in_f >= 0;
-    const IO ks = (IO)item.ks, kf = (IO)item.kf;
-#pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      const int h = lane + 64 * k;
-      if (h < C.n_opp) {
-        const int rk = (int)P.rank[C.rank_off + h];
-        if (rk >= 0) {
-          const IO w = lam[C.lam_opp_off + h];
-          us[pd(rk)] = has_s ? ks * w * in[item.in_s + h] : (IO)0;
-          uf[pd(rk)] = has_f ? kf * w * in[item.in_f + h] : (IO)0;
-        }
-      }
-    }
-    __syncthreads();
-    // phase 2: segmented exclusive scan over the entry list (FP64 sums)
-    double rs = 0.0, rf = 0.0;
-    bool flag = false;
-#pragma unroll
-    for (int j = 0; j < KE; ++j) {
-      const int e = lane * KE + j;
-      if (e < C.n_ent) {
-        const int sidx = (j & 1) ? hi16(srcp[j >> 1]) : lo16(srcp[j >> 1]);
-        if (sidx >= 0) {
-          rs += (double)us[pd(sidx)];
-          rf += (double)uf[pd(sidx)];
-        } else {
-          flag = true;
-          rs = 0.0;
-          rf = 0.0;
-        }
-      }
-    }
-    double cs, cf;
-    wave_seg_scan(flag, rs, rf, cs, cf);
-    rs = cs;
-    rf = cf;
-#pragma unroll
-    for (int j = 0; j < KE; ++j) {
-      const int e = lane * KE + j;
-      if (e < C.n_ent) {
-        const int sidx = (j & 1) ? hi16(srcp[j >> 1]) : lo16(srcp[j >> 1]);
-        Pc[pd(e)] = rs;
-        if (sidx >= 0) {
-          rs += (double)us[pd(sidx)];
-          rf += (double)uf[pd(sidx)];
-        } else {
-          segF[-1 - sidx] = rf;
-          rs = 0.0;
-          rf = 0.0;
-        }
-      }
-    }
-    __syncthreads();
-    // phase 3
-    const double tot_s = Pc[pd(C.n_live)];
-    const double tot_f = segF[0];
-#pragma unroll
-    for (int k = 0; k < KH; ++k) {
-      const int h = lane + 64 * k;
-      if (h < C.n_own) {
-        const uint4 r = P.q[C.q_off + h];
-        const int lt = lo16(r.x);
-        if (lt >= 0) {
-          double sd = Pc[pd(lt)] + Pc[pd(hi16(r.x))] - tot_s;
-          double fo = tot_f;
-          const int c0 = r.w & 255;
-          sd -= Pc[pd(lo16(r.y))] + Pc[pd(hi16(r.y))] - Pc[pd(segEnd[1 + c0])];
-          fo -= segF[1 + c0];
-          if (C.cph == 2) {
-            const int c1 = (r.w >> 8) & 255;
-            sd -= Pc[pd(lo16(r.z))] + Pc[pd(hi16(r.z))] - Pc[pd(segEnd[1 + c1])];
-            fo -= segF[1 + c1];
-            const int self = hi16(r.w);
-            if (self >= 0) fo += (double)uf[pd(self)];
-          }
-          acc[k] += sd + fo;
-        }
-      }
-    }
-    if (item.last) {
-#pragma unroll
-      for (int k = 0; k < KH; ++k) {
-        const int h = lane + 64 * k;
-        if (h < item.stride) {
-          double v = 0.0;
-          if (h < C.n_own) v = P.scale * (double)lam[C.lam_own_off + h] * acc[k];
-          out[item.out + h] = (IO)v;
-        }
-        acc[k] = 0.0;
-      }
     }
   }
 }
@@ -2200,17 +1752,9 @@ struct DBuf {
   }
 };
 
-struct DevDir {
+struct DevDir {                 // the row chunks of one direction (the layouts' shared item list)
   DBuf<MvItem> items;
-  DBuf<int32_t> blk, blk_inst;
-  DBuf<MvCtx> ctx;
-  DBuf<QueryRec16> q;
-  DBuf<int16_t> rank, seg;
-  DBuf<int32_t> segend;
-  int nblk = 0, max_ent = 0, max_n = 0, max_seg = 0;
-  DBuf<int32_t> cls_chunks[MvDir::kClasses];
-  int cls_count[MvDir::kClasses] = {0, 0, 0};
-  int cls_ent[MvDir::kClasses] = {0, 0, 0}, cls_n[MvDir::kClasses] = {0, 0, 0};
+  int nblk = 0;
 };
 
 struct DevMc {                  // chunk-aligned matvec layout of one direction
@@ -2348,7 +1892,7 @@ static int upload_mc_active(Game* g, int d) {
 static int upload_mc(Game* g, int d) {
   HostGame& hg = g->hg;
   DevMc& E = g->dm[d];
-  const int block = hg.mv_kernel == 3 ? 512 : 256;   // kernel 4: its FP64 form runs kernel 2
+  const int block = hg.mc_block;
   std::string m;
   int rc = build_mc_layout(hg, d, block, m);
   if (rc) return fail(rc, m);
@@ -2427,40 +1971,13 @@ static int upload_grp(Game* g, int d) {
 static int upload_dir(Game* g, int d) {
   int rc;
   HostGame& hg = g->hg;
-  {
-    MvDir& D = hg.dir[d];
-    const int p = d, q = 1 - d;
-    const std::vector<int64_t>* lam_off = g->lam_off;
-    // fill lambda offsets: contexts are emitted instance by instance
-    size_t ci = 0;
-    for (size_t ii = 0; ii < hg.inst.size(); ++ii) {
-      for (int c = 0; c < hg.inst[ii].n_ctx; ++c, ++ci) {
-        D.ctx[ci].lam_own_off = lam_off[p][ii];
-        D.ctx[ci].lam_opp_off = lam_off[q][ii];
-      }
-    }
-    DevDir& E = g->dd[d];
-    if ((rc = E.items.upload(D.items)) || (rc = E.blk.upload(D.blk)) || (rc = E.blk_inst.upload(D.blk_inst)) ||
-        (rc = E.ctx.upload(D.ctx)) ||
-        (rc = E.q.upload(D.q)) || (rc = E.rank.upload(D.rank)) || (rc = E.seg.upload(D.seg)) ||
-        (rc = E.segend.upload(D.segend)))
-      return rc;
-    E.nblk = (int)D.blk.size() - 1;
-    E.max_ent = D.max_ent;
-    E.max_n = D.max_n;
-    E.max_seg = D.max_seg;
-    for (int c = 0; c < MvDir::kClasses; ++c) {
-      if ((rc = E.cls_chunks[c].upload(D.cls_chunks[c]))) return rc;
-      E.cls_count[c] = (int)D.cls_chunks[c].size();
-      E.cls_ent[c] = D.cls_ent[c];
-      E.cls_n[c] = D.cls_n[c];
-    }
-  }
+  const MvDir& D = hg.dir[d];
+  DevDir& E = g->dd[d];
+  if ((rc = E.items.upload(D.items))) return rc;
+  E.nblk = (int)D.blk.size() - 1;
   g->dg[d].built = false;
   if (hg.mv_kernel == 4 && (rc = upload_grp(g, d))) return rc;
-  if (hg.mv_kernel >= 2) return upload_mc(g, d);
-  g->dm[d].block = 0;
-  return PMX_OK;
+  return upload_mc(g, d);
 }
 
 // Block records of one player's regret launches for the instances marked in
@@ -2624,62 +2141,12 @@ static int upload_game(Game* g) {
 // launchers
 // ---------------------------------------------------------------------------
 static MvParams mv_params(Game* g, int d, double scale) {
-  DevDir& E = g->dd[d];
   MvParams P;
-  P.items = E.items.p;
-  P.blk = E.blk.p;
-  P.ctx = E.ctx.p;
-  P.q = (const uint4*)E.q.p;
-  P.rank = E.rank.p;
-  P.seg = E.seg.p;
-  P.segend = E.segend.p;
-  P.lam = g->lam.p;
-  P.lamf = g->lamf.p;
   P.scale = scale;
   P.dir = d;
-  P.blk_inst = E.blk_inst.p;
   P.active = nullptr;
-  P.nblk = E.nblk;
-  P.max_ent = E.max_ent;
-  P.max_n = E.max_n;
-  P.max_seg = E.max_seg;
+  P.nblk = g->dd[d].nblk;
   return P;
-}
-
-template <int BLOCK, typename IO>
-static size_t mv_lds(const MvParams& a, const MvParams& b) {
-  size_t me = pd(std::max(a.max_ent, b.max_ent)) + 1, mn = pd(std::max(a.max_n, b.max_n)) + 1,
-         ms = std::max(a.max_seg, b.max_seg);
-  const size_t bufs = sizeof(IO) == 4 ? 2 : 1;
-  return sizeof(double) * (me + ms + 6 * (BLOCK / 64)) + 2 * bufs * mn * sizeof(IO) + sizeof(int) * ms;
-}
-
-template <int KH, int KE, typename IO>
-static int launch_mv_w_class(Game* g, const MvParams& P, int c, const IO* in, IO* out, hipStream_t s,
-                             double* tick) {
-  DevDir& E = g->dd[P.dir];
-  if (E.cls_count[c] == 0) return PMX_OK;
-  if (E.cls_ent[c] > KE * 64 || E.cls_n[c] > KH * 64)
-    return fail(PMX_EINVAL, "row chunk exceeds its size class");
-  const int me = pd(std::max(E.cls_ent[c], 1)) + 1, mn = pd(std::max(E.cls_n[c], 1)) + 1, ms = E.max_seg;
-  const size_t lds = sizeof(double) * (me + ms) + 2 * sizeof(IO) * mn + sizeof(int) * ms;
-  if (lds > 64 * 1024) return fail(PMX_EINVAL, "wave matvec LDS footprint exceeds 64 KB");
-  hipLaunchKernelGGL((k_matvec_w<KH, KE, IO>), dim3(E.cls_count[c]), dim3(64), lds, s, P,
-                     E.cls_chunks[c].p, in, out, tick, me, mn, ms);
-  HIP_TRY(hipGetLastError());
-  return PMX_OK;
-}
-
-template <typename IO>
-static int launch_mv_w(Game* g, const MvParams& P, const IO* in, IO* out, hipStream_t s,
-                       double* tick) {
-  int rc;
-  // the iteration tick belongs to the first launch only
-  if ((rc = launch_mv_w_class<8, 26, IO>(g, P, 0, in, out, s, tick))) return rc;
-  if (g->dd[P.dir].cls_count[0]) tick = nullptr;
-  if ((rc = launch_mv_w_class<16, 50, IO>(g, P, 1, in, out, s, tick))) return rc;
-  if (g->dd[P.dir].cls_count[1]) tick = nullptr;
-  return launch_mv_w_class<20, 62, IO>(g, P, 2, in, out, s, tick);
 }
 
 static McParams mc_params(Game* g, int d, const MvParams& like, int c) {
@@ -2834,28 +2301,10 @@ static int launch_mv(Game* g, MvParams P0, const IO* in0, IO* out0, MvParams P1,
   if constexpr (sizeof(IO) == 4) {
     if (g->hg.mv_kernel == 4) return launch_grp(g, P0, in0, out0, P1, in1, out1, s, tick);
   }
-  // the chunk-aligned layout, unless its FP64 form needs more LDS than a
-  // workgroup may take here (then the workgroup kernel on the sentinel entry
-  // list serves the call)
-  if (g->hg.mv_kernel >= 2 && mc_lds_max<IO>(g) <= (size_t)g->max_lds)
-    return launch_mc<IO>(g, P0, in0, out0, P1, in1, out1, s, tick);
-  if (g->hg.mv_kernel == 1) {
-    int rc;
-    if (P0.nblk && (rc = launch_mv_w<IO>(g, P0, in0, out0, s, tick))) return rc;
-    if (P0.nblk) tick = nullptr;
-    if (P1.nblk && (rc = launch_mv_w<IO>(g, P1, in1, out1, s, tick))) return rc;
-    return PMX_OK;
-  }
-  // shape checks: every hand and entry must have a thread slot
-  const int mn = std::max(P0.max_n, P1.max_n), me = std::max(P0.max_ent, P1.max_ent);
-  constexpr int B = 512, KH = 3, KE = 8;
-  if (mn > KH * B || me > KE * B) return fail(PMX_EINVAL, "instance too large for the matvec kernel");
-  size_t lds = mv_lds<B, IO>(P0, P1);
-  if (lds > 64 * 1024) return fail(PMX_EINVAL, "matvec LDS footprint exceeds 64 KB");
-  hipLaunchKernelGGL((k_matvec<B, KH, KE, IO>), dim3(nb), dim3(B), lds, s, P0, in0, out0, P1, in1,
-                     out1, tick);
-  HIP_TRY(hipGetLastError());
-  return PMX_OK;
+  if (g->hg.mv_kernel < 2 || g->hg.mv_kernel > 4) return fail(PMX_ESTATE, "no matvec schedule set");
+  if (mc_lds_max<IO>(g) > (size_t)g->max_lds)
+    return fail(PMX_EINVAL, "matvec workgroup needs more LDS than this device gives a workgroup");
+  return launch_mc<IO>(g, P0, in0, out0, P1, in1, out1, s, tick);
 }
 
 static MvParams empty_params(const MvParams& like) {
@@ -3143,7 +2592,7 @@ int game_hand_meta(const Game* g, int32_t instance, int32_t ctx, int32_t player,
 int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk) {
   int rc = ensure_device(g);
   if (rc) return rc;
-  if (kernel < 0 || kernel > 4) return fail(PMX_EINVAL, "kernel must be in [0, 4]");
+  if (kernel < 2 || kernel > 4) return fail(PMX_EINVAL, "kernel must be in [2, 4]");
   if (rows_per_chunk < 1 || rows_per_chunk > 64) return fail(PMX_EINVAL, "rows_per_chunk must be in [1, 64]");
   HIP_TRY(hipDeviceSynchronize());
   if (g->graph_exec) {
@@ -3155,11 +2604,14 @@ int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk) {
     g->graph = nullptr;
   }
   g->hg.mv_kernel = kernel;
-  g->hg.rows_per_block = rows_per_chunk;
-  if (kernel == 4) g->hg.groups_per_chunk = rows_per_chunk;
+  if (kernel == 4) {
+    g->hg.groups_per_chunk = rows_per_chunk;   // the FP64 products keep their chunk-aligned layout
+  } else {
+    g->hg.rows_per_block = rows_per_chunk;
+    g->hg.mc_block = kernel == 3 ? 512 : 256;
+  }
   for (int d = 0; d < 2; ++d) {
-    build_matvec_plan(g->hg, d, rows_per_chunk);
-    classify_chunks(g->hg.dir[d]);
+    build_matvec_plan(g->hg, d, g->hg.rows_per_block);
     if ((rc = upload_dir(g, d))) return rc;
   }
   return PMX_OK;
@@ -3215,7 +2667,7 @@ int solver_set_task_rows(Game* g, int32_t rows) {
 int game_get_tuning(const Game* g, int32_t* kernel, int32_t* rows_per_chunk) {
   if (!g || !kernel || !rows_per_chunk) return fail(PMX_EINVAL, "null argument");
   *kernel = g->hg.mv_kernel;
-  *rows_per_chunk = g->hg.rows_per_block;
+  *rows_per_chunk = g->hg.mv_kernel == 4 ? g->hg.groups_per_chunk : g->hg.rows_per_block;
   return PMX_OK;
 }
 

@@ -345,13 +345,14 @@ struct RmPlan {                         // one player
 struct HostGame {
   std::vector<Built> inst;
   int64_t elems[2] = {0, 0};
-  int rows_per_block = 1;
-  int mv_kernel = 2;                    // 0 / 1: sentinel entry list, workgroup / wavefront per row
-                                        // chunk; 2 / 3: chunk-aligned layout, 256 / 512 threads
+  int mv_kernel = 4;                    // FP32 products: 2 / 3 chunk-aligned layout with 256 / 512
+                                        // threads, 4 grouped layout
+  int rows_per_block = 1;               // chunk-aligned layout (also the FP64 products): rows per chunk
+  int mc_block = 256;                   // chunk-aligned layout: threads per workgroup
+  int groups_per_chunk = 1;             // kernel 4: groups per workgroup
   MvDir dir[2];
   McDir mc[2];
   GrpDir grp[2];
-  int groups_per_chunk = 8;             // kernel 4: groups per workgroup
   TpPlan tp[2];
   RmPlan rm[2];
   int task_rows = kTaskRowsMax;
@@ -366,7 +367,6 @@ void build_hand_meta(Built& b);
 int build_game(const GameDesc* descs, int n, HostGame& hg, std::string& msg);
 int default_rows_per_block(int64_t rows, int kernel);
 int default_mv_kernel(int64_t mean_hands);
-void classify_chunks(MvDir& D);
 void build_matvec_plan(HostGame& hg, int d, int rows_per_block);
 int build_rm_plan(HostGame& hg, int p, int task_rows, std::string& msg);
 int build_mc_layout(HostGame& hg, int d, int block, std::string& msg);

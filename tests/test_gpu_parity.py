@@ -136,7 +136,7 @@ def test_matvec_river_full_size():
     _check_matvecs(pmx, I.config(1), seed=3)
 
 
-@pytest.mark.parametrize("kernel", [2, 3, 0, 4])
+@pytest.mark.parametrize("kernel", [2, 3, 4])
 def test_matvec_max_hands(kernel):
     """The largest hand lists a game may hold (1280 per player, the top
     hands-per-thread class of each workgroup size) on a 57-card deck."""
@@ -167,7 +167,7 @@ def test_matvec_max_hands(kernel):
     g.close()
 
 
-@pytest.mark.parametrize("kernel,rows", [(2, 1), (3, 2), (0, 1), (4, 1), (4, 8)])
+@pytest.mark.parametrize("kernel,rows", [(2, 1), (3, 2), (4, 1), (4, 8)])
 def test_matvec_extreme_ragged_batch(kernel, rows):
     """One batch holding a 2-vs-3-hand instance, a 1280-hand instance on a
     57-card deck and a mid-size one (every hands-per-thread class at once);
@@ -235,7 +235,7 @@ def test_matvec_batched_uneven():
     g.close()
 
 
-TR_SCHEDULES = [(0, 8), (2, 4), (2, 8), (3, 4), (3, 8), (4, 4), (4, 8)]   # the candidates the bench tunes over
+TR_SCHEDULES = [(2, 4), (2, 8), (3, 4), (3, 8), (4, 1), (4, 2), (4, 8)]   # the candidates the bench tunes over
 
 
 def test_matvec_turn_river_full_size():
@@ -561,13 +561,12 @@ def test_solver_state_round_trip_and_reset():
     g.close()
 
 
-@pytest.mark.parametrize("kernel,rows", [(1, 1), (1, 3), (0, 2), (0, 5), (2, 1), (2, 3), (3, 1), (3, 4), (4, 1), (4, 3), (4, 8)])
+@pytest.mark.parametrize("kernel,rows", [(2, 1), (2, 3), (3, 1), (3, 4), (4, 1), (4, 3), (4, 8)])
 def test_matvec_schedules_agree(kernel, rows):
-    """Every matvec schedule (workgroup or wavefront per row chunk with the
-    sentinel entry list, or the chunk-aligned layout with 256- or 512-thread
-    workgroups; any chunk length) gives the oracle's products on a batch of
-    uneven games, including a turn + river game whose rows span several board
-    contexts."""
+    """Every matvec schedule (the chunk-aligned layout with 256- or 512-thread
+    workgroups, or the grouped layout; any chunk length) gives the oracle's
+    products on a batch of uneven games, including a turn + river game whose
+    rows span several board contexts."""
     pmx = _need_gpu()
     descs = [I.river_config(seed=500 + i, n_keep=(90 + 170 * i, 700 - 120 * i),
                             bet_fracs=((0.5,), (0.33, 1.0), (0.75, 1.5, 2.0))[i % 3],
