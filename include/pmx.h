@@ -308,6 +308,23 @@ int saddle_gap(Game* g, double* gap, double* br1, double* br2, void* stream);
 int saddle_gap_of(Game* g, const double* x_dev, const double* y_dev, double* gap,
                   double* br1, double* br2, void* stream);
 
+/* saddle_gap_of for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels, with the FP64 gradients, stage rows, per-hand values and
+ * per-instance sums in one static device array of 32 MiB per GPU (set up at
+ * game_create on the game's device, held until the process ends).  The
+ * call allocates nothing, on the device or the host: br1 and br2 (host
+ * arrays, one entry per instance) are required and receive the sums; gap
+ * may be NULL.  PMX_EINVAL when the game needs more scratch than the array
+ * holds (8 bytes per element of both players' vectors, deep-piece stage
+ * rows and hands, each part rounded up to 256 bytes; about 4 M elements:
+ * single river endgames and small batches fit, the batch of 512 and the
+ * turn + river game do not).  Calls on one GPU share its array: calls that
+ * overlap on one GPU (other streams or threads) race.  Synchronizes
+ * `stream`. */
+int saddle_gap_of_static(Game* g, const double* x_dev, const double* y_dev, double* gap,
+                         double* br1, double* br2, void* stream);
+
 /* Copy solver state to / from host arrays (NULL skips a field).  Regrets and
  * current plans are FP32, averages FP64 (weighted sums).  t = iterations
  * done; wsum = sum of the averaging weights of all iterations, which is each

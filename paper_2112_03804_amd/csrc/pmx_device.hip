@@ -37,6 +37,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2409,32 +2410,35 @@ static TpParams tp_params_for(Game* g, int p, const int2* blocks, const int32_t*
 
 // Best-response values per hand and their per-instance sums; need (device,
 // NULL: all) limits the work to the instances flagged.
-static int br_values(Game* g, int p, double* gvec, hipStream_t s, const int32_t* need) {
+// Best-response values of player p from the FP64 gradient gvec; stage_d
+// (the deep pieces' root values) and hv (per-hand values) are scratch, and
+// the per-instance sums go to br_out[0 .. instances).
+static int br_values(Game* g, int p, double* gvec, double* stage_d, double* hv, double* br_out, hipStream_t s,
+                     const int32_t* need) {
   DevTp& E = g->dt[p];
   if (p == 0) {
     if (E.n_single)
       hipLaunchKernelGGL((k_br<0, true>), dim3(E.n_single), dim3(TPB), 0, s,
-                         tp_params_for(g, p, E.b_single.p, need), gvec, E.stage_d.p, E.hv.p);
+                         tp_params_for(g, p, E.b_single.p, need), gvec, stage_d, hv);
     if (E.n_deep)
       hipLaunchKernelGGL((k_br<1, true>), dim3(E.n_deep), dim3(TPB), 0, s,
-                         tp_params_for(g, p, E.b_deep.p, need), gvec, E.stage_d.p, E.hv.p);
+                         tp_params_for(g, p, E.b_deep.p, need), gvec, stage_d, hv);
     if (E.n_top)
       hipLaunchKernelGGL((k_br<2, true>), dim3(E.n_top), dim3(TPB), 0, s,
-                         tp_params_for(g, p, E.b_top.p, need), gvec, E.stage_d.p, E.hv.p);
+                         tp_params_for(g, p, E.b_top.p, need), gvec, stage_d, hv);
   } else {
     if (E.n_single)
       hipLaunchKernelGGL((k_br<0, false>), dim3(E.n_single), dim3(TPB), 0, s,
-                         tp_params_for(g, p, E.b_single.p, need), gvec, E.stage_d.p, E.hv.p);
+                         tp_params_for(g, p, E.b_single.p, need), gvec, stage_d, hv);
     if (E.n_deep)
       hipLaunchKernelGGL((k_br<1, false>), dim3(E.n_deep), dim3(TPB), 0, s,
-                         tp_params_for(g, p, E.b_deep.p, need), gvec, E.stage_d.p, E.hv.p);
+                         tp_params_for(g, p, E.b_deep.p, need), gvec, stage_d, hv);
     if (E.n_top)
       hipLaunchKernelGGL((k_br<2, false>), dim3(E.n_top), dim3(TPB), 0, s,
-                         tp_params_for(g, p, E.b_top.p, need), gvec, E.stage_d.p, E.hv.p);
+                         tp_params_for(g, p, E.b_top.p, need), gvec, stage_d, hv);
   }
   const int ni = (int)g->hg.inst.size();
-  hipLaunchKernelGGL(k_sum_instances, dim3(ni), dim3(256), 0, s, E.hv.p, g->inst_hand_off[p].p,
-                     g->br_inst.p + (size_t)p * ni);
+  hipLaunchKernelGGL(k_sum_instances, dim3(ni), dim3(256), 0, s, hv, g->inst_hand_off[p].p, br_out);
   HIP_TRY(hipGetLastError());
   return PMX_OK;
 }
@@ -2473,6 +2477,8 @@ extern "C" {
 
 const char* pmx_last_error(void) { return g_err.c_str(); }
 
+static int static_scratch(int dev, double** out);
+
 static int create_common(const GameDesc* descs, int32_t n, bool device, Game** out) {
   if (!out) return fail(PMX_EINVAL, "out is NULL");
   if (!descs || n < 1) return fail(PMX_EINVAL, "need at least one descriptor");
@@ -2497,6 +2503,9 @@ static int create_common(const GameDesc* descs, int32_t n, bool device, Game** o
       g->max_lds = lds;
     int rc = upload_game(g.get());
     if (rc) return rc;
+    // set-up of the allocation-free gap on this device (once per device)
+    double* scr = nullptr;
+    if ((rc = static_scratch(dev, &scr))) return rc;
     hipStream_t s = nullptr;
     if ((rc = solver_reset(g.get(), s))) return rc;
     HIP_TRY(hipStreamSynchronize(s));
@@ -2906,19 +2915,38 @@ static void inst_range(const Game* g, int p, size_t i, int64_t* b, int64_t* e) {
 // instances flagged, whose row chunks must all be in the solver's launch
 // lists (the matvec then takes those lists); need_host is the same set on
 // the host, and only its instances are written.
+// Device scratch of an FP64 gap: both players' gradients, deep-piece stage
+// rows and per-hand values, and the per-instance sums (2 x instances).
+struct GapBufs {
+  double* gd[2];
+  double* stage[2];
+  double* hv[2];
+  double* br;
+};
+static GapBufs game_gap_bufs(Game* g) {
+  GapBufs B;
+  for (int p = 0; p < 2; ++p) {
+    B.gd[p] = g->gd[p].p;
+    B.stage[p] = g->dt[p].stage_d.p;
+    B.hv[p] = g->dt[p].hv.p;
+  }
+  B.br = g->br_inst.p;
+  return B;
+}
+
 static int gap_from_sums(Game* g, const double* xsum, const double* ysum, const double* scale,
                          const int32_t* need_dev, const int32_t* need_host, double* gap, double* br1,
-                         double* br2, hipStream_t s) {
+                         double* br2, hipStream_t s, const GapBufs& B) {
   int rc;
   MvParams PA = mv_params(g, 0, 1.0), PT = mv_params(g, 1, 1.0);
   PA.active = PT.active = need_dev;
-  if ((rc = launch_mv<double>(g, PA, ysum, g->gd[0].p, empty_params(PA), nullptr, nullptr, s))) return rc;
-  if ((rc = launch_mv<double>(g, PT, xsum, g->gd[1].p, empty_params(PT), nullptr, nullptr, s))) return rc;
-  if ((rc = br_values(g, 0, g->gd[0].p, s, need_dev))) return rc;
-  if ((rc = br_values(g, 1, g->gd[1].p, s, need_dev))) return rc;
   const int ni = (int)g->hg.inst.size();
+  if ((rc = launch_mv<double>(g, PA, ysum, B.gd[0], empty_params(PA), nullptr, nullptr, s))) return rc;
+  if ((rc = launch_mv<double>(g, PT, xsum, B.gd[1], empty_params(PT), nullptr, nullptr, s))) return rc;
+  if ((rc = br_values(g, 0, B.gd[0], B.stage[0], B.hv[0], B.br, s, need_dev))) return rc;
+  if ((rc = br_values(g, 1, B.gd[1], B.stage[1], B.hv[1], B.br + ni, s, need_dev))) return rc;
   std::vector<double> h(2 * (size_t)ni);
-  HIP_TRY(hipMemcpyAsync(h.data(), g->br_inst.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h.data(), B.br, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   for (int i = 0; i < ni; ++i) {
     if (need_host && !need_host[i]) continue;
@@ -2999,7 +3027,7 @@ int saddle_gap(Game* g, double* gap, double* br1, double* br2, void* stream) {
       ya = g->sd[1].p;
     }
     if ((rc = gap_from_sums(g, xa, ya, scale.data(), need_dev, need.data(), g->gap_c.data(),
-                            g->br1_c.data(), g->br2_c.data(), s)))
+                            g->br1_c.data(), g->br2_c.data(), s, game_gap_bufs(g))))
       return rc;
     for (size_t i = 0; i < ni; ++i) g->gap_ok[i] = 1;
   }
@@ -3011,12 +3039,87 @@ int saddle_gap(Game* g, double* gap, double* br1, double* br2, void* stream) {
   return PMX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// the gap of given strategies with no allocation (for callers that cannot
+// allocate device memory)
+// ---------------------------------------------------------------------------
+// Scratch of saddle_gap_of_static: one array per GPU the library runs on,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, once per
+// device with that device current, and only that address is used.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_dev;   // per device id; nullptr until resolved
+
+static int static_scratch(int dev, double** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    HIP_TRY(hipSetDevice(dev));
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(PMX_EDEVICE, "hipGetSymbolAddress gave no address for the static scratch");
+    g_scratch_dev[dev] = (double*)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return PMX_OK;
+}
+
+int saddle_gap_of_static(Game* g, const double* x, const double* y, double* gap, double* br1, double* br2,
+                         void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!x || !y) return fail(PMX_EINVAL, "null vector");
+  if (!br1 || !br2) return fail(PMX_EINVAL, "br1 and br2 are required (they receive the per-instance sums)");
+  double* base = nullptr;
+  if ((rc = static_scratch(g->device_id, &base))) return rc;
+  // carve the FP64 gradients, stage rows, per-hand values and the
+  // per-instance sums out of the static array, each on 256-byte boundaries
+  const int ni = (int)g->hg.inst.size();
+  size_t need[7] = {(size_t)g->hg.elems[0], (size_t)g->hg.elems[1], g->dt[0].stage_d.n, g->dt[1].stage_d.n,
+                    g->dt[0].hv.n, g->dt[1].hv.n, 2 * (size_t)ni};
+  double* part[7];
+  size_t off = 0;
+  for (int k = 0; k < 7; ++k) {
+    part[k] = base + off;
+    off += (need[k] + 31) / 32 * 32;
+  }
+  if (off * sizeof(double) > kStaticScratchBytes)
+    return fail(PMX_EINVAL, "saddle_gap_of_static: the game needs " + std::to_string(off * sizeof(double)) +
+                                " bytes of scratch; the static buffer holds " +
+                                std::to_string(kStaticScratchBytes) + " (use saddle_gap_of)");
+  GapBufs B;
+  B.gd[0] = part[0];
+  B.gd[1] = part[1];
+  B.stage[0] = part[2];
+  B.stage[1] = part[3];
+  B.hv[0] = part[4];
+  B.hv[1] = part[5];
+  B.br = part[6];
+  hipStream_t s = (hipStream_t)stream;
+  MvParams PA = mv_params(g, 0, 1.0), PT = mv_params(g, 1, 1.0);
+  if ((rc = launch_mv<double>(g, PA, y, B.gd[0], empty_params(PA), nullptr, nullptr, s))) return rc;
+  if ((rc = launch_mv<double>(g, PT, x, B.gd[1], empty_params(PT), nullptr, nullptr, s))) return rc;
+  if ((rc = br_values(g, 0, B.gd[0], B.stage[0], B.hv[0], B.br, s, nullptr))) return rc;
+  if ((rc = br_values(g, 1, B.gd[1], B.stage[1], B.hv[1], B.br + ni, s, nullptr))) return rc;
+  // the sums straight into the caller's arrays (no host buffer either)
+  HIP_TRY(hipMemcpyAsync(br1, B.br, (size_t)ni * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(br2, B.br + ni, (size_t)ni * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < ni; ++i) {
+    if (!std::isfinite(br1[i]) || !std::isfinite(br2[i])) return fail(PMX_ENUMERIC, "non-finite best response");
+    if (gap) gap[i] = br1[i] - br2[i];
+  }
+  return PMX_OK;
+}
+
 int saddle_gap_of(Game* g, const double* x, const double* y, double* gap, double* br1, double* br2,
                   void* stream) {
   int rc = ensure_device(g);
   if (rc) return rc;
   if (!x || !y) return fail(PMX_EINVAL, "null vector");
-  return gap_from_sums(g, x, y, nullptr, nullptr, nullptr, gap, br1, br2, (hipStream_t)stream);
+  return gap_from_sums(g, x, y, nullptr, nullptr, nullptr, gap, br1, br2, (hipStream_t)stream, game_gap_bufs(g));
 }
 
 int solver_get_state(Game* g, int32_t player, float* regret, float* plan, double* avg_sum, int32_t* t,

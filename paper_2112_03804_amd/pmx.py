@@ -73,7 +73,7 @@ EXPORTS = [
     "game_create", "game_create_batch", "game_create_host", "game_destroy",
     "game_num_instances", "game_layout", "game_terminals", "game_hand_meta",
     "matvec_A", "matvec_AT", "matvec_A_f64", "matvec_AT_f64", "matvec_pair",
-    "solver_reset", "solver_step", "saddle_gap", "saddle_gap_of",
+    "solver_reset", "solver_step", "saddle_gap", "saddle_gap_of", "saddle_gap_of_static",
     "solver_get_state", "solver_set_state", "solver_get_weights", "solver_set_weights",
     "get_average_strategy",
     "set_initial_strategy", "pmx_last_error", "game_tune", "game_get_tuning",
@@ -111,6 +111,7 @@ def lib():
     L.solver_set_params.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32]
     L.saddle_gap.argtypes = [vp, _c_f64p, _c_f64p, _c_f64p, vp]
     L.saddle_gap_of.argtypes = [vp, vp, vp, _c_f64p, _c_f64p, _c_f64p, vp]
+    L.saddle_gap_of_static.argtypes = [vp, vp, vp, _c_f64p, _c_f64p, _c_f64p, vp]
     L.solver_get_state.argtypes = [vp, ctypes.c_int32, _c_f32p, _c_f32p, _c_f64p, _c_i32p, _c_f64p]
     L.solver_set_state.argtypes = [vp, ctypes.c_int32, _c_f32p, _c_f32p, _c_f64p, ctypes.c_int32,
                                    ctypes.c_double]
@@ -365,6 +366,14 @@ class Game:
         _check(lib().saddle_gap_of(self._h, _dptr(x), _dptr(y), _ptr(gap, ctypes.c_double),
                                    _ptr(b1, ctypes.c_double), _ptr(b2, ctypes.c_double),
                                    _stream(stream)))
+        return gap, b1, b2
+
+    def saddle_gap_of_static(self, x, y, stream=None):
+        n = self.n_instances
+        gap, b1, b2 = (np.zeros(n) for _ in range(3))
+        _check(lib().saddle_gap_of_static(self._h, _dptr(x), _dptr(y), _ptr(gap, ctypes.c_double),
+                                          _ptr(b1, ctypes.c_double), _ptr(b2, ctypes.c_double),
+                                          _stream(stream)))
         return gap, b1, b2
 
     def solver_get_state(self, player: int):
