@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 # known size (profiles/matvec_pair_traffic_counters.md).  They describe the
 # kernel sources whose code (comments and whitespace removed) has the SHA-1
 # recorded here and are reported as null for any other version of that code.
-TRAFFIC = {"sources_sha1": "a5a7042461077e7be5be6559e39d2750cc55c2be", "river": 1637386, "batch": 449587515}
+TRAFFIC = {"sources_sha1": "48e40e99319bca55ab3954f59b5b7cd56907c237", "river": 1415219, "batch": 321993014}
 TRAFFIC_SOURCES = ("paper_2112_03804_amd/csrc/pmx_device.hip", "paper_2112_03804_amd/csrc/host_build.cpp")
 
 
@@ -57,6 +57,14 @@ def sources_sha1(root=None):
         text = re.sub(r"//[^\n]*", " ", text)
         h.update(" ".join(text.split()).encode())
     return h.hexdigest()
+
+
+def kernel_label(sched):
+    """The matvec kernel a schedule (kernel, rows) launches."""
+    k, r = int(sched[0]), int(sched[1])
+    if k == 4:
+        return f"k_mvg (matvec_pair launch, schedule 4:{r}, grouped layout)"
+    return f"k_mvc (matvec_pair launch, schedule {k}:{r}, chunk-aligned layout)"
 
 
 def measured_traffic(key):
@@ -325,7 +333,7 @@ def batched_leg(args, stream):
         "matvec_pairs_per_s": len(descs) / (it_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("batch"),
-                     "kernel": "k_mvc (matvec_pair launch, schedule %d:%d)" % tuple(sched),
+                     "kernel": kernel_label(sched),
                      "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair},
         "time_to_gap_batched_s": ttg_batched,
         "time_to_gap_batched_no_retirement_s": ttg_noretire,
@@ -408,7 +416,7 @@ def turn_river_leg(args, stream):
            "roofline": {"bound": "hbm", "achieved": bytes_pair / (pair_us * 1e-6) / 1e9,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": bytes_pair / (pair_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
-                        "kernel": "k_mvc (matvec_pair launch, schedule %d:%d)" % tuple(sched),
+                        "kernel": kernel_label(sched),
                         "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair},
            "matvec_pairs_per_s": 1e6 / pair_us,
            "iteration_ms": it_ms,
@@ -506,10 +514,7 @@ def pmc_probe(args):
     for _ in range(5):
         b.copy_(a)
     torch.cuda.synchronize()
-    games = [("river", pmx.Game(I.config(1)))]
-    if not args.no_batched:
-        gb = pmx.Game(I.batched_configs(args.batch))
-        games.append(("batch", gb))
+    games = [("river", pmx.Game(I.config(1))), ("batch", pmx.Game(I.batched_configs(args.batch)))]
     for name, g in games:
         rng = np.random.default_rng(0)
         y = torch.from_numpy(rng.random(g.elems[1]).astype(np.float32)).cuda()
@@ -589,6 +594,40 @@ def river_leg(args, stream):
     pair_us = e0.elapsed_time(e1) * 1e3 / reps
     bytes_pair = algorithmic_bytes_pair(L)
 
+    # Technique B's explicit factors (Table 1's size metric) and their FP64
+    # product on the GPU beside the structured FP64 and FP32 products
+    t0 = time.perf_counter()
+    tb_sizes = g.tb_build()
+    tb_build_s = time.perf_counter() - t0
+    yd, xd = y.double(), x.double()
+    Ayd = torch.empty(g.elems[0], dtype=torch.float64, device="cuda")
+    ATxd = torch.empty(g.elems[1], dtype=torch.float64, device="cuda")
+
+    def pair_time(fa, fat, reps=200):
+        for _ in range(10):
+            fa(yd, Ayd)
+            fat(xd, ATxd)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fa(yd, Ayd)
+            fat(xd, ATxd)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    tb_us = pair_time(g.matvec_A_tb, g.matvec_AT_tb)
+    f64_us = pair_time(g.matvec_A_f64, g.matvec_AT_f64)
+    nnz_tb = tb_sizes["nnz_ahat"] + tb_sizes["nnz_u"] + tb_sizes["nnz_m"] + tb_sizes["nnz_v"]
+    nnz_tb_pp = tb_sizes["nnz_ahat"] + tb_sizes["nnz_u_pp"] + tb_sizes["nnz_m_pp"] + tb_sizes["nnz_v_pp"]
+    technique_b = {"sizes": tb_sizes, "size_technique_b": nnz_tb, "size_technique_b_postprocessed": nnz_tb_pp,
+                   "nnz_A_over_size": tb_sizes["nnz_A"] / max(nnz_tb_pp, 1), "build_s": tb_build_s,
+                   "pair_us_explicit_factors_fp64": tb_us, "pair_us_structured_fp64": f64_us,
+                   "pair_us_structured_fp32": pair_us,
+                   "note": "explicit factors: CSR products for Ahat, U, V and M's chain solve (pointer jumping); "
+                           "structured: the hand operators applied without forming any factor"}
+    del yd, xd, Ayd, ATxd
+
     def time_to_gap(gm, kind, target, tpot):
         gm.solver_set_params(kind)
         gm.solver_reset()
@@ -611,11 +650,12 @@ def river_leg(args, stream):
            "n_seq": [L[0][0]["n_seq"], L[0][1]["n_seq"]], "n_hands": [L[0][0]["n_hands"], L[0][1]["n_hands"]],
            "game_create_s": t_create,
            "iterations_per_s": steps / (ms / 1e3), "iteration_us": ms * 1e3 / steps,
-           "matvec_pair": {"kernel": "k_mvc (matvec_pair launch, schedule %d:%d)" % g.game_get_tuning(),
+           "matvec_pair": {"kernel": kernel_label(g.game_get_tuning()),
                            "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair,
                            "achieved_gbs": bytes_pair / (pair_us * 1e-6) / 1e9,
                            "traffic": measured_traffic("river"),
                            "note": "0.86 MB per pair stays in the caches; the launch is latency bound"},
+           "technique_b_factors": technique_b,
            "time_to_gap": {"target": "1e-4*pot", "seconds": ttg, "iterations": iters,
                            "gap_over_pot": gap / pot, "solver": "plain RM+, uniform start, "
                            "FP64 gap checked every 25 iterations",

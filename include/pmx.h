@@ -260,6 +260,32 @@ int matvec_AT_f64(Game* g, const double* x_dev, double* out_dev, void* stream);
 int matvec_pair(Game* g, const float* y_dev, const float* x_dev, float* Ay_dev,
                 float* ATx_dev, void* stream);
 
+/* ---- Technique B's explicit factors (Section 4; a cross-check) ----------- */
+/* Sizes of the explicit sparsification A = Ahat + U M^-1 V^T of a
+ * one-instance river endgame (Technique B with the Postprocessing
+ * subsection's removal of V's zero columns), as stored nonzeros (Table 1's
+ * size metric), and the solve's dimension. */
+typedef struct {
+  int64_t nnz_A;                          /* nonzeros of A itself                  */
+  int64_t nnz_ahat, nnz_u, nnz_m, nnz_v;  /* before postprocessing                  */
+  int64_t nnz_u_pp, nnz_m_pp, nnz_v_pp;   /* after (Ahat is unchanged)              */
+  int64_t m_dim, m_dim_pp;                /* unknowns of M before / after            */
+  int32_t chain_depth;                    /* longest chain of M after postprocessing */
+} TbSizes;
+/* Build the explicit factors on the host (and, for a device game, their CSR
+ * forms and M's chains on the device; the device path needs every row and
+ * column of the postprocessed M to hold at most one off-diagonal entry).
+ * PMX_EINVAL for a batch or a turn + river game.  sizes may be NULL.
+ * Synchronous. */
+int tb_build(Game* g, TbSizes* sizes);
+/* A y and A^T x through the explicit factors, FP64, on the device: CSR
+ * products for Ahat, U and V (one wavefront per row) and M's unit triangular
+ * solve by pointer jumping along its chains (ceil(log2 depth) rounds).  Same
+ * vectors as matvec_A_f64 / matvec_AT_f64.  PMX_ESTATE before tb_build.
+ * Asynchronous. */
+int matvec_A_tb(Game* g, const double* y_dev, double* out_dev, void* stream);
+int matvec_AT_tb(Game* g, const double* x_dev, double* out_dev, void* stream);
+
 /* ---- regret matching+ solver (Section 5; per hand, all hands in parallel) -- */
 
 /* Reset to t = 0: zero regrets and averages, uniform current strategies.
@@ -302,6 +328,16 @@ int solver_set_active(Game* g, const int32_t* active_host, void* stream);
  * entry per instance: br1 = max_x x^T A ybar, br2 = min_y xbar^T A y,
  * gap = br1 - br2 >= 0 (chips).  Synchronizes `stream`. */
 int saddle_gap(Game* g, double* gap, double* br1, double* br2, void* stream);
+
+/* Divergence guard of saddle_gap (failure detection): PMX_ENUMERIC, naming
+ * the instance, once an instance's computed gap has grown (by more than
+ * 1e-12 of its pot) over k computations in a row; the out arrays of that
+ * call are then left untouched.  The count restarts whenever the gap does
+ * not grow and at solver_reset, solver_set_state, set_initial_strategy and
+ * warm_apply (not at solver_set_weights: new weight totals rescale the
+ * averages of the same run).  k = 0 disables the guard; the
+ * default is 16.  A non-finite best response is PMX_ENUMERIC whatever k. */
+int solver_set_gap_guard(Game* g, int32_t k);
 
 /* The same for given sequence-form strategies (device FP64 vectors of each
  * player, vec_elems each).  Synchronizes `stream`. */

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpmx.so")
 
-SOURCES = ["host_build.cpp", "pmx_device.hip", "pmx_mlp.hip"]
+SOURCES = ["host_build.cpp", "host_sparsify.cpp", "pmx_device.hip", "pmx_mlp.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -1529,8 +1529,10 @@ __global__ __launch_bounds__(TPB) void k_br(TpParams P, double* __restrict__ g,
     const int par = P.inf_parent[I], f = P.inf_first[I], n = P.inf_nact[I];
     double V = g[base + (int64_t)f * stride];
     for (int a = 1; a < n; ++a) {
-      double q = g[base + (int64_t)(f + a) * stride];
-      V = MAXIMIZE ? fmax(V, q) : fmin(V, q);
+      const double q = g[base + (int64_t)(f + a) * stride];
+      // a NaN propagates (fmax / fmin would drop it): a non-finite gradient
+      // must reach the host check
+      if (isnan(q) || (MAXIMIZE ? q > V : q < V)) V = q;
     }
     if (par == T.ext_parent) vroot += V;
     else g[base + (int64_t)par * stride] += V;
@@ -1618,10 +1620,6 @@ __global__ void k_f32_to_f64(const float* __restrict__ a, double* __restrict__ b
 }
 __global__ void k_fill_i32(int* p, int n, int v) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
-}
-__global__ void k_nonfinite(const double* p, int n, int* flag) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && !isfinite(p[i])) *flag = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1718,6 +1716,46 @@ __global__ __launch_bounds__(TPB) void k_warm_apply(TpParams P, const int64_t* _
       x[j] = xp * pa;
       xs[j] = avg_w * (double)(xp * pa);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Technique B's explicit factors: CSR products and the chain solve of M
+// ---------------------------------------------------------------------------
+// y[r] (+)= sum_j val[j] x[idx[j]] over row r's entries; one wavefront per
+// row, lanes striding over the entries, a butterfly sum across the lanes.
+__global__ __launch_bounds__(256) void k_csr_spmv(int64_t rows, const int64_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ idx, const double* __restrict__ val,
+                                                  const double* __restrict__ x, double* __restrict__ y, int accumulate) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= rows) return;
+  double s = 0.0;
+  for (int64_t j = ptr[r] + lane; j < ptr[r + 1]; j += 64) s += val[j] * x[idx[j]];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) y[r] = accumulate ? y[r] + s : s;
+}
+
+// One round of pointer jumping on M's chains: an unknown's value is its
+// right-hand side plus coef times the value at ptr; each round folds in the
+// target's own term and doubles the span (z = r + c z_p -> z = (r + c r_p) +
+// c c_p z_pp).
+__global__ __launch_bounds__(256) void k_chain_round(int64_t m, const double* __restrict__ va,
+                                                     const double* __restrict__ ca, const int32_t* __restrict__ pa,
+                                                     double* __restrict__ vb, double* __restrict__ cb,
+                                                     int32_t* __restrict__ pb) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int32_t p = pa[k];
+  if (p >= 0) {
+    vb[k] = va[k] + ca[k] * va[p];
+    cb[k] = ca[k] * ca[p];
+    pb[k] = pa[p];
+  } else {
+    vb[k] = va[k];
+    cb[k] = 0.0;
+    pb[k] = -1;
   }
 }
 
@@ -1826,10 +1864,27 @@ struct Game {
   // last FP64 gap per instance; valid while the instance's state is unchanged
   std::vector<double> gap_c, br1_c, br2_c;
   std::vector<char> gap_ok;
+  // divergence guard: each instance's last computed gap and how many
+  // computations in a row found it grown
+  int gap_guard = 16;
+  std::vector<double> gap_prev;
+  std::vector<int> gap_grow;
   DBuf<int32_t> gap_need;           // per instance: 1 = the gap call computes it
   int mv_block = 256;
   int max_lds = 64 * 1024;          // dynamic LDS bytes a workgroup may use on this device
   DBuf<double> tdev;                // iteration index of the next step (device)
+  // Technique B's explicit factors (tb_build): CSR matrices and M's chains
+  struct TbDev {
+    DBuf<int64_t> ptr[6];
+    DBuf<int32_t> idx[6];
+    DBuf<double> val[6];
+    int64_t rows[6] = {0, 0, 0, 0, 0, 0};
+    DBuf<int32_t> par, chi, ptrbuf[2];
+    DBuf<double> cpar, cchi, tvec, valbuf[2], coefbuf[2];
+    int64_t m = 0;
+    int rounds = 0;
+    bool built = false;
+  } tb;
   DBuf<int32_t> active;             // per-instance: 1 = iterated by solver_step
   std::vector<char> listed;         // instances the solver's launch lists include
   int n_listed = 0;
@@ -1857,6 +1912,16 @@ struct Game {
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
+
+// Every instance's gap is computed again at the next saddle_gap; a new start
+// of the solver state (reset, a loaded state, a warm start) also restarts the
+// divergence guard's history, new weight totals do not.
+static void invalidate_gaps(Game* g, bool restart = true) {
+  g->gap_ok.assign(g->gap_ok.size(), 0);
+  if (!restart) return;
+  g->gap_prev.assign(g->gap_prev.size(), std::nan(""));
+  g->gap_grow.assign(g->gap_grow.size(), 0);
+}
 
 static int ensure_device(Game* g) {
   if (!g) return fail(PMX_EINVAL, "null game");
@@ -2094,6 +2159,8 @@ static int upload_game(Game* g) {
   g->br1_c.assign(hg.inst.size(), 0.0);
   g->br2_c.assign(hg.inst.size(), 0.0);
   g->gap_ok.assign(hg.inst.size(), 0);
+  g->gap_prev.assign(hg.inst.size(), std::nan(""));
+  g->gap_grow.assign(hg.inst.size(), 0);
   if ((rc = g->gap_need.alloc(hg.inst.size()))) return rc;
   for (int p = 0; p < 2; ++p) {
     std::vector<WarmSeg> segs;
@@ -2626,6 +2693,15 @@ int game_tune(Game* g, int32_t kernel, int32_t rows_per_chunk) {
   return PMX_OK;
 }
 
+int solver_set_gap_guard(Game* g, int32_t k) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (k < 0) return fail(PMX_EINVAL, "k must be >= 0 (0 disables the guard)");
+  g->gap_guard = k;
+  g->gap_grow.assign(g->gap_grow.size(), 0);
+  return PMX_OK;
+}
+
 int solver_set_rm_quad(Game* g, int32_t max_records) {
   int rc = ensure_device(g);
   if (rc) return rc;
@@ -2720,6 +2796,104 @@ int matvec_pair(Game* g, const float* y, const float* x, float* Ay, float* ATx, 
                           (hipStream_t)stream);
 }
 
+// ---------------------------------------------------------------------------
+// Technique B's explicit factors (a cross-check of the structured operator)
+// ---------------------------------------------------------------------------
+int tb_build(Game* g, TbSizes* sizes) {
+  if (!g) return fail(PMX_EINVAL, "null game");
+  TbHost T;
+  std::string msg;
+  int rc = build_tb_factors(g->hg, T, msg);
+  if (rc) return fail(rc, msg);
+  if (g->device) {
+    HIP_TRY(hipSetDevice(g->device_id));
+    auto& D = g->tb;
+    const TbCsr* m[6] = {&T.ahat, &T.ahat_t, &T.u, &T.u_t, &T.v, &T.v_t};
+    for (int i = 0; i < 6; ++i) {
+      if ((rc = D.ptr[i].upload(m[i]->ptr)) || (rc = D.idx[i].upload(m[i]->idx)) ||
+          (rc = D.val[i].upload(m[i]->val)))
+        return rc;
+      D.rows[i] = m[i]->rows;
+    }
+    D.m = T.m_dim_pp;
+    if ((rc = D.par.upload(T.par)) || (rc = D.chi.upload(T.chi)) || (rc = D.cpar.upload(T.cpar)) ||
+        (rc = D.cchi.upload(T.cchi)) || (rc = D.tvec.alloc(std::max<int64_t>(D.m, 1))))
+      return rc;
+    for (int i = 0; i < 2; ++i)
+      if ((rc = D.valbuf[i].alloc(std::max<int64_t>(D.m, 1))) || (rc = D.coefbuf[i].alloc(std::max<int64_t>(D.m, 1))) ||
+          (rc = D.ptrbuf[i].alloc(std::max<int64_t>(D.m, 1))))
+        return rc;
+    int r = 0;
+    while ((1 << r) < T.depth) ++r;
+    D.rounds = r;
+    D.built = true;
+  }
+  if (sizes) {
+    TbSizes z;
+    z.nnz_A = T.nnz_A;
+    z.nnz_ahat = T.nnz[0];
+    z.nnz_u = T.nnz[1];
+    z.nnz_m = T.nnz[2];
+    z.nnz_v = T.nnz[3];
+    z.nnz_u_pp = T.nnz_pp[1];
+    z.nnz_m_pp = T.nnz_pp[2];
+    z.nnz_v_pp = T.nnz_pp[3];
+    z.m_dim = T.m_dim;
+    z.m_dim_pp = T.m_dim_pp;
+    z.chain_depth = T.depth;
+    *sizes = z;
+  }
+  return PMX_OK;
+}
+
+// out = Ahat in + U (M^-1 (V^T in)) for dir 0 (A y); Ahat^T in + V (M^-T (U^T in))
+// for dir 1 (A^T x).
+static int tb_apply(Game* g, int dir, const double* in, double* out, hipStream_t s) {
+  auto& D = g->tb;
+  if (!D.built) return fail(PMX_ESTATE, "tb_build has not been called on this game");
+  // CSR indices: 0 Ahat, 1 Ahat^T, 2 U, 3 U^T, 4 V, 5 V^T
+  const int first = dir == 0 ? 5 : 3;    // V^T in  /  U^T in
+  const int direct = dir == 0 ? 0 : 1;   // Ahat in /  Ahat^T in
+  const int last = dir == 0 ? 2 : 4;     // U z     /  V w
+  auto spmv = [&](int i, const double* x, double* y, int acc) {
+    const int64_t rows = D.rows[i];
+    if (rows == 0) return;
+    hipLaunchKernelGGL(k_csr_spmv, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, D.ptr[i].p, D.idx[i].p,
+                       D.val[i].p, x, y, acc);
+  };
+  spmv(first, in, D.valbuf[0].p, 0);
+  // the chains: parents for M z = r, children for M^T w = r
+  const int32_t* p0 = dir == 0 ? D.par.p : D.chi.p;
+  const double* c0 = dir == 0 ? D.cpar.p : D.cchi.p;
+  HIP_TRY(hipMemcpyAsync(D.coefbuf[0].p, c0, D.m * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(D.ptrbuf[0].p, p0, D.m * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  int a = 0;
+  const unsigned nb = (unsigned)((D.m + 255) / 256);
+  for (int r = 0; r < D.rounds && D.m > 0; ++r) {
+    hipLaunchKernelGGL(k_chain_round, dim3(nb), dim3(256), 0, s, D.m, D.valbuf[a].p, D.coefbuf[a].p,
+                       D.ptrbuf[a].p, D.valbuf[1 - a].p, D.coefbuf[1 - a].p, D.ptrbuf[1 - a].p);
+    a = 1 - a;
+  }
+  spmv(direct, in, out, 0);
+  spmv(last, D.valbuf[a].p, out, 1);
+  HIP_TRY(hipGetLastError());
+  return PMX_OK;
+}
+
+int matvec_A_tb(Game* g, const double* y, double* out, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!y || !out) return fail(PMX_EINVAL, "null vector");
+  return tb_apply(g, 0, y, out, (hipStream_t)stream);
+}
+
+int matvec_AT_tb(Game* g, const double* x, double* out, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!x || !out) return fail(PMX_EINVAL, "null vector");
+  return tb_apply(g, 1, x, out, (hipStream_t)stream);
+}
+
 // The solver's launch lists restricted to the instances marked in `act`: the
 // matvec row chunks and regret blocks of the others are left out, so their
 // workgroups are not dispatched at all (they would return at once on the
@@ -2766,7 +2940,7 @@ int solver_reset(Game* g, void* stream) {
   g->wsum = 0.0;
   g->wsum_i.assign(g->wsum_i.size(), 0.0);
   g->act_h.assign(g->act_h.size(), 1);
-  g->gap_ok.assign(g->gap_ok.size(), 0);
+  invalidate_gaps(g);
   // every instance is active again: the launch lists must include them all
   if (g->n_listed < (int)g->hg.inst.size()) {
     if ((rc = set_solver_lists(g, std::vector<char>(g->hg.inst.size(), 1)))) return rc;
@@ -3030,6 +3204,18 @@ int saddle_gap(Game* g, double* gap, double* br1, double* br2, void* stream) {
                             g->br1_c.data(), g->br2_c.data(), s, game_gap_bufs(g))))
       return rc;
     for (size_t i = 0; i < ni; ++i) g->gap_ok[i] = 1;
+    // divergence guard: a gap that grows over gap_guard computations in a row
+    int bad = -1;
+    for (size_t i = 0; i < ni; ++i) {
+      if (!need[i]) continue;
+      const double pot = 2.0 * g->hg.inst[i].inst.contrib, prev = g->gap_prev[i];
+      g->gap_grow[i] = (!std::isnan(prev) && g->gap_c[i] > prev + 1e-12 * pot) ? g->gap_grow[i] + 1 : 0;
+      g->gap_prev[i] = g->gap_c[i];
+      if (g->gap_guard > 0 && g->gap_grow[i] >= g->gap_guard && bad < 0) bad = (int)i;
+    }
+    if (bad >= 0)
+      return fail(PMX_ENUMERIC, "instance " + std::to_string(bad) + ": the FP64 gap grew over " +
+                                    std::to_string(g->gap_guard) + " computations in a row (the solve diverges)");
   }
   for (size_t i = 0; i < ni; ++i) {
     if (gap) gap[i] = g->gap_c[i];
@@ -3151,7 +3337,7 @@ int solver_set_state(Game* g, int32_t player, const float* regret, const float* 
   g->t = t;
   g->wsum = wsum;
   g->wsum_i.assign(g->wsum_i.size(), wsum);
-  g->gap_ok.assign(g->gap_ok.size(), 0);
+  invalidate_gaps(g);
   const double cur = (double)t;   // the next iteration's first launch makes it t + 1
   HIP_TRY(hipMemcpy(g->tdev.p, &cur, sizeof(double), hipMemcpyHostToDevice));
   return PMX_OK;
@@ -3173,7 +3359,7 @@ int solver_set_weights(Game* g, const double* wsum_host) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(wsum_host[i]) || wsum_host[i] < 0) return fail(PMX_EINVAL, "bad weight total");
   std::copy(wsum_host, wsum_host + n, g->wsum_i.begin());
-  g->gap_ok.assign(g->gap_ok.size(), 0);
+  invalidate_gaps(g, false);
   return PMX_OK;
 }
 
@@ -3209,7 +3395,7 @@ int set_initial_strategy(Game* g, int32_t player, const float* behav, float scal
   if (player < 0 || player > 1 || !behav) return fail(PMX_EINVAL, "bad argument");
   if (!(scale >= 0) || !std::isfinite(scale)) return fail(PMX_EINVAL, "scale must be finite and >= 0");
   hipStream_t s = (hipStream_t)stream;
-  g->gap_ok.assign(g->gap_ok.size(), 0);
+  invalidate_gaps(g);
   DevTp& E = g->dt[player];
   if (E.n_single)
     hipLaunchKernelGGL(k_warm, dim3(E.n_single), dim3(TPB), 0, s, tp_params(g, player, E.b_single.p),
@@ -3292,7 +3478,7 @@ int warm_apply(Game* g, const float* logits0_dev, const float* logits1_dev, int3
   g->t = 0;
   g->wsum = avg_weight;
   g->wsum_i.assign(g->wsum_i.size(), avg_weight);
-  g->gap_ok.assign(g->gap_ok.size(), 0);
+  invalidate_gaps(g);
   return PMX_OK;
 }
 

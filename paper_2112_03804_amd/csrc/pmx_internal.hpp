@@ -247,6 +247,25 @@ struct GrpDir {
   int max_chunk[kGrpClasses] = {0, 0, 0, 0, 0};
 };
 
+// Technique B's explicit factors of a one-instance river endgame (host and
+// the GPU cross-check path; see host_sparsify.cpp).
+struct TbCsr {
+  int64_t rows = 0, cols = 0;
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> idx;
+  std::vector<double> val;
+};
+struct TbHost {
+  int64_t nnz_A = 0;
+  int64_t nnz[4] = {0, 0, 0, 0};        // Ahat, U, M, V before postprocessing
+  int64_t nnz_pp[4] = {0, 0, 0, 0};     // after postprocessing
+  int64_t m_dim = 0, m_dim_pp = 0;      // the solve's dimension before / after
+  TbCsr ahat, ahat_t, u, u_t, v, v_t;   // over vector elements (rows x cols as named)
+  std::vector<int32_t> par, chi;        // M's chains: parent / child of each unknown (-1: none)
+  std::vector<double> cpar, cchi;       // z_k = r_k + cpar_k z_par(k);  w_i = r_i + cchi_i w_chi(i)
+  int depth = 0;                        // longest chain
+};
+
 struct TpTask {                         // treeplex task: one subtree of one instance
   int64_t vec_base;
   int32_t stride, n_hands;
@@ -371,5 +390,7 @@ void build_matvec_plan(HostGame& hg, int d, int rows_per_block);
 int build_rm_plan(HostGame& hg, int p, int task_rows, std::string& msg);
 int build_mc_layout(HostGame& hg, int d, int block, std::string& msg);
 int build_grp_layout(HostGame& hg, int d, int groups_per_chunk, std::string& msg);
+// host_sparsify.cpp
+int build_tb_factors(const HostGame& hg, TbHost& out, std::string& msg);
 
 }  // namespace pmx

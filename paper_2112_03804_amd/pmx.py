@@ -67,6 +67,13 @@ class HandMetaC(ctypes.Structure):
     ]
 
 
+class TbSizesC(ctypes.Structure):
+    _fields_ = [("nnz_A", ctypes.c_int64), ("nnz_ahat", ctypes.c_int64), ("nnz_u", ctypes.c_int64),
+                ("nnz_m", ctypes.c_int64), ("nnz_v", ctypes.c_int64), ("nnz_u_pp", ctypes.c_int64),
+                ("nnz_m_pp", ctypes.c_int64), ("nnz_v_pp", ctypes.c_int64), ("m_dim", ctypes.c_int64),
+                ("m_dim_pp", ctypes.c_int64), ("chain_depth", ctypes.c_int32)]
+
+
 _lib = None
 
 EXPORTS = [
@@ -80,6 +87,7 @@ EXPORTS = [
     "warm_num_rows", "warm_features", "warm_targets", "warm_apply",
     "mlp_gemm_bf16", "mlp_softmax_xent", "mlp_colsum", "mlp_adam", "mlp_gather_bf16",
     "mlp_gather_f32", "mlp_cast_bf16", "solver_set_active", "solver_set_params", "solver_set_task_rows", "solver_set_rm_quad",
+    "solver_set_gap_guard", "tb_build", "matvec_A_tb", "matvec_AT_tb",
 ]
 
 
@@ -123,6 +131,10 @@ def lib():
     L.game_get_tuning.argtypes = [vp, _c_i32p, _c_i32p]
     L.solver_set_task_rows.argtypes = [vp, ctypes.c_int32]
     L.solver_set_rm_quad.argtypes = [vp, ctypes.c_int32]
+    L.solver_set_gap_guard.argtypes = [vp, ctypes.c_int32]
+    L.tb_build.argtypes = [vp, ctypes.POINTER(TbSizesC)]
+    L.matvec_A_tb.argtypes = [vp, vp, vp, vp]
+    L.matvec_AT_tb.argtypes = [vp, vp, vp, vp]
     i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     L.warm_num_rows.argtypes = [vp, i32, ctypes.POINTER(i64)]
     L.warm_features.argtypes = [vp, i32, vp, vp]
@@ -288,6 +300,9 @@ class Game:
     def game_tune(self, kernel: int, rows_per_chunk: int):
         _check(lib().game_tune(self._h, int(kernel), int(rows_per_chunk)))
 
+    def solver_set_gap_guard(self, k: int):
+        _check(lib().solver_set_gap_guard(self._h, int(k)))
+
     def solver_set_rm_quad(self, max_records: int):
         """Regret launches of at most max_records block records use the
         four-lanes-per-hand kernel (0: never)."""
@@ -333,6 +348,19 @@ class Game:
 
     def matvec_AT_f64(self, x, out, stream=None):
         _check(lib().matvec_AT_f64(self._h, _dptr(x), _dptr(out), _stream(stream)))
+
+    def tb_build(self) -> dict:
+        """Technique B's explicit factors (host sizes; device CSR forms for a
+        device game).  Returns the sizes as a dict."""
+        z = TbSizesC()
+        _check(lib().tb_build(self._h, ctypes.byref(z)))
+        return {f: getattr(z, f) for f, _ in TbSizesC._fields_}
+
+    def matvec_A_tb(self, y, out, stream=None):
+        _check(lib().matvec_A_tb(self._h, _dptr(y), _dptr(out), _stream(stream)))
+
+    def matvec_AT_tb(self, x, out, stream=None):
+        _check(lib().matvec_AT_tb(self._h, _dptr(x), _dptr(out), _stream(stream)))
 
     def matvec_pair(self, y, x, Ay, ATx, stream=None):
         _check(lib().matvec_pair(self._h, _dptr(y), _dptr(x), _dptr(Ay), _dptr(ATx), _stream(stream)))

@@ -916,3 +916,83 @@ def test_turn_river_gap_full_size_certified():
     assert abs(gap[0] - rgap) <= 1e-9 * pot
     assert 0 <= gap[0] < 1e-3 * pot
     g.close()
+
+
+def test_gap_guard_flags_a_growing_gap():
+    """Failure detection: the gap of a solve that keeps growing is an error.
+    Halving the weight totals doubles every average (a best-response value is
+    positively homogeneous), so each check finds the gap grown: the third
+    growth in a row raises with guard 3, never with the guard off, and an
+    ordinary solve checked 20 times under the default guard raises nothing.
+    A non-finite average is an error whatever the guard."""
+    pmx = _need_gpu()
+    d = I.small_river(0)
+    _say("gap guard")
+    g = pmx.Game(d)
+    for _ in range(20):
+        g.solver_step(16)
+        g.saddle_gap()
+    w = g.solver_get_weights()
+    g.solver_set_gap_guard(3)
+    g0 = g.saddle_gap()[0][0]
+    for k in range(2):
+        w = w * 0.5
+        g.solver_set_weights(w)
+        assert g.saddle_gap()[0][0] > g0
+    w = w * 0.5
+    g.solver_set_weights(w)
+    with pytest.raises(pmx.PmxError, match="grew"):
+        g.saddle_gap()
+    g.solver_set_gap_guard(0)
+    for _ in range(4):
+        w = w * 0.5
+        g.solver_set_weights(w)
+        g.saddle_gap()
+    with pytest.raises(pmx.PmxError):
+        g.solver_set_gap_guard(-1)
+    # a NaN in the averages: a non-finite best response
+    st = g.solver_get_state(0)
+    s = st["avg_sum"].copy()
+    s[0] = np.nan
+    g.solver_set_state(0, regret=st["regret"], plan=st["plan"], avg_sum=s, t=st["t"], wsum=st["wsum"])
+    g.solver_set_weights(w)
+    with pytest.raises(pmx.PmxError, match="non-finite"):
+        g.saddle_gap()
+    g.close()
+
+
+@pytest.mark.parametrize("name,fn", [("small_river_pruned", SMALL[3][1]), ("river_pruned_mid", SMALL[7][1]),
+                                     ("river", lambda: I.config(1))])
+def test_matvec_through_explicit_technique_b_factors(name, fn):
+    """The library's own explicit Technique-B factors (CSR products for Ahat,
+    U, V and M's chain solve by pointer jumping, FP64) give the oracle's A y
+    and A^T x elementwise, and the structured FP64 products."""
+    pmx = _need_gpu()
+    d = fn()
+    _say("explicit factors", name)
+    o = payoff.Game(d)
+    g = pmx.Game(d)
+    sizes = g.tb_build()
+    rng = np.random.default_rng(5)
+    y = _rand_vectors(o, rng, 1)
+    x = _rand_vectors(o, rng, 0)
+    yd, xd = _dev(g.pack(1, [y], np.float64), np.float64), _dev(g.pack(0, [x], np.float64), np.float64)
+    Ay = torch.full((g.elems[0],), 3.0, dtype=torch.float64, device="cuda")
+    ATx = torch.full((g.elems[1],), 3.0, dtype=torch.float64, device="cuda")
+    g.matvec_A_tb(yd, Ay)
+    g.matvec_AT_tb(xd, ATx)
+    torch.cuda.synchronize()
+    ref_A, ref_AT = o.matvec_A(y), o.matvec_AT(x)
+    normA = o.abs_row_sums().max() * np.abs(y).max()
+    normAT = o.abs_col_sums().max() * np.abs(x).max()
+    _assert_close(g.unpack(0, Ay.cpu().numpy())[0], ref_A, payoff.abs_matvec_A(o, y), 1e-12, F64_FLOOR * normA,
+                  "A y (explicit factors)")
+    _assert_close(g.unpack(1, ATx.cpu().numpy())[0], ref_AT, payoff.abs_matvec_AT(o, x), 1e-12,
+                  F64_FLOOR * normAT, "A^T x (explicit factors)")
+    # padding rows are written as zero
+    for p, t in ((0, Ay), (1, ATx)):
+        L = g.layouts[0][p]
+        blk = t.cpu().numpy()[:L["n_seq"] * L["stride"]].reshape(L["n_seq"], L["stride"])
+        assert np.all(blk[:, L["n_hands"]:] == 0)
+    assert sizes["nnz_v_pp"] <= sizes["nnz_v"] and sizes["m_dim_pp"] <= sizes["m_dim"]
+    g.close()
