@@ -278,6 +278,20 @@ typedef struct {
  * PMX_EINVAL for a batch or a turn + river game.  sizes may be NULL.
  * Synchronous. */
 int tb_build(Game* g, TbSizes* sizes);
+/* The factors after postprocessing as CSR (library-owned host arrays, valid
+ * until the next tb_build or game_destroy): which = 0 Ahat (rows: Player 1's
+ * vector elements, columns: Player 2's), 1 U (rows: Player 1's elements,
+ * columns: the solve's unknowns), 2 M (unknowns x unknowns, unit lower
+ * triangular, diagonal included), 3 V (rows: Player 2's elements, columns:
+ * the unknowns); so that A = Ahat + U M^-1 V^T over the vector layout of
+ * game_layout.  PMX_ESTATE before tb_build, PMX_EINVAL for another which. */
+typedef struct {
+  int64_t rows, cols, nnz;
+  const int64_t* ptr;                     /* rows + 1 */
+  const int32_t* idx;                     /* nnz column indices */
+  const double* val;                      /* nnz values */
+} TbMatrix;
+int tb_matrix(const Game* g, int32_t which, TbMatrix* out);
 /* A y and A^T x through the explicit factors, FP64, on the device: CSR
  * products for Ahat, U and V (one wavefront per row) and M's unit triangular
  * solve by pointer jumping along its chains (ceil(log2 depth) rounds).  Same

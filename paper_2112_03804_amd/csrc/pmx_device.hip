@@ -1885,6 +1885,8 @@ struct Game {
     int rounds = 0;
     bool built = false;
   } tb;
+  std::unique_ptr<TbHost> tb_host;   // the host factors of the last tb_build
+  TbCsr tb_m;                        // M after postprocessing as CSR (diagonal included)
   DBuf<int32_t> active;             // per-instance: 1 = iterated by solver_step
   std::vector<char> listed;         // instances the solver's launch lists include
   int n_listed = 0;
@@ -2828,6 +2830,23 @@ int tb_build(Game* g, TbSizes* sizes) {
     D.rounds = r;
     D.built = true;
   }
+  // M as CSR from its chains: the unit diagonal and each row's parent entry
+  {
+    TbCsr& Mc = g->tb_m;
+    Mc.rows = Mc.cols = T.m_dim_pp;
+    Mc.ptr.assign(T.m_dim_pp + 1, 0);
+    Mc.idx.clear();
+    Mc.val.clear();
+    for (int64_t k = 0; k < T.m_dim_pp; ++k) {
+      if (T.par[k] >= 0) {
+        Mc.idx.push_back(T.par[k]);
+        Mc.val.push_back(-T.cpar[k]);
+      }
+      Mc.idx.push_back((int32_t)k);
+      Mc.val.push_back(1.0);
+      Mc.ptr[k + 1] = (int64_t)Mc.idx.size();
+    }
+  }
   if (sizes) {
     TbSizes z;
     z.nnz_A = T.nnz_A;
@@ -2843,6 +2862,24 @@ int tb_build(Game* g, TbSizes* sizes) {
     z.chain_depth = T.depth;
     *sizes = z;
   }
+  g->tb_host.reset(new TbHost(std::move(T)));
+  return PMX_OK;
+}
+
+int tb_matrix(const Game* g, int32_t which, TbMatrix* out) {
+  if (!g || !out) return fail(PMX_EINVAL, "null argument");
+  if (!g->tb_host) return fail(PMX_ESTATE, "tb_build has not been called on this game");
+  const TbCsr* m = which == 0 ? &g->tb_host->ahat : which == 1 ? &g->tb_host->u : which == 2 ? &g->tb_m
+                 : which == 3 ? &g->tb_host->v : nullptr;
+  if (!m) return fail(PMX_EINVAL, "which must be 0 (Ahat), 1 (U), 2 (M) or 3 (V)");
+  TbMatrix M;
+  M.rows = m->rows;
+  M.cols = m->cols;
+  M.nnz = (int64_t)m->idx.size();
+  M.ptr = m->ptr.data();
+  M.idx = m->idx.data();
+  M.val = m->val.data();
+  *out = M;
   return PMX_OK;
 }
 

@@ -74,6 +74,12 @@ class TbSizesC(ctypes.Structure):
                 ("m_dim_pp", ctypes.c_int64), ("chain_depth", ctypes.c_int32)]
 
 
+class TbMatrixC(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("ptr", ctypes.POINTER(ctypes.c_int64)), ("idx", ctypes.POINTER(ctypes.c_int32)),
+                ("val", ctypes.POINTER(ctypes.c_double))]
+
+
 _lib = None
 
 EXPORTS = [
@@ -87,7 +93,7 @@ EXPORTS = [
     "warm_num_rows", "warm_features", "warm_targets", "warm_apply",
     "mlp_gemm_bf16", "mlp_softmax_xent", "mlp_colsum", "mlp_adam", "mlp_gather_bf16",
     "mlp_gather_f32", "mlp_cast_bf16", "solver_set_active", "solver_set_params", "solver_set_task_rows", "solver_set_rm_quad",
-    "solver_set_gap_guard", "tb_build", "matvec_A_tb", "matvec_AT_tb",
+    "solver_set_gap_guard", "tb_build", "tb_matrix", "matvec_A_tb", "matvec_AT_tb",
 ]
 
 
@@ -133,6 +139,7 @@ def lib():
     L.solver_set_rm_quad.argtypes = [vp, ctypes.c_int32]
     L.solver_set_gap_guard.argtypes = [vp, ctypes.c_int32]
     L.tb_build.argtypes = [vp, ctypes.POINTER(TbSizesC)]
+    L.tb_matrix.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(TbMatrixC)]
     L.matvec_A_tb.argtypes = [vp, vp, vp, vp]
     L.matvec_AT_tb.argtypes = [vp, vp, vp, vp]
     i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
@@ -355,6 +362,15 @@ class Game:
         z = TbSizesC()
         _check(lib().tb_build(self._h, ctypes.byref(z)))
         return {f: getattr(z, f) for f, _ in TbSizesC._fields_}
+
+    def tb_matrix(self, which: int):
+        """One explicit factor as (indptr, indices, values, shape) host copies."""
+        m = TbMatrixC()
+        _check(lib().tb_matrix(self._h, int(which), ctypes.byref(m)))
+        ptr = np.ctypeslib.as_array(m.ptr, shape=(m.rows + 1,)).copy()
+        idx = np.ctypeslib.as_array(m.idx, shape=(m.nnz,)).copy() if m.nnz else np.zeros(0, np.int32)
+        val = np.ctypeslib.as_array(m.val, shape=(m.nnz,)).copy() if m.nnz else np.zeros(0)
+        return ptr, idx, val, (int(m.rows), int(m.cols))
 
     def matvec_A_tb(self, y, out, stream=None):
         _check(lib().matvec_A_tb(self._h, _dptr(y), _dptr(out), _stream(stream)))
