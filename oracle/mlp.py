@@ -55,3 +55,15 @@ def init(d_in, width, k, seed=0):
     W2, b2 = lin(width, width)
     W3, b3 = lin(k, width)
     return {"W1": W1, "b1": b1, "W2": W2, "b2": b2, "W3": W3, "b3": b3 * 0.0}
+
+
+def adam_step(w, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
+    """One Adam step (Kingma and Ba, ICLR 2015: moving averages of the
+    gradient and its square, each divided by its bias correction 1 - beta^t)
+    on the gradient g + wd * w.  Returns the new (w, m, v); t counts from 1."""
+    gt = g + wd * w
+    m = b1 * m + (1.0 - b1) * gt
+    v = b2 * v + (1.0 - b2) * gt * gt
+    mhat = m / (1.0 - b1 ** t)
+    vhat = v / (1.0 - b2 ** t)
+    return w - lr * mhat / (np.sqrt(vhat) + eps), m, v

@@ -236,11 +236,77 @@ def apply_prior(game, mlp: WarmMLP, regret_scale: float, avg_weight: float):
     return logits
 
 
+def _instance_rows(game, p: int) -> np.ndarray:
+    """Row offsets of each instance among player p's network rows ((infoset,
+    hand) pairs, instance by instance)."""
+    n = [L[p]["n_infosets"] * L[p]["n_hands"] for L in game.layouts]
+    return np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+
+
+def apply_logits_with_fallback(game, logits, regret_scale: float, avg_weight: float, probe: int = 64):
+    """Warm start with the uniform start as the fallback (per instance).
+
+    The uniform start and the prior from `logits` (one [rows, 8] FP32 tensor
+    per player) each run `probe` solver iterations; an instance keeps the
+    prior's run only if its logits are finite and its FP64 gap after the
+    probe is below the uniform run's; the others continue from the uniform
+    run's state (regrets, plans, averages and weight totals spliced in per
+    instance).  The game ends `probe` iterations in either way.  Returns the
+    per-instance flags (True: the prior was kept) and both probe gaps."""
+    torch = _torch()
+    ni = game.n_instances
+    game.solver_reset()
+    game.solver_step(probe)
+    gap_u = game.saddle_gap()[0]
+    st_u = [game.solver_get_state(p) for p in range(2)]
+    w_u = game.solver_get_weights()
+    finite = np.ones(ni, dtype=bool)
+    for p in range(2):
+        off = _instance_rows(game, p)
+        ok = torch.isfinite(logits[p]).all(dim=1).cpu().numpy()
+        for i in range(ni):
+            finite[i] &= bool(ok[off[i]:off[i + 1]].all())
+    game.warm_apply(logits[0], logits[1], K, regret_scale, avg_weight)
+    game.solver_step(probe)
+    gap_w = game.saddle_gap()[0]
+    keep = finite & (gap_w < gap_u)
+    if not keep.all():
+        st_w = [game.solver_get_state(p) for p in range(2)]
+        w = game.solver_get_weights()
+        for p in range(2):
+            st = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st_w[p].items()}
+            for i in np.flatnonzero(~keep):
+                L = game.layouts[i][p]
+                a, b = L["vec_offset"], L["vec_offset"] + L["n_seq"] * L["stride"]
+                for k in ("regret", "plan", "avg_sum"):
+                    st[k][a:b] = st_u[p][k][a:b]
+            game.solver_set_state(p, regret=st["regret"], plan=st["plan"], avg_sum=st["avg_sum"], t=st["t"],
+                                  wsum=st["wsum"])
+        w = np.where(keep, w, w_u)
+        game.solver_set_weights(w)
+    return keep, gap_u, gap_w
+
+
+def apply_prior_with_fallback(game, mlp: WarmMLP, regret_scale: float, avg_weight: float, probe: int = 64):
+    """The network's prior with the uniform start as fallback (see
+    apply_logits_with_fallback)."""
+    torch = _torch()
+    logits = []
+    for p in range(2):
+        n = game.warm_num_rows(p)
+        X = torch.empty((n, D_IN), dtype=torch.bfloat16, device="cuda")
+        game.warm_features(p, X)
+        logits.append(mlp.logits(X, n))
+    return apply_logits_with_fallback(game, logits, regret_scale, avg_weight, probe)
+
+
 def solve_to_gap(game, target_rel: float, check_every: int = 32, max_iters: int = 100000,
-                 retire: bool = True):
+                 retire: bool = True, start_iters: int = 0):
     """Iterate until every instance's gap <= target_rel * its pot, retiring
     instances (``solver_set_active``) as they reach it; returns (seconds,
-    iterations, per-instance first iteration at target)."""
+    iterations, per-instance first iteration at target).  `start_iters`
+    counts iterations the game has already run (a probe) in the reported
+    iteration numbers."""
     torch = _torch()
     pots = np.array([2 * d.contrib for d in game.descs])
     done = np.full(game.n_instances, -1)
@@ -248,7 +314,9 @@ def solve_to_gap(game, target_rel: float, check_every: int = 32, max_iters: int 
     t0 = time.perf_counter()
     it = 0
     gap = game.saddle_gap()[0]
-    done[gap <= target_rel * pots] = 0
+    if start_iters:
+        it = start_iters
+    done[gap <= target_rel * pots] = it
     if retire:
         game.solver_set_active(done < 0)
     while (done < 0).any() and it < max_iters:

@@ -237,3 +237,103 @@ def test_targets_of_retired_instance_use_its_own_weight():
         assert before[p][1][:r0].max() > 0
         assert not np.array_equal(before[p][1][r0:], after[p][1][r0:])
     g.close()
+
+
+def test_adam_matches_the_oracle():
+    """mlp_adam (FP32, with the BF16 weight copy) follows the oracle's FP64
+    Adam over five steps with changing gradients and weight decay."""
+    pmx, _ = _need()
+    L = pmx.lib()
+    rng = np.random.default_rng(17)
+    n = 3001
+    w0 = rng.standard_normal(n).astype(np.float32)
+    wd = 0.01
+    w = torch.from_numpy(w0.copy()).cuda()
+    m = torch.zeros(n, dtype=torch.float32, device="cuda")
+    v = torch.zeros(n, dtype=torch.float32, device="cuda")
+    wb = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+    rw, rm, rv = w0.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t in range(1, 6):
+        g = rng.standard_normal(n).astype(np.float32) * (0.1 * t)
+        gd = torch.from_numpy(g).cuda()
+        pmx.check(L.mlp_adam(n, pmx.dptr(w), pmx.dptr(gd), pmx.dptr(m), pmx.dptr(v), pmx.dptr(wb), 1e-2, 0.9,
+                             0.999, 1e-8, wd, t, pmx.stream_ptr()))
+        rw, rm, rv = omlp.adam_step(rw, g.astype(np.float64), rm, rv, t, lr=1e-2, b1=0.9, b2=0.999, eps=1e-8, wd=wd)
+    torch.cuda.synchronize()
+    got = w.cpu().numpy().astype(np.float64)
+    assert np.abs(got - rw).max() <= 1e-5 * max(1.0, np.abs(rw).max())
+    assert np.allclose(wb.float().cpu().numpy(), bf16_round(w.cpu().numpy()), rtol=0, atol=0)
+
+
+def _target_logits(g, ws, p):
+    """Logits whose softmax is the solver's current average behaviour."""
+    n = g.warm_num_rows(p)
+    T = torch.empty((n, ws.K), dtype=torch.float32, device="cuda")
+    W = torch.empty((n,), dtype=torch.float32, device="cuda")
+    g.warm_targets(p, T, W)
+    return torch.where(T >= 0, torch.log(T.clamp_min(1e-6)), torch.full_like(T, -30.0))
+
+
+def test_warm_start_fallback_per_instance():
+    """A prior that is a near-equilibrium keeps its run; a prior that folds
+    everything and one with a non-finite logit fall back to the uniform start:
+    those instances end the probe exactly in the uniform run's state."""
+    pmx, ws = _need()
+    descs = [I.river_config(seed=810 + i, n_keep=(120, 140), bet_fracs=(0.5, 1.0), max_raises=2,
+                            pot=40.0, stack=120.0) for i in range(3)]
+    _say("warm start fallback")
+    g = pmx.Game(descs)
+    g.solver_set_params("dcfr")
+    g.solver_step(2000)                       # a good prior: the averages of a long run
+    logits = [_target_logits(g, ws, p) for p in range(2)]
+    g.solver_set_params("rm+")
+    for p in range(2):
+        off = ws._instance_rows(g, p)
+        Z = logits[p]
+        # instance 1: fold (slot 0) everywhere; instance 2: one NaN logit
+        Z[off[1]:off[2]] = -5.0
+        Z[off[1]:off[2], 0] = 5.0
+        Z[off[2], 1] = float("nan")
+    probe = 32
+    keep, gap_u, gap_w = ws.apply_logits_with_fallback(g, logits, 1.0, 0.0, probe=probe)
+    assert keep.tolist() == [True, False, False], (keep, gap_u, gap_w)
+    # the fallen-back instances stand where the uniform run stood
+    u = pmx.Game(descs)
+    u.solver_step(probe)
+    for p in range(2):
+        a = g.unpack(p, g.solver_get_state(p)["avg_sum"])
+        b = u.unpack(p, u.solver_get_state(p)["avg_sum"])
+        for i in (1, 2):
+            assert np.array_equal(a[i], b[i])
+        assert not np.array_equal(a[0], b[0])
+    gap = g.saddle_gap()[0]
+    ugap = u.saddle_gap()[0]
+    assert gap[1] == ugap[1] and gap[2] == ugap[2]
+    assert gap[0] < ugap[0]
+    u.close()
+    g.close()
+
+
+def test_trained_prior_lowers_held_out_iterations():
+    """A network trained on 256 solved endgames (DCFR averages at
+    1e-5 * pot) lowers the total RM+ iterations to 1e-4 * pot on 32 held-out
+    endgames of the batched distribution against the uniform start, with the
+    same solver and batch."""
+    pmx, ws = _need()
+    _say("warm start gain: labelling")
+    train = I.batched_configs(256, seed=23)
+    ds = ws.make_dataset(train, batch=256, target=1e-5, kind="dcfr", max_iters=8192)
+    net = ws.WarmMLP(seed=0)
+    _say("warm start gain: training on", ds.rows, "rows")
+    ws.train(net, ds, steps=800, batch_rows=8192, lr=1e-3)
+    del ds
+    held = I.batched_configs(32)
+    g = pmx.Game(held)
+    _, _, done_u = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=40000)
+    g.solver_reset()
+    ws.apply_prior(g, net, 1.0, 0.0)
+    _, _, done_w = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=40000)
+    g.close()
+    _say(f"  iterations to 1e-4 * pot: uniform {done_u.sum()}, prior {done_w.sum()}")
+    assert (done_u >= 0).all() and (done_w >= 0).all()
+    assert done_w.sum() < 0.9 * done_u.sum(), (done_w.sum(), done_u.sum())

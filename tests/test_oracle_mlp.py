@@ -53,3 +53,24 @@ def test_masked_softmax_and_loss_definition():
         assert np.allclose(P[r][v], q) and np.all(P[r][~v] == 0)
         ref += w[r] * -(T[r][v] * np.log(q)).sum()
     assert abs(loss - ref) < 1e-12 * max(1.0, abs(ref))
+
+
+def test_adam_first_steps_closed_form():
+    """Adam's bias correction makes the first step lr * g / (|g| + eps) for
+    every weight whatever beta1, beta2 (m1 / (1 - b1) = g, v1 / (1 - b2) =
+    g^2), and a second step with the same gradient moves by the same amount;
+    weight decay adds wd * w to the gradient."""
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    z = np.zeros(50)
+    lr, eps = 1e-2, 1e-8
+    for b1, b2 in ((0.9, 0.999), (0.5, 0.9)):
+        w1, m1, v1 = mlp.adam_step(w, g, z, z, 1, lr=lr, b1=b1, b2=b2, eps=eps)
+        assert np.allclose(w1, w - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-15)
+        w2, _, _ = mlp.adam_step(w1, g, m1, v1, 2, lr=lr, b1=b1, b2=b2, eps=eps)
+        assert np.allclose(w2, w1 - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-14)
+    wd = 0.3
+    w1, _, _ = mlp.adam_step(w, g, z, z, 1, lr=lr, eps=eps, wd=wd)
+    ge = g + wd * w
+    assert np.allclose(w1, w - lr * ge / (np.abs(ge) + eps), rtol=0, atol=1e-15)
