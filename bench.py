@@ -551,6 +551,103 @@ def trace_probe(args):
         g.close()
 
 
+def dcfr_sweep(args):
+    """Discounted CFR parameters (Section 5 names the solver, not its
+    parameters): time and iterations to 1e-4 * pot for alpha in {1, 1.5, 2},
+    beta in {0, 0.5}, gamma in {1, 2, 3} (and RM+ beside them) on the river
+    endgame and on the batch of 512 endgames (instances retire at the
+    target); then RM+ against DCFR (1.5, 0, 2) to 1e-6 * pot on the turn +
+    river game.  One JSON line per measurement, then a summary line."""
+    import torch
+    from paper_2112_03804_amd import instances as I
+    from paper_2112_03804_amd import pmx
+    from paper_2112_03804_amd import warmstart as ws
+
+    grid = [(a, b, c) for a in (1.0, 1.5, 2.0) for b in (0.0, 0.5) for c in (1, 2, 3)]
+    rows = []
+
+    def emit(row):
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+
+    # river endgame: one instance, FP64 gap every 25 iterations
+    desc = I.config(1)
+    pot = 2 * desc.contrib
+    g = pmx.Game(desc)
+    g.solver_set_gap_guard(0)   # some settings are not monotone for long stretches
+    for kind, prm in [("rm+", None)] + [("dcfr", p) for p in grid]:
+        if prm:
+            g.solver_set_params("dcfr", *prm)
+        else:
+            g.solver_set_params("rm+")
+        g.solver_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, gap = 0, float("inf")
+        while it < 200000:
+            g.solver_step(25)
+            it += 25
+            gap = float(g.saddle_gap()[0][0])
+            if gap <= 1e-4 * pot:
+                break
+        emit({"game": "river", "solver": kind, "alpha_beta_gamma": prm, "target": "1e-4*pot",
+              "seconds": time.perf_counter() - t0, "iterations": it, "gap_over_pot": gap / pot})
+    g.close()
+
+    # the batch of 512 endgames
+    g = pmx.Game(I.batched_configs(args.batch))
+    g.game_tune(4, 1)
+    g.solver_set_gap_guard(0)
+    for kind, prm in [("rm+", None)] + [("dcfr", p) for p in grid]:
+        if prm:
+            g.solver_set_params("dcfr", *prm)
+        else:
+            g.solver_set_params("rm+")
+        g.solver_reset()
+        sec, iters, done = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=min(args.max_iters, 40000))
+        emit({"game": f"batch of {args.batch}", "solver": kind, "alpha_beta_gamma": prm, "target": "1e-4*pot",
+              "seconds": sec, "iterations": iters, "instances_reached": int((done >= 0).sum()),
+              "iterations_per_instance_mean": float(done[done >= 0].mean()) if (done >= 0).any() else None})
+    g.close()
+
+    # turn + river: RM+ against DCFR to 1e-6 * pot
+    desc = I.config(2)
+    pot = 2 * desc.contrib
+    g = pmx.Game(desc)
+    g.game_tune(3, 8)
+    g.solver_set_gap_guard(0)
+    for kind, prm in (("rm+", None), ("dcfr", (1.5, 0.0, 2))):
+        if prm:
+            g.solver_set_params("dcfr", *prm)
+        else:
+            g.solver_set_params("rm+")
+        g.solver_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, gap, traj = 0, float("inf"), []
+        while time.perf_counter() - t0 < args.turn_budget:
+            g.solver_step(256)
+            it += 256
+            gap = float(g.saddle_gap()[0][0])
+            if it % 2048 == 0:
+                traj.append([it, round(time.perf_counter() - t0, 3), gap / pot])
+            if gap <= 1e-6 * pot:
+                break
+        emit({"game": "turn+river", "solver": kind, "alpha_beta_gamma": prm, "target": "1e-6*pot",
+              "seconds": time.perf_counter() - t0, "iterations": it, "gap_over_pot": gap / pot,
+              "reached": gap <= 1e-6 * pot, "trajectory_iters_s_gap": traj})
+    g.close()
+    best = {}
+    for r in rows:
+        if r["solver"] == "dcfr" and r["target"] == "1e-4*pot":
+            b = best.get(r["game"])
+            if b is None or r["seconds"] < b["seconds"]:
+                best[r["game"]] = r
+    print(json.dumps({"summary": "dcfr sweep",
+                      "fastest": {k: {"alpha_beta_gamma": v["alpha_beta_gamma"], "seconds": v["seconds"],
+                                      "iterations": v["iterations"]} for k, v in best.items()}}), flush=True)
+
+
 def river_leg(args, stream):
     """The single river endgame (52-card deck, 5-card board, 1081 hands per
     player, bets {0.5, 1, 2} x pot + all-in, 3 raises): solver iterations per
@@ -697,6 +794,8 @@ def main():
                     help="only run the launches profiled for HBM traffic counters")
     ap.add_argument("--trace-probe", action="store_true",
                     help="only run solver iterations on the batch and the turn + river game")
+    ap.add_argument("--dcfr-sweep", action="store_true",
+                    help="only sweep the discounted-CFR parameters (river, batch, turn + river)")
     ap.add_argument("--turn-steps", type=int, default=20)
     ap.add_argument("--turn-budget", type=float, default=90.0,
                     help="seconds for the turn + river precision run")
@@ -724,6 +823,9 @@ def main():
         return
     if args.trace_probe:
         trace_probe(args)
+        return
+    if args.dcfr_sweep:
+        dcfr_sweep(args)
         return
     stream = torch.cuda.current_stream()
     log("batch leg (headline)")

@@ -434,19 +434,27 @@ int warm_apply(Game* g, const float* logits0_dev, const float* logits1_dev, int3
  * op(A)(m,k) = transA ? A[k*lda + m] : A[m*lda + k], op(B)(k,n) = transB ?
  * B[n*ldb + k] : B[k*ldb + n].  Epilogue: + bias[n] (if bias), ReLU (if relu),
  * zero where mask[m*ldm + n] <= 0 (if mask); stored as FP32 C and / or BF16 Cb
- * (either may be NULL, not both). */
+ * (either may be NULL, not both).  work: optional caller-owned device FP32
+ * workspace of work_elems elements (NULL / 0: none).  When M x N gives few
+ * 64 x 64 tiles and K is long (weight gradients), K is split into ranges
+ * whose partial products go to work (at most work_elems / (M*N) ranges, up
+ * to 64) and are added in range order, so the result does not depend on
+ * timing; it does depend on the number of ranges.  Must not alias C or Cb. */
 int mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t lda, int32_t transA,
                   const uint16_t* B, int32_t ldb, int32_t transB, const float* bias, int32_t relu,
                   const float* mask, int32_t ldm, float* C, int32_t ldc, uint16_t* Cb, int32_t ldcb,
-                  void* stream);
+                  float* work, int64_t work_elems, void* stream);
 /* Masked softmax cross-entropy over K <= 64 slots (target < 0 = invalid):
  * dlogits[r][a] = weight[r] (softmax - target) (FP32 and / or BF16, stride K);
  * loss_partial[b] = sum of weight[r] * cross-entropy over block b's 256 rows. */
 int mlp_softmax_xent(int32_t rows, int32_t K, const float* logits, int32_t ldl, const float* target,
                      const float* weight, float* dlogits, uint16_t* dlogits_bf16, float* loss_partial,
                      void* stream);
-/* db[n] = sum_m dz[m][n] (bias gradient). */
-int mlp_colsum(int32_t rows, int32_t cols, const float* dz, float* db, void* stream);
+/* db[n] = sum_m dz[m][n] (bias gradient), in a fixed order.  work: optional
+ * device FP32 workspace of ceil(rows / 64) * cols elements (NULL, or too
+ * small: one thread per column walks every row). */
+int mlp_colsum(int32_t rows, int32_t cols, const float* dz, float* db, float* work, int64_t work_elems,
+               void* stream);
 /* Adam with bias correction and decoupled-free L2 weight decay; writes the
  * BF16 copy of the weights when w_bf16 is not NULL. */
 int mlp_adam(int64_t n, float* w, const float* g, float* m, float* v, uint16_t* w_bf16, float lr,

@@ -148,9 +148,9 @@ def lib():
     L.warm_targets.argtypes = [vp, i32, vp, vp, vp]
     L.warm_apply.argtypes = [vp, vp, vp, i32, f32, ctypes.c_double, vp]
     L.mlp_gemm_bf16.argtypes = [i32, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, vp, i32, vp, i32,
-                                vp, i32, vp]
+                                vp, i32, vp, i64, vp]
     L.mlp_softmax_xent.argtypes = [i32, i32, vp, i32, vp, vp, vp, vp, vp, vp]
-    L.mlp_colsum.argtypes = [i32, i32, vp, vp, vp]
+    L.mlp_colsum.argtypes = [i32, i32, vp, vp, vp, i64, vp]
     L.mlp_adam.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, f32, i32, vp]
     L.mlp_gather_bf16.argtypes = [i64, i32, vp, vp, vp, vp]
     L.mlp_gather_f32.argtypes = [i64, i32, vp, vp, vp, vp]

@@ -72,16 +72,25 @@ class WarmMLP:
                 "dZ2": torch.empty((M, WIDTH), **f32), "dZ2b": torch.empty((M, WIDTH), **b16),
                 "dZ1": torch.empty((M, WIDTH), **f32), "dZ1b": torch.empty((M, WIDTH), **b16),
                 "loss": torch.empty(((M + 255) // 256,), **f32),
+                # split-K partial products of the weight gradients and partial
+                # column sums of the bias gradients
+                "work": torch.empty((32 * WIDTH * WIDTH,), **f32),
             }
         return self._ws
 
     @staticmethod
     def gemm(M, N, Kd, A, lda, tA, B, ldb, tB, C=None, ldc=0, Cb=None, ldcb=0, bias=None, relu=False,
-             mask=None, ldm=0):
+             mask=None, ldm=0, work=None):
         L = pmx.lib()
         pmx.check(L.mlp_gemm_bf16(M, N, Kd, pmx.dptr(A), lda, tA, pmx.dptr(B), ldb, tB, pmx.dptr(bias),
                                   1 if relu else 0, pmx.dptr(mask), ldm, pmx.dptr(C), ldc, pmx.dptr(Cb),
-                                  ldcb, pmx.stream_ptr()))
+                                  ldcb, pmx.dptr(work), 0 if work is None else work.numel(),
+                                  pmx.stream_ptr()))
+
+    @staticmethod
+    def colsum(M, N, dz, db, work):
+        pmx.check(pmx.lib().mlp_colsum(M, N, pmx.dptr(dz), pmx.dptr(db), pmx.dptr(work), work.numel(),
+                                       pmx.stream_ptr()))
 
     # -- forward / backward ------------------------------------------------
     def forward(self, Xb, M: int):
@@ -104,20 +113,20 @@ class WarmMLP:
         pmx.check(L.mlp_softmax_xent(M, K, pmx.dptr(w["Z3"]), K, pmx.dptr(T), pmx.dptr(Wt),
                                      pmx.dptr(w["dZ3"]), pmx.dptr(w["dZ3b"]), pmx.dptr(w["loss"]),
                                      pmx.stream_ptr()))
-        s = pmx.stream_ptr()
+        wk = w["work"]
         # layer 3
-        self.gemm(K, WIDTH, M, w["dZ3b"], K, 1, w["H2b"], WIDTH, 0, C=self.g["W3"], ldc=WIDTH)
-        pmx.check(L.mlp_colsum(M, K, pmx.dptr(w["dZ3"]), pmx.dptr(self.g["b3"]), s))
+        self.gemm(K, WIDTH, M, w["dZ3b"], K, 1, w["H2b"], WIDTH, 0, C=self.g["W3"], ldc=WIDTH, work=wk)
+        self.colsum(M, K, w["dZ3"], self.g["b3"], wk)
         self.gemm(M, WIDTH, K, w["dZ3b"], K, 0, self.pb["W3"], WIDTH, 0, C=w["dZ2"], ldc=WIDTH,
                   Cb=w["dZ2b"], ldcb=WIDTH, mask=w["H2"], ldm=WIDTH)
         # layer 2
-        self.gemm(WIDTH, WIDTH, M, w["dZ2b"], WIDTH, 1, w["H1b"], WIDTH, 0, C=self.g["W2"], ldc=WIDTH)
-        pmx.check(L.mlp_colsum(M, WIDTH, pmx.dptr(w["dZ2"]), pmx.dptr(self.g["b2"]), s))
+        self.gemm(WIDTH, WIDTH, M, w["dZ2b"], WIDTH, 1, w["H1b"], WIDTH, 0, C=self.g["W2"], ldc=WIDTH, work=wk)
+        self.colsum(M, WIDTH, w["dZ2"], self.g["b2"], wk)
         self.gemm(M, WIDTH, WIDTH, w["dZ2b"], WIDTH, 0, self.pb["W2"], WIDTH, 0, C=w["dZ1"], ldc=WIDTH,
                   Cb=w["dZ1b"], ldcb=WIDTH, mask=w["H1"], ldm=WIDTH)
         # layer 1
-        self.gemm(WIDTH, D_IN, M, w["dZ1b"], WIDTH, 1, Xb, D_IN, 0, C=self.g["W1"], ldc=D_IN)
-        pmx.check(L.mlp_colsum(M, WIDTH, pmx.dptr(w["dZ1"]), pmx.dptr(self.g["b1"]), s))
+        self.gemm(WIDTH, D_IN, M, w["dZ1b"], WIDTH, 1, Xb, D_IN, 0, C=self.g["W1"], ldc=D_IN, work=wk)
+        self.colsum(M, WIDTH, w["dZ1"], self.g["b1"], wk)
         return w["loss"][: (M + 255) // 256]
 
     def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):

@@ -44,10 +44,14 @@ def to_bf16_dev(a):
 
 
 @pytest.mark.parametrize("tA,tB", [(0, 0), (0, 1), (1, 0), (1, 1)])
-@pytest.mark.parametrize("M,N,K", [(77, 45, 83), (130, 8, 512), (64, 64, 32), (5, 200, 3)])
-def test_gemm_bf16_matches_fp32_product(tA, tB, M, N, K):
+@pytest.mark.parametrize("M,N,K,split", [(77, 45, 83, 0), (130, 8, 512, 0), (64, 64, 32, 0), (5, 200, 3, 0),
+                                         (128, 192, 640, 0), (8, 136, 3000, 1), (70, 64, 2050, 1),
+                                         (200, 72, 8192, 1)])
+def test_gemm_bf16_matches_fp32_product(tA, tB, M, N, K, split):
+    """Every operand layout, ragged edges (unaligned leading dimensions take
+    the element-wise loads), and split K through a workspace."""
     pmx, _ = _need()
-    _say("gemm", tA, tB, M, N, K)
+    _say("gemm", tA, tB, M, N, K, split)
     rng = np.random.default_rng(M * 7 + N + K + 3 * tA + tB)
     A = bf16_round(rng.standard_normal((K, M) if tA else (M, K)).astype(np.float32))
     B = bf16_round(rng.standard_normal((N, K) if tB else (K, N)).astype(np.float32))
@@ -63,16 +67,36 @@ def test_gemm_bf16_matches_fp32_product(tA, tB, M, N, K):
     # device tensors stay referenced until the launch is enqueued
     bias_d = torch.from_numpy(bias).cuda()
     mask_d = torch.from_numpy(mask).cuda()
+    work = torch.full((64 * M * N,), float("nan"), dtype=torch.float32, device="cuda") if split else None
     L = pmx.lib()
     pmx.check(L.mlp_gemm_bf16(M, N, K, pmx.dptr(Ad), M if tA else K, tA, pmx.dptr(Bd), K if tB else N, tB,
                               pmx.dptr(bias_d), 1, pmx.dptr(mask_d), N, pmx.dptr(C), N, pmx.dptr(Cb), N,
-                              pmx.stream_ptr()))
+                              pmx.dptr(work), 0 if work is None else work.numel(), pmx.stream_ptr()))
     torch.cuda.synchronize()
     got = C.cpu().numpy().astype(np.float64)
     scale = np.abs(opA).astype(np.float64) @ np.abs(opB).astype(np.float64) + np.abs(bias)
     assert np.all(np.abs(got - ref) <= 1e-5 * scale + 1e-6)
     gotb = Cb.float().cpu().numpy()
     assert np.allclose(gotb, bf16_round(got.astype(np.float32)), rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("rows,cols", [(1, 5), (300, 8), (8192, 512), (1000, 300)])
+def test_colsum_with_and_without_workspace(rows, cols):
+    pmx, _ = _need()
+    _say("colsum", rows, cols)
+    rng = np.random.default_rng(rows + cols)
+    dz = rng.standard_normal((rows, cols)).astype(np.float32)
+    ref = dz.astype(np.float64).sum(axis=0)
+    d = torch.from_numpy(dz).cuda()
+    L = pmx.lib()
+    for use_work in (False, True):
+        db = torch.full((cols,), float("nan"), dtype=torch.float32, device="cuda")
+        work = torch.full((((rows + 63) // 64) * cols,), float("nan"), dtype=torch.float32, device="cuda")
+        pmx.check(L.mlp_colsum(rows, cols, pmx.dptr(d), pmx.dptr(db), pmx.dptr(work) if use_work else None,
+                               work.numel() if use_work else 0, pmx.stream_ptr()))
+        torch.cuda.synchronize()
+        got = db.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got - ref) <= 1e-5 * np.abs(dz).astype(np.float64).sum(axis=0) + 1e-6), use_work
 
 
 def test_network_loss_and_gradients_match_fp64_oracle():
