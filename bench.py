@@ -434,8 +434,13 @@ def turn_river_leg(args, stream):
 
 def warm_leg(args, stream, batched):
     """Learned warm start on the batched workload: label instances with the
-    plain batched solver, train the BF16 network on the GPU, then solve the
-    512 held-out instances (the batched workload) from the network's prior."""
+    plain batched solver (to --warm-label-gap of the pot), train the BF16
+    network on the GPU, then solve the 512 held-out instances (the batched
+    workload) from the network's prior under RM+ and under DCFR, each with
+    the uniform start as the per-instance fallback (a probe of both starts;
+    an instance keeps the prior only where its FP64 gap is finite and below
+    the uniform start's).  `batched` holds the uniform-start baselines of the
+    same instances; None measures them here."""
     import torch
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
@@ -443,7 +448,7 @@ def warm_leg(args, stream, batched):
 
     t0 = time.perf_counter()
     train_descs = I.batched_configs(args.warm_train, seed=11)
-    ds = ws.make_dataset(train_descs, batch=512, target=args.warm_label_gap, kind="rm+",
+    ds = ws.make_dataset(train_descs, batch=512, target=args.warm_label_gap, kind=args.warm_label_kind,
                          max_iters=args.warm_label_iters,
                          progress=lambda a, n: log(f"warm start: labelled {a}/{n} instances"))
     torch.cuda.synchronize()
@@ -458,46 +463,58 @@ def warm_leg(args, stream, batched):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     rows_trained = args.warm_steps * 8192
-    flops_per_row = 2 * (64 * 512 + 512 * 512 + 512 * 8) * 3     # forward + backward
+    flops_per_row = 2 * (ws.D_IN * ws.WIDTH + ws.WIDTH * ws.WIDTH + ws.WIDTH * ws.K) * 3   # forward + backward
     n_rows = ds.rows
     del ds
     descs = I.batched_configs(args.batch)
     g = pmx.Game(descs)
-    g.game_tune(*batched["schedule"]["tuned"])
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    ws.apply_prior(g, net, args.warm_scale, args.warm_avg)
-    sec, iters, done = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters)
-    t_warm = time.perf_counter() - t2
-    # the same prior under discounted CFR
-    log(f"warm start: RM+ {t_warm:.2f} s; DCFR from the same prior")
-    g.solver_set_params("dcfr")
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    ws.apply_prior(g, net, args.warm_scale, args.warm_avg)
-    _, iters_d, done_d = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters)
-    t_warm_d = time.perf_counter() - t3
+    g.game_tune(4, 1)
+    base = {}
+    if batched is None:
+        for kind in ("rm+", "dcfr"):
+            g.solver_set_params(kind)
+            g.solver_reset()
+            base[kind], _, _ = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters)
+            log(f"warm start: uniform {kind} {base[kind]:.2f} s")
+    else:
+        base = {"rm+": batched["time_to_gap_batched_s"], "dcfr": batched["time_to_gap_batched_dcfr_s"]}
+    res = {}
+    for kind in ("rm+", "dcfr"):
+        g.solver_set_params(kind)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        keep, gap_u, gap_w = ws.apply_prior_with_fallback(g, net, args.warm_scale, args.warm_avg,
+                                                          probe=args.warm_probe)
+        sec, iters, done = ws.solve_to_gap(g, 1e-4, check_every=32, max_iters=args.max_iters,
+                                           start_iters=args.warm_probe)
+        t_warm = time.perf_counter() - t2
+        r = {"time_to_gap_warm_batched_s": t_warm, "iterations": iters,
+             "instances_reached": int((done >= 0).sum()),
+             "instances_kept_prior": int(keep.sum()),
+             "probe_iterations": args.warm_probe,
+             "iterations_per_instance_p50_p90_max": [float(np.percentile(done[done >= 0], q))
+                                                     for q in (50, 90, 100)] if (done >= 0).any() else None,
+             "speedup_vs_batched_uniform": base[kind] / t_warm,
+             "time_to_gap_batched_uniform_s": base[kind]}
+        if batched is not None:
+            r["speedup_vs_plain_single_instance_rm+"] = (batched["plain_single_instance"]["sum_over_batch_s"]
+                                                         / t_warm)
+        res[kind] = r
+        log(f"warm start: {kind} {t_warm:.2f} s from the prior ({int(keep.sum())} of {len(keep)} kept it)")
     g.solver_set_params("rm+")
     g.close()
-    plain_total = batched["plain_single_instance"]["sum_over_batch_s"]
-    return {"train_instances": len(train_descs),
-            "labels": f"average strategies of the plain batched RM+ solver run to {args.warm_label_gap:g} * pot "
-                      f"(at most {args.warm_label_iters} iterations)",
+    return {"workload": f"network trained on {len(train_descs)} synthetic river endgames drawn as the batch "
+                        f"(other seeds), evaluated on the batch's {args.batch} instances",
+            "train_instances": len(train_descs),
+            "labels": f"average strategies of the plain batched {args.warm_label_kind.upper()} solver run to "
+                      f"{args.warm_label_gap:g} * pot (at most {args.warm_label_iters} iterations)",
             "dataset_rows": n_rows, "data_s": t_data,
-            "train_steps": args.warm_steps, "train_s": t_train, "loss_history": hist,
+            "train_steps": args.warm_steps, "train_rows_per_step": 8192, "train_s": t_train,
+            "loss_history": hist,
             "train_tflops": rows_trained * flops_per_row / t_train / 1e12,
-            "prior": {"regret_scale": args.warm_scale, "avg_weight": args.warm_avg},
-            "time_to_gap_warm_batched_s": t_warm,
-            "iterations": iters,
-            "iterations_per_instance_p50_p90_max": [float(np.percentile(done[done >= 0], q))
-                                                    for q in (50, 90, 100)] if (done >= 0).any() else None,
-            "instances_reached": int((done >= 0).sum()),
-            "speedup_vs_plain_single_instance": plain_total / t_warm,
-            "speedup_vs_batched_uniform": batched["time_to_gap_batched_s"] / t_warm,
-            "dcfr": {"time_to_gap_warm_batched_s": t_warm_d, "iterations": iters_d,
-                     "instances_reached": int((done_d >= 0).sum()),
-                     "speedup_vs_plain_single_instance_rm+": plain_total / t_warm_d,
-                     "speedup_vs_batched_uniform_dcfr": batched["time_to_gap_batched_dcfr_s"] / t_warm_d}}
+            "prior": {"regret_scale": args.warm_scale, "avg_weight": args.warm_avg,
+                      "fallback": "uniform start per instance, judged by the FP64 gap after the probe"},
+            "rm+": res["rm+"], "dcfr": res["dcfr"]}
 
 
 def pmc_probe(args):
@@ -800,10 +817,14 @@ def main():
     ap.add_argument("--turn-budget", type=float, default=90.0,
                     help="seconds for the turn + river precision run")
     ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--warm-only", action="store_true",
+                    help="only the warm-start leg (with its own uniform-start baselines)")
     ap.add_argument("--warm-train", type=int, default=2048)
     ap.add_argument("--warm-label-gap", type=float, default=1e-5)
-    ap.add_argument("--warm-label-iters", type=int, default=12288)
-    ap.add_argument("--warm-steps", type=int, default=4000)
+    ap.add_argument("--warm-label-kind", choices=("rm+", "dcfr"), default="dcfr")
+    ap.add_argument("--warm-label-iters", type=int, default=16384)
+    ap.add_argument("--warm-steps", type=int, default=8000)
+    ap.add_argument("--warm-probe", type=int, default=64)
     ap.add_argument("--warm-scale", type=float, default=1.0)
     ap.add_argument("--warm-avg", type=float, default=0.0)
     args = ap.parse_args()
@@ -826,6 +847,9 @@ def main():
         return
     if args.dcfr_sweep:
         dcfr_sweep(args)
+        return
+    if args.warm_only:
+        print(json.dumps({"warm_start": warm_leg(args, torch.cuda.current_stream(), None)}), flush=True)
         return
     stream = torch.cuda.current_stream()
     log("batch leg (headline)")
