@@ -393,6 +393,18 @@ int solver_set_state(Game* g, int32_t player, const float* regret, const float* 
 int solver_get_weights(Game* g, double* wsum_host);
 int solver_set_weights(Game* g, const double* wsum_host);
 
+/* A device-side copy of the solver state (both players' regrets, plans and
+ * average sums, the per-instance weight totals and the iteration count),
+ * kept by the game (allocated at the first call: 16 B per vector element);
+ * asynchronous on `stream`.  solver_restore_instances copies the snapshot's
+ * state back for every instance i with restore[i] != 0 (host array, one flag
+ * per instance) and leaves the others as they are: the per-instance choice
+ * between two runs of the same length, e.g. the uniform start as the
+ * fallback of a warm start judged by the FP64 gap.  PMX_ESTATE without a
+ * snapshot or when the iteration count differs from the snapshot's. */
+int solver_snapshot(Game* g, void* stream);
+int solver_restore_instances(Game* g, const int32_t* restore, void* stream);
+
 /* Average strategy in sequence form (FP64 host array, vec_elems): each
  * instance's weighted sums over its own weight total, or its current plan if
  * it has none. */

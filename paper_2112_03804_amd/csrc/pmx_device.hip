@@ -763,6 +763,15 @@ void k_mvg(GParams P0, const float* __restrict__ in0,
     for (; gi < g1; ++gi) {
       const GGroupS G = load_group(P.groups + gi);
       if (G.ctx != ctx) break;
+      // the next group's input rows, read with this group's record so that
+      // its inputs can be requested right after the staging
+      int nin[NC], nn_in = 0;
+      {
+        const auto np = cst(P.groups + min(gi + 1, g1 - 1));
+#pragma unroll
+        for (int j = 0; j < NC; ++j) nin[j] = np->in[j];
+        nn_in = np->n_in;
+      }
       // the per-hand records are decoded again in every group: hoisting the
       // decoded LDS addresses out of the loop costs more registers than the
       // few integer operations it saves
@@ -781,13 +790,12 @@ void k_mvg(GParams P0, const float* __restrict__ in0,
       }
       if (tid == 0) *(float4*)(R + zrow) = make_float4(0.f, 0.f, 0.f, 0.f);
       if (gi + 1 < g1) {
-        const GGroupS N = load_group(P.groups + gi + 1);
 #pragma unroll
         for (int j = 0; j < NC; ++j)
 #pragma unroll
           for (int k = 0; k < KH; ++k) {
             const int h = tid + k * BLK;
-            v[j][k] = ld_sel(in, N.in[j] + h, N.in[j] >= 0 && h < N.n_in, 0.f);
+            v[j][k] = ld_sel(in, nin[j] + h, nin[j] >= 0 && h < nn_in, 0.f);
           }
       }
       __syncthreads();
@@ -1834,6 +1842,7 @@ struct DevRm {                  // regret-update pieces of one player
   DBuf<int32_t> rows, infs, pulls, ext_seq, ext_slot, grp;
   DBuf<RmBlock> blocks;         // blocks of the active instances, depth d at [blk_off[d], blk_off[d + 1])
   std::vector<int> blk_off;
+  int blk_pull0 = 0;            // depth 0: blocks [blk_off[0], blk_pull0) have no pulls
   std::vector<int> max_rows, max_ext;   // per depth
   DBuf<float> stage;
   int stage_stride = 1;
@@ -1888,6 +1897,10 @@ struct Game {
   std::unique_ptr<TbHost> tb_host;   // the host factors of the last tb_build
   TbCsr tb_m;                        // M after postprocessing as CSR (diagonal included)
   DBuf<int32_t> active;             // per-instance: 1 = iterated by solver_step
+  DBuf<float> snap_R[2], snap_x[2];   // solver_snapshot: regrets, plans
+  DBuf<double> snap_xs[2];            //   and average sums
+  std::vector<double> snap_wsum_i;    //   per-instance weight totals
+  int snap_t = -1;                    //   iterations at the snapshot (-1: none)
   std::vector<char> listed;         // instances the solver's launch lists include
   int n_listed = 0;
   int dcfr = 0, gamma = 1;          // solver rule (see solver_set_params)
@@ -1908,12 +1921,40 @@ struct Game {
   hipGraphExec_t graph_exec = nullptr;
   int graph_iters = 0;
   bool use_graph = true;
+  // the hands-per-thread classes of one grouped matvec run concurrently: the
+  // caller's stream forks to side streams (default priority) and joins them
+  static constexpr int kSide = 3;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kSide] = {};
+  bool fork_ok = false;
   ~Game() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (int i = 0; i < kSide; ++i) {
+      if (side[i]) (void)hipStreamDestroy(side[i]);
+      if (join_ev[i]) (void)hipEventDestroy(join_ev[i]);
+    }
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
   }
 };
+
+// Streams a grouped matvec spreads its class launches over: the caller's
+// and Game::kSide side streams.
+constexpr int kForkStreams = 1 + Game::kSide;
+
+// Side streams and events of the concurrent class launches (created once,
+// outside any capture).
+static int ensure_fork(Game* g) {
+  if (g->fork_ok) return PMX_OK;
+  HIP_TRY(hipEventCreateWithFlags(&g->fork_ev, hipEventDisableTiming));
+  for (int i = 0; i < Game::kSide; ++i) {
+    HIP_TRY(hipStreamCreateWithFlags(&g->side[i], hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&g->join_ev[i], hipEventDisableTiming));
+  }
+  g->fork_ok = true;
+  return PMX_OK;
+}
 
 // Every instance's gap is computed again at the next saddle_gap; a new start
 // of the solver state (reset, a loaded state, a warm start) also restarts the
@@ -2059,17 +2100,24 @@ static int upload_rm_blocks(Game* g, int p, const std::vector<char>& act) {
   E.blk_off.assign(D + 1, 0);
   for (int d = 0; d < D; ++d) {
     E.blk_off[d] = (int)blocks.size();
-    for (int id : T.by_depth[d]) {
-      const RmTask& t = T.tasks[id];
-      if (!act.empty() && !act[t.inst]) continue;
-      for (int h0 = 0; h0 < t.n_hands; h0 += 64) {
-        RmBlock bk{};
-        bk.t = t;
-        bk.h0 = h0;
-        blocks.push_back(bk);
+    // depth 0: the pieces without pulls (no deeper piece hangs from them)
+    // first, so that they can run beside the deep passes
+    for (int pass = 0; pass < (d == 0 ? 2 : 1); ++pass) {
+      if (d == 0 && pass == 1) E.blk_pull0 = (int)blocks.size();
+      for (int id : T.by_depth[d]) {
+        const RmTask& t = T.tasks[id];
+        if (!act.empty() && !act[t.inst]) continue;
+        if (d == 0 && (t.n_pull > 0) != (pass == 1)) continue;
+        for (int h0 = 0; h0 < t.n_hands; h0 += 64) {
+          RmBlock bk{};
+          bk.t = t;
+          bk.h0 = h0;
+          blocks.push_back(bk);
+        }
       }
     }
   }
+  if (D == 0) E.blk_pull0 = 0;
   E.blk_off[D] = (int)blocks.size();
   return E.blocks.upload(blocks);
 }
@@ -2272,34 +2320,92 @@ static void launch_mc_class(const McParams& A, const IO* in0, IO* out0, const Mc
 }
 
 // Kernels 2 and 3: one launch per hands-per-thread class present.
+// Independent launches (the hands-per-thread classes of one product: they
+// write disjoint output rows) run concurrently: largest first, each onto the
+// stream with the least work so far, among the caller's stream and up to
+// Game::kSide side streams forked from it (an event recorded on s, waited
+// for by each side stream) and joined back into s before the call returns.
+// Under stream capture the fork and join become graph edges.  A class's
+// tail then overlaps the others' work, and workgroups of different classes
+// share a CU's LDS.  `launch(i, stream, first)` enqueues launch i; `first`
+// marks the one launch that carries the iteration tick.
+template <typename F>
+static int fork_launches(Game* g, hipStream_t s, int n, const int64_t* work_in, F&& launch) {
+  int order[16];
+  int64_t work[16];
+  if (n > 16) return fail(PMX_EINVAL, "too many concurrent launches");
+  for (int i = 0; i < n; ++i) {
+    order[i] = i;
+    work[i] = work_in[i];
+  }
+  for (int i = 1; i < n; ++i)
+    for (int j = i; j > 0 && work[j] > work[j - 1]; --j) {
+      std::swap(work[j], work[j - 1]);
+      std::swap(order[j], order[j - 1]);
+    }
+  const int ns = g->fork_ok ? std::min(n, kForkStreams) : 1;
+  int on[16];
+  int64_t load[kForkStreams] = {};
+  for (int i = 0; i < n; ++i) {
+    int best = 0;
+    for (int k = 1; k < ns; ++k)
+      if (load[k] < load[best]) best = k;
+    on[i] = best;
+    load[best] += work[i];
+  }
+  if (ns > 1) {
+    HIP_TRY(hipEventRecord(g->fork_ev, s));
+    for (int k = 1; k < ns; ++k) HIP_TRY(hipStreamWaitEvent(g->side[k - 1], g->fork_ev, 0));
+  }
+  for (int i = 0; i < n; ++i) {
+    const int rc = launch(order[i], on[i] > 0 ? g->side[on[i] - 1] : s, i == 0);
+    if (rc) return rc;
+  }
+  for (int k = 1; k < ns; ++k) {
+    HIP_TRY(hipEventRecord(g->join_ev[k - 1], g->side[k - 1]));
+    HIP_TRY(hipStreamWaitEvent(s, g->join_ev[k - 1], 0));
+  }
+  return PMX_OK;
+}
+
 template <typename IO>
 static int launch_mc(Game* g, const MvParams& P0, const IO* in0, IO* out0, const MvParams& P1, const IO* in1,
                      IO* out1, hipStream_t s, double* tick) {
   const int block = g->dm[0].block;
   if (block == 0 || g->dm[1].block != block) return fail(PMX_ESTATE, "matvec layout not built");
+  int cls[kMcClasses], n = 0;
+  int64_t work[kMcClasses];
   for (int c = 0; c < kMcClasses; ++c) {
     const McParams A = mc_params(g, P0.dir, P0, c), B = mc_params(g, P1.dir, P1, c);
     if (A.nchunk + B.nchunk == 0) continue;
+    if (block == 512 && c > 2) return fail(PMX_EINVAL, "no 512-thread matvec class for this hand count");
+    work[n] = (int64_t)(A.nchunk + B.nchunk) * (c + 1);
+    cls[n++] = c;
+  }
+  int rc = fork_launches(g, s, n, work, [&](int i, hipStream_t st, bool first) {
+    const int c = cls[i];
+    const McParams A = mc_params(g, P0.dir, P0, c), B = mc_params(g, P1.dir, P1, c);
+    double* tk = first ? tick : nullptr;
     if (block == 512) {
       switch (c) {
-        case 0: launch_mc_class<512, 1, IO>(A, in0, out0, B, in1, out1, s, tick); break;
-        case 1: launch_mc_class<512, 2, IO>(A, in0, out0, B, in1, out1, s, tick); break;
-        case 2: launch_mc_class<512, 3, IO>(A, in0, out0, B, in1, out1, s, tick); break;
-        default: return fail(PMX_EINVAL, "no 512-thread matvec class for this hand count");
+        case 0: launch_mc_class<512, 1, IO>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 1: launch_mc_class<512, 2, IO>(A, in0, out0, B, in1, out1, st, tk); break;
+        default: launch_mc_class<512, 3, IO>(A, in0, out0, B, in1, out1, st, tk); break;
       }
     } else {
       switch (c) {
-        case 0: launch_mc_class<256, 1, IO>(A, in0, out0, B, in1, out1, s, tick); break;
-        case 1: launch_mc_class<256, 2, IO>(A, in0, out0, B, in1, out1, s, tick); break;
-        case 2: launch_mc_class<256, 3, IO>(A, in0, out0, B, in1, out1, s, tick); break;
-        case 3: launch_mc_class<256, 4, IO>(A, in0, out0, B, in1, out1, s, tick); break;
-        default: launch_mc_class<256, 5, IO>(A, in0, out0, B, in1, out1, s, tick); break;
+        case 0: launch_mc_class<256, 1, IO>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 1: launch_mc_class<256, 2, IO>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 2: launch_mc_class<256, 3, IO>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 3: launch_mc_class<256, 4, IO>(A, in0, out0, B, in1, out1, st, tk); break;
+        default: launch_mc_class<256, 5, IO>(A, in0, out0, B, in1, out1, st, tk); break;
       }
     }
-    tick = nullptr;   // the iteration tick belongs to the first launch
-  }
+    return PMX_OK;
+  });
+  if (rc) return rc;
   // every instance retired from the lists: the iteration still counts
-  if (tick) hipLaunchKernelGGL(k_add1, dim3(1), dim3(1), 0, s, tick);
+  if (n == 0 && tick) hipLaunchKernelGGL(k_add1, dim3(1), dim3(1), 0, s, tick);
   HIP_TRY(hipGetLastError());
   return PMX_OK;
 }
@@ -2331,34 +2437,46 @@ static void launch_grp_class(const GParams& A, const float* in0, float* out0, co
                      in1, out1, tick);
 }
 
-// Kernel 4 (FP32 only): one launch per hands-per-thread class present.
+// Kernel 4 (FP32 only): one launch per hands-per-thread class present, the
+// classes concurrently (fork_launches).
 static int launch_grp(Game* g, const MvParams& P0, const float* in0, float* out0, const MvParams& P1,
                       const float* in1, float* out1, hipStream_t s, double* tick) {
   if (!g->dg[0].built || !g->dg[1].built) return fail(PMX_ESTATE, "grouped matvec layout not built");
+  int cls[2 * kGrpClasses], n = 0;
+  int64_t work[2 * kGrpClasses];
   for (int kind = 0; kind < 2; ++kind)
     for (int c = 0; c < kGrpClasses; ++c) {
       const GParams A = grp_params(g, P0.dir, P0, kind, c), B = grp_params(g, P1.dir, P1, kind, c);
       if (A.nchunk + B.nchunk == 0) continue;
-      if (kind == 0) {
-        switch (c) {
-          case 0: launch_grp_class<1, false>(A, in0, out0, B, in1, out1, s, tick); break;
-          case 1: launch_grp_class<2, false>(A, in0, out0, B, in1, out1, s, tick); break;
-          case 2: launch_grp_class<3, false>(A, in0, out0, B, in1, out1, s, tick); break;
-          case 3: launch_grp_class<4, false>(A, in0, out0, B, in1, out1, s, tick); break;
-          default: launch_grp_class<5, false>(A, in0, out0, B, in1, out1, s, tick); break;
-        }
-      } else {
-        switch (c) {
-          case 0: launch_grp_class<1, true>(A, in0, out0, B, in1, out1, s, tick); break;
-          case 1: launch_grp_class<2, true>(A, in0, out0, B, in1, out1, s, tick); break;
-          case 2: launch_grp_class<3, true>(A, in0, out0, B, in1, out1, s, tick); break;
-          case 3: launch_grp_class<4, true>(A, in0, out0, B, in1, out1, s, tick); break;
-          default: launch_grp_class<5, true>(A, in0, out0, B, in1, out1, s, tick); break;
-        }
-      }
-      tick = nullptr;   // the iteration tick belongs to the first launch
+      work[n] = (int64_t)(A.nchunk + B.nchunk) * kGrpKE[c];
+      cls[n++] = kind * kGrpClasses + c;
     }
-  if (tick) hipLaunchKernelGGL(k_add1, dim3(1), dim3(1), 0, s, tick);
+  int rc = fork_launches(g, s, n, work, [&](int i, hipStream_t st, bool first) {
+    const int kind = cls[i] / kGrpClasses, c = cls[i] % kGrpClasses;
+    const GParams A = grp_params(g, P0.dir, P0, kind, c), B = grp_params(g, P1.dir, P1, kind, c);
+    double* tk = first ? tick : nullptr;
+    if (kind == 0) {
+      switch (c) {
+        case 0: launch_grp_class<1, false>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 1: launch_grp_class<2, false>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 2: launch_grp_class<3, false>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 3: launch_grp_class<4, false>(A, in0, out0, B, in1, out1, st, tk); break;
+        default: launch_grp_class<5, false>(A, in0, out0, B, in1, out1, st, tk); break;
+      }
+    } else {
+      switch (c) {
+        case 0: launch_grp_class<1, true>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 1: launch_grp_class<2, true>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 2: launch_grp_class<3, true>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 3: launch_grp_class<4, true>(A, in0, out0, B, in1, out1, st, tk); break;
+        default: launch_grp_class<5, true>(A, in0, out0, B, in1, out1, st, tk); break;
+      }
+    }
+    return PMX_OK;
+  });
+  if (rc) return rc;
+  // every instance retired from the lists: the iteration still counts
+  if (n == 0 && tick) hipLaunchKernelGGL(k_add1, dim3(1), dim3(1), 0, s, tick);
   HIP_TRY(hipGetLastError());
   return PMX_OK;
 }
@@ -2403,10 +2521,10 @@ static TpParams tp_params(Game* g, int p, const int2* blocks) {
 }
 
 
-static RmParams rm_params(Game* g, int p, int depth) {
+static RmParams rm_params(Game* g, int p, int depth, int first_block) {
   DevRm& E = g->drm[p];
   RmParams P;
-  P.blocks = E.blocks.p + E.blk_off[depth];
+  P.blocks = E.blocks.p + first_block;
   P.rows = E.rows.p;
   P.infs = E.infs.p;
   P.pulls = E.pulls.p;
@@ -2432,10 +2550,10 @@ static int rm_update(Game* g, int p, hipStream_t s) {
   float* gr = g->grad[p].p;
   const double* td = g->tdev.p;
   const int D = (int)E.max_rows.size();
-  auto launch = [&](int mode, int d) {
-    const int nb = E.blk_off[d + 1] - E.blk_off[d];
-    if (nb == 0) return;
-    const RmParams P = rm_params(g, p, d);
+  auto launch_range = [&](int mode, int d, int b0, int b1, hipStream_t s) {
+    const int nb = b1 - b0;
+    if (nb <= 0) return;
+    const RmParams P = rm_params(g, p, d, b0);
     // few workgroups: the walk's latency is the cost, four lanes per hand
     // (k_rmq); many: the bytes are, one lane per hand (k_rmp)
     const bool quad = nb <= g->hg.rm_quad_max;
@@ -2464,9 +2582,25 @@ static int rm_update(Game* g, int p, hipStream_t s) {
       else go(k_rmp<2, false>);
     }
   };
+  auto launch = [&](int mode, int d) { launch_range(mode, d, E.blk_off[d], E.blk_off[d + 1], s); };
+  if (D == 0) return PMX_OK;
+  // the pieces of depth 0 without pulls run on a side stream beside the
+  // chain deep bottom-up -> depth 0 with pulls -> deep top-down (the
+  // pieces of one pass are independent; only the chain is ordered)
+  const bool side = g->fork_ok && D > 1 && E.blk_pull0 > E.blk_off[0] && E.blk_off[1] > E.blk_pull0;
+  if (side) {
+    HIP_TRY(hipEventRecord(g->fork_ev, s));
+    HIP_TRY(hipStreamWaitEvent(g->side[0], g->fork_ev, 0));
+    launch_range(0, 0, E.blk_off[0], E.blk_pull0, g->side[0]);
+  }
   for (int d = D - 1; d >= 1; --d) launch(1, d);
-  if (D > 0) launch(0, 0);
+  if (side) launch_range(0, 0, E.blk_pull0, E.blk_off[1], s);
+  else launch(0, 0);
   for (int d = 1; d < D; ++d) launch(2, d);
+  if (side) {
+    HIP_TRY(hipEventRecord(g->join_ev[0], g->side[0]));
+    HIP_TRY(hipStreamWaitEvent(s, g->join_ev[0], 0));
+  }
   HIP_TRY(hipGetLastError());
   return PMX_OK;
 }
@@ -2572,6 +2706,7 @@ static int create_common(const GameDesc* descs, int32_t n, bool device, Game** o
       g->max_lds = lds;
     int rc = upload_game(g.get());
     if (rc) return rc;
+    if ((rc = ensure_fork(g.get()))) return rc;
     // set-up of the allocation-free gap on this device (once per device)
     double* scr = nullptr;
     if ((rc = static_scratch(dev, &scr))) return rc;
@@ -3385,6 +3520,52 @@ int solver_get_weights(Game* g, double* wsum_host) {
   if (rc) return rc;
   if (!wsum_host) return fail(PMX_EINVAL, "null argument");
   std::copy(g->wsum_i.begin(), g->wsum_i.end(), wsum_host);
+  return PMX_OK;
+}
+
+int solver_snapshot(Game* g, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  for (int p = 0; p < 2; ++p) {
+    const size_t n = (size_t)g->hg.elems[p];
+    if (g->snap_R[p].n != n) {
+      if ((rc = g->snap_R[p].alloc(n)) || (rc = g->snap_x[p].alloc(n)) || (rc = g->snap_xs[p].alloc(n))) return rc;
+    }
+    if (n) {
+      HIP_TRY(hipMemcpyAsync(g->snap_R[p].p, g->R[p].p, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+      HIP_TRY(hipMemcpyAsync(g->snap_x[p].p, g->x[p].p, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+      HIP_TRY(hipMemcpyAsync(g->snap_xs[p].p, g->xs[p].p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+  }
+  g->snap_wsum_i = g->wsum_i;
+  g->snap_t = g->t;
+  return PMX_OK;
+}
+
+int solver_restore_instances(Game* g, const int32_t* restore, void* stream) {
+  int rc = ensure_device(g);
+  if (rc) return rc;
+  if (!restore) return fail(PMX_EINVAL, "null argument");
+  if (g->snap_t < 0) return fail(PMX_ESTATE, "no snapshot");
+  if (g->snap_t != g->t) return fail(PMX_ESTATE, "the snapshot was taken at another iteration count");
+  hipStream_t s = (hipStream_t)stream;
+  bool any = false;
+  for (size_t i = 0; i < g->hg.inst.size(); ++i) {
+    if (!restore[i]) continue;
+    any = true;
+    const Built& b = g->hg.inst[i];
+    for (int p = 0; p < 2; ++p) {
+      const size_t off = (size_t)b.vec_off[p], n = (size_t)b.sf.n_seq[p] * (size_t)b.stride[p];
+      if (!n) continue;
+      HIP_TRY(hipMemcpyAsync(g->R[p].p + off, g->snap_R[p].p + off, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+      HIP_TRY(hipMemcpyAsync(g->x[p].p + off, g->snap_x[p].p + off, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+      HIP_TRY(hipMemcpyAsync(g->xs[p].p + off, g->snap_xs[p].p + off, n * sizeof(double), hipMemcpyDeviceToDevice,
+                             s));
+    }
+    g->wsum_i[i] = g->snap_wsum_i[i];
+  }
+  if (any) invalidate_gaps(g);
   return PMX_OK;
 }
 

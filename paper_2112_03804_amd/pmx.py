@@ -94,6 +94,7 @@ EXPORTS = [
     "mlp_gemm_bf16", "mlp_softmax_xent", "mlp_colsum", "mlp_adam", "mlp_gather_bf16",
     "mlp_gather_f32", "mlp_cast_bf16", "solver_set_active", "solver_set_params", "solver_set_task_rows", "solver_set_rm_quad",
     "solver_set_gap_guard", "tb_build", "tb_matrix", "matvec_A_tb", "matvec_AT_tb",
+    "solver_snapshot", "solver_restore_instances",
 ]
 
 
@@ -138,6 +139,8 @@ def lib():
     L.solver_set_task_rows.argtypes = [vp, ctypes.c_int32]
     L.solver_set_rm_quad.argtypes = [vp, ctypes.c_int32]
     L.solver_set_gap_guard.argtypes = [vp, ctypes.c_int32]
+    L.solver_snapshot.argtypes = [vp, vp]
+    L.solver_restore_instances.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     L.tb_build.argtypes = [vp, ctypes.POINTER(TbSizesC)]
     L.tb_matrix.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(TbMatrixC)]
     L.matvec_A_tb.argtypes = [vp, vp, vp, vp]
@@ -309,6 +312,15 @@ class Game:
 
     def solver_set_gap_guard(self, k: int):
         _check(lib().solver_set_gap_guard(self._h, int(k)))
+
+    def solver_snapshot(self, stream=None):
+        _check(lib().solver_snapshot(self._h, _stream(stream)))
+
+    def solver_restore_instances(self, restore, stream=None):
+        a = np.ascontiguousarray(restore, dtype=np.int32)
+        if a.shape != (self.n_instances,):
+            raise ValueError("one flag per instance")
+        _check(lib().solver_restore_instances(self._h, _ptr(a, ctypes.c_int32), _stream(stream)))
 
     def solver_set_rm_quad(self, max_records: int):
         """Regret launches of at most max_records block records use the

@@ -259,16 +259,16 @@ def apply_logits_with_fallback(game, logits, regret_scale: float, avg_weight: fl
     per player) each run `probe` solver iterations; an instance keeps the
     prior's run only if its logits are finite and its FP64 gap after the
     probe is below the uniform run's; the others continue from the uniform
-    run's state (regrets, plans, averages and weight totals spliced in per
-    instance).  The game ends `probe` iterations in either way.  Returns the
-    per-instance flags (True: the prior was kept) and both probe gaps."""
+    run's state (regrets, plans, averages and weight totals, restored on the
+    device from a snapshot).  The game ends `probe` iterations in either way.
+    Returns the per-instance flags (True: the prior was kept) and both probe
+    gaps."""
     torch = _torch()
     ni = game.n_instances
     game.solver_reset()
     game.solver_step(probe)
     gap_u = game.saddle_gap()[0]
-    st_u = [game.solver_get_state(p) for p in range(2)]
-    w_u = game.solver_get_weights()
+    game.solver_snapshot()
     finite = np.ones(ni, dtype=bool)
     for p in range(2):
         off = _instance_rows(game, p)
@@ -280,19 +280,7 @@ def apply_logits_with_fallback(game, logits, regret_scale: float, avg_weight: fl
     gap_w = game.saddle_gap()[0]
     keep = finite & (gap_w < gap_u)
     if not keep.all():
-        st_w = [game.solver_get_state(p) for p in range(2)]
-        w = game.solver_get_weights()
-        for p in range(2):
-            st = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st_w[p].items()}
-            for i in np.flatnonzero(~keep):
-                L = game.layouts[i][p]
-                a, b = L["vec_offset"], L["vec_offset"] + L["n_seq"] * L["stride"]
-                for k in ("regret", "plan", "avg_sum"):
-                    st[k][a:b] = st_u[p][k][a:b]
-            game.solver_set_state(p, regret=st["regret"], plan=st["plan"], avg_sum=st["avg_sum"], t=st["t"],
-                                  wsum=st["wsum"])
-        w = np.where(keep, w, w_u)
-        game.solver_set_weights(w)
+        game.solver_restore_instances((~keep).astype(np.int32))
     return keep, gap_u, gap_w
 
 

@@ -325,16 +325,33 @@ def test_warm_start_fallback_per_instance():
     u = pmx.Game(descs)
     u.solver_step(probe)
     for p in range(2):
-        a = g.unpack(p, g.solver_get_state(p)["avg_sum"])
-        b = u.unpack(p, u.solver_get_state(p)["avg_sum"])
-        for i in (1, 2):
-            assert np.array_equal(a[i], b[i])
-        assert not np.array_equal(a[0], b[0])
+        sg, su = g.solver_get_state(p), u.solver_get_state(p)
+        for field in ("regret", "plan", "avg_sum"):
+            a = g.unpack(p, sg[field])
+            b = u.unpack(p, su[field])
+            for i in (1, 2):
+                assert np.array_equal(a[i], b[i]), field
+        assert not np.array_equal(g.unpack(p, sg["avg_sum"])[0], u.unpack(p, su["avg_sum"])[0])
+    assert np.array_equal(g.solver_get_weights()[1:], u.solver_get_weights()[1:])
     gap = g.saddle_gap()[0]
     ugap = u.saddle_gap()[0]
     assert gap[1] == ugap[1] and gap[2] == ugap[2]
     assert gap[0] < ugap[0]
     u.close()
+    g.close()
+
+
+def test_snapshot_restore_errors():
+    """Restoring needs a snapshot taken at the same iteration count."""
+    pmx, _ = _need()
+    g = pmx.Game([I.small_river(0), I.small_river(1)])
+    with pytest.raises(pmx.PmxError):
+        g.solver_restore_instances([1, 0])
+    g.solver_step(4)
+    g.solver_snapshot()
+    g.solver_step(1)
+    with pytest.raises(pmx.PmxError):
+        g.solver_restore_instances([1, 1])
     g.close()
 
 
