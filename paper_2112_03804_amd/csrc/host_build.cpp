@@ -1099,6 +1099,7 @@ int build_grp_layout(HostGame& hg, int d, int gpc, std::string& msg) {
         G.stride = b.stride[p];
         G.n_in = in.n[q];
         G.fc = 0;
+        G.sc = 0xe4;   // output o: showdown component o
         G.acc = 0;
         for (int o = 0; o < kGrpComps; ++o) {
           G.in[o] = H.in[o] >= 0 ? (int32_t)(in_base + H.in[o] * sq) : -1;
@@ -1234,22 +1235,56 @@ int build_grp_layout(HostGame& hg, int d, int gpc, std::string& msg) {
       for (size_t k = a; k < std::min(empty.size(), a + kGrpComps); ++k) sl[k - a] = empty[k];
       emit(sl, {GroupH()});
     }
-    // workgroup chunks: about gpc groups, cut at sequence boundaries
+    // workgroup chunks: about gpc groups, cut at sequence boundaries.  A
+    // single group that reads at most two input rows (often four outputs,
+    // each a fold or a showdown term of one of two rows) runs two-wide: its
+    // components move to 0 and 1 and each output names the component of its
+    // showdown term (sc) as it names that of its fold term (fc)
+    auto narrow = [&](int gi) {
+      const GGroup& G = M.groups[gi];
+      if (G.ctx < 0) return false;
+      int used = 0;
+      for (int j = 0; j < kGrpComps; ++j) used += G.in[j] >= 0;
+      return used <= 2;
+    };
+    auto compact = [&](int gi) {
+      GGroup& G = M.groups[gi];
+      int to[kGrpComps] = {0, 0, 0, 0}, in2[kGrpComps] = {-1, -1, -1, -1}, n = 0;
+      for (int j = 0; j < kGrpComps; ++j)
+        if (G.in[j] >= 0) {
+          to[j] = n;
+          in2[n++] = G.in[j];
+        }
+      int fc = 0, sc = 0;
+      for (int o = 0; o < kGrpComps; ++o) {
+        const int fj = (G.fc >> (2 * o)) & 3;
+        fc |= (G.in[fj] >= 0 ? to[fj] : 0) << (2 * o);
+        sc |= (G.in[o] >= 0 ? to[o] : 0) << (2 * o);   // no row there: no showdown term (ks = 0)
+      }
+      for (int j = 0; j < kGrpComps; ++j) G.in[j] = in2[j];
+      G.fc = fc;
+      G.sc = sc;
+    };
+    auto kind_of = [&](const std::pair<int, int>& sq) {
+      if (sq.second - sq.first > 1) return 1;
+      return narrow(sq.first) ? 2 : 0;
+    };
+    for (const auto& sq : seqs)
+      if (kind_of(sq) == 2) compact(sq.first);
     size_t k = 0;
     while (k < seqs.size()) {
       const int g0 = seqs[k].first;
       int g1 = seqs[k].second;
-      const bool carry = g1 - g0 > 1;
+      const int kind = kind_of(seqs[k]);
       ++k;
       // rows without terms take chunks of their own (a separate path of the
-      // kernel), and sequences of several groups chunks of the carrying kind
+      // kernel), and every chunk holds sequences of one kind
       while (k < seqs.size() && seqs[k].second - g0 <= gpc &&
-             (M.groups[seqs[k].first].ctx < 0) == (M.groups[g0].ctx < 0) &&
-             (seqs[k].second - seqs[k].first > 1) == carry) {
+             (M.groups[seqs[k].first].ctx < 0) == (M.groups[g0].ctx < 0) && kind_of(seqs[k]) == kind) {
         g1 = seqs[k].second;
         ++k;
       }
-      std::vector<int32_t>& L = M.chunks[carry ? 1 : 0][cls];
+      std::vector<int32_t>& L = M.chunks[kind][cls];
       L.push_back(g0);
       L.push_back(g1);
       L.push_back((int32_t)ii);

@@ -503,55 +503,54 @@ template <int CTRL>
 __device__ inline double dpp_dz(double v) {
   return __hiloint2double(dpp_iz<CTRL>(__double2hiint(v)), dpp_iz<CTRL>(__double2loint(v)));
 }
-template <int CTRL, int RM>
-__device__ inline void seg_step4(int& f, double (&a)[kGrpComps]) {
+template <int CTRL, int RM, int NC>
+__device__ inline void seg_step4(int& f, double (&a)[NC]) {
   const int f2 = RM == 0xf ? dpp_iz<CTRL>(f) : dpp_i<CTRL, RM>(f);
   const double m = f ? 0.0 : 1.0;
 #pragma unroll
-  for (int j = 0; j < kGrpComps; ++j) a[j] = fma(RM == 0xf ? dpp_dz<CTRL>(a[j]) : dpp_d<CTRL, RM>(a[j]), m, a[j]);
+  for (int j = 0; j < NC; ++j) a[j] = fma(RM == 0xf ? dpp_dz<CTRL>(a[j]) : dpp_d<CTRL, RM>(a[j]), m, a[j]);
   f |= f2;
 }
 
-// Exclusive segmented scan of four values over the threads of a block (as
+// Exclusive segmented scan of NC values over the threads of a block (as
 // block_seg_scan_x): the exclusive sum is the inclusive one minus the own
 // value.  One barrier; `scr` holds 5 doubles per wavefront.
-template <int NW>
-__device__ inline void block_seg_scan4(int flag, const double (&a)[kGrpComps], double* scr,
-                                       double (&e)[kGrpComps]) {
+template <int NW, int NC>
+__device__ inline void block_seg_scan4(int flag, const double (&a)[NC], double* scr, double (&e)[NC]) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   int f = flag;
-  double ai[kGrpComps];
+  double ai[NC];
 #pragma unroll
-  for (int j = 0; j < kGrpComps; ++j) ai[j] = a[j];
-  seg_step4<0x111, 0xf>(f, ai);
-  seg_step4<0x112, 0xf>(f, ai);
-  seg_step4<0x114, 0xf>(f, ai);
-  seg_step4<0x118, 0xf>(f, ai);
-  seg_step4<0x142, 0xa>(f, ai);
-  seg_step4<0x143, 0xc>(f, ai);
+  for (int j = 0; j < NC; ++j) ai[j] = a[j];
+  seg_step4<0x111, 0xf, NC>(f, ai);
+  seg_step4<0x112, 0xf, NC>(f, ai);
+  seg_step4<0x114, 0xf, NC>(f, ai);
+  seg_step4<0x118, 0xf, NC>(f, ai);
+  seg_step4<0x142, 0xa, NC>(f, ai);
+  seg_step4<0x143, 0xc, NC>(f, ai);
   if (lane == 63) {
     scr[5 * wid] = (double)f;
 #pragma unroll
-    for (int j = 0; j < kGrpComps; ++j) scr[5 * wid + 1 + j] = ai[j];
+    for (int j = 0; j < NC; ++j) scr[5 * wid + 1 + j] = ai[j];
   }
   __syncthreads();
   static_assert(NW <= 8, "wavefront totals are scanned within one DPP row");
   int fw = 0;
-  double aw[kGrpComps];
+  double aw[NC];
 #pragma unroll
-  for (int j = 0; j < kGrpComps; ++j) aw[j] = 0.0;
+  for (int j = 0; j < NC; ++j) aw[j] = 0.0;
   if (lane < NW) {
     fw = scr[5 * lane] != 0.0;
 #pragma unroll
-    for (int j = 0; j < kGrpComps; ++j) aw[j] = scr[5 * lane + 1 + j];
+    for (int j = 0; j < NC; ++j) aw[j] = scr[5 * lane + 1 + j];
   }
-  seg_step4<0x111, 0xf>(fw, aw);
-  seg_step4<0x112, 0xf>(fw, aw);
-  seg_step4<0x114, 0xf>(fw, aw);
+  seg_step4<0x111, 0xf, NC>(fw, aw);
+  seg_step4<0x112, 0xf, NC>(fw, aw);
+  seg_step4<0x114, 0xf, NC>(fw, aw);
   const double m = (wid > 0 && !f) ? 1.0 : 0.0;
   const int src = wid > 0 ? wid - 1 : 0;
 #pragma unroll
-  for (int j = 0; j < kGrpComps; ++j) {
+  for (int j = 0; j < NC; ++j) {
     const double c = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(aw[j]), src),
                                       __builtin_amdgcn_readlane(__double2loint(aw[j]), src));
     e[j] = fma(c, m, ai[j]) - a[j];
@@ -578,7 +577,7 @@ __device__ inline T ld_sel(const T* p, int64_t i, bool ok, T zero) {
 struct GGroupS {
   int32_t in[kGrpComps], out[kGrpComps];
   double ks[kGrpComps], kf[kGrpComps];
-  int32_t ctx, fc, acc, n_own, stride, n_in;
+  int32_t ctx, fc, sc, acc, n_own, stride, n_in;
 };
 __device__ inline GGroupS load_group(const GGroup* p) {
   const auto gp = cst(p);
@@ -592,6 +591,7 @@ __device__ inline GGroupS load_group(const GGroup* p) {
   }
   G.ctx = gp->ctx;
   G.fc = gp->fc;
+  G.sc = gp->sc;
   G.acc = gp->acc;
   G.n_own = gp->n_own;
   G.stride = gp->stride;
@@ -608,49 +608,76 @@ __device__ inline int xcd_chunk(int b, int n) {
   return x * q + min(x, r) + (b >> 3);
 }
 
-__device__ inline float4 grp_slot(const char* R, uint32_t slot) { return *(const float4*)(R + 16 * slot); }
+// LDS slots of a group: NC FP32 values (16 bytes for four components, 8 for
+// two).  The layout's byte offsets are built for 16-byte slots; a two-wide
+// launch halves them.
+template <int NC>
+struct GSlot;
+template <>
+struct GSlot<4> {
+  static constexpr int SB = 16, SH = 0;
+  __device__ static void ld(const char* p, float (&v)[4]) {
+    const float4 t = *(const float4*)p;
+    v[0] = t.x, v[1] = t.y, v[2] = t.z, v[3] = t.w;
+  }
+  __device__ static void st(char* p, const float (&v)[4]) { *(float4*)p = make_float4(v[0], v[1], v[2], v[3]); }
+};
+template <>
+struct GSlot<2> {
+  static constexpr int SB = 8, SH = 1;
+  __device__ static void ld(const char* p, float (&v)[2]) {
+    const float2 t = *(const float2*)p;
+    v[0] = t.x, v[1] = t.y;
+  }
+  __device__ static void st(char* p, const float (&v)[2]) { *(float2*)p = make_float2(v[0], v[1]); }
+};
+template <int NC>
+__device__ inline void grp_slot(const char* R, uint32_t slot, float (&v)[NC]) {
+  GSlot<NC>::ld(R + GSlot<NC>::SB * slot, v);
+}
 
-// Showdown and fold values of the four components for one own hand from the
+// Showdown and fold values of the NC components for one own hand from the
 // prefix slots, the segment totals and the identical hand.
-template <int KE>
-__device__ inline void grp_query(const char* R, const double* segT, uint4 r, int cph, double (&sd)[kGrpComps],
-                                 double (&fo)[kGrpComps]) {
+template <int KE, int NC>
+__device__ inline void grp_query(const char* R, const double* segT, uint4 r, int cph, double (&sd)[NC],
+                                 double (&fo)[NC]) {
   constexpr int BLK = kGrpBlock;
-  const float4 g0 = grp_slot(R, r.x & 0xffffu), g1 = grp_slot(R, r.x >> 16);
-  const float4 a0 = grp_slot(R, r.y & 0xffffu), a1 = grp_slot(R, r.y >> 16);
+  float g0[NC], g1[NC], a0[NC], a1[NC];
+  grp_slot<NC>(R, r.x & 0xffffu, g0);
+  grp_slot<NC>(R, r.x >> 16, g1);
+  grp_slot<NC>(R, r.y & 0xffffu, a0);
+  grp_slot<NC>(R, r.y >> 16, a1);
   const int c0 = r.w & 63, c1 = (r.w >> 6) & 63;
-  const double2* T = (const double2*)segT;   // 4 doubles per segment
-  const double2 t0a = T[0], t0b = T[1];
-  const double2 taa = T[2 * (1 + c0)], tab = T[2 * (1 + c0) + 1];
-  const double t0[4] = {t0a.x, t0a.y, t0b.x, t0b.y}, ta[4] = {taa.x, taa.y, tab.x, tab.y};
-  const float gs[4] = {g0.x + g1.x, g0.y + g1.y, g0.z + g1.z, g0.w + g1.w};
-  const float as[4] = {a0.x + a1.x, a0.y + a1.y, a0.z + a1.z, a0.w + a1.w};
+  const double* T = segT;   // NC doubles per segment
 #pragma unroll
-  for (int j = 0; j < kGrpComps; ++j) {
-    sd[j] = ((double)gs[j] - t0[j]) - ((double)as[j] - ta[j]);
-    fo[j] = t0[j] - ta[j];
+  for (int j = 0; j < NC; ++j) {
+    const double t0 = T[j], ta = T[NC * (1 + c0) + j];
+    sd[j] = ((double)(g0[j] + g1[j]) - t0) - ((double)(a0[j] + a1[j]) - ta);
+    fo[j] = t0 - ta;
   }
   if (cph == 2) {
-    const float4 b0 = grp_slot(R, r.z & 0xffffu), b1 = grp_slot(R, r.z >> 16);
-    const double2 tba = T[2 * (1 + c1)], tbb = T[2 * (1 + c1) + 1];
-    const double tb[4] = {tba.x, tba.y, tbb.x, tbb.y};
-    const float bs[4] = {b0.x + b1.x, b0.y + b1.y, b0.z + b1.z, b0.w + b1.w};
-    float4 us = make_float4(0.f, 0.f, 0.f, 0.f);
+    float b0[NC], b1[NC], u[NC];
+    grp_slot<NC>(R, r.z & 0xffffu, b0);
+    grp_slot<NC>(R, r.z >> 16, b1);
+#pragma unroll
+    for (int j = 0; j < NC; ++j) u[j] = 0.f;
     if (r.w & (1u << 12)) {
       // the identical opponent hand: the difference of the prefix sums at
       // its global entry and the next one (the next chunk's first entry when
       // it ends its chunk)
       const uint32_t s0 = r.w >> 14;
       const uint32_t s1 = (r.w & (1u << 13)) ? s0 - (uint32_t)((KE - 1) * BLK) + 1u : s0 + (uint32_t)BLK;
-      const float4 p0 = grp_slot(R, s0);
-      const float4 p1 = grp_slot(R, s1);
-      us = make_float4(p1.x - p0.x, p1.y - p0.y, p1.z - p0.z, p1.w - p0.w);
-    }
-    const float u[4] = {us.x, us.y, us.z, us.w};
+      float p0[NC], p1[NC];
+      grp_slot<NC>(R, s0, p0);
+      grp_slot<NC>(R, s1, p1);
 #pragma unroll
-    for (int j = 0; j < kGrpComps; ++j) {
-      sd[j] -= (double)bs[j] - tb[j];
-      fo[j] += (double)u[j] - tb[j];
+      for (int j = 0; j < NC; ++j) u[j] = p1[j] - p0[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const double tb = T[NC * (1 + c1) + j];
+      sd[j] -= (double)(b0[j] + b1[j]) - tb;
+      fo[j] += (double)u[j] - tb;
     }
   }
 }
@@ -668,18 +695,20 @@ __device__ inline void grp_query(const char* R, const double* segT, uint4 r, int
 // its LDS region allows (four for one hand per thread, three for two or three,
 // two beyond), lowered where the registers of a class would otherwise spill
 // (the carrying form serves only the few sequences of rows summed over boards).
-template <int KH, bool CARRY>
+// Groups of at most two components (about half of a batch's) take launches
+// of their own with two-wide slots: half the LDS, so more workgroups per CU.
+template <int KH, bool CARRY, int NC>
 constexpr int mvg_waves_per_simd() {
-  return KH == 1 ? 4 : (KH == 2 || (KH == 3 && !CARRY)) ? 3 : (KH == 5 && CARRY) ? 1 : 2;
+  return NC == 2 ? (KH <= 2 ? 4 : 3)
+                 : KH == 1 ? 4 : (KH == 2 || (KH == 3 && !CARRY)) ? 3 : (KH == 5 && CARRY) ? 1 : 2;
 }
 
-template <int KH, int KE, bool CARRY>
-__global__ __launch_bounds__(kGrpBlock) __attribute__((amdgpu_waves_per_eu(mvg_waves_per_simd<KH, CARRY>())))
-void k_mvg(GParams P0, const float* __restrict__ in0,
-                                                  float* __restrict__ out0, GParams P1,
-                                                  const float* __restrict__ in1, float* __restrict__ out1,
-                                                  double* __restrict__ tick) {
-  constexpr int BLK = kGrpBlock, NW = BLK / 64, NC = kGrpComps;
+template <int KH, int KE, bool CARRY, int NC>
+__global__ __launch_bounds__(kGrpBlock) __attribute__((amdgpu_waves_per_eu(mvg_waves_per_simd<KH, CARRY, NC>())))
+void k_mvg(GParams P0, const float* __restrict__ in0, float* __restrict__ out0, GParams P1,
+           const float* __restrict__ in1, float* __restrict__ out1, double* __restrict__ tick) {
+  constexpr int BLK = kGrpBlock, NW = BLK / 64, SB = GSlot<NC>::SB, SH = GSlot<NC>::SH;
+  static_assert(NC == 2 || NC == kGrpComps, "two or four components");
   static_assert(KE % 2 == 0, "entry sources are stored in pairs");
   if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1.0;
   const int b = xcd_chunk((int)blockIdx.x, P0.nchunk + P1.nchunk);
@@ -692,9 +721,9 @@ void k_mvg(GParams P0, const float* __restrict__ in0,
   if (P.active && !*cst(P.active + cr.z)) return;   // retired instance
   const int tid = threadIdx.x;
   extern __shared__ double smem[];
-  double* segT = smem;                         // [kMcSegMax][4] segment totals
+  double* segT = smem;                         // [kMcSegMax][NC] segment totals
   double* scr = segT + NC * kMcSegMax;         // [5 * NW] scan scratch
-  char* R = (char*)(scr + 5 * NW);             // staging rows, then prefix slots (16 bytes each)
+  char* R = (char*)(scr + 5 * NW);             // staging rows, then prefix slots (SB bytes each)
 
   const int g0 = cr.x, g1 = cr.y;
   if (cr.w < 0) {
@@ -702,7 +731,7 @@ void k_mvg(GParams P0, const float* __restrict__ in0,
     for (int gi = g0; gi < g1; ++gi) {
       const GGroupS G = load_group(P.groups + gi);
 #pragma unroll
-      for (int o = 0; o < NC; ++o) {
+      for (int o = 0; o < kGrpComps; ++o) {
         if (G.out[o] < 0) continue;
 #pragma unroll
         for (int k = 0; k < KH; ++k) {
@@ -714,10 +743,10 @@ void k_mvg(GParams P0, const float* __restrict__ in0,
     return;
   }
 
-  double acc[CARRY ? NC : 1][CARRY ? KH : 1];   // sums of rows over several groups
+  double acc[CARRY ? kGrpComps : 1][CARRY ? KH : 1];   // sums of rows over several groups
   float v[NC][KH];                             // the inputs of the group in flight
 #pragma unroll
-  for (int o = 0; o < (CARRY ? NC : 1); ++o)
+  for (int o = 0; o < (CARRY ? kGrpComps : 1); ++o)
 #pragma unroll
     for (int k = 0; k < (CARRY ? KH : 1); ++k) acc[o][k] = 0.0;
   {
@@ -784,11 +813,19 @@ void k_mvg(GParams P0, const float* __restrict__ in0,
 #pragma unroll
       for (int k = 0; k < KH; ++k) {
         const int h = tid + k * BLK;
-        if (h < n_opp)
-          *(float4*)(R + rko[k]) =
-              make_float4(lop[k] * v[0][k], lop[k] * v[1][k], lop[k] * v[2][k], lop[k] * v[3][k]);
+        if (h < n_opp) {
+          float w[NC];
+#pragma unroll
+          for (int j = 0; j < NC; ++j) w[j] = lop[k] * v[j][k];
+          GSlot<NC>::st(R + (rko[k] >> SH), w);
+        }
       }
-      if (tid == 0) *(float4*)(R + zrow) = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (tid == 0) {
+        float z[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) z[j] = 0.f;
+        GSlot<NC>::st(R + (zrow >> SH), z);
+      }
       if (gi + 1 < g1) {
 #pragma unroll
         for (int j = 0; j < NC; ++j)
@@ -800,23 +837,23 @@ void k_mvg(GParams P0, const float* __restrict__ in0,
       }
       __syncthreads();
       // gather the chunk and sum it; carry the sums across the segment's chunks
-      float4 ev[KE];
-      float s4[NC] = {0.f, 0.f, 0.f, 0.f};
+      float ev[KE][NC];
+      float s4[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) s4[j] = 0.f;
       if (wlive) {
 #pragma unroll
         for (int i = 0; i < KE; ++i) {
           const uint32_t off = (i & 1) ? srcp[i / 2] >> 16 : srcp[i / 2] & 0xffffu;
-          ev[i] = *(const float4*)(R + off);
-          s4[0] += ev[i].x;
-          s4[1] += ev[i].y;
-          s4[2] += ev[i].z;
-          s4[3] += ev[i].w;
+          GSlot<NC>::ld(R + (off >> SH), ev[i]);
+#pragma unroll
+          for (int j = 0; j < NC; ++j) s4[j] += ev[i][j];
         }
       }
       double a[NC], e[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) a[j] = (double)s4[j];
-      block_seg_scan4<NW>((int)((cm >> 8) & 1u), a, scr, e);
+      block_seg_scan4<NW, NC>((int)((cm >> 8) & 1u), a, scr, e);
       // every gather is done (the scan's barrier): the exclusive prefix sums
       // overwrite the staging rows, each the FP64 carry's FP32 head plus
       // (remainder + partial)
@@ -829,19 +866,20 @@ void k_mvg(GParams P0, const float* __restrict__ in0,
         }
 #pragma unroll
         for (int i = 0; i < KE; ++i) {
-          *(float4*)(R + 16 * (i * BLK + tid)) = make_float4(eh[0] + run[0], eh[1] + run[1], eh[2] + run[2],
-                                                             eh[3] + run[3]);
-          run[0] += ev[i].x;
-          run[1] += ev[i].y;
-          run[2] += ev[i].z;
-          run[3] += ev[i].w;
+          float w[NC];
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            w[j] = eh[j] + run[j];
+            run[j] += ev[i][j];
+          }
+          GSlot<NC>::st(R + SB * (i * BLK + tid), w);
         }
       }
       const int endseg = (int)((cm >> 16) & 255u);
       if (endseg) {
-        double2* T = (double2*)(segT + NC * (endseg - 1));
-        T[0] = make_double2(e[0] + a[0], e[1] + a[1]);
-        T[1] = make_double2(e[2] + a[2], e[3] + a[3]);
+        double* T = segT + NC * (endseg - 1);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) T[j] = e[j] + a[j];
       }
       __syncthreads();
       // own hands: the outputs' values, stored (or carried to the next group
@@ -849,20 +887,27 @@ void k_mvg(GParams P0, const float* __restrict__ in0,
 #pragma unroll
       for (int k = 0; k < KH; ++k) {
         const int h = tid + k * BLK;
-        double val[NC] = {0.0, 0.0, 0.0, 0.0};
+        // outputs: four in every kind; components: NC (a two-wide group's
+        // outputs name their showdown component too)
+        double val[kGrpComps];
+#pragma unroll
+        for (int o = 0; o < kGrpComps; ++o) val[o] = 0.0;
         if (h < n_own && qr[k].x != 0xffffffffu) {
           double sd[NC], fo[NC];
-          grp_query<KE>(R, segT, qr[k], cph, sd, fo);
+          grp_query<KE, NC>(R, segT, qr[k], cph, sd, fo);
 #pragma unroll
-          for (int o = 0; o < NC; ++o) {
+          for (int o = 0; o < kGrpComps; ++o) {
             const int fj = (G.fc >> (2 * o)) & 3;
-            const double f = fj == 0 ? fo[0] : fj == 1 ? fo[1] : fj == 2 ? fo[2] : fo[3];
-            val[o] = G.ks[o] * sd[o] + G.kf[o] * f;
+            double f = fo[0];
+#pragma unroll
+            for (int c = 1; c < NC; ++c) f = fj == c ? fo[c] : f;
+            const double sv = NC == 2 ? (((G.sc >> (2 * o)) & 3) == 1 ? sd[1] : sd[0]) : sd[o % NC];
+            val[o] = G.ks[o] * sv + G.kf[o] * f;
           }
         }
         const double sl = P.scale * (double)low[k];
 #pragma unroll
-        for (int o = 0; o < NC; ++o) {
+        for (int o = 0; o < kGrpComps; ++o) {
           if (CARRY) {
             acc[o][k] = ((G.acc & (1 << o)) ? 0.0 : acc[o][k]) + val[o];
             if (G.out[o] >= 0 && (G.acc & (1 << (4 + o))) && h < G.stride)
@@ -1819,10 +1864,10 @@ struct DevGrp {                 // grouped matvec layout of one direction (kerne
   DBuf<GGroup> groups;
   DBuf<uint32_t> q, src, meta;
   DBuf<uint16_t> rk;
-  DBuf<int32_t> chunks[2][kGrpClasses];       // [plain, carrying sums over groups][class]
-  int count[2][kGrpClasses] = {};
-  DBuf<int32_t> chunks_act[2][kGrpClasses];   // the solver's lists: chunks of active instances only
-  int count_act[2][kGrpClasses] = {};
+  DBuf<int32_t> chunks[GrpDir::kKinds][kGrpClasses];       // [plain, carrying, two-wide][class]
+  int count[GrpDir::kKinds][kGrpClasses] = {};
+  DBuf<int32_t> chunks_act[GrpDir::kKinds][kGrpClasses];   // the solver's lists: active instances only
+  int count_act[GrpDir::kKinds][kGrpClasses] = {};
   bool built = false;
 };
 
@@ -2037,7 +2082,7 @@ static int upload_grp_active(Game* g, int d) {
   DevGrp& E = g->dg[d];
   const GrpDir& M = g->hg.grp[d];
   const bool all = g->listed.size() != g->hg.inst.size();
-  for (int kind = 0; kind < 2; ++kind)
+  for (int kind = 0; kind < GrpDir::kKinds; ++kind)
     for (int c = 0; c < kGrpClasses; ++c) {
       std::vector<int32_t> L;
       const std::vector<int32_t>& F = M.chunks[kind][c];
@@ -2068,7 +2113,7 @@ static int upload_grp(Game* g, int d) {
   if ((rc = E.ctx.upload(M.ctx)) || (rc = E.groups.upload(M.groups)) || (rc = E.q.upload(M.q)) ||
       (rc = E.src.upload(M.src)) || (rc = E.meta.upload(M.meta)) || (rc = E.rk.upload(M.rk)))
     return rc;
-  for (int kind = 0; kind < 2; ++kind)
+  for (int kind = 0; kind < GrpDir::kKinds; ++kind)
     for (int c = 0; c < kGrpClasses; ++c) {
       if ((rc = E.chunks[kind][c].upload(M.chunks[kind][c]))) return rc;
       E.count[kind][c] = (int)M.chunks[kind][c].size() / 4;
@@ -2428,13 +2473,14 @@ static GParams grp_params(Game* g, int d, const MvParams& like, int kind, int c)
   return P;
 }
 
-template <int KH, bool CARRY>
+template <int KH, bool CARRY, int NC>
 static void launch_grp_class(const GParams& A, const float* in0, float* out0, const GParams& B, const float* in1,
                              float* out1, hipStream_t s, double* tick) {
   constexpr int KE = kGrpKE[KH - 1];
-  const size_t lds = sizeof(double) * (kGrpComps * kMcSegMax + 5 * (kGrpBlock / 64)) + 16 * (size_t)kGrpBlock * KE;
-  hipLaunchKernelGGL((k_mvg<KH, KE, CARRY>), dim3(A.nchunk + B.nchunk), dim3(kGrpBlock), lds, s, A, in0, out0, B,
-                     in1, out1, tick);
+  const size_t lds = sizeof(double) * (NC * kMcSegMax + 5 * (kGrpBlock / 64)) +
+                     (size_t)GSlot<NC>::SB * kGrpBlock * KE;
+  hipLaunchKernelGGL((k_mvg<KH, KE, CARRY, NC>), dim3(A.nchunk + B.nchunk), dim3(kGrpBlock), lds, s, A, in0, out0,
+                     B, in1, out1, tick);
 }
 
 // Kernel 4 (FP32 only): one launch per hands-per-thread class present, the
@@ -2442,13 +2488,13 @@ static void launch_grp_class(const GParams& A, const float* in0, float* out0, co
 static int launch_grp(Game* g, const MvParams& P0, const float* in0, float* out0, const MvParams& P1,
                       const float* in1, float* out1, hipStream_t s, double* tick) {
   if (!g->dg[0].built || !g->dg[1].built) return fail(PMX_ESTATE, "grouped matvec layout not built");
-  int cls[2 * kGrpClasses], n = 0;
-  int64_t work[2 * kGrpClasses];
-  for (int kind = 0; kind < 2; ++kind)
+  int cls[GrpDir::kKinds * kGrpClasses], n = 0;
+  int64_t work[GrpDir::kKinds * kGrpClasses];
+  for (int kind = 0; kind < GrpDir::kKinds; ++kind)
     for (int c = 0; c < kGrpClasses; ++c) {
       const GParams A = grp_params(g, P0.dir, P0, kind, c), B = grp_params(g, P1.dir, P1, kind, c);
       if (A.nchunk + B.nchunk == 0) continue;
-      work[n] = (int64_t)(A.nchunk + B.nchunk) * kGrpKE[c];
+      work[n] = (int64_t)(A.nchunk + B.nchunk) * kGrpKE[c] * (kind == 2 ? 1 : 2);
       cls[n++] = kind * kGrpClasses + c;
     }
   int rc = fork_launches(g, s, n, work, [&](int i, hipStream_t st, bool first) {
@@ -2457,19 +2503,27 @@ static int launch_grp(Game* g, const MvParams& P0, const float* in0, float* out0
     double* tk = first ? tick : nullptr;
     if (kind == 0) {
       switch (c) {
-        case 0: launch_grp_class<1, false>(A, in0, out0, B, in1, out1, st, tk); break;
-        case 1: launch_grp_class<2, false>(A, in0, out0, B, in1, out1, st, tk); break;
-        case 2: launch_grp_class<3, false>(A, in0, out0, B, in1, out1, st, tk); break;
-        case 3: launch_grp_class<4, false>(A, in0, out0, B, in1, out1, st, tk); break;
-        default: launch_grp_class<5, false>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 0: launch_grp_class<1, false, 4>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 1: launch_grp_class<2, false, 4>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 2: launch_grp_class<3, false, 4>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 3: launch_grp_class<4, false, 4>(A, in0, out0, B, in1, out1, st, tk); break;
+        default: launch_grp_class<5, false, 4>(A, in0, out0, B, in1, out1, st, tk); break;
+      }
+    } else if (kind == 1) {
+      switch (c) {
+        case 0: launch_grp_class<1, true, 4>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 1: launch_grp_class<2, true, 4>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 2: launch_grp_class<3, true, 4>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 3: launch_grp_class<4, true, 4>(A, in0, out0, B, in1, out1, st, tk); break;
+        default: launch_grp_class<5, true, 4>(A, in0, out0, B, in1, out1, st, tk); break;
       }
     } else {
       switch (c) {
-        case 0: launch_grp_class<1, true>(A, in0, out0, B, in1, out1, st, tk); break;
-        case 1: launch_grp_class<2, true>(A, in0, out0, B, in1, out1, st, tk); break;
-        case 2: launch_grp_class<3, true>(A, in0, out0, B, in1, out1, st, tk); break;
-        case 3: launch_grp_class<4, true>(A, in0, out0, B, in1, out1, st, tk); break;
-        default: launch_grp_class<5, true>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 0: launch_grp_class<1, false, 2>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 1: launch_grp_class<2, false, 2>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 2: launch_grp_class<3, false, 2>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 3: launch_grp_class<4, false, 2>(A, in0, out0, B, in1, out1, st, tk); break;
+        default: launch_grp_class<5, false, 2>(A, in0, out0, B, in1, out1, st, tk); break;
       }
     }
     return PMX_OK;

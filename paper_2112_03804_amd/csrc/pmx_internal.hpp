@@ -220,14 +220,16 @@ struct GCtx {                           // (instance, context) as seen by one di
 struct GGroup {
   int32_t in[kGrpComps];                // component input rows (element offsets; -1: none)
   int32_t out[kGrpComps];               // output rows (element offsets; -1: none)
-  double ks[kGrpComps];                 // output o: coefficient of the showdown operator on component o
+  double ks[kGrpComps];                 // output o: coefficient of the showdown operator on component sc(o)
   double kf[kGrpComps];                 // output o: coefficient of the fold operator on component fc(o)
   int32_t ctx;                          // -1: the group only writes rows without terminals (zeros)
   int32_t fc;                           // fold component of output o in bits 2o, 2o + 1
   int32_t acc;                          // bit o: output o starts its sum here; bit 4 + o: it ends here (stored)
   int32_t n_own, stride;                // row length and stride of the outputs
   int32_t n_in;                         // row length of the inputs (opponent hands)
-  int32_t pad[2];
+  int32_t sc;                           // showdown component of output o in bits 2o, 2o + 1: o itself,
+                                        // except in two-wide groups (components compacted to 0 and 1)
+  int32_t pad;
 };   // element offsets are 32-bit: the layout builder rejects vectors of 2^31 elements or more
 // Group query record (uint4): x = prefix slot of lt | slot of le << 16 (global
 // segment), y = the same in card c0's segment, z = in card c1's segment,
@@ -242,8 +244,11 @@ struct GrpDir {
   std::vector<uint32_t> q, src, meta;
   std::vector<uint16_t> rk;
   // per kind (0: every sequence one group, 1: sequences carrying sums over
-  // several groups) and class: 4 ints per chunk (g0, g1, inst, ctx of g0)
-  std::vector<int32_t> chunks[2][kGrpClasses];
+  // several groups, 2: as 0 for groups of at most two components, whose
+  // launches use two-wide slots) and class: 4 ints per chunk (g0, g1, inst,
+  // ctx of g0)
+  static constexpr int kKinds = 3;
+  std::vector<int32_t> chunks[kKinds][kGrpClasses];
   int max_chunk[kGrpClasses] = {0, 0, 0, 0, 0};
 };
 

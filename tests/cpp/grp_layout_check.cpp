@@ -51,13 +51,23 @@ extern "C" int grp_matvec(const GameDesc* d, int n, int gpc, int dir, const doub
   for (int cls = 0; cls < kGrpClasses; ++cls) {
     const int KE = kGrpKE[cls], KH = cls + 1;
     const int region = 16 * BLK * KE;   // bytes of the shared staging / prefix region
-    for (int kind = 0; kind < 2; ++kind) {
+    for (int kind = 0; kind < GrpDir::kKinds; ++kind) {
     const std::vector<int32_t>& L = M.chunks[kind][cls];
     for (size_t c = 0; c + 3 < L.size(); c += 4) {
       const int g0 = L[c], g1 = L[c + 1];
       std::vector<std::vector<double>> acc(NC);
       for (int gi = g0; gi < g1; ++gi) {
         const GGroup& G = M.groups[gi];
+        // two-wide chunks: terms on components 0 and 1 only, one group each
+        if (kind == 2) {
+          if ((G.acc >> 4 & 0x0f) != (G.acc & 0x0f)) return fail("a two-wide chunk carries sums");
+          if (G.ctx < 0 || G.in[2] >= 0 || G.in[3] >= 0) return fail("a two-wide group uses components 2 or 3");
+          for (int o = 0; o < NC; ++o)
+            if (((G.fc >> (2 * o)) & 3) >= 2 || ((G.sc >> (2 * o)) & 3) >= 2)
+              return fail("a two-wide output names component 2 or 3");
+        } else if (G.sc != 0xe4) {
+          return fail("a four-wide group permutes its showdown components");
+        }
         if (G.ctx < 0) {
           for (int o = 0; o < NC; ++o)
             if (G.out[o] >= 0)
@@ -138,8 +148,8 @@ extern "C" int grp_matvec(const GameDesc* d, int n, int gpc, int dir, const doub
           }
           for (int o = 0; o < NC; ++o) {
             if (G.out[o] < 0) continue;
-            const int fj = (G.fc >> (2 * o)) & 3;
-            acc[o][h] += G.ks[o] * sd[o] + G.kf[o] * fo[fj];
+            const int fj = (G.fc >> (2 * o)) & 3, sj = (G.sc >> (2 * o)) & 3;
+            acc[o][h] += G.ks[o] * sd[sj] + G.kf[o] * fo[fj];
           }
         }
         for (int o = 0; o < NC; ++o) {
