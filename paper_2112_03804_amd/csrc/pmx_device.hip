@@ -1232,9 +1232,10 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
   const int grpv = grouped ? P.grp[T.grp_off + lane] : 0;
   const int extv = (MODE != 0 && wv == 0 && lane < T.n_ext)
                        ? (MODE == 1 ? P.ext_slot[T.ext_off + lane] : P.ext_seq[T.ext_off + lane]) : 0;
-  // unconditional loads at clamped (in-bounds) rows and hands, so that all of
-  // them issue before the first is waited for; the old plan and the running
-  // average stay in registers until the stores at the end
+  // loads at in-bounds hands (clamped) of the wavefront's rows, all issued
+  // before the first is waited for (the rows past the piece's end are not
+  // loaded: a uniform exit, no wait); the old plan and the running average
+  // stay in registers until the stores at the end
   float c[RMR];
   double d[RMR];
   {
@@ -1242,7 +1243,8 @@ __global__ __launch_bounds__(64 * RMW) void k_rmp(RmParams P, float* __restrict_
     const int64_t cbase = T.vec_base + (act ? h : T.n_hands - 1);
 #pragma unroll
     for (int k = 0; k < RMR; ++k) {
-      const int r = min(wv + RMW * k, SL - 1);
+      if (wv + RMW * k >= SL) break;
+      const int r = wv + RMW * k;
       const int64_t idx = cbase + (int64_t)row_id(r) * stride;
       if (MODE != 2) a[k] = g[idx];
       b[k] = R[idx];
