@@ -35,8 +35,11 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 # known size (profiles/matvec_pair_traffic_counters.md).  They describe the
 # kernel sources whose code (comments and whitespace removed) has the SHA-1
 # recorded here and are reported as null for any other version of that code.
-TRAFFIC = {"sources_sha1": "48e40e99319bca55ab3954f59b5b7cd56907c237", "river": 1415219, "batch": 321993014}
+TRAFFIC = {"sources_sha1": "75d07b29cbf02cdbe7c5ba7a0cd39da3c2e4a1a7", "river": 1418182, "batch": 350876053,
+           "batch_schedule": [4, 2]}
 TRAFFIC_SOURCES = ("paper_2112_03804_amd/csrc/pmx_device.hip", "paper_2112_03804_amd/csrc/host_build.cpp")
+# the batch schedule of the counter and trace probes (the autotuner's usual choice)
+PROBE_BATCH_SCHEDULE = (4, 2)
 
 
 def log(msg):
@@ -67,8 +70,15 @@ def kernel_label(sched):
     return f"k_mvc (matvec_pair launch, schedule {k}:{r}, chunk-aligned layout)"
 
 
-def measured_traffic(key):
-    return TRAFFIC[key] if TRAFFIC["sources_sha1"] == sources_sha1() else None
+def measured_traffic(key, sched=None):
+    """The counted HBM bytes of a matvec-pair launch, or None when the
+    kernel sources or (for the batch) the schedule differ from those the
+    counters were taken with."""
+    if TRAFFIC["sources_sha1"] != sources_sha1():
+        return None
+    if sched is not None and list(sched) != TRAFFIC.get(f"{key}_schedule"):
+        return None
+    return TRAFFIC[key]
 
 
 def algorithmic_bytes_pair(layouts):
@@ -327,12 +337,12 @@ def batched_leg(args, stream):
                                                for p in range(2)]},
         "game_create_s": t_create,
         "schedule": {"default": list(default_sched), "tuned": list(sched),
-                     "us_per_pair_by_schedule": sched_us},
+                     "us_A_then_AT_by_schedule": sched_us},
         "steps": args.steps, "warmup": args.warmup, "ms": ms,
         "iteration_ms": it_ms,
         "matvec_pairs_per_s": len(descs) / (it_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("batch"),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("batch", sched),
                      "kernel": kernel_label(sched),
                      "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair},
         "time_to_gap_batched_s": ttg_batched,
@@ -374,7 +384,7 @@ def turn_river_leg(args, stream):
     sched, sched_us = autotune.tune(g, candidates=[(2, 4), (2, 8), (3, 4), (3, 8), (4, 1), (4, 2)], reps=10,
                                     use_cache=False)
     bytes_pair = algorithmic_bytes_pair(g.layouts)
-    pair_us = min(sched_us.values())
+    pair_us = autotune.time_schedule(g, *sched, reps=20, pair=True)   # the matvec-pair launch (roofline)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     g.solver_reset()
     g.solver_step(4)
@@ -412,7 +422,7 @@ def turn_river_leg(args, stream):
     out = {"workload": "turn + river endgame: 4-card board, 48 river cards, 1128 hands/player, "
                        "bets {0.33,0.75,1.5}xpot + all-in, max 3 raises per street, pot 100, stacks 400",
            "game_create_s": t_create,
-           "schedule": {"tuned": list(sched), "us_per_pair_by_schedule": sched_us},
+           "schedule": {"tuned": list(sched), "us_A_then_AT_by_schedule": sched_us},
            "roofline": {"bound": "hbm", "achieved": bytes_pair / (pair_us * 1e-6) / 1e9,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": bytes_pair / (pair_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
@@ -521,7 +531,7 @@ def pmc_probe(args):
     """Launches for hardware-counter runs (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE):
     a plain 256 MiB device-to-device copy (known bytes: calibrates the counters),
     then matvec-pair launches on the river endgame (default schedule) and on
-    the batch (default schedule)."""
+    the batch (PROBE_BATCH_SCHEDULE)."""
     import torch
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
@@ -532,6 +542,7 @@ def pmc_probe(args):
         b.copy_(a)
     torch.cuda.synchronize()
     games = [("river", pmx.Game(I.config(1))), ("batch", pmx.Game(I.batched_configs(args.batch)))]
+    games[1][1].game_tune(*PROBE_BATCH_SCHEDULE)
     for name, g in games:
         rng = np.random.default_rng(0)
         y = torch.from_numpy(rng.random(g.elems[1]).astype(np.float32)).cuda()
@@ -553,7 +564,7 @@ def trace_probe(args):
     import torch
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
-    for name, make, sched, iters in (("batch", lambda: pmx.Game(I.batched_configs(args.batch)), (4, 1), 64),
+    for name, make, sched, iters in (("batch", lambda: pmx.Game(I.batched_configs(args.batch)), PROBE_BATCH_SCHEDULE, 64),
                                      ("turn_river", lambda: pmx.Game(I.config(2)), (3, 8), 32)):
         g = make()
         g.game_tune(*sched)

@@ -4,8 +4,8 @@ For a game it times every candidate schedule (``game_tune(kernel, rows)``:
 kernel 2 / 3 = chunk-aligned scan layout with 256- / 512-thread workgroups,
 rows = output rows per chunk; kernel 4 = grouped layout, rows = groups of
 up to four input rows per chunk; each launched per hands-per-thread class)
-on the matvec-pair launch with
-HIP events, keeps the fastest, and remembers the choice in a JSON cache keyed
+on A y followed by A^T x (two single-direction launches, as the solver
+makes them) with HIP events, keeps the fastest, and remembers the choice in a JSON cache keyed
 by GPU architecture and a size class of the game (instances, rows, largest
 hand count), so later games of the same class are tuned without timing.
 """
@@ -46,8 +46,10 @@ def _load(path: str) -> Dict[str, list]:
         return {}
 
 
-def time_schedule(game, kernel: int, rows: int, reps: int = 20) -> float:
-    """Average microseconds of one matvec-pair launch under a schedule."""
+def time_schedule(game, kernel: int, rows: int, reps: int = 20, pair: bool = False) -> float:
+    """Average microseconds of A y followed by A^T x under a schedule: two
+    single-direction launches, as the solver makes them (or, with `pair`,
+    one matvec-pair launch)."""
     import torch
     game.game_tune(kernel, rows)
     rng = np.random.default_rng(0)
@@ -55,14 +57,21 @@ def time_schedule(game, kernel: int, rows: int, reps: int = 20) -> float:
     x = torch.from_numpy(rng.random(game.elems[0]).astype(np.float32)).cuda()
     Ay = torch.empty(game.elems[0], dtype=torch.float32, device="cuda")
     ATx = torch.empty(game.elems[1], dtype=torch.float32, device="cuda")
+    def once():
+        if pair:
+            game.matvec_pair(y, x, Ay, ATx)
+        else:
+            game.matvec_A(y, Ay)
+            game.matvec_AT(x, ATx)
+
     for _ in range(3):
-        game.matvec_pair(y, x, Ay, ATx)
+        once()
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(s)
     for _ in range(reps):
-        game.matvec_pair(y, x, Ay, ATx)
+        once()
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) * 1e3 / reps

@@ -941,6 +941,11 @@ int build_grp_layout(HostGame& hg, int d, int gpc, std::string& msg) {
   }
   const int BLK = kGrpBlock;
   auto lohi = [](uint32_t lo, uint32_t hi) { return (lo & 0xffffu) | ((hi & 0xffffu) << 16); };
+  // two-wide launches pay when the product has many groups; a small one (a
+  // single river endgame) keeps one launch per class
+  int64_t out_rows = 0;
+  for (const Built& b : hg.inst) out_rows += b.sf.n_seq[d];
+  const bool two_wide = out_rows >= kGrpTwoWideMinRows;
   for (size_t ii = 0; ii < hg.inst.size(); ++ii) {
     const Built& b = hg.inst[ii];
     const Instance& in = b.inst;
@@ -1242,7 +1247,7 @@ int build_grp_layout(HostGame& hg, int d, int gpc, std::string& msg) {
     // showdown term (sc) as it names that of its fold term (fc)
     auto narrow = [&](int gi) {
       const GGroup& G = M.groups[gi];
-      if (G.ctx < 0) return false;
+      if (!two_wide || G.ctx < 0) return false;
       int used = 0;
       for (int j = 0; j < kGrpComps; ++j) used += G.in[j] >= 0;
       return used <= 2;

@@ -1987,8 +1987,10 @@ struct Game {
 };
 
 // Streams a grouped matvec spreads its class launches over: the caller's
-// and Game::kSide side streams.
+// and Game::kSide side streams; products of fewer workgroups in all than
+// kForkMinWorkgroups are not spread.
 constexpr int kForkStreams = 1 + Game::kSide;
+constexpr int kForkMinWorkgroups = 512;
 
 // Side streams and events of the concurrent class launches (created once,
 // outside any capture).
@@ -2377,7 +2379,7 @@ static void launch_mc_class(const McParams& A, const IO* in0, IO* out0, const Mc
 // share a CU's LDS.  `launch(i, stream, first)` enqueues launch i; `first`
 // marks the one launch that carries the iteration tick.
 template <typename F>
-static int fork_launches(Game* g, hipStream_t s, int n, const int64_t* work_in, F&& launch) {
+static int fork_launches(Game* g, hipStream_t s, int n, const int64_t* work_in, int64_t workgroups, F&& launch) {
   int order[16];
   int64_t work[16];
   if (n > 16) return fail(PMX_EINVAL, "too many concurrent launches");
@@ -2390,7 +2392,9 @@ static int fork_launches(Game* g, hipStream_t s, int n, const int64_t* work_in, 
       std::swap(work[j], work[j - 1]);
       std::swap(order[j], order[j - 1]);
     }
-  const int ns = g->fork_ok ? std::min(n, kForkStreams) : 1;
+  // a fork and join cost about ten microseconds: small products (a single
+  // river endgame's) stay on the caller's stream
+  const int ns = (g->fork_ok && workgroups >= kForkMinWorkgroups) ? std::min(n, kForkStreams) : 1;
   int on[16];
   int64_t load[kForkStreams] = {};
   for (int i = 0; i < n; ++i) {
@@ -2421,15 +2425,16 @@ static int launch_mc(Game* g, const MvParams& P0, const IO* in0, IO* out0, const
   const int block = g->dm[0].block;
   if (block == 0 || g->dm[1].block != block) return fail(PMX_ESTATE, "matvec layout not built");
   int cls[kMcClasses], n = 0;
-  int64_t work[kMcClasses];
+  int64_t work[kMcClasses], wgs = 0;
   for (int c = 0; c < kMcClasses; ++c) {
     const McParams A = mc_params(g, P0.dir, P0, c), B = mc_params(g, P1.dir, P1, c);
     if (A.nchunk + B.nchunk == 0) continue;
     if (block == 512 && c > 2) return fail(PMX_EINVAL, "no 512-thread matvec class for this hand count");
     work[n] = (int64_t)(A.nchunk + B.nchunk) * (c + 1);
+    wgs += A.nchunk + B.nchunk;
     cls[n++] = c;
   }
-  int rc = fork_launches(g, s, n, work, [&](int i, hipStream_t st, bool first) {
+  int rc = fork_launches(g, s, n, work, wgs, [&](int i, hipStream_t st, bool first) {
     const int c = cls[i];
     const McParams A = mc_params(g, P0.dir, P0, c), B = mc_params(g, P1.dir, P1, c);
     double* tk = first ? tick : nullptr;
@@ -2491,15 +2496,16 @@ static int launch_grp(Game* g, const MvParams& P0, const float* in0, float* out0
                       const float* in1, float* out1, hipStream_t s, double* tick) {
   if (!g->dg[0].built || !g->dg[1].built) return fail(PMX_ESTATE, "grouped matvec layout not built");
   int cls[GrpDir::kKinds * kGrpClasses], n = 0;
-  int64_t work[GrpDir::kKinds * kGrpClasses];
+  int64_t work[GrpDir::kKinds * kGrpClasses], wgs = 0;
   for (int kind = 0; kind < GrpDir::kKinds; ++kind)
     for (int c = 0; c < kGrpClasses; ++c) {
       const GParams A = grp_params(g, P0.dir, P0, kind, c), B = grp_params(g, P1.dir, P1, kind, c);
       if (A.nchunk + B.nchunk == 0) continue;
       work[n] = (int64_t)(A.nchunk + B.nchunk) * kGrpKE[c] * (kind == 2 ? 1 : 2);
+      wgs += A.nchunk + B.nchunk;
       cls[n++] = kind * kGrpClasses + c;
     }
-  int rc = fork_launches(g, s, n, work, [&](int i, hipStream_t st, bool first) {
+  int rc = fork_launches(g, s, n, work, wgs, [&](int i, hipStream_t st, bool first) {
     const int kind = cls[i] / kGrpClasses, c = cls[i] % kGrpClasses;
     const GParams A = grp_params(g, P0.dir, P0, kind, c), B = grp_params(g, P1.dir, P1, kind, c);
     double* tk = first ? tick : nullptr;
@@ -2643,7 +2649,8 @@ static int rm_update(Game* g, int p, hipStream_t s) {
   // the pieces of depth 0 without pulls run on a side stream beside the
   // chain deep bottom-up -> depth 0 with pulls -> deep top-down (the
   // pieces of one pass are independent; only the chain is ordered)
-  const bool side = g->fork_ok && D > 1 && E.blk_pull0 > E.blk_off[0] && E.blk_off[1] > E.blk_pull0;
+  const bool side = g->fork_ok && D > 1 && E.blk_pull0 > E.blk_off[0] && E.blk_off[1] > E.blk_pull0 &&
+                    E.blk_off[D] - E.blk_off[0] >= kForkMinWorkgroups;
   if (side) {
     HIP_TRY(hipEventRecord(g->fork_ev, s));
     HIP_TRY(hipStreamWaitEvent(g->side[0], g->fork_ev, 0));

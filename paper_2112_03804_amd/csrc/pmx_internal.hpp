@@ -204,6 +204,7 @@ struct McDir {
 constexpr int kGrpComps = 4;
 constexpr int kGrpBlock = 256;                  // threads per workgroup
 constexpr int kGrpClasses = 5;                  // hands per thread 1..5
+constexpr int kGrpTwoWideMinRows = 1024;        // output rows of a product from which two-wide launches are used
 constexpr int kGrpKE[kGrpClasses] = {4, 8, 12, 16, 18};   // scan entries per thread per class
 inline int grp_urow(int i) { return i + (i >> 4); }
 struct GCtx {                           // (instance, context) as seen by one direction
