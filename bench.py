@@ -35,10 +35,12 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 # known size (profiles/matvec_pair_traffic_counters.md).  They describe the
 # kernel sources whose code (comments and whitespace removed) has the SHA-1
 # recorded here and are reported as null for any other version of that code.
-TRAFFIC = {"sources_sha1": "75d07b29cbf02cdbe7c5ba7a0cd39da3c2e4a1a7", "river": 1418182, "batch": 350876053,
-           "batch_schedule": [4, 2]}
+TRAFFIC = {"sources_sha1": "75d07b29cbf02cdbe7c5ba7a0cd39da3c2e4a1a7", "river": 1418284,
+           "batch": {"4:1": 351510071, "4:2": 350877954}}
 TRAFFIC_SOURCES = ("paper_2112_03804_amd/csrc/pmx_device.hip", "paper_2112_03804_amd/csrc/host_build.cpp")
-# the batch schedule of the counter and trace probes (the autotuner's usual choice)
+# the batch schedules of the counter probe (the autotuner's usual choices;
+# traffic is reported for these only) and the schedule of the trace probe
+PROBE_BATCH_SCHEDULES = ((4, 1), (4, 2))
 PROBE_BATCH_SCHEDULE = (4, 2)
 
 
@@ -72,13 +74,14 @@ def kernel_label(sched):
 
 def measured_traffic(key, sched=None):
     """The counted HBM bytes of a matvec-pair launch, or None when the
-    kernel sources or (for the batch) the schedule differ from those the
-    counters were taken with."""
+    kernel sources differ from those the counters were taken with or (for
+    the batch) the schedule is not one of those counted."""
     if TRAFFIC["sources_sha1"] != sources_sha1():
         return None
-    if sched is not None and list(sched) != TRAFFIC.get(f"{key}_schedule"):
-        return None
-    return TRAFFIC[key]
+    v = TRAFFIC.get(key)
+    if isinstance(v, dict):
+        return v.get(f"{sched[0]}:{sched[1]}") if sched is not None else None
+    return v
 
 
 def algorithmic_bytes_pair(layouts):
@@ -531,7 +534,7 @@ def pmc_probe(args):
     """Launches for hardware-counter runs (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE):
     a plain 256 MiB device-to-device copy (known bytes: calibrates the counters),
     then matvec-pair launches on the river endgame (default schedule) and on
-    the batch (PROBE_BATCH_SCHEDULE)."""
+    the batch at each of PROBE_BATCH_SCHEDULES."""
     import torch
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
@@ -541,9 +544,12 @@ def pmc_probe(args):
     for _ in range(5):
         b.copy_(a)
     torch.cuda.synchronize()
-    games = [("river", pmx.Game(I.config(1))), ("batch", pmx.Game(I.batched_configs(args.batch)))]
-    games[1][1].game_tune(*PROBE_BATCH_SCHEDULE)
-    for name, g in games:
+    games = [("river", pmx.Game(I.config(1)), None)]
+    for sc in PROBE_BATCH_SCHEDULES:
+        games.append((f"batch {sc[0]}:{sc[1]}", pmx.Game(I.batched_configs(args.batch)), sc))
+    for name, g, sc in games:
+        if sc is not None:
+            g.game_tune(*sc)
         rng = np.random.default_rng(0)
         y = torch.from_numpy(rng.random(g.elems[1]).astype(np.float32)).cuda()
         x = torch.from_numpy(rng.random(g.elems[0]).astype(np.float32)).cuda()
