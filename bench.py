@@ -35,11 +35,13 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 # known size (profiles/matvec_pair_traffic_counters.md).  They describe the
 # kernel sources whose code (comments and whitespace removed) has the SHA-1
 # recorded here and are reported as null for any other version of that code.
-TRAFFIC = {"sources_sha1": "75d07b29cbf02cdbe7c5ba7a0cd39da3c2e4a1a7", "river": 1418284,
-           "batch": {"4:1": 351510071, "4:2": 350877954}}
+TRAFFIC = {"sources_sha1": "1c93ae994ef4ffc108cc03774a0874607e66c1f8",
+           "river": {"4:1": 1418182, "3:1": 1633163},
+           "batch": {"4:1": 351509908, "4:2": 350876600}}
 TRAFFIC_SOURCES = ("paper_2112_03804_amd/csrc/pmx_device.hip", "paper_2112_03804_amd/csrc/host_build.cpp")
-# the batch schedules of the counter probe (the autotuner's usual choices;
-# traffic is reported for these only) and the schedule of the trace probe
+# the schedules of the counter probe (the autotuner's usual choices; traffic
+# is reported for these only) and the batch schedule of the trace probe
+PROBE_RIVER_SCHEDULES = ((4, 1), (3, 1))
 PROBE_BATCH_SCHEDULES = ((4, 1), (4, 2))
 PROBE_BATCH_SCHEDULE = (4, 2)
 
@@ -74,8 +76,8 @@ def kernel_label(sched):
 
 def measured_traffic(key, sched=None):
     """The counted HBM bytes of a matvec-pair launch, or None when the
-    kernel sources differ from those the counters were taken with or (for
-    the batch) the schedule is not one of those counted."""
+    kernel sources differ from those the counters were taken with or the
+    schedule is not one of those counted."""
     if TRAFFIC["sources_sha1"] != sources_sha1():
         return None
     v = TRAFFIC.get(key)
@@ -533,8 +535,8 @@ def warm_leg(args, stream, batched):
 def pmc_probe(args):
     """Launches for hardware-counter runs (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE):
     a plain 256 MiB device-to-device copy (known bytes: calibrates the counters),
-    then matvec-pair launches on the river endgame (default schedule) and on
-    the batch at each of PROBE_BATCH_SCHEDULES."""
+    then matvec-pair launches on the river endgame at each of
+    PROBE_RIVER_SCHEDULES and on the batch at each of PROBE_BATCH_SCHEDULES."""
     import torch
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
@@ -544,12 +546,11 @@ def pmc_probe(args):
     for _ in range(5):
         b.copy_(a)
     torch.cuda.synchronize()
-    games = [("river", pmx.Game(I.config(1)), None)]
+    games = [(f"river {sc[0]}:{sc[1]}", pmx.Game(I.config(1)), sc) for sc in PROBE_RIVER_SCHEDULES]
     for sc in PROBE_BATCH_SCHEDULES:
         games.append((f"batch {sc[0]}:{sc[1]}", pmx.Game(I.batched_configs(args.batch)), sc))
     for name, g, sc in games:
-        if sc is not None:
-            g.game_tune(*sc)
+        g.game_tune(*sc)
         rng = np.random.default_rng(0)
         y = torch.from_numpy(rng.random(g.elems[1]).astype(np.float32)).cuda()
         x = torch.from_numpy(rng.random(g.elems[0]).astype(np.float32)).cuda()
@@ -682,6 +683,82 @@ def dcfr_sweep(args):
                                       "iterations": v["iterations"]} for k, v in best.items()}}), flush=True)
 
 
+def _time_to_gap(gm, kind, target, tpot):
+    """Seconds and iterations of a single game's solver (uniform start) to an
+    FP64 gap of target * pot, checked every 25 iterations."""
+    import torch
+    gm.solver_set_params(kind)
+    gm.solver_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, gap = 0, float("inf")
+    while iters < 200000:
+        gm.solver_step(25)
+        iters += 25
+        gap = float(gm.saddle_gap()[0][0])
+        if gap <= target * tpot:
+            break
+    gm.solver_set_params("rm+")
+    return time.perf_counter() - t0, iters, gap
+
+
+def libratus_leg(args, stream):
+    """A river endgame closer to the paper's: hold'em hand ranking for the
+    strengths and the asymmetric betting abstraction of its appendix
+    (Libratus' sizes, all-in everywhere, no raise cap), pot 100, stacks 1000:
+    solver iterations per second, the matvec pair, time to 1e-4 * pot, and
+    Table 1's size metric (nnz of A against Technique B's factors)."""
+    import torch
+    from paper_2112_03804_amd import autotune, handeval
+    from paper_2112_03804_amd import instances as I
+    from paper_2112_03804_amd import pmx
+
+    d = I.libratus_river(stack=1000.0)
+    pot = 2 * d.contrib
+    g = pmx.Game(d)
+    sched, sched_us = autotune.tune(g, use_cache=False)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g.solver_reset()
+    g.solver_step(100)
+    torch.cuda.synchronize()
+    steps = 1000
+    e0.record(stream)
+    g.solver_step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    it_us = e0.elapsed_time(e1) * 1e3 / steps
+    pair_us = autotune.time_schedule(g, *sched, reps=500, pair=True)
+    bytes_pair = algorithmic_bytes_pair(g.layouts)
+    ttg, iters, gap = _time_to_gap(g, "rm+", 1e-4, pot)
+    ttg_d, iters_d, gap_d = _time_to_gap(g, "dcfr", 1e-4, pot)
+    t0 = time.perf_counter()
+    tb = g.tb_build()
+    tb_s = time.perf_counter() - t0
+    size_pp = tb["nnz_ahat"] + tb["nnz_u_pp"] + tb["nnz_m_pp"] + tb["nnz_v_pp"]
+    L = g.layouts[0]
+    classes = int(handeval.suit_classes(d.hands[0], d.board).max()) + 1
+    out = {"workload": "river endgame, hold'em hand ranking on a seeded board, 1081 hands/player, Libratus' "
+                       "asymmetric bet sizes (player 1 the AI) + all-in, no raise cap, pot 100, stacks 1000",
+           "n_seq": [L[0]["n_seq"], L[1]["n_seq"]], "n_hands": [L[0]["n_hands"], L[1]["n_hands"]],
+           "distinct_strengths": int(d.strength[0].max()) + 1,
+           "suit_isomorphism_classes": classes,
+           "schedule": {"tuned": list(sched), "us_A_then_AT_by_schedule": sched_us},
+           "iterations_per_s": 1e6 / it_us, "iteration_us": it_us,
+           "matvec_pair": {"kernel": kernel_label(sched), "us_per_launch": pair_us,
+                           "algorithmic_bytes_per_launch": bytes_pair,
+                           "achieved_gbs": bytes_pair / (pair_us * 1e-6) / 1e9},
+           "time_to_gap": {"target": "1e-4*pot", "seconds": ttg, "iterations": iters, "gap_over_pot": gap / pot,
+                           "solver": "plain RM+, uniform start, FP64 gap checked every 25 iterations",
+                           "dcfr": {"seconds": ttg_d, "iterations": iters_d, "gap_over_pot": gap_d / pot,
+                                    "params": "alpha 1.5, beta 0, gamma 2"}},
+           "technique_b_factors": {"nnz_A": tb["nnz_A"], "size_technique_b_postprocessed": size_pp,
+                                   "nnz_A_over_size": tb["nnz_A"] / max(size_pp, 1), "build_s": tb_s}}
+    g.close()
+    log(f"libratus river: {out['iterations_per_s']:.0f} iterations/s, {out['n_seq']} sequences, "
+        f"time to gap {ttg:.3f} s")
+    return out
+
+
 def river_leg(args, stream):
     """The single river endgame (52-card deck, 5-card board, 1081 hands per
     player, bets {0.5, 1, 2} x pot + all-in, 3 raises): solver iterations per
@@ -689,6 +766,7 @@ def river_leg(args, stream):
     bound), time to 1e-4 * pot (RM+ and DCFR) and the 13-card game to
     1e-6 * pot."""
     import torch
+    from paper_2112_03804_amd import autotune
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
 
@@ -697,6 +775,9 @@ def river_leg(args, stream):
     t_create = time.perf_counter()
     g = pmx.Game(desc)
     t_create = time.perf_counter() - t_create
+    # few rows: the chunk-aligned layout's one row per workgroup usually
+    # beats the grouped layout's few long-lived workgroups
+    sched, sched_us = autotune.tune(g, use_cache=False)
     steps, warmup = 2000, 100
     g.solver_reset()
     g.solver_step(warmup)
@@ -759,32 +840,19 @@ def river_leg(args, stream):
                            "structured: the hand operators applied without forming any factor"}
     del yd, xd, Ayd, ATxd
 
-    def time_to_gap(gm, kind, target, tpot):
-        gm.solver_set_params(kind)
-        gm.solver_reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        iters, gap = 0, float("inf")
-        while iters < 200000:
-            gm.solver_step(25)
-            iters += 25
-            gap = float(gm.saddle_gap()[0][0])
-            if gap <= target * tpot:
-                break
-        gm.solver_set_params("rm+")
-        return time.perf_counter() - t0, iters, gap
-
+    time_to_gap = _time_to_gap
     ttg, iters, gap = time_to_gap(g, "rm+", 1e-4, pot)
     ttg_d, iters_d, gap_d = time_to_gap(g, "dcfr", 1e-4, pot)
     out = {"workload": "river endgame: 52-card deck, 5-card board, 1081 hands/player, bets {0.5,1,2}xpot + "
                        "all-in, max 3 raises, pot 100, stacks 400",
            "n_seq": [L[0][0]["n_seq"], L[0][1]["n_seq"]], "n_hands": [L[0][0]["n_hands"], L[0][1]["n_hands"]],
            "game_create_s": t_create,
+           "schedule": {"tuned": list(sched), "us_A_then_AT_by_schedule": sched_us},
            "iterations_per_s": steps / (ms / 1e3), "iteration_us": ms * 1e3 / steps,
            "matvec_pair": {"kernel": kernel_label(g.game_get_tuning()),
                            "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair,
                            "achieved_gbs": bytes_pair / (pair_us * 1e-6) / 1e9,
-                           "traffic": measured_traffic("river"),
+                           "traffic": measured_traffic("river", g.game_get_tuning()),
                            "note": "0.86 MB per pair stays in the caches; the launch is latency bound"},
            "technique_b_factors": technique_b,
            "time_to_gap": {"target": "1e-4*pot", "seconds": ttg, "iterations": iters,
@@ -823,6 +891,8 @@ def main():
     ap.add_argument("--max-iters", type=int, default=100000)
     ap.add_argument("--no-river", action="store_true")
     ap.add_argument("--no-turn", action="store_true")
+    ap.add_argument("--no-libratus", action="store_true",
+                    help="skip the river endgame with hand ranking and Libratus' bet sizes")
     ap.add_argument("--no-tiny", action="store_true", help="skip the 13-card game's time to gap")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run the launches profiled for HBM traffic counters")
@@ -899,6 +969,9 @@ def main():
         out["river"] = river_leg(args, stream)
         river_iters = out["river"]["time_to_gap"]["iterations"]
         log("river leg done")
+    if not args.no_libratus:
+        out["libratus_river"] = libratus_leg(args, stream)
+        log("libratus river leg done")
     precision = None
     if not args.no_turn:
         tr = turn_river_leg(args, stream)

@@ -103,6 +103,15 @@ typedef struct Game Game;   /* opaque; owns host and device state */
  *                   x the pot after matching (Fig. 1 caption); each > 0.
  *  max_raises       raises allowed after the opening bet of a round (>= 0)
  *  allow_allin      nonzero: offer all-in (also past the raise cap)
+ *  bet_menu_len, bet_menu
+ *                   optional asymmetric betting abstraction (the paper's
+ *                   appendix on the betting abstraction): NULL, or
+ *                   bet_menu_len[5 p + k] fractions of player p in situation
+ *                   k (0 opening the round, 1 answering a check, 2 facing a
+ *                   bet, 3 facing one raise, 4 facing two or more raises),
+ *                   read in that order from bet_menu, each > 0 and at most 64
+ *                   per list; they replace bet_fracs.  A zeroed descriptor
+ *                   tail (both NULL) keeps bet_fracs everywhere.
  */
 typedef struct {
   int32_t deck_size, cards_per_hand;
@@ -120,6 +129,8 @@ typedef struct {
   const double* bet_fracs;
   int32_t max_raises;
   int32_t allow_allin;
+  const int32_t* bet_menu_len;
+  const double* bet_menu;
 } GameDesc;
 
 /*

@@ -23,7 +23,8 @@ from . import skeleton as sk
 
 def expected_payoff(desc, b1, b2):
     root = sk.build_tree(desc.contrib, desc.stack, list(desc.bet_fracs), int(desc.max_raises),
-                         bool(desc.allow_allin), two_rounds=len(desc.river_cards) > 0)
+                         bool(desc.allow_allin), two_rounds=len(desc.river_cards) > 0,
+                         menu=getattr(desc, "bet_menu", None))
     hands = [np.asarray(h, dtype=np.int64) for h in desc.hands]
     mu = [np.asarray(r, dtype=np.float64) for r in desc.range_]
     rivers = [int(r) for r in desc.river_cards]

@@ -16,6 +16,11 @@ Rules followed (paper, Appendix A "Betting rounds", and the caption of Fig. 1):
   K and O).
 * Action order inside a decision node: fold, check/call, bets and raises by
   ascending size, all-in.
+* Bet sizes are one list for every decision, or a menu per player and
+  situation, as in the asymmetric abstraction of the paper's appendix on the
+  betting abstraction (the two players draw on different lists, and each
+  player's list depends on whether it opens the round, answers a check, or
+  faces a bet, one raise, or more raises).
 
 Payoffs are Player 1's (Section 3): a fold costs the folder its contribution,
 a showdown moves the (equal) contribution of the loser to the winner.
@@ -88,10 +93,23 @@ def _snap(x: float) -> float:
     return 0.0 if abs(x) < EPS else x
 
 
-def _round(c, s, fracs, max_raises, allow_allin, last_round):
+# situations of a betting menu
+OPEN, AFTER_CHECK, FACING_BET, FACING_RAISE, FACING_RERAISE = range(5)
+
+
+def situation(facing, raises, checked):
+    """Situation of a decision for the betting menu: opening the round,
+    answering a check, facing a bet, one raise, or two and more raises."""
+    if not facing:
+        return AFTER_CHECK if checked else OPEN
+    return FACING_BET + min(raises, 2)
+
+
+def _round(c, s, fracs, max_raises, allow_allin, last_round, menu=None):
     """Build one betting round starting with Player 1 to act, contributions c
     and stacks s.  Round ends become 'leaf' (showdown) when last_round, else
-    'chance' (next round) unless a player is all-in (then a run-out leaf)."""
+    'chance' (next round) unless a player is all-in (then a run-out leaf).
+    menu[p][k]: player p's bet fractions in situation k (None: fracs)."""
 
     def end_of_round(c, s):
         if last_round:
@@ -128,8 +146,9 @@ def _round(c, s, fracs, max_raises, allow_allin, last_round):
         # bets / raises ascending, then all-in
         can_grow = allin_to > cj + EPS
         targets = []
+        sizes = fracs if menu is None else sorted(menu[p][situation(facing, raises, checked)])
         if can_grow and (not facing or raises < max_raises):
-            for f in fracs:
+            for f in sizes:
                 t = cj + f * 2.0 * cj
                 if t >= allin_to - EPS:
                     t = allin_to
@@ -148,17 +167,18 @@ def _round(c, s, fracs, max_raises, allow_allin, last_round):
     return node(0, tuple(c), tuple(s), False, 0, False)
 
 
-def build_tree(contrib, stacks, fracs, max_raises, allow_allin, two_rounds=False):
+def build_tree(contrib, stacks, fracs, max_raises, allow_allin, two_rounds=False, menu=None):
     """Skeleton of a river endgame (two_rounds=False) or of a turn + river
     endgame, whose chance nodes get river-round children later (the river
-    round depends only on the contributions and stacks at the chance node)."""
+    round depends only on the contributions and stacks at the chance node).
+    menu: per-player, per-situation bet fractions replacing fracs."""
     root = _round((contrib, contrib), tuple(stacks), list(fracs), max_raises,
-                  allow_allin, last_round=not two_rounds)
+                  allow_allin, last_round=not two_rounds, menu=menu)
     if two_rounds:
         def attach(n):
             if n.kind == 'chance':
                 n.children = [_round(n.c, n.s, list(fracs), max_raises, allow_allin,
-                                     last_round=True)]
+                                     last_round=True, menu=menu)]
                 return
             for ch in n.children:
                 attach(ch)
@@ -228,7 +248,7 @@ def from_desc(desc) -> SequenceForm:
     """Sequence form of a GameDesc-like instance."""
     two = len(desc.river_cards) > 0
     root = build_tree(desc.contrib, desc.stack, list(desc.bet_fracs), int(desc.max_raises),
-                      bool(desc.allow_allin), two_rounds=two)
+                      bool(desc.allow_allin), two_rounds=two, menu=getattr(desc, "bet_menu", None))
     return sequence_form(root, len(desc.river_cards))
 
 

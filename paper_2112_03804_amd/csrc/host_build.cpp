@@ -127,6 +127,24 @@ int validate(const GameDesc& d, Instance& o, std::string& msg) {
     o.fracs.push_back(f);
   }
   std::sort(o.fracs.begin(), o.fracs.end());
+  if (d.bet_menu_len) {
+    o.has_menu = true;
+    size_t at = 0;
+    for (int p = 0; p < 2; ++p)
+      for (int k = 0; k < 5; ++k) {
+        const int len = d.bet_menu_len[5 * p + k];
+        if (len < 0 || len > 64) return bad("bet_menu_len entries must be in [0, 64]");
+        if (len > 0 && !d.bet_menu) return bad("bet_menu is NULL");
+        for (int i = 0; i < len; ++i) {
+          const double f = d.bet_menu[at++];
+          if (!std::isfinite(f) || f <= 0) return bad("bet fractions must be finite and > 0");
+          o.menu[p][k].push_back(f);
+        }
+        std::sort(o.menu[p][k].begin(), o.menu[p][k].end());
+      }
+  } else if (d.bet_menu) {
+    return bad("bet_menu without bet_menu_len");
+  }
   if (d.max_raises < 0 || d.max_raises > 64) return bad("max_raises must be in [0, 64]");
   o.max_raises = d.max_raises;
   o.allin = d.allow_allin != 0;
@@ -206,8 +224,12 @@ struct TreeBuilder {
     }
     const bool grow = allin_to > c[o] + kEps;
     std::vector<double> targets;
+    // bet sizes: one list, or the acting player's list for the situation
+    // (opening, after a check, facing a bet, one raise, more raises)
+    const int sit = facing ? 2 + std::min(raises, 2) : (checked ? 1 : 0);
+    const std::vector<double>& sizes = in.has_menu ? in.menu[p][sit] : in.fracs;
     if (grow && (!facing || raises < in.max_raises)) {
-      for (double f : in.fracs) {
+      for (double f : sizes) {
         double t = c[o] + f * 2.0 * c[o];
         if (t >= allin_to - kEps) t = allin_to;
         if (!targets.empty() && std::fabs(targets.back() - t) <= kEps) continue;
@@ -898,7 +920,7 @@ void place_terms(const Slots& slots, int ctx, std::vector<GTerm> pending, std::v
       if (!t.fold) continue;
       const int o = slot_of(t.out);
       if (G.f[o]) {
-        if (G.in[G.fc[o] ? o ^ 1 : o] == t.in) G.kf[o] += t.coef;
+        if (G.in[G.fc[o]] == t.in) G.kf[o] += t.coef;
         else next.push_back(t);
         continue;
       }

@@ -32,6 +32,8 @@ struct Instance {
   std::vector<double> mu[2];
   double contrib = 0, stack[2] = {0, 0};
   std::vector<double> fracs;            // ascending
+  bool has_menu = false;                // per-player, per-situation sizes replace fracs
+  std::vector<double> menu[2][5];       // ascending; situations as in bet_situation
   int max_raises = 0;
   bool allin = false;
   int nb = 1;                           // final boards (max(1, n_river))

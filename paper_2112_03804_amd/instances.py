@@ -35,6 +35,8 @@ __all__ = [
     "batched_configs",
     "small_river",
     "small_turn_river",
+    "libratus_menu",
+    "libratus_river",
     "config",
 ]
 
@@ -60,6 +62,10 @@ class GameDesc:
     bet_fracs       : bet/raise sizes as fractions of the pot after matching.
     max_raises      : raises allowed after the opening bet of a round.
     allow_allin     : whether an all-in action is offered.
+    bet_menu        : None, or per player five tuples of fractions that
+                      replace bet_fracs by situation: opening the round,
+                      answering a check, facing a bet, facing one raise,
+                      facing two or more raises (an asymmetric abstraction).
     """
 
     deck_size: int
@@ -75,6 +81,7 @@ class GameDesc:
     max_raises: int
     allow_allin: bool
     name: str = ""
+    bet_menu: Optional[tuple] = None
 
     @property
     def n_hands(self):
@@ -139,6 +146,21 @@ def _dirichlet_range(n: int, rng: np.random.Generator, zero_frac: float) -> np.n
     return w.astype(np.float64)
 
 
+def _board_strengths(universe: np.ndarray, board: np.ndarray, deck_size: int, rng: np.random.Generator,
+                     tie_p: float, strengths: str) -> np.ndarray:
+    """Strength levels of the hands in universe on a final board: a seeded
+    random order with ties ("random") or the hold'em hand ranking ("eval",
+    52-card deck and two-card hands only)."""
+    if strengths == "random":
+        return _strength_with_ties(len(universe), rng, tie_p)
+    if strengths == "eval":
+        if deck_size != 52 or universe.shape[1] != 2 or len(board) != 5:
+            raise ValueError("hand-ranking strengths need a 52-card deck, two-card hands and a 5-card board")
+        from . import handeval
+        return handeval.strength_levels(universe, board)
+    raise ValueError(f"unknown strengths {strengths!r}")
+
+
 def _lookup(universe_keys: np.ndarray, keys: np.ndarray) -> np.ndarray:
     pos = {int(k): i for i, k in enumerate(universe_keys)}
     return np.array([pos[int(k)] for k in keys], dtype=np.int64)
@@ -182,18 +204,32 @@ def river_config(seed: int = 1, deck_size: int = 52, bet_fracs=(0.5, 1.0, 2.0),
                  max_raises: int = 3, pot: float = 100.0, stack: float = 400.0,
                  zero_frac: float = 0.30, tie_p: float = 0.05,
                  n_keep: Optional[Sequence[int]] = None,
-                 name: str = "river") -> GameDesc:
-    """River endgame: 5 fixed board cards, two-card hands, seeded strengths
-    (random order with ~tie_p tie groups), Dirichlet(1) ranges with a
-    zero_frac share zeroed.  With n_keep=(n1, n2) each player's list is pruned
-    to a random subset of that size (ranges then strictly positive)."""
+                 name: str = "river", strengths: str = "random",
+                 bet_menu: Optional[tuple] = None, board: Optional[Sequence[int]] = None,
+                 iso_ranges: bool = False) -> GameDesc:
+    """River endgame: 5 board cards (seeded, or the given board), two-card
+    hands, seeded strengths (random order with ~tie_p tie groups, or the
+    hand ranking with strengths="eval"), Dirichlet(1) ranges with a
+    zero_frac share zeroed (drawn per suit-isomorphism class of the board
+    with iso_ranges, so that hands a suit symmetry of the board maps onto
+    each other weigh the same).  With n_keep=(n1, n2) each player's list is
+    pruned to a random subset of that size (ranges then strictly
+    positive)."""
     rng = np.random.default_rng([seed, 1])
-    board = np.sort(rng.choice(deck_size, size=5, replace=False)).astype(np.uint8)
+    if board is None:
+        board = np.sort(rng.choice(deck_size, size=5, replace=False)).astype(np.uint8)
+    else:
+        board = np.sort(np.asarray(board, dtype=np.uint8))
     universe = _all_hands(deck_size, 2, board)
-    s_univ = _strength_with_ties(len(universe), rng, tie_p)
+    s_univ = _board_strengths(universe, board, deck_size, rng, tie_p, strengths)
     hands, strength, ranges = [], [], []
     for p in range(2):
-        if n_keep is None:
+        if n_keep is None and iso_ranges:
+            from . import handeval
+            idx = np.arange(len(universe))
+            cls = handeval.suit_classes(universe, board)
+            r = _dirichlet_range(int(cls.max()) + 1, rng, zero_frac)[cls]
+        elif n_keep is None:
             idx = np.arange(len(universe))
             r = _dirichlet_range(len(idx), rng, zero_frac)
         else:
@@ -207,7 +243,7 @@ def river_config(seed: int = 1, deck_size: int = 52, bet_fracs=(0.5, 1.0, 2.0),
         river_cards=np.zeros(0, np.uint8), hands=hands, strength=strength,
         range_=ranges, contrib=pot / 2.0, stack=(float(stack), float(stack)),
         bet_fracs=np.array(sorted(bet_fracs), dtype=np.float64),
-        max_raises=max_raises, allow_allin=True, name=name)
+        max_raises=max_raises, allow_allin=True, name=name, bet_menu=bet_menu)
 
 
 def turn_river_config(seed: int = 2, deck_size: int = 52,
@@ -215,11 +251,12 @@ def turn_river_config(seed: int = 2, deck_size: int = 52,
                       pot: float = 100.0, stack: float = 400.0,
                       zero_frac: float = 0.30, tie_p: float = 0.05,
                       n_board: int = 4, cards_per_hand: int = 2,
-                      name: str = "turn_river") -> GameDesc:
+                      name: str = "turn_river", strengths: str = "random") -> GameDesc:
     """Turn-plus-river endgame: n_board (4) fixed cards, a betting round, then a
     chance node revealing one card uniformly from those not on the board or in
     either hand, then a river betting round.  Every possible river board gets
-    its own seeded strength order."""
+    its own seeded strength order (or, with strengths="eval", the hand
+    ranking on that board)."""
     rng = np.random.default_rng([seed, 2])
     board = np.sort(rng.choice(deck_size, size=n_board, replace=False)).astype(np.uint8)
     live = np.array([c for c in range(deck_size) if c not in set(board.tolist())], np.uint8)
@@ -229,7 +266,11 @@ def turn_river_config(seed: int = 2, deck_size: int = 52,
     s = np.zeros((len(rivers), n), dtype=np.int32)
     for bi, r in enumerate(rivers):
         alive = ~(universe == r).any(axis=1)
-        sa = _strength_with_ties(int(alive.sum()), rng, tie_p)
+        if strengths == "random":
+            sa = _strength_with_ties(int(alive.sum()), rng, tie_p)
+        else:
+            sa = _board_strengths(universe[alive], np.sort(np.append(board, r)), deck_size, rng, tie_p,
+                                  strengths)
         s[bi, alive] = sa
         s[bi, ~alive] = -1
     ranges = [_dirichlet_range(n, rng, zero_frac) for _ in range(2)]
@@ -306,6 +347,34 @@ def small_turn_river(seed: int = 0, deck_size: int = 10, n_board: int = 2,
                              zero_frac=zero_frac, tie_p=tie_p, n_board=n_board,
                              cards_per_hand=cards_per_hand,
                              name=f"small_turn{seed}")
+
+
+def libratus_menu(ai: int = 0) -> tuple:
+    """The asymmetric river abstraction of the paper's appendix on the
+    betting abstraction, as a bet_menu: the AI (player ``ai``) opens with
+    0.25 / 0.5 / 1 / 2 / 4 / 8 x pot and answers a check with the same sizes,
+    raises a bet by 0.4 / 0.7 / 1.1 / 2, a single raise by 0.4 / 0.7 / 2 and
+    later raises by 0.7; the opponent opens with 0.35 / 0.65 / 1, answers a
+    check with 0.5 / 0.75 / 1, raises a bet by 0.7 / 1.1 and any raise by 0.7.
+    All-in is offered everywhere; there is no raise cap."""
+    ai_sizes = ((0.25, 0.5, 1.0, 2.0, 4.0, 8.0), (0.25, 0.5, 1.0, 2.0, 4.0, 8.0),
+                (0.4, 0.7, 1.1, 2.0), (0.4, 0.7, 2.0), (0.7,))
+    opp_sizes = ((0.35, 0.65, 1.0), (0.5, 0.75, 1.0), (0.7, 1.1), (0.7,), (0.7,))
+    return (ai_sizes, opp_sizes) if ai == 0 else (opp_sizes, ai_sizes)
+
+
+# raise cap standing in for "no cap": the all-in ends every raise war long before
+LIBRATUS_MAX_RAISES = 64
+
+
+def libratus_river(seed: int = 1, ai: int = 0, pot: float = 100.0, stack: float = 400.0,
+                   zero_frac: float = 0.30, n_keep: Optional[Sequence[int]] = None,
+                   name: str = "libratus_river") -> GameDesc:
+    """A river endgame with hand-ranking strengths and the asymmetric
+    betting abstraction of libratus_menu (otherwise as river_config)."""
+    return river_config(seed=seed, bet_fracs=(1.0,), max_raises=LIBRATUS_MAX_RAISES, pot=pot, stack=stack,
+                        zero_frac=zero_frac, n_keep=n_keep, name=name, strengths="eval",
+                        bet_menu=libratus_menu(ai))
 
 
 def config(k: int, seed: Optional[int] = None):

@@ -38,6 +38,7 @@ class GameDescC(ctypes.Structure):
         ("contrib", ctypes.c_double), ("stack", ctypes.c_double * 2),
         ("n_bet_fracs", ctypes.c_int32), ("bet_fracs", _c_f64p),
         ("max_raises", ctypes.c_int32), ("allow_allin", ctypes.c_int32),
+        ("bet_menu_len", _c_i32p), ("bet_menu", _c_f64p),
     ]
 
 
@@ -232,6 +233,15 @@ class _DescPack:
         c.bet_fracs = _ptr(self.fracs, ctypes.c_double)
         c.max_raises = int(d.max_raises)
         c.allow_allin = 1 if d.allow_allin else 0
+        menu = getattr(d, "bet_menu", None)
+        if menu is not None:
+            if len(menu) != 2 or any(len(m) != 5 for m in menu):
+                raise ValueError("bet_menu needs five lists of fractions per player")
+            self.menu_len = np.array([len(menu[p][k]) for p in range(2) for k in range(5)], dtype=np.int32)
+            self.menu = np.array([float(f) for p in range(2) for k in range(5) for f in menu[p][k]] or [0.0],
+                                 dtype=np.float64)
+            c.bet_menu_len = _ptr(self.menu_len, ctypes.c_int32)
+            c.bet_menu = _ptr(self.menu, ctypes.c_double)
         self.c = c
 
 

@@ -26,7 +26,8 @@ namespace {
 struct Owned {
   std::vector<uint8_t> board, rivers, cards[2];
   std::vector<int32_t> strength[2];
-  std::vector<double> range[2], fracs;
+  std::vector<double> range[2], fracs, menu;
+  std::vector<int32_t> menu_len;
   GameDesc d{};
 };
 
@@ -73,7 +74,17 @@ int main(int argc, char** argv) {
     in >> d.contrib >> d.stack[0] >> d.stack[1] >> nf;
     if (!read_vec(in, o.fracs, nf)) return 2;
     in >> d.max_raises >> d.allow_allin;
+    int has_menu = 0;
+    in >> has_menu;
     if (!in) return 2;
+    if (has_menu) {
+      if (!read_vec(in, o.menu_len, 10)) return 2;
+      size_t tot = 0;
+      for (int32_t l : o.menu_len) tot += (size_t)l;
+      if (!read_vec(in, o.menu, tot)) return 2;
+      d.bet_menu_len = o.menu_len.data();
+      d.bet_menu = o.menu.data();
+    }
     d.n_board = nb;
     d.board = o.board.data();
     d.n_river = nr;

@@ -136,6 +136,122 @@ def test_matvec_river_full_size():
     _check_matvecs(pmx, I.config(1), seed=3)
 
 
+# river endgames with hand-ranking strengths and the asymmetric betting menu
+# of the paper's appendix on Libratus' betting abstraction (166 and 82
+# sequences per player)
+LIBRATUS = [
+    ("libratus_river_full", lambda: I.libratus_river(stack=1000.0)),
+    ("libratus_river_ai2_pruned", lambda: I.libratus_river(seed=3, ai=1, stack=400.0, n_keep=(300, 260))),
+]
+
+
+@pytest.mark.parametrize("name,fn", LIBRATUS)
+def test_matvec_libratus_menu_real_strengths(name, fn):
+    pmx = _need_gpu()
+    d = fn()
+    _say("matvec parity", name)
+    _check_matvecs(pmx, d, seed=5)
+    o = payoff.Game(d)
+    g = pmx.Game(d)
+    rng = np.random.default_rng(6)
+    y = _rand_vectors(o, rng, 1)
+    x = _rand_vectors(o, rng, 0)
+    ref_A, ref_AT = o.matvec_A(y), o.matvec_AT(x)
+    mag_A, mag_AT = payoff.abs_matvec_A(o, y), payoff.abs_matvec_AT(o, x)
+    fl_A = F32_FLOOR * o.abs_row_sums().max() * np.abs(y).max()
+    fl_AT = F32_FLOOR * o.abs_col_sums().max() * np.abs(x).max()
+    yd, xd = _dev(g.pack(1, [y]), np.float32), _dev(g.pack(0, [x]), np.float32)
+    for sched in [(2, 1), (3, 1), (3, 4), (4, 2), (4, 8)]:
+        _say("  schedule", sched)
+        g.game_tune(*sched)
+        Ay = torch.full((g.elems[0],), 3.0, dtype=torch.float32, device="cuda")
+        ATx = torch.full((g.elems[1],), 3.0, dtype=torch.float32, device="cuda")
+        g.matvec_pair(yd, xd, Ay, ATx)
+        torch.cuda.synchronize()
+        _assert_close(g.unpack(0, Ay.cpu().numpy())[0], ref_A, mag_A, 1e-6, fl_A, f"A y {sched}")
+        _assert_close(g.unpack(1, ATx.cpu().numpy())[0], ref_AT, mag_AT, 1e-6, fl_AT, f"A^T x {sched}")
+    g.close()
+
+
+def test_isomorphic_hands_get_equal_values():
+    """A monotone board (the three other suits permute freely) with ranges
+    drawn per suit-isomorphism class and vectors constant on the classes:
+    the oracle's and the device's A y and A^T x are constant on each class,
+    so collapsing each class into one meta-hand (as the paper's experiments
+    do) would lose nothing."""
+    pmx = _need_gpu()
+    from paper_2112_03804_amd import handeval
+    board = [4 * r + 3 for r in (0, 3, 7, 9, 11)]          # 2s 5s 9s Js Ks
+    d = I.river_config(seed=2, board=board, strengths="eval", iso_ranges=True, bet_fracs=(0.5, 1.0),
+                       max_raises=2)
+    _say("isomorphism invariance")
+    cls = handeval.suit_classes(d.hands[0], d.board)
+    assert np.array_equal(d.hands[0], d.hands[1]) and cls.max() + 1 < len(cls) // 2
+    o = payoff.Game(d)
+    g = pmx.Game(d)
+    rng = np.random.default_rng(3)
+    y = rng.random((o.S[1], cls.max() + 1))[:, cls]
+    x = rng.random((o.S[0], cls.max() + 1))[:, cls]
+    Ay = torch.zeros(g.elems[0], dtype=torch.float32, device="cuda")
+    ATx = torch.zeros(g.elems[1], dtype=torch.float32, device="cuda")
+    g.matvec_pair(_dev(g.pack(1, [y]), np.float32), _dev(g.pack(0, [x]), np.float32), Ay, ATx)
+    Ayd = torch.zeros(g.elems[0], dtype=torch.float64, device="cuda")
+    g.matvec_A_f64(_dev(g.pack(1, [y], np.float64), np.float64), Ayd)
+    torch.cuda.synchronize()
+    normA = o.abs_row_sums().max() * np.abs(y).max()
+    normAT = o.abs_col_sums().max() * np.abs(x).max()
+    for got, norm, rel in ((o.matvec_A(y), normA, 1e-12), (o.matvec_AT(x), normAT, 1e-12),
+                           (g.unpack(0, Ay.cpu().numpy())[0].astype(np.float64), normA, 2e-6),
+                           (g.unpack(1, ATx.cpu().numpy())[0].astype(np.float64), normAT, 2e-6),
+                           (g.unpack(0, Ayd.cpu().numpy())[0], normA, 1e-12)):
+        for c in range(cls.max() + 1):
+            v = got[:, cls == c]
+            assert np.abs(v - v[:, :1]).max() <= rel * norm, c
+    g.close()
+
+
+@pytest.mark.parametrize("name,fn", LIBRATUS)
+def test_gap_and_step_libratus_menu(name, fn):
+    """The FP64 gap of given strategies and one RM+ step from a given state
+    on the menu games (trees deeper than one regret-update piece)."""
+    pmx = _need_gpu()
+    d = fn()
+    _say("gap and step parity", name)
+    o = payoff.Game(d)
+    g = pmx.Game(d)
+    rng = np.random.default_rng(12)
+    x, y = _random_plans(o, rng)
+    gap, b1, b2 = g.saddle_gap_of(_dev(g.pack(0, [x], np.float64), np.float64),
+                                  _dev(g.pack(1, [y], np.float64), np.float64))
+    rgap, rb1, rb2 = solver.saddle_gap(o, x, y)
+    pot = 2 * d.contrib
+    assert abs(b1[0] - rb1) <= 1e-9 * pot and abs(b2[0] - rb2) <= 1e-9 * pot
+    assert abs(gap[0] - rgap) <= 1e-9 * pot and gap[0] >= 0
+    ref = solver.RMPlus(o)
+    t0, w0 = 3, 6.0
+    for p in range(2):
+        R = (rng.random((o.S[p], o.N[p])) * 3.0).astype(np.float32).astype(np.float64)
+        xp = ref.tp[p].realization(ref.tp[p].behaviour_from_regret(R)).astype(np.float32).astype(np.float64)
+        sm = rng.random((o.S[p], o.N[p]))
+        ref.R[p], ref.x[p], ref.sum[p] = R, xp, sm.copy()
+        g.solver_set_state(p, regret=g.pack(p, [R]), plan=g.pack(p, [xp]),
+                           avg_sum=g.pack(p, [sm], np.float64), t=t0, wsum=w0)
+    ref.t, ref.wsum = t0, w0
+    g.solver_step(1)
+    torch.cuda.synchronize()
+    ref.step()
+    for p in range(2):
+        st = g.solver_get_state(p)
+        R = g.unpack(p, st["regret"])[0]
+        xp = g.unpack(p, st["plan"])[0]
+        sm = g.unpack(p, st["avg_sum"])[0]
+        scale = max(1.0, np.abs(ref.R[p]).max())
+        assert np.abs(R - ref.R[p]).max() <= 1e-5 * scale, p
+        assert np.abs(xp - ref.x[p]).max() <= 1e-5, p
+        assert np.abs(sm - ref.sum[p]).max() <= 1e-6 * max(1.0, np.abs(ref.sum[p]).max()), p
+    g.close()
+
+
 @pytest.mark.parametrize("kernel", [2, 3, 4])
 def test_matvec_max_hands(kernel):
     """The largest hand lists a game may hold (1280 per player, the top

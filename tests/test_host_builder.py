@@ -44,6 +44,9 @@ GAMES = [
     ("small_turn_1card", lambda: I.small_turn_river(0)),
     ("small_turn_2card", lambda: I.small_turn_river(1, deck_size=9, n_board=3, cards_per_hand=2,
                                                     bet_fracs=(0.5,), max_raises=0, stack=8.0)),
+    ("libratus_river", lambda: I.libratus_river(stack=1000.0)),
+    ("libratus_river_ai2", lambda: I.libratus_river(seed=3, ai=1, stack=400.0, n_keep=(200, 150))),
+    ("turn_menu_eval", lambda: I.turn_river_config(seed=5, bet_fracs=(0.75,), max_raises=1, strengths="eval")),
 ]
 
 
@@ -166,6 +169,17 @@ def test_rejects_invalid_descriptors():
     _bad(lambda d: setattr(d, "deck_size", 70))
     _bad(lambda d: d.strength[1].__setitem__((0, 0), d.strength[1][0, 0] + 1000))  # inconsistent strength
     _bad(lambda d: setattr(d, "river_cards", np.array([0], np.uint8)))             # incomplete river list
+    menu = I.libratus_menu(0)
+    _bad(lambda d: setattr(d, "bet_menu", (menu[0], menu[1][:4] + ((0.7, -0.5),))))
+    _bad(lambda d: setattr(d, "bet_menu", (menu[0], menu[1][:4] + ((0.7,) * 65,))))
+
+
+def test_binding_rejects_a_menu_without_five_situations():
+    d = I.small_river(0)
+    menu = I.libratus_menu(0)
+    d.bet_menu = (menu[0], menu[1][:4])
+    with pytest.raises(ValueError):
+        pmx.Game(d, device=False)
 
 
 def test_rejects_empty_hand_list():

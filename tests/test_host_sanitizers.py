@@ -32,6 +32,12 @@ def _write(descs, path):
         rng = " ".join(repr(float(v)) for p in range(2) for v in np.asarray(d.range_[p]))
         tail = [repr(float(d.contrib)), repr(float(d.stack[0])), repr(float(d.stack[1])), str(len(d.bet_fracs))]
         tail += [repr(float(f)) for f in d.bet_fracs] + [str(int(d.max_raises)), str(1 if d.allow_allin else 0)]
+        menu = getattr(d, "bet_menu", None)
+        if menu is None:
+            tail.append("0")
+        else:
+            tail += ["1"] + [str(len(menu[p][k])) for p in range(2) for k in range(5)]
+            tail += [repr(float(f)) for p in range(2) for k in range(5) for f in menu[p][k]]
         out.append(line + " " + rng + " " + " ".join(tail))
     with open(path, "w") as f:
         f.write("\n".join(out) + "\n")
@@ -65,6 +71,8 @@ CASES = [
     ("river", lambda: [I.config(1)]),
     ("small_river_alone", lambda: [I.small_river(5, deck_size=11, n_keep=(20, 13))]),
     ("uneven_batch", lambda: I.batched_configs(16)),
+    ("libratus_menu", lambda: [I.libratus_river(stack=1000.0, n_keep=(300, 250)),
+                               I.libratus_river(seed=3, ai=1, stack=400.0, n_keep=(40, 60))]),
     ("ragged", lambda: [I.river_config(seed=41, n_keep=(2, 3), bet_fracs=(1.0,), max_raises=1),
                         I.river_config(seed=42, deck_size=57, n_keep=(1280, 1277), bet_fracs=(0.5,),
                                        max_raises=1)]),

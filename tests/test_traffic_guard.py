@@ -33,12 +33,15 @@ def test_code_edits_change_the_hash(tmp_path):
     assert bench.sources_sha1(root) != h0
 
 
-def test_batch_traffic_is_tied_to_its_schedule(monkeypatch):
-    monkeypatch.setattr(bench, "TRAFFIC", {"sources_sha1": bench.sources_sha1(), "river": 7,
+def test_traffic_is_tied_to_its_schedule(monkeypatch):
+    monkeypatch.setattr(bench, "TRAFFIC", {"sources_sha1": bench.sources_sha1(), "river": {"4:1": 7, "3:1": 8},
                                            "batch": {"4:1": 5, "4:2": 6}})
     assert bench.measured_traffic("batch", (4, 1)) == 5
     assert bench.measured_traffic("batch", (4, 2)) == 6
     assert bench.measured_traffic("batch", (3, 8)) is None
-    assert bench.measured_traffic("river") == 7
-    monkeypatch.setattr(bench, "TRAFFIC", {"sources_sha1": "0" * 40, "river": 7, "batch": {"4:2": 6}})
+    assert bench.measured_traffic("river", (4, 1)) == 7
+    assert bench.measured_traffic("river", (3, 1)) == 8
+    assert bench.measured_traffic("river", (2, 1)) is None
+    monkeypatch.setattr(bench, "TRAFFIC", {"sources_sha1": "0" * 40, "river": {"4:1": 7}, "batch": {"4:2": 6}})
     assert bench.measured_traffic("batch", (4, 2)) is None
+    assert bench.measured_traffic("river", (4, 1)) is None
