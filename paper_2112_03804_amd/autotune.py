@@ -5,9 +5,10 @@ kernel 2 / 3 = chunk-aligned scan layout with 256- / 512-thread workgroups,
 rows = output rows per chunk; kernel 4 = grouped layout, rows = groups of
 up to four input rows per chunk; each launched per hands-per-thread class)
 on A y followed by A^T x (two single-direction launches, as the solver
-makes them) with HIP events, keeps the fastest, and remembers the choice in a JSON cache keyed
-by GPU architecture and a size class of the game (instances, rows, largest
-hand count), so later games of the same class are tuned without timing.
+makes them), or on whole solver iterations, with HIP events, keeps the
+fastest, and remembers the choice in a JSON cache keyed by GPU architecture,
+a size class of the game (instances, rows, largest hand count) and the
+objective, so later games of the same class are tuned without timing.
 """
 from __future__ import annotations
 
@@ -77,11 +78,36 @@ def time_schedule(game, kernel: int, rows: int, reps: int = 20, pair: bool = Fal
     return e0.elapsed_time(e1) * 1e3 / reps
 
 
+def time_iterations(game, kernel: int, rows: int, iters: int = 256) -> float:
+    """Average microseconds of one solver iteration under a schedule (the
+    graph-replayed sequence A y, Player 1's update, A^T x, Player 2's
+    update), from a uniform start after one captured warm-up; the solver is
+    left reset."""
+    import torch
+    game.game_tune(kernel, rows)
+    game.solver_reset()
+    game.solver_step(32)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    game.solver_step(iters)
+    e1.record(s)
+    torch.cuda.synchronize()
+    game.solver_reset()
+    return e0.elapsed_time(e1) * 1e3 / iters
+
+
 def tune(game, candidates=None, reps: int = 20, cache_path: Optional[str] = None,
-         use_cache: bool = True) -> Tuple[Tuple[int, int], Dict[str, float]]:
-    """Pick and apply the fastest schedule.  Returns ((kernel, rows), timings)."""
+         use_cache: bool = True, objective: str = "products") -> Tuple[Tuple[int, int], Dict[str, float]]:
+    """Pick and apply the fastest schedule.  Returns ((kernel, rows), timings).
+    objective "products" times A y then A^T x (time_schedule); "iteration"
+    times whole solver iterations (time_iterations; resets the solver), which
+    also sees how the products overlap the regret updates in the graph."""
+    if objective not in ("products", "iteration"):
+        raise ValueError(f"unknown objective {objective!r}")
     cache_path = cache_path or os.environ.get(CACHE_ENV)
-    key = signature(game)
+    key = signature(game) + ("" if objective == "products" else "|iteration")
     cache = _load(cache_path) if cache_path else {}
     if use_cache and key in cache:
         k, r = cache[key]
@@ -89,7 +115,8 @@ def tune(game, candidates=None, reps: int = 20, cache_path: Optional[str] = None
         return (int(k), int(r)), {}
     timings = {}
     for k, r in (candidates or DEFAULT_CANDIDATES):
-        timings[f"{k}:{r}"] = time_schedule(game, k, r, reps)
+        timings[f"{k}:{r}"] = (time_schedule(game, k, r, reps) if objective == "products"
+                               else time_iterations(game, k, r))
     best = min(timings, key=timings.get)
     k, r = (int(v) for v in best.split(":"))
     game.game_tune(k, r)

@@ -1112,3 +1112,30 @@ def test_matvec_through_explicit_technique_b_factors(name, fn):
         assert np.all(blk[:, L["n_hands"]:] == 0)
     assert sizes["nnz_v_pp"] <= sizes["nnz_v"] and sizes["m_dim_pp"] <= sizes["m_dim"]
     g.close()
+
+
+def test_autotuner_picks_the_fastest_timed_schedule_and_caches_it(tmp_path):
+    """Both objectives time every candidate, apply the fastest and store it
+    under a key of their own; a second game of the same size class takes the
+    stored choice without timing.  The iteration objective leaves the solver
+    reset."""
+    pmx = _need_gpu()
+    from paper_2112_03804_amd import autotune
+    d = I.river_config(seed=7, n_keep=(300, 517), bet_fracs=(0.33, 1.5))
+    _say("autotuner")
+    g = pmx.Game(d)
+    cands = [(2, 1), (3, 1), (4, 1)]
+    cache = str(tmp_path / "tune.json")
+    for obj in ("products", "iteration"):
+        sched, t = autotune.tune(g, candidates=cands, cache_path=cache, objective=obj)
+        assert set(t) == {f"{k}:{r}" for k, r in cands} and all(v > 0 for v in t.values())
+        assert t[f"{sched[0]}:{sched[1]}"] == min(t.values())
+        assert g.game_get_tuning() == sched
+        g2 = pmx.Game(d)
+        g2.game_tune(2, 4)
+        sched2, t2 = autotune.tune(g2, candidates=cands, cache_path=cache, objective=obj)
+        assert sched2 == sched and t2 == {} and g2.game_get_tuning() == sched
+        g2.close()
+    st = g.solver_get_state(0)
+    assert st["t"] == 0 and np.all(st["regret"] == 0)
+    g.close()
