@@ -226,7 +226,7 @@ def batched_leg(args, stream):
     from paper_2112_03804_amd import pmx
     from paper_2112_03804_amd import warmstart as ws
 
-    descs = I.batched_configs(args.batch)
+    descs = I.load_json(args.instances) if args.instances else I.batched_configs(args.batch)
     t_create = time.perf_counter()
     g = pmx.Game(descs)
     t_create = time.perf_counter() - t_create
@@ -333,9 +333,11 @@ def batched_leg(args, stream):
     n_seq = [[l[p]["n_seq"] for l in L] for p in range(2)]
     n_hands = [[l[p]["n_hands"] for l in L] for p in range(2)]
     return {
-        "workload": f"{len(descs)} river endgames in one game: hands U[200,1081] per player, 1-3 bet "
-                    "sizes from {0.33,0.5,0.75,1,1.5,2}xpot + all-in, raise caps 2-4, pots U[20,400], "
-                    "stack/pot U[1,10]",
+        "workload": (f"{len(descs)} instances of the spec {os.path.basename(args.instances)} in one game"
+                     if args.instances else
+                     f"{len(descs)} river endgames in one game: hands U[200,1081] per player, 1-3 bet "
+                     "sizes from {0.33,0.5,0.75,1,1.5,2}xpot + all-in, raise caps 2-4, pots U[20,400], "
+                     "stack/pot U[1,10]"),
         "instances": len(descs),
         "sizes": {"sequences_per_player_mean": [float(np.mean(s)) for s in n_seq],
                   "hands_per_player_mean": [float(np.mean(h)) for h in n_hands],
@@ -348,7 +350,7 @@ def batched_leg(args, stream):
         "iteration_ms": it_ms,
         "matvec_pairs_per_s": len(descs) / (it_ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("batch", sched),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None if args.instances else measured_traffic("batch", sched),
                      "kernel": kernel_label(sched),
                      "us_per_launch": pair_us, "algorithmic_bytes_per_launch": bytes_pair},
         "time_to_gap_batched_s": ttg_batched,
@@ -886,6 +888,8 @@ def main():
     ap.add_argument("--cpu-batch-sample", type=int, default=16,
                     help="instances of the batch in the oracle's timed sample")
     ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--instances", default=None,
+                    help="JSON instance spec (instances.save_json) solved as the batch instead of the synthetic one")
     ap.add_argument("--plain-sample", type=int, default=0,
                     help="instances solved by the plain single-instance solver (0: all of the batch)")
     ap.add_argument("--batch-big", type=int, default=2048,
@@ -963,7 +967,7 @@ def main():
         "roofline": batched["roofline"],
     }
     out["batched"] = batched
-    if not args.no_warm:
+    if not args.no_warm and not args.instances:   # the warm start is trained for the synthetic batch
         out["warm_start"] = warm_leg(args, stream, batched)
         log("warm-start leg done")
     river_iters = None
@@ -981,7 +985,8 @@ def main():
         out["turn_river"] = tr
         log("turn+river leg done")
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(args, I.config(1), I.batched_configs(args.batch), gpu_iters=river_iters,
+        cb = cpu_baseline(args, I.config(1), I.load_json(args.instances) if args.instances else
+                          I.batched_configs(args.batch), gpu_iters=river_iters,
                           precision=precision)
         og = cb.pop("precision_run_oracle_gap", None)
         if og is not None:

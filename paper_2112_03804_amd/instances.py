@@ -38,6 +38,10 @@ __all__ = [
     "libratus_menu",
     "libratus_river",
     "config",
+    "to_dict",
+    "from_dict",
+    "save_json",
+    "load_json",
 ]
 
 
@@ -390,3 +394,64 @@ def config(k: int, seed: Optional[int] = None):
     if k in (3, 4):
         return batched_configs(512, seed=3 if seed is None else seed)
     raise ValueError(f"unknown workload {k}")
+
+
+# --------------------------------------------------------------------------
+# JSON instance specs
+# --------------------------------------------------------------------------
+
+SPEC_FORMAT = "pmx-instances"
+SPEC_VERSION = 1
+
+
+def to_dict(d: GameDesc) -> dict:
+    """A JSON-ready dictionary of one instance (exact: floats keep every bit
+    through Python's JSON round trip)."""
+    return {
+        "name": d.name,
+        "deck_size": int(d.deck_size), "cards_per_hand": int(d.cards_per_hand),
+        "board": [int(c) for c in d.board], "river_cards": [int(c) for c in d.river_cards],
+        "hands": [np.asarray(h, dtype=np.int64).tolist() for h in d.hands],
+        "strength": [np.asarray(st, dtype=np.int64).tolist() for st in d.strength],
+        "range": [[float(v) for v in r] for r in d.range_],
+        "contrib": float(d.contrib), "stack": [float(d.stack[0]), float(d.stack[1])],
+        "bet_fracs": [float(f) for f in d.bet_fracs], "max_raises": int(d.max_raises),
+        "allow_allin": bool(d.allow_allin),
+        "bet_menu": None if d.bet_menu is None else [[[float(f) for f in lst] for lst in pl] for pl in d.bet_menu],
+    }
+
+
+def from_dict(o: dict) -> GameDesc:
+    """The instance of a dictionary written by to_dict (or by hand, with the
+    same keys; "name" and "bet_menu" may be left out)."""
+    cph = int(o["cards_per_hand"])
+    menu = o.get("bet_menu")
+    return GameDesc(
+        deck_size=int(o["deck_size"]), cards_per_hand=cph,
+        board=np.array(o["board"], dtype=np.uint8).reshape(-1),
+        river_cards=np.array(o["river_cards"], dtype=np.uint8).reshape(-1),
+        hands=[np.array(h, dtype=np.uint8).reshape(-1, cph) for h in o["hands"]],
+        strength=[np.array(st, dtype=np.int32).reshape(max(1, len(o["river_cards"])), -1) for st in o["strength"]],
+        range_=[np.array(r, dtype=np.float64) for r in o["range"]],
+        contrib=float(o["contrib"]), stack=(float(o["stack"][0]), float(o["stack"][1])),
+        bet_fracs=np.array(o["bet_fracs"], dtype=np.float64), max_raises=int(o["max_raises"]),
+        allow_allin=bool(o["allow_allin"]), name=str(o.get("name", "")),
+        bet_menu=None if menu is None else tuple(tuple(tuple(float(f) for f in lst) for lst in pl) for pl in menu))
+
+
+def save_json(path: str, descs) -> None:
+    """Write one instance or a list of them as a JSON spec."""
+    import json
+    lst = [descs] if isinstance(descs, GameDesc) else list(descs)
+    with open(path, "w") as f:
+        json.dump({"format": SPEC_FORMAT, "version": SPEC_VERSION, "instances": [to_dict(d) for d in lst]}, f)
+
+
+def load_json(path: str) -> List[GameDesc]:
+    """The instances of a JSON spec written by save_json."""
+    import json
+    with open(path) as f:
+        o = json.load(f)
+    if o.get("format") != SPEC_FORMAT or o.get("version") != SPEC_VERSION:
+        raise ValueError(f"{path}: not a {SPEC_FORMAT} version {SPEC_VERSION} file")
+    return [from_dict(x) for x in o["instances"]]
