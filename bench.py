@@ -43,7 +43,7 @@ TRAFFIC_SOURCES = ("paper_2112_03804_amd/csrc/pmx_device.hip", "paper_2112_03804
 # is reported for these only) and the batch schedule of the trace probe
 PROBE_RIVER_SCHEDULES = ((4, 1), (3, 1))
 PROBE_BATCH_SCHEDULES = ((4, 1), (4, 2))
-PROBE_BATCH_SCHEDULE = (4, 2)
+PROBE_BATCH_SCHEDULE = (4, 1)
 
 
 def log(msg):
@@ -568,14 +568,21 @@ def pmc_probe(args):
 
 
 def trace_probe(args):
-    """Launches for a kernel trace of the solver iteration on the batch and on
-    the turn + river game: each at its tuned schedule, a few graph-captured
-    iterations after a warm-up."""
+    """Launches for a kernel trace of the solver iteration: the batch, the turn
+    + river game, the river endgame and the river with Libratus' sizes, each
+    at the schedule the bench's autotuner picks there (``--trace-game``
+    selects one), a few graph-captured iterations after a warm-up, then one
+    FP64 gap."""
     import torch
     from paper_2112_03804_amd import instances as I
     from paper_2112_03804_amd import pmx
-    for name, make, sched, iters in (("batch", lambda: pmx.Game(I.batched_configs(args.batch)), PROBE_BATCH_SCHEDULE, 64),
-                                     ("turn_river", lambda: pmx.Game(I.config(2)), (3, 8), 32)):
+    games = (("batch", lambda: pmx.Game(I.batched_configs(args.batch)), PROBE_BATCH_SCHEDULE, 64),
+             ("turn_river", lambda: pmx.Game(I.config(2)), (3, 8), 32),
+             ("river", lambda: pmx.Game(I.config(1)), (3, 1), 64),
+             ("libratus_river", lambda: pmx.Game(I.libratus_river(stack=1000.0)), (3, 1), 64))
+    for name, make, sched, iters in games:
+        if args.trace_game and name != args.trace_game:
+            continue
         g = make()
         g.game_tune(*sched)
         g.solver_reset()
@@ -585,7 +592,7 @@ def trace_probe(args):
         torch.cuda.synchronize()
         g.saddle_gap()
         torch.cuda.synchronize()
-        print(json.dumps({"probe": name, "iterations": 32 + iters}), flush=True)
+        print(json.dumps({"probe": name, "schedule": list(sched), "iterations": 32 + iters}), flush=True)
         g.close()
 
 
@@ -903,7 +910,9 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run the launches profiled for HBM traffic counters")
     ap.add_argument("--trace-probe", action="store_true",
-                    help="only run solver iterations on the batch and the turn + river game")
+                    help="only run solver iterations on the batch, the turn + river game and the rivers")
+    ap.add_argument("--trace-game", default=None, choices=("batch", "turn_river", "river", "libratus_river"),
+                    help="with --trace-probe: only this game")
     ap.add_argument("--dcfr-sweep", action="store_true",
                     help="only sweep the discounted-CFR parameters (river, batch, turn + river)")
     ap.add_argument("--turn-steps", type=int, default=20)
