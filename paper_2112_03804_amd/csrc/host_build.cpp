@@ -1292,12 +1292,82 @@ int build_grp_layout(HostGame& hg, int d, int gpc, std::string& msg) {
       G.fc = fc;
       G.sc = sc;
     };
+    // a single group of more components whose showdown terms read at most
+    // two of them: those move to 0 and 1 (the only ones given prefix slots),
+    // the fold-only ones to 2 and 3
+    auto sd_comps = [&](int gi) {
+      const GGroup& G = M.groups[gi];
+      int m = 0;
+      for (int o = 0; o < kGrpComps; ++o)
+        if (G.out[o] >= 0 && G.ks[o] != 0.0) m |= 1 << o;   // a plain group's output o: showdown on component o
+      return m;
+    };
+    auto split = [&](int gi) {
+      if (!two_wide || M.groups[gi].ctx < 0) return false;
+      return __builtin_popcount(sd_comps(gi)) <= 2;
+    };
+    auto split_order = [&](int gi) {
+      const int m = sd_comps(gi);
+      GGroup& G = M.groups[gi];
+      int to[kGrpComps], in2[kGrpComps], n = 0;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int j = 0; j < kGrpComps; ++j)
+          if (((m >> j) & 1) == (pass == 0 ? 1 : 0)) {
+            to[j] = n;
+            in2[n++] = G.in[j];
+          }
+      int fc = 0, sc = 0;
+      for (int o = 0; o < kGrpComps; ++o) {
+        fc |= to[(G.fc >> (2 * o)) & 3] << (2 * o);
+        sc |= (((m >> o) & 1) ? to[o] : 0) << (2 * o);   // no showdown term: ks = 0
+      }
+      for (int j = 0; j < kGrpComps; ++j) G.in[j] = in2[j];
+      G.fc = fc;
+      G.sc = sc;
+    };
+    // with two-wide launches, a single group whose showdown terms read more
+    // than two components gives the outputs of all but two of them to a new
+    // group (each output's value comes from one group either way), so that
+    // both are two-wide or split and no four-wide launch is left
+    if (two_wide) {
+      const size_t n_seq_before = seqs.size();
+      for (size_t q = 0; q < n_seq_before; ++q) {
+        if (seqs[q].second - seqs[q].first != 1) continue;
+        const int gi = seqs[q].first;
+        const int m = sd_comps(gi);
+        if (M.groups[gi].ctx < 0 || __builtin_popcount(m) <= 2) continue;
+        GGroup G = M.groups[gi], H = M.groups[gi];
+        int kept = 0;
+        for (int o = 0; o < kGrpComps; ++o) {
+          if (G.out[o] < 0) continue;
+          const bool move = ((m >> o) & 1) && kept++ >= 2;
+          GGroup& drop = move ? G : H;     // the group that loses output o
+          drop.out[o] = -1;
+          drop.ks[o] = drop.kf[o] = 0.0;
+          drop.acc &= ~((1 << o) | (1 << (4 + o)));
+        }
+        for (GGroup* X : {&G, &H})
+          for (int j = 0; j < kGrpComps; ++j) {
+            bool used = false;
+            for (int o = 0; o < kGrpComps; ++o)
+              if (X->out[o] >= 0 && ((o == j && X->ks[o] != 0.0) || (((X->fc >> (2 * o)) & 3) == j && X->kf[o] != 0.0)))
+                used = true;
+            if (!used) X->in[j] = -1;
+          }
+        M.groups[gi] = G;
+        M.groups.push_back(H);
+        seqs.push_back({(int)M.groups.size() - 1, (int)M.groups.size()});
+      }
+    }
     auto kind_of = [&](const std::pair<int, int>& sq) {
       if (sq.second - sq.first > 1) return 1;
-      return narrow(sq.first) ? 2 : 0;
+      return narrow(sq.first) ? 2 : split(sq.first) ? 3 : 0;
     };
-    for (const auto& sq : seqs)
-      if (kind_of(sq) == 2) compact(sq.first);
+    for (const auto& sq : seqs) {
+      const int kd = kind_of(sq);
+      if (kd == 2) compact(sq.first);
+      else if (kd == 3) split_order(sq.first);
+    }
     size_t k = 0;
     while (k < seqs.size()) {
       const int g0 = seqs[k].first;

@@ -636,49 +636,62 @@ __device__ inline void grp_slot(const char* R, uint32_t slot, float (&v)[NC]) {
   GSlot<NC>::ld(R + GSlot<NC>::SB * slot, v);
 }
 
-// Showdown and fold values of the NC components for one own hand from the
-// prefix slots, the segment totals and the identical hand.
-template <int KE, int NC>
-__device__ inline void grp_query(const char* R, const double* segT, uint4 r, int cph, double (&sd)[NC],
-                                 double (&fo)[NC]) {
+// Showdown values of the NS components held in prefix slots and fold values
+// of all NC components for one own hand, from the prefix slots, the segment
+// totals and the identical hand.  With NS == NC the identical hand's value
+// is the difference of the prefix sums at its global entry and the next one;
+// with NS < NC (the fold-only components have no slots) it is read from its
+// staging row in St.
+template <int KE, int NC, int NS>
+__device__ inline void grp_query(const char* R, const char* St, const double* segT, uint4 r, int cph,
+                                 double (&sd)[NS], double (&fo)[NC]) {
   constexpr int BLK = kGrpBlock;
-  float g0[NC], g1[NC], a0[NC], a1[NC];
-  grp_slot<NC>(R, r.x & 0xffffu, g0);
-  grp_slot<NC>(R, r.x >> 16, g1);
-  grp_slot<NC>(R, r.y & 0xffffu, a0);
-  grp_slot<NC>(R, r.y >> 16, a1);
+  float g0[NS], g1[NS], a0[NS], a1[NS];
+  grp_slot<NS>(R, r.x & 0xffffu, g0);
+  grp_slot<NS>(R, r.x >> 16, g1);
+  grp_slot<NS>(R, r.y & 0xffffu, a0);
+  grp_slot<NS>(R, r.y >> 16, a1);
   const int c0 = r.w & 63, c1 = (r.w >> 6) & 63;
   const double* T = segT;   // NC doubles per segment
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
+  for (int j = 0; j < NS; ++j) {
     const double t0 = T[j], ta = T[NC * (1 + c0) + j];
     sd[j] = ((double)(g0[j] + g1[j]) - t0) - ((double)(a0[j] + a1[j]) - ta);
-    fo[j] = t0 - ta;
   }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) fo[j] = T[j] - T[NC * (1 + c0) + j];
   if (cph == 2) {
-    float b0[NC], b1[NC], u[NC];
-    grp_slot<NC>(R, r.z & 0xffffu, b0);
-    grp_slot<NC>(R, r.z >> 16, b1);
+    float b0[NS], b1[NS], u[NC];
+    grp_slot<NS>(R, r.z & 0xffffu, b0);
+    grp_slot<NS>(R, r.z >> 16, b1);
 #pragma unroll
     for (int j = 0; j < NC; ++j) u[j] = 0.f;
     if (r.w & (1u << 12)) {
-      // the identical opponent hand: the difference of the prefix sums at
-      // its global entry and the next one (the next chunk's first entry when
-      // it ends its chunk)
       const uint32_t s0 = r.w >> 14;
-      const uint32_t s1 = (r.w & (1u << 13)) ? s0 - (uint32_t)((KE - 1) * BLK) + 1u : s0 + (uint32_t)BLK;
-      float p0[NC], p1[NC];
-      grp_slot<NC>(R, s0, p0);
-      grp_slot<NC>(R, s1, p1);
+      if (NS == NC) {
+        // the difference of the prefix sums at the identical hand's global
+        // entry and the next one (the next chunk's first entry when it ends
+        // its chunk)
+        const uint32_t s1 = (r.w & (1u << 13)) ? s0 - (uint32_t)((KE - 1) * BLK) + 1u : s0 + (uint32_t)BLK;
+        float p0[NS], p1[NS];
+        grp_slot<NS>(R, s0, p0);
+        grp_slot<NS>(R, s1, p1);
 #pragma unroll
-      for (int j = 0; j < NC; ++j) u[j] = p1[j] - p0[j];
+        for (int j = 0; j < NS; ++j) u[j] = p1[j] - p0[j];
+      } else {
+        // global entry i sits at slot (i % KE) * BLK + i / KE; its staging
+        // row is the one of strength position i
+        const int i = (int)(s0 % (uint32_t)BLK) * KE + (int)(s0 / (uint32_t)BLK);
+        float uv[NC];
+        GSlot<NC>::ld(St + GSlot<NC>::SB * (i + (i >> 4)), uv);   // rows padded one per 16
+#pragma unroll
+        for (int j = 0; j < NC; ++j) u[j] = uv[j];
+      }
     }
 #pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      const double tb = T[NC * (1 + c1) + j];
-      sd[j] -= (double)(b0[j] + b1[j]) - tb;
-      fo[j] += (double)u[j] - tb;
-    }
+    for (int j = 0; j < NS; ++j) sd[j] -= (double)(b0[j] + b1[j]) - T[NC * (1 + c1) + j];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) fo[j] += (double)u[j] - T[NC * (1 + c1) + j];
   }
 }
 
@@ -697,18 +710,32 @@ __device__ inline void grp_query(const char* R, const double* segT, uint4 r, int
 // (the carrying form serves only the few sequences of rows summed over boards).
 // Groups of at most two components (about half of a batch's) take launches
 // of their own with two-wide slots: half the LDS, so more workgroups per CU.
-template <int KH, bool CARRY, int NC>
+// Four-component groups whose showdown terms read only two of them (most of
+// the rest) keep prefix slots for those two (NS = 2): the staging rows of all
+// four sit in a region of their own, and the fold-only components need no
+// slots, only their segment totals and the identical hand's staging row.
+template <int KH, bool CARRY, int NC, int NS>
 constexpr int mvg_waves_per_simd() {
   return NC == 2 ? (KH <= 2 ? 4 : 3)
+       : NS == 2 ? (KH <= 2 ? 4 : KH <= 4 ? 3 : 2)
                  : KH == 1 ? 4 : (KH == 2 || (KH == 3 && !CARRY)) ? 3 : (KH == 5 && CARRY) ? 1 : 2;
 }
 
-template <int KH, int KE, bool CARRY, int NC>
-__global__ __launch_bounds__(kGrpBlock) __attribute__((amdgpu_waves_per_eu(mvg_waves_per_simd<KH, CARRY, NC>())))
+// Bytes of the staging region of a launch whose prefix slots hold fewer
+// components than it stages (NS < NC): 16-byte rows for KH * block hands,
+// one padding row per 16, the zero row and the trash row.
+template <int KH>
+constexpr int grp_stage_bytes() {
+  return 16 * (KH * kGrpBlock + KH * kGrpBlock / 16 + 2);
+}
+
+template <int KH, int KE, bool CARRY, int NC, int NS>
+__global__ __launch_bounds__(kGrpBlock) __attribute__((amdgpu_waves_per_eu(mvg_waves_per_simd<KH, CARRY, NC, NS>())))
 void k_mvg(GParams P0, const float* __restrict__ in0, float* __restrict__ out0, GParams P1,
            const float* __restrict__ in1, float* __restrict__ out1, double* __restrict__ tick) {
-  constexpr int BLK = kGrpBlock, NW = BLK / 64, SB = GSlot<NC>::SB, SH = GSlot<NC>::SH;
+  constexpr int BLK = kGrpBlock, NW = BLK / 64, SH = GSlot<NC>::SH, SBS = GSlot<NS>::SB;
   static_assert(NC == 2 || NC == kGrpComps, "two or four components");
+  static_assert(NS == NC || (NC == kGrpComps && NS == 2 && !CARRY), "prefix slots for all, or two of four");
   static_assert(KE % 2 == 0, "entry sources are stored in pairs");
   if (tick && blockIdx.x == 0 && threadIdx.x == 0) tick[0] += 1.0;
   const int b = xcd_chunk((int)blockIdx.x, P0.nchunk + P1.nchunk);
@@ -723,7 +750,8 @@ void k_mvg(GParams P0, const float* __restrict__ in0, float* __restrict__ out0, 
   extern __shared__ double smem[];
   double* segT = smem;                         // [kMcSegMax][NC] segment totals
   double* scr = segT + NC * kMcSegMax;         // [5 * NW] scan scratch
-  char* R = (char*)(scr + 5 * NW);             // staging rows, then prefix slots (SB bytes each)
+  char* R = (char*)(scr + 5 * NW);             // prefix slots (SBS bytes each), over the staging rows
+  char* St = NS < NC ? R + SBS * KE * BLK : R; //   or staging rows of their own (NS < NC)
 
   const int g0 = cr.x, g1 = cr.y;
   if (cr.w < 0) {
@@ -817,14 +845,14 @@ void k_mvg(GParams P0, const float* __restrict__ in0, float* __restrict__ out0, 
           float w[NC];
 #pragma unroll
           for (int j = 0; j < NC; ++j) w[j] = lop[k] * v[j][k];
-          GSlot<NC>::st(R + (rko[k] >> SH), w);
+          GSlot<NC>::st(St + (rko[k] >> SH), w);
         }
       }
       if (tid == 0) {
         float z[NC];
 #pragma unroll
         for (int j = 0; j < NC; ++j) z[j] = 0.f;
-        GSlot<NC>::st(R + (zrow >> SH), z);
+        GSlot<NC>::st(St + (zrow >> SH), z);
       }
       if (gi + 1 < g1) {
 #pragma unroll
@@ -836,8 +864,10 @@ void k_mvg(GParams P0, const float* __restrict__ in0, float* __restrict__ out0, 
           }
       }
       __syncthreads();
-      // gather the chunk and sum it; carry the sums across the segment's chunks
-      float ev[KE][NC];
+      // gather the chunk and sum it (the entries of the components with
+      // prefix slots stay in registers); carry the sums across the
+      // segment's chunks
+      float ev[KE][NS];
       float s4[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) s4[j] = 0.f;
@@ -845,9 +875,12 @@ void k_mvg(GParams P0, const float* __restrict__ in0, float* __restrict__ out0, 
 #pragma unroll
         for (int i = 0; i < KE; ++i) {
           const uint32_t off = (i & 1) ? srcp[i / 2] >> 16 : srcp[i / 2] & 0xffffu;
-          GSlot<NC>::ld(R + (off >> SH), ev[i]);
+          float evf[NC];
+          GSlot<NC>::ld(St + (off >> SH), evf);
 #pragma unroll
-          for (int j = 0; j < NC; ++j) s4[j] += ev[i][j];
+          for (int j = 0; j < NC; ++j) s4[j] += evf[j];
+#pragma unroll
+          for (int j = 0; j < NS; ++j) ev[i][j] = evf[j];
         }
       }
       double a[NC], e[NC];
@@ -855,24 +888,25 @@ void k_mvg(GParams P0, const float* __restrict__ in0, float* __restrict__ out0, 
       for (int j = 0; j < NC; ++j) a[j] = (double)s4[j];
       block_seg_scan4<NW, NC>((int)((cm >> 8) & 1u), a, scr, e);
       // every gather is done (the scan's barrier): the exclusive prefix sums
-      // overwrite the staging rows, each the FP64 carry's FP32 head plus
-      // (remainder + partial)
+      // of the slotted components overwrite the staging rows (or fill their
+      // own region), each the FP64 carry's FP32 head plus (remainder +
+      // partial)
       if (wlive) {
-        float eh[NC], run[NC];
+        float eh[NS], run[NS];
 #pragma unroll
-        for (int j = 0; j < NC; ++j) {
+        for (int j = 0; j < NS; ++j) {
           eh[j] = (float)e[j];
           run[j] = (float)(e[j] - (double)eh[j]);
         }
 #pragma unroll
         for (int i = 0; i < KE; ++i) {
-          float w[NC];
+          float w[NS];
 #pragma unroll
-          for (int j = 0; j < NC; ++j) {
+          for (int j = 0; j < NS; ++j) {
             w[j] = eh[j] + run[j];
             run[j] += ev[i][j];
           }
-          GSlot<NC>::st(R + SB * (i * BLK + tid), w);
+          GSlot<NS>::st(R + SBS * (i * BLK + tid), w);
         }
       }
       const int endseg = (int)((cm >> 16) & 255u);
@@ -887,21 +921,22 @@ void k_mvg(GParams P0, const float* __restrict__ in0, float* __restrict__ out0, 
 #pragma unroll
       for (int k = 0; k < KH; ++k) {
         const int h = tid + k * BLK;
-        // outputs: four in every kind; components: NC (a two-wide group's
-        // outputs name their showdown component too)
+        // outputs: four in every kind; components: NC, NS of them with
+        // prefix slots (with two, the outputs name their showdown component
+        // as they name their fold component)
         double val[kGrpComps];
 #pragma unroll
         for (int o = 0; o < kGrpComps; ++o) val[o] = 0.0;
         if (h < n_own && qr[k].x != 0xffffffffu) {
-          double sd[NC], fo[NC];
-          grp_query<KE, NC>(R, segT, qr[k], cph, sd, fo);
+          double sd[NS], fo[NC];
+          grp_query<KE, NC, NS>(R, St, segT, qr[k], cph, sd, fo);
 #pragma unroll
           for (int o = 0; o < kGrpComps; ++o) {
             const int fj = (G.fc >> (2 * o)) & 3;
             double f = fo[0];
 #pragma unroll
             for (int c = 1; c < NC; ++c) f = fj == c ? fo[c] : f;
-            const double sv = NC == 2 ? (((G.sc >> (2 * o)) & 3) == 1 ? sd[1] : sd[0]) : sd[o % NC];
+            const double sv = NS == 2 ? (((G.sc >> (2 * o)) & 3) == 1 ? sd[1] : sd[0]) : sd[o % NS];
             val[o] = G.ks[o] * sv + G.kf[o] * f;
           }
         }
@@ -2380,9 +2415,9 @@ static void launch_mc_class(const McParams& A, const IO* in0, IO* out0, const Mc
 // marks the one launch that carries the iteration tick.
 template <typename F>
 static int fork_launches(Game* g, hipStream_t s, int n, const int64_t* work_in, int64_t workgroups, F&& launch) {
-  int order[16];
-  int64_t work[16];
-  if (n > 16) return fail(PMX_EINVAL, "too many concurrent launches");
+  int order[32];
+  int64_t work[32];
+  if (n > 32) return fail(PMX_EINVAL, "too many concurrent launches");
   for (int i = 0; i < n; ++i) {
     order[i] = i;
     work[i] = work_in[i];
@@ -2395,7 +2430,7 @@ static int fork_launches(Game* g, hipStream_t s, int n, const int64_t* work_in, 
   // a fork and join cost about ten microseconds: small products (a single
   // river endgame's) stay on the caller's stream
   const int ns = (g->fork_ok && workgroups >= kForkMinWorkgroups) ? std::min(n, kForkStreams) : 1;
-  int on[16];
+  int on[32];
   int64_t load[kForkStreams] = {};
   for (int i = 0; i < n; ++i) {
     int best = 0;
@@ -2480,14 +2515,14 @@ static GParams grp_params(Game* g, int d, const MvParams& like, int kind, int c)
   return P;
 }
 
-template <int KH, bool CARRY, int NC>
+template <int KH, bool CARRY, int NC, int NS = NC>
 static void launch_grp_class(const GParams& A, const float* in0, float* out0, const GParams& B, const float* in1,
                              float* out1, hipStream_t s, double* tick) {
   constexpr int KE = kGrpKE[KH - 1];
   const size_t lds = sizeof(double) * (NC * kMcSegMax + 5 * (kGrpBlock / 64)) +
-                     (size_t)GSlot<NC>::SB * kGrpBlock * KE;
-  hipLaunchKernelGGL((k_mvg<KH, KE, CARRY, NC>), dim3(A.nchunk + B.nchunk), dim3(kGrpBlock), lds, s, A, in0, out0,
-                     B, in1, out1, tick);
+                     (size_t)GSlot<NS>::SB * kGrpBlock * KE + (NS < NC ? (size_t)grp_stage_bytes<KH>() : 0);
+  hipLaunchKernelGGL((k_mvg<KH, KE, CARRY, NC, NS>), dim3(A.nchunk + B.nchunk), dim3(kGrpBlock), lds, s, A, in0,
+                     out0, B, in1, out1, tick);
 }
 
 // Kernel 4 (FP32 only): one launch per hands-per-thread class present, the
@@ -2501,7 +2536,7 @@ static int launch_grp(Game* g, const MvParams& P0, const float* in0, float* out0
     for (int c = 0; c < kGrpClasses; ++c) {
       const GParams A = grp_params(g, P0.dir, P0, kind, c), B = grp_params(g, P1.dir, P1, kind, c);
       if (A.nchunk + B.nchunk == 0) continue;
-      work[n] = (int64_t)(A.nchunk + B.nchunk) * kGrpKE[c] * (kind == 2 ? 1 : 2);
+      work[n] = (int64_t)(A.nchunk + B.nchunk) * kGrpKE[c] * (kind == 2 ? 2 : kind == 3 ? 3 : 4);
       wgs += A.nchunk + B.nchunk;
       cls[n++] = kind * kGrpClasses + c;
     }
@@ -2525,13 +2560,21 @@ static int launch_grp(Game* g, const MvParams& P0, const float* in0, float* out0
         case 3: launch_grp_class<4, true, 4>(A, in0, out0, B, in1, out1, st, tk); break;
         default: launch_grp_class<5, true, 4>(A, in0, out0, B, in1, out1, st, tk); break;
       }
-    } else {
+    } else if (kind == 2) {
       switch (c) {
         case 0: launch_grp_class<1, false, 2>(A, in0, out0, B, in1, out1, st, tk); break;
         case 1: launch_grp_class<2, false, 2>(A, in0, out0, B, in1, out1, st, tk); break;
         case 2: launch_grp_class<3, false, 2>(A, in0, out0, B, in1, out1, st, tk); break;
         case 3: launch_grp_class<4, false, 2>(A, in0, out0, B, in1, out1, st, tk); break;
         default: launch_grp_class<5, false, 2>(A, in0, out0, B, in1, out1, st, tk); break;
+      }
+    } else {
+      switch (c) {
+        case 0: launch_grp_class<1, false, 4, 2>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 1: launch_grp_class<2, false, 4, 2>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 2: launch_grp_class<3, false, 4, 2>(A, in0, out0, B, in1, out1, st, tk); break;
+        case 3: launch_grp_class<4, false, 4, 2>(A, in0, out0, B, in1, out1, st, tk); break;
+        default: launch_grp_class<5, false, 4, 2>(A, in0, out0, B, in1, out1, st, tk); break;
       }
     }
     return PMX_OK;

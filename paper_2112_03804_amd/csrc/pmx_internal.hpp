@@ -248,9 +248,10 @@ struct GrpDir {
   std::vector<uint16_t> rk;
   // per kind (0: every sequence one group, 1: sequences carrying sums over
   // several groups, 2: as 0 for groups of at most two components, whose
-  // launches use two-wide slots) and class: 4 ints per chunk (g0, g1, inst,
-  // ctx of g0)
-  static constexpr int kKinds = 3;
+  // launches use two-wide slots, 3: as 0 for groups whose showdown terms
+  // read at most two of their components, which alone get prefix slots) and
+  // class: 4 ints per chunk (g0, g1, inst, ctx of g0)
+  static constexpr int kKinds = 4;
   std::vector<int32_t> chunks[kKinds][kGrpClasses];
   int max_chunk[kGrpClasses] = {0, 0, 0, 0, 0};
 };

@@ -50,8 +50,10 @@ extern "C" int grp_matvec(const GameDesc* d, int n, int gpc, int dir, const doub
   };
   for (int cls = 0; cls < kGrpClasses; ++cls) {
     const int KE = kGrpKE[cls], KH = cls + 1;
-    const int region = 16 * BLK * KE;   // bytes of the shared staging / prefix region
     for (int kind = 0; kind < GrpDir::kKinds; ++kind) {
+    // bytes of the staging rows: the shared staging / prefix region, or (kind
+    // 3, prefix slots for two components only) a region of their own
+    const int region = kind == 3 ? 16 * (KH * BLK + KH * BLK / 16 + 2) : 16 * BLK * KE;
     const std::vector<int32_t>& L = M.chunks[kind][cls];
     for (size_t c = 0; c + 3 < L.size(); c += 4) {
       const int g0 = L[c], g1 = L[c + 1];
@@ -65,6 +67,12 @@ extern "C" int grp_matvec(const GameDesc* d, int n, int gpc, int dir, const doub
           for (int o = 0; o < NC; ++o)
             if (((G.fc >> (2 * o)) & 3) >= 2 || ((G.sc >> (2 * o)) & 3) >= 2)
               return fail("a two-wide output names component 2 or 3");
+        } else if (kind == 3) {
+          if ((G.acc >> 4 & 0x0f) != (G.acc & 0x0f)) return fail("a split chunk carries sums");
+          if (G.ctx < 0) return fail("a split group has no context");
+          for (int o = 0; o < NC; ++o)
+            if (G.out[o] >= 0 && G.ks[o] != 0.0 && ((G.sc >> (2 * o)) & 3) >= 2)
+              return fail("a split group's showdown term names a component without prefix slots");
         } else if (G.sc != 0xe4) {
           return fail("a four-wide group permutes its showdown components");
         }
@@ -140,7 +148,19 @@ extern "C" int grp_matvec(const GameDesc* d, int n, int gpc, int dir, const doub
               if (has_self) {
                 const uint32_t s1 = wrap ? s0 - (uint32_t)((KE - 1) * BLK) + 1u : s0 + (uint32_t)BLK;
                 if (s0 >= (uint32_t)(BLK * KE) || s1 >= (uint32_t)(BLK * KE)) return fail("self slot out of range");
-                f += pf(s1, j) - pf(s0, j);
+                if (kind == 3) {
+                  // the kernel reads the identical hand from the staging row
+                  // of global entry i = (s0 % BLK) * KE + s0 / BLK
+                  const int i = (int)(s0 % (uint32_t)BLK) * KE + (int)(s0 / (uint32_t)BLK);
+                  const int row = i + (i >> 4);
+                  if (16 * row + 16 > region) return fail("identical hand's staging row out of the region");
+                  const double u = U[(size_t)row * NC + j];
+                  if (std::fabs(u - (pf(s1, j) - pf(s0, j))) > 1e-9 * (1.0 + std::fabs(u)))
+                    return fail("the identical hand's staging row is not its global entry");
+                  f += u;
+                } else {
+                  f += pf(s1, j) - pf(s0, j);
+                }
               }
             }
             sd[j] = v;

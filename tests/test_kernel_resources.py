@@ -25,7 +25,11 @@ def test_no_scratch_or_spills(source):
 def test_matvec_occupancy_targets():
     """The matvec classes reach the waves per SIMD their launch bounds ask for."""
     res = build.kernel_resources("pmx_device.hip")
-    want = {"_Z5k_mvcILi512ELi3EfEv": 4, "_Z5k_mvcILi256ELi4EfEv": 3, "_Z5k_mvcILi256ELi2EfEv": 4}
+    want = {"_Z5k_mvcILi512ELi3EfEv": 4, "_Z5k_mvcILi256ELi4EfEv": 3, "_Z5k_mvcILi256ELi2EfEv": 4,
+            # grouped kernel: four-wide, two-wide, and four staged with two slotted (k_mvg<KH, KE, CARRY, NC, NS>)
+            "_Z5k_mvgILi4ELi16ELb0ELi4ELi4EEv": 2, "_Z5k_mvgILi4ELi16ELb0ELi2ELi2EEv": 3,
+            "_Z5k_mvgILi3ELi12ELb0ELi4ELi2EEv": 3, "_Z5k_mvgILi4ELi16ELb0ELi4ELi2EEv": 3,
+            "_Z5k_mvgILi2ELi8ELb0ELi4ELi2EEv": 4}
     for prefix, waves in want.items():
         hits = [r for n, r in res.items() if n.startswith(prefix)]
         assert hits, prefix

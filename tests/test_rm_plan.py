@@ -170,6 +170,8 @@ def grp_helper(tmp_path_factory):
 
 
 GRP_CASES = MC_CASES + [
+    # enough rows (at least 1024 per direction) for the two-wide and the split kinds
+    ("batch_24", lambda: I.batched_configs(24, seed=8)),
     ("turn_1card", lambda: [I.small_turn_river(0)]),
     ("river", lambda: [I.config(1)]),
     ("max_hands", lambda: [I.river_config(seed=5, deck_size=57, n_keep=(1280, 1280), bet_fracs=(0.5,),
