@@ -1405,7 +1405,7 @@ int build_grp_layout(HostGame& hg, int d, int gpc, std::string& msg) {
 int build_rm_plan(HostGame& hg, int p, int cap, std::string& msg) {
   RmPlan& P = hg.rm[p];
   P = RmPlan();
-  if (cap < 1 || cap > kTaskRowsMax) {
+  if (cap < 1 || cap > (hg.rm_whole ? kTaskRowsWhole : kTaskRowsMax)) {
     msg = "task_rows must be in [1, " + std::to_string(kTaskRowsMax) + "]";
     return PMX_EINVAL;
   }
@@ -1853,8 +1853,20 @@ int build_game(const GameDesc* descs, int n, HostGame& hg, std::string& msg) {
     build_matvec_plan(hg, d, hg.rows_per_block);
   }
   for (int p = 0; p < 2; ++p) build_treeplex_plan(hg, p);
+  // small games: one piece per treeplex when every instance's fits one and
+  // the whole update stays a launch of few workgroups
+  {
+    bool whole = true;
+    int64_t blocks = 0;
+    for (const Built& b : hg.inst)
+      for (int p = 0; p < 2; ++p) {
+        if (b.sf.n_seq[p] > kTaskRowsWhole || (int)b.sf.inf[p].size() > kTaskInfMax) whole = false;
+        blocks += (b.inst.n[p] + 63) / 64;
+      }
+    hg.rm_whole = whole && blocks <= hg.rm_quad_max;
+  }
   for (int p = 0; p < 2; ++p) {
-    int rc = build_rm_plan(hg, p, hg.task_rows, msg);
+    int rc = build_rm_plan(hg, p, hg.rm_whole ? kTaskRowsWhole : hg.task_rows, msg);
     if (rc) return rc;
   }
   return PMX_OK;

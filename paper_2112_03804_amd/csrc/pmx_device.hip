@@ -1463,7 +1463,7 @@ __device__ inline void rmq_down(float* __restrict__ Al, const float* __restrict_
   }
 }
 
-template <int MODE, bool DC>
+template <int MODE, bool DC, int ROWS = kTaskRowsMax>
 __global__ __launch_bounds__(64 * RMW) void k_rmq(RmParams P, float* __restrict__ g, float* __restrict__ R,
                                                   float* __restrict__ x, double* __restrict__ xs,
                                                   float* __restrict__ stage, const double* __restrict__ tdev) {
@@ -1493,7 +1493,8 @@ __global__ __launch_bounds__(64 * RMW) void k_rmq(RmParams P, float* __restrict_
                        ? (MODE == 1 ? P.ext_slot[T.ext_off + lane] : P.ext_seq[T.ext_off + lane]) : 0;
   // rows 4 (wv + RMW k) + q for k < 4, 16 hands each: lane (hl, q) takes
   // row 4 (wv + RMW k) + q of hand hl
-  constexpr int RQK = kTaskRowsMax / (4 * RMW);
+  constexpr int RQK = ROWS / (4 * RMW);
+  static_assert(ROWS == kTaskRowsMax || MODE == 0, "whole-treeplex pieces have no external parents");
   float c[RQK];
   double d[RQK];
   int rid[RQK];
@@ -1502,7 +1503,7 @@ __global__ __launch_bounds__(64 * RMW) void k_rmq(RmParams P, float* __restrict_
 #pragma unroll
     for (int k = 0; k < RQK; ++k) {
       const int r = min(4 * (wv + RMW * k) + q, SL - 1);
-      rid[k] = T.row0 >= 0 ? T.row0 + r : __shfl(rowv, r, 64);
+      rid[k] = T.row0 >= 0 ? T.row0 + r : r < 64 ? __shfl(rowv, r, 64) : P.rows[T.rows_off + r];
       const int64_t idx = T.vec_base + hc + (int64_t)rid[k] * stride;
       if (MODE != 2) a[k] = g[idx];
       b[k] = R[idx];
@@ -2661,13 +2662,20 @@ static int rm_update(Game* g, int p, hipStream_t s) {
     const RmParams P = rm_params(g, p, d, b0);
     // few workgroups: the walk's latency is the cost, four lanes per hand
     // (k_rmq); many: the bytes are, one lane per hand (k_rmp)
-    const bool quad = nb <= g->hg.rm_quad_max;
+    // pieces beyond a wavefront's rows (whole treeplexes) only fit the
+    // four-lane form
+    const bool whole = P.max_rows > kTaskRowsMax;
+    const bool quad = whole || nb <= g->hg.rm_quad_max;
     const size_t lds = sizeof(float) * (quad ? RQH : 64) * (size_t)(kRmRowLocal + 2 * P.max_rows);
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(quad ? 4 * nb : nb), dim3(64 * RMW), lds, s, P, gr, g->R[p].p, g->x[p].p,
                          g->xs[p].p, E.stage.p, td);
     };
-    if (quad) {
+    if (whole) {
+      // one piece per treeplex: the fused pass only
+      if (P.dcfr) go(k_rmq<0, true, kTaskRowsWhole>);
+      else go(k_rmq<0, false, kTaskRowsWhole>);
+    } else if (quad) {
       if (P.dcfr) {
         if (mode == 0) go(k_rmq<0, true>);
         else if (mode == 1) go(k_rmq<1, true>);
@@ -2967,6 +2975,7 @@ int solver_set_task_rows(Game* g, int32_t rows) {
   if (rc) return rc;
   if (rows < 1 || rows > kTaskRowsMax)
     return fail(PMX_EINVAL, "rows must be in [1, " + std::to_string(kTaskRowsMax) + "]");
+  const bool was_whole = g->hg.rm_whole;
   HIP_TRY(hipDeviceSynchronize());
   if (g->graph_exec) {
     (void)hipGraphExecDestroy(g->graph_exec);
@@ -2976,12 +2985,15 @@ int solver_set_task_rows(Game* g, int32_t rows) {
     (void)hipGraphDestroy(g->graph);
     g->graph = nullptr;
   }
+  // an explicit cut replaces a whole-treeplex plan
+  g->hg.rm_whole = false;
   for (int p = 0; p < 2; ++p) {
     std::string m;
     if ((rc = build_rm_plan(g->hg, p, rows, m))) {
       // keep a consistent plan: rebuild the previous one
       std::string m2;
-      for (int q = 0; q < 2; ++q) (void)build_rm_plan(g->hg, q, g->hg.task_rows, m2);
+      g->hg.rm_whole = was_whole;
+      for (int q = 0; q < 2; ++q) (void)build_rm_plan(g->hg, q, was_whole ? kTaskRowsWhole : g->hg.task_rows, m2);
       for (int q = 0; q < 2; ++q) (void)upload_rm(g, q);
       return fail(rc, m);
     }

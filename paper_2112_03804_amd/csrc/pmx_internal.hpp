@@ -310,6 +310,11 @@ struct TpPlan {                         // one player
 // the parent sequence's realization weight back in its top-down pass.
 constexpr int kTaskRowsMax = 64;        // rows per piece (one per lane of a wavefront)
 constexpr int kTaskInfMax = 64;         // infosets per piece (one per lane)
+// A game whose every treeplex fits one piece of at most kTaskRowsWhole rows
+// (and kTaskInfMax infosets), with few hand blocks in all, takes one piece per
+// treeplex: one fused launch per player, four lanes per hand (16 hands per
+// workgroup keep the rows in LDS; LDS row numbers stay below 256).
+constexpr int kTaskRowsWhole = 192;
 constexpr int kTaskExtMax = 15;         // distinct external parents per piece
 constexpr int kRmGroups = 4;            // subtree groups walked concurrently (wavefronts per block)
 constexpr int kRmGroupSlots = 4;        // distinct parent targets of one group's roots
@@ -385,6 +390,7 @@ struct HostGame {
   RmPlan rm[2];
   int task_rows = kTaskRowsMax;
   int rm_quad_max = 256;                // regret launches of at most this many block records use k_rmq
+  bool rm_whole = false;                // one piece per treeplex (kTaskRowsWhole; see above)
   int max_stride = 0;
 };
 

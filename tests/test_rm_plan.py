@@ -82,6 +82,18 @@ def test_small_caps_give_several_levels_and_groups(helper):
     assert rc != 0 and "task_rows" in msg
 
 
+def test_small_games_take_one_piece_per_treeplex(helper):
+    """A game whose treeplexes each fit one piece of 192 rows (the river
+    with Libratus' sizes: 166 rows, 56 infosets per player) is planned as one
+    piece per player, which the replay still matches; a larger cap is refused
+    where it does not apply (the batch)."""
+    rc, msg, n_tasks, n_grouped, depth = _run(helper, [I.libratus_river(stack=1000.0)], 192)
+    assert rc == 0, msg
+    assert n_tasks == 2 and depth == 0, (n_tasks, depth)   # no deep pieces
+    rc, msg, *_ = _run(helper, I.batched_configs(64), 192)
+    assert rc != 0 and "task_rows" in msg
+
+
 # ---------------------------------------------------------------------------
 # chunk-aligned matvec layout
 # ---------------------------------------------------------------------------
