@@ -1139,3 +1139,38 @@ def test_autotuner_picks_the_fastest_timed_schedule_and_caches_it(tmp_path):
     st = g.solver_get_state(0)
     assert st["t"] == 0 and np.all(st["regret"] == 0)
     g.close()
+
+
+@pytest.mark.parametrize("rows", [1, 2, 8])
+def test_matvec_batch_with_two_wide_and_split_groups(rows):
+    """A batch with enough output rows (at least 1024 per direction) for the
+    two-wide groups and the split groups (prefix slots for the showdown
+    components only, the identical hand read from its staging row): every
+    entry of A y and A^T x against the oracle."""
+    pmx = _need_gpu()
+    descs = I.batched_configs(24, seed=8)
+    _say("matvec parity, batch with two-wide and split groups, groups per chunk", rows)
+    g = pmx.Game(descs)
+    g.game_tune(4, rows)
+    os_ = [payoff.Game(d) for d in descs]
+    assert sum(o.S[0] for o in os_) >= 1024 and sum(o.S[1] for o in os_) >= 1024
+    rng = np.random.default_rng(30 + rows)
+    ys = [_rand_vectors(o, rng, 1) for o in os_]
+    xs = [_rand_vectors(o, rng, 0) for o in os_]
+    Ay = torch.full((g.elems[0],), 9.0, dtype=torch.float32, device="cuda")
+    ATx = torch.full((g.elems[1],), 9.0, dtype=torch.float32, device="cuda")
+    g.matvec_pair(_dev(g.pack(1, ys), np.float32), _dev(g.pack(0, xs), np.float32), Ay, ATx)
+    # the single-direction launches the solver makes give the same bits
+    Ay1 = torch.zeros_like(Ay)
+    ATx1 = torch.zeros_like(ATx)
+    g.matvec_A(_dev(g.pack(1, ys), np.float32), Ay1)
+    g.matvec_AT(_dev(g.pack(0, xs), np.float32), ATx1)
+    torch.cuda.synchronize()
+    assert torch.equal(Ay, Ay1) and torch.equal(ATx, ATx1)
+    gA, gAT = g.unpack(0, Ay.cpu().numpy()), g.unpack(1, ATx.cpu().numpy())
+    for i, o in enumerate(os_):
+        fl = F32_FLOOR * o.abs_row_sums().max() * np.abs(ys[i]).max()
+        _assert_close(gA[i], o.matvec_A(ys[i]), payoff.abs_matvec_A(o, ys[i]), 1e-6, fl, f"A y inst {i}")
+        fl = F32_FLOOR * o.abs_col_sums().max() * np.abs(xs[i]).max()
+        _assert_close(gAT[i], o.matvec_AT(xs[i]), payoff.abs_matvec_AT(o, xs[i]), 1e-6, fl, f"A^T x inst {i}")
+    g.close()
