@@ -2526,6 +2526,21 @@ static void launch_grp_class(const GParams& A, const float* in0, float* out0, co
                      out0, B, in1, out1, tick);
 }
 
+// Weights for spreading a product's class launches over the streams (longest
+// first, each to the least loaded stream).  A single-direction product (the
+// solver's) weighs a class by per-workgroup durations measured on a batch of
+// river endgames, by kind and class, plus a floor for the latency of a launch
+// whose workgroups fit one round (the smallest and the largest hand classes);
+// a pair launch, whose classes cover both directions, balances by scan
+// entries, which measured better there.
+static constexpr int64_t kGrpWgNs[GrpDir::kKinds][kGrpClasses] = {
+    {300, 35, 57, 51, 127}, {300, 35, 57, 51, 127}, {200, 22, 31, 25, 59}, {300, 27, 44, 39, 98}};
+
+static int64_t grp_launch_weight(int kind, int c, int nchunk, bool pair) {
+  if (pair) return (int64_t)nchunk * kGrpKE[c] * (kind == 2 ? 2 : kind == 3 ? 3 : 4);
+  return (int64_t)nchunk * kGrpWgNs[kind][c] + (kind == 2 ? 5000 : 7000) * (c == kGrpClasses - 1 ? 4 : 1);
+}
+
 // Kernel 4 (FP32 only): one launch per hands-per-thread class present, the
 // classes concurrently (fork_launches).
 static int launch_grp(Game* g, const MvParams& P0, const float* in0, float* out0, const MvParams& P1,
@@ -2537,7 +2552,7 @@ static int launch_grp(Game* g, const MvParams& P0, const float* in0, float* out0
     for (int c = 0; c < kGrpClasses; ++c) {
       const GParams A = grp_params(g, P0.dir, P0, kind, c), B = grp_params(g, P1.dir, P1, kind, c);
       if (A.nchunk + B.nchunk == 0) continue;
-      work[n] = (int64_t)(A.nchunk + B.nchunk) * kGrpKE[c] * (kind == 2 ? 2 : kind == 3 ? 3 : 4);
+      work[n] = grp_launch_weight(kind, c, A.nchunk + B.nchunk, A.nchunk > 0 && B.nchunk > 0);
       wgs += A.nchunk + B.nchunk;
       cls[n++] = kind * kGrpClasses + c;
     }
