@@ -640,23 +640,25 @@ void build_matvec_plan(HostGame& hg, int d, int rows_per_block) {
     }
     const int64_t out_base = b.vec_off[p], in_base = b.vec_off[q];
     const int64_t sp = b.stride[p], sq = b.stride[q];
-    auto emit_row = [&](int sg) {
+    // the items of contributions cl[c0, c1) (sorted by context) of row sg,
+    // written to element offset `out` of the output (last = 1) or of the
+    // partial buffer (last = 2)
+    auto emit_items = [&](int sg, size_t c0, size_t c1, int64_t out, int last) {
       // group this row's contributions by context; pair a fold and a showdown input per item
-      std::vector<Contrib>& cl = rows[sg];
-      std::stable_sort(cl.begin(), cl.end(), [](const Contrib& a, const Contrib& c) { return a.ctx < c.ctx; });
-      size_t i = 0;
+      const std::vector<Contrib>& cl = rows[sg];
+      size_t i = c0;
       const size_t first_item = D.items.size();
-      while (i < cl.size()) {
+      while (i < c1) {
         size_t j = i;
         std::vector<const Contrib*> fs, ss;
-        while (j < cl.size() && cl[j].ctx == cl[i].ctx) {
+        while (j < c1 && cl[j].ctx == cl[i].ctx) {
           (cl[j].fold ? fs : ss).push_back(&cl[j]);
           ++j;
         }
         size_t k = std::max(fs.size(), ss.size());
         for (size_t t = 0; t < k; ++t) {
           MvItem it{};
-          it.out = out_base + sg * sp;
+          it.out = out;
           it.n_own = in.n[p];
           it.stride = b.stride[p];
           it.ctx = ctx_base + cl[i].ctx;
@@ -678,7 +680,12 @@ void build_matvec_plan(HostGame& hg, int d, int rows_per_block) {
         it.in_f = it.in_s = -1;
         D.items.push_back(it);
       }
-      D.items.back().last = 1;
+      D.items.back().last = last;
+    };
+    auto emit_row = [&](int sg) {
+      std::vector<Contrib>& cl = rows[sg];
+      std::stable_sort(cl.begin(), cl.end(), [](const Contrib& a, const Contrib& c) { return a.ctx < c.ctx; });
+      emit_items(sg, 0, cl.size(), out_base + sg * sp, 1);
     };
     auto n_ctx_of = [&](int sg) {
       int prev = -2, cnt = 0;
@@ -709,9 +716,40 @@ void build_matvec_plan(HostGame& hg, int d, int rows_per_block) {
       }
       if (cnt) { D.blk.push_back((int32_t)D.items.size()); D.blk_inst.push_back((int32_t)ii); }
     }
+    // a row over more contexts than a chunk's rows: parts of about that many
+    // contexts, each a chunk writing a partial row (one workgroup would
+    // otherwise walk every context in turn, the product's longest chain)
+    const int per_part = std::max(1, rows_per_block);
     for (int sg : multi) {
-      emit_row(sg);
-      { D.blk.push_back((int32_t)D.items.size()); D.blk_inst.push_back((int32_t)ii); }
+      std::vector<Contrib>& cl = rows[sg];
+      std::stable_sort(cl.begin(), cl.end(), [](const Contrib& a, const Contrib& c) { return a.ctx < c.ctx; });
+      std::vector<size_t> cut{0};   // first contribution of each context
+      for (size_t i = 1; i < cl.size(); ++i)
+        if (cl[i].ctx != cl[i - 1].ctx) cut.push_back(i);
+      const int nc = (int)cut.size();
+      cut.push_back(cl.size());
+      if (nc <= per_part) {
+        emit_items(sg, 0, cl.size(), out_base + sg * sp, 1);
+        D.blk.push_back((int32_t)D.items.size());
+        D.blk_inst.push_back((int32_t)ii);
+        continue;
+      }
+      const int n_parts = (nc + per_part - 1) / per_part;
+      MvRed r{};
+      r.out = out_base + sg * sp;
+      r.part = D.part_elems;
+      r.n_parts = n_parts;
+      r.stride = (int32_t)sp;
+      r.inst = (int32_t)ii;
+      for (int j = 0; j < n_parts; ++j) {
+        // contexts [j nc / n_parts, (j + 1) nc / n_parts): parts differ by at most one context
+        const int k0 = (int)((int64_t)j * nc / n_parts), k1 = (int)((int64_t)(j + 1) * nc / n_parts);
+        emit_items(sg, cut[k0], cut[k1], r.part + (int64_t)j * sp, 2);
+        D.blk.push_back((int32_t)D.items.size());
+        D.blk_inst.push_back((int32_t)ii);
+      }
+      D.part_elems += (int64_t)n_parts * sp;
+      D.red.push_back(r);
     }
     {
       int cnt = 0;

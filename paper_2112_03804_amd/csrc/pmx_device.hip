@@ -175,6 +175,7 @@ struct McParams {
   const double* lam;
   const float* lamf;
   const int32_t* active;         // per-instance flag (NULL: all)
+  void* part;                    // partial rows of rows cut into parts (IO elements)
   double scale;
   int32_t nchunk;
 };
@@ -464,13 +465,34 @@ void k_mvc(McParams P0, const IO* __restrict__ in0, IO* __restrict__ out0,
       }
     }
     if (item.last) {
+      IO* __restrict__ dst = item.last == 2 ? (IO*)P.part : out;
 #pragma unroll
       for (int k = 0; k < KH; ++k) {
         const int h = tid + k * BLOCK;
-        if (h < item.stride) out[item.out + h] = (IO)(h < n_own ? P.scale * (double)lo[k] * acc[k] : 0.0);
+        if (h < item.stride) dst[item.out + h] = (IO)(h < n_own ? P.scale * (double)lo[k] * acc[k] : 0.0);
         acc[k] = 0.0;
       }
     }
+  }
+}
+
+// Rows cut into parts: each output row is the sum of its partial rows, taken
+// in part order (FP64 sum, one rounding to IO).  One workgroup per row of
+// either direction; rows of retired instances are skipped.
+template <typename IO>
+__global__ __launch_bounds__(256) void k_mv_reduce(const MvRed* __restrict__ r0, int n0, const IO* __restrict__ part0,
+                                                   IO* __restrict__ out0, const MvRed* __restrict__ r1,
+                                                   const IO* __restrict__ part1, IO* __restrict__ out1,
+                                                   const int32_t* __restrict__ active) {
+  const bool second = (int)blockIdx.x >= n0;
+  const MvRed r = second ? r1[blockIdx.x - n0] : r0[blockIdx.x];
+  if (active && !active[r.inst]) return;
+  const IO* __restrict__ part = (second ? part1 : part0) + r.part;
+  IO* __restrict__ out = (second ? out1 : out0) + r.out;
+  for (int h = threadIdx.x; h < r.stride; h += 256) {
+    double v = 0.0;
+    for (int j = 0; j < r.n_parts; ++j) v += (double)part[(int64_t)j * r.stride + h];
+    out[h] = (IO)v;
   }
 }
 
@@ -1884,7 +1906,9 @@ struct DBuf {
 
 struct DevDir {                 // the row chunks of one direction (the layouts' shared item list)
   DBuf<MvItem> items;
-  int nblk = 0;
+  DBuf<MvRed> red;              // rows summed from partial rows
+  DBuf<double> part;            // partial rows (FP32 products use the first half)
+  int nblk = 0, nred = 0;
 };
 
 struct DevMc {                  // chunk-aligned matvec layout of one direction
@@ -2169,6 +2193,9 @@ static int upload_dir(Game* g, int d) {
   DevDir& E = g->dd[d];
   if ((rc = E.items.upload(D.items))) return rc;
   E.nblk = (int)D.blk.size() - 1;
+  if ((rc = E.red.upload(D.red))) return rc;
+  E.nred = (int)D.red.size();
+  if ((rc = E.part.alloc((size_t)std::max<int64_t>(D.part_elems, 1)))) return rc;
   g->dg[d].built = false;
   if (hg.mv_kernel == 4 && (rc = upload_grp(g, d))) return rc;
   return upload_mc(g, d);
@@ -2367,6 +2394,7 @@ static McParams mc_params(Game* g, int d, const MvParams& like, int c) {
   P.lam = g->lam.p;
   P.lamf = g->lamf.p;
   P.active = like.active;
+  P.part = g->dd[d].part.p;
   P.scale = like.scale;
   P.nchunk = like.nblk > 0 ? (solver ? E.count_act[c] : E.count[c]) : 0;
   return P;
@@ -2494,6 +2522,12 @@ static int launch_mc(Game* g, const MvParams& P0, const IO* in0, IO* out0, const
   if (rc) return rc;
   // every instance retired from the lists: the iteration still counts
   if (n == 0 && tick) hipLaunchKernelGGL(k_add1, dim3(1), dim3(1), 0, s, tick);
+  // rows cut into parts: sum the partial rows (after the join into s)
+  const int nr0 = P0.nblk > 0 ? g->dd[P0.dir].nred : 0, nr1 = P1.nblk > 0 ? g->dd[P1.dir].nred : 0;
+  if (n > 0 && nr0 + nr1 > 0)
+    hipLaunchKernelGGL((k_mv_reduce<IO>), dim3(nr0 + nr1), dim3(256), 0, s, g->dd[P0.dir].red.p, nr0,
+                       (const IO*)g->dd[P0.dir].part.p, out0, g->dd[P1.dir].red.p,
+                       (const IO*)g->dd[P1.dir].part.p, out1, P0.active);
   HIP_TRY(hipGetLastError());
   return PMX_OK;
 }

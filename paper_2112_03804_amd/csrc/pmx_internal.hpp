@@ -136,15 +136,28 @@ struct MvCtx {                          // (instance, context) as seen by one di
 struct MvItem {
   int64_t out, in_f, in_s;              // element offsets (in_* = -1: absent)
   int32_t ctx;                          // -1: the row has no terminal, write zeros
-  int32_t last;                         // 1: last item of its output row
+  int32_t last;                         // 1: last item of its output row; 2: last item of a
+                                        //    partial row (out indexes the direction's partial buffer)
   int32_t n_own, stride;                // output row length and padded stride
   double kf, ks;                        // coefficients (payoff x chance)
   int32_t run_end;                      // one past the last item of this chunk with the same ctx
   int32_t n_opp;                        // opponent hands of the context (0 without one)
 };
+// An output row whose terms span many board contexts (a turn all-in run-out
+// sums over every river card) is cut into parts of a few contexts each; the
+// parts run as chunks of their own and write partial rows, which one more
+// launch sums in part order into the output row.
+struct MvRed {
+  int64_t out;                          // element offset of the output row
+  int64_t part;                         // element offset of its first partial row (rows `stride` apart)
+  int32_t n_parts, stride;              // partial rows; row length incl. padding
+  int32_t inst, pad;                    // instance (skipped when retired)
+};
 struct MvDir {                          // host copy of one direction's plan
   std::vector<MvCtx> ctx;
   std::vector<MvItem> items;
+  std::vector<MvRed> red;               // rows summed from partial rows
+  int64_t part_elems = 0;               // length of the partial buffer
   std::vector<int32_t> blk;             // item ranges: blk[b] .. blk[b+1]
   std::vector<int32_t> blk_inst;        // instance of each chunk
   std::vector<QueryRec16> q;

@@ -42,6 +42,7 @@ extern "C" int mc_matvec(const GameDesc* d, int n, int block, int dir, const dou
       lam_opp.push_back(&b.lam[1 - dir]);
     }
   for (int64_t i = 0; i < out_len; ++i) out[i] = 0.0;
+  std::vector<double> part((size_t)D.part_elems, 0.0);
   for (int cls = 0; cls < kMcClasses; ++cls) {
     const int ke = mc_ke(block, cls + 1), sk = mc_sk(ke), nslot = block * sk;
     const std::vector<int32_t>& L = M.chunks[cls];
@@ -107,12 +108,21 @@ extern "C" int mc_matvec(const GameDesc* d, int n, int block, int dir, const dou
           acc[h] += (item.in_s >= 0 ? sd : 0.0) + (item.in_f >= 0 ? fo : 0.0);
         }
         if (item.last) {
-          for (int h = 0; h < C.n_own; ++h) out[item.out + h] = (*lam_own[item.ctx])[h] * acc[h];
+          // last = 2: a partial row of a row cut into parts
+          double* dst = item.last == 2 ? part.data() : out;
+          for (int h = 0; h < C.n_own; ++h) dst[item.out + h] = (*lam_own[item.ctx])[h] * acc[h];
           acc.assign(C.n_own, 0.0);
         }
       }
     }
   }
-  snprintf(msg, msglen, "ok");
+  // rows cut into parts: the sum of their partial rows in part order
+  for (const MvRed& r : D.red)
+    for (int h = 0; h < r.stride; ++h) {
+      double v = 0.0;
+      for (int j = 0; j < r.n_parts; ++j) v += part[(size_t)(r.part + (int64_t)j * r.stride + h)];
+      out[r.out + h] = v;
+    }
+  snprintf(msg, msglen, "ok parts=%d", (int)D.red.size());
   return 0;
 }
