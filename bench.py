@@ -35,9 +35,9 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
 # known size (profiles/matvec_pair_traffic_counters.md).  They describe the
 # kernel sources whose code (comments and whitespace removed) has the SHA-1
 # recorded here and are reported as null for any other version of that code.
-TRAFFIC = {"sources_sha1": "821d90dc505e6a6a9ef15169a69f47f3c9a6dc02",
-           "river": {"4:1": 1393608, "3:1": 1637258},
-           "batch": {"4:1": 351623682, "4:2": 351282754}}
+TRAFFIC = {"sources_sha1": "c20201a0c633536cff3f342b511300e6ece60a70",
+           "river": {"4:1": 1421393, "3:1": 1623947},
+           "batch": {"4:1": 351616011, "4:2": 351270363}}
 TRAFFIC_SOURCES = ("paper_2112_03804_amd/csrc/pmx_device.hip", "paper_2112_03804_amd/csrc/host_build.cpp")
 # the schedules of the counter probe (the autotuner's usual choices; traffic
 # is reported for these only) and the batch schedule of the trace probe
